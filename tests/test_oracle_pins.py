@@ -1,0 +1,489 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each checks a closed form, an
+invariant, a bound the paper proves, a textbook definition evaluated by brute
+force, or an independent implementation (rocRAND's Philox engine).
+"""
+
+import itertools
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, philox, sipf, stencil
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10 and the normal stream
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    gxx = shutil.which("g++")
+    hdr = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+    if gxx is None or not os.path.exists(hdr):
+        pytest.skip("g++ or rocRAND headers not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rr")
+    src = os.path.join(HERE, "helpers", "rocrand_philox_ref.cpp")
+    subprocess.run([gxx, "-O1", "-std=c++17", "-w", "-D__HIP_PLATFORM_AMD__",
+                    "-I/opt/rocm/include", src, "-o", exe], check=True)
+    return exe
+
+
+def test_philox_matches_rocrand_engine(rocrand_ref):
+    rng = np.random.default_rng(1)
+    rows = rng.integers(0, 2 ** 32, size=(300, 6), dtype=np.uint64)
+    rows[0] = 0
+    rows[1] = 2 ** 32 - 1
+    rows[2, :4] = np.arange(4)
+    inp = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_ref], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(t) for t in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
+    got = np.stack(philox.philox4x32_10(*[rows[:, i] for i in range(6)]), axis=1)
+    assert np.array_equal(got, ref)
+
+
+def test_uniforms_exact_in_float32_and_open_interval():
+    r = np.array([0, 1, 511, 512, 2 ** 31, 2 ** 32 - 1], dtype=np.uint64)
+    u = philox.uniforms(r)
+    assert np.array_equal(u.astype(np.float32).astype(np.float64), u)
+    assert u.min() == 2.0 ** -24 and u.max() == 1.0 - 2.0 ** -24
+
+
+def test_normals_statistics():
+    ids = np.arange(400_000, dtype=np.uint64)
+    z = philox.normals3(ids, 7, 0, seed=123)
+    n = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    # fourth moment of N(0,1) is 3
+    assert abs((z ** 4).mean() - 3.0) < 0.05
+    # components and neighbouring ids are uncorrelated
+    c = np.corrcoef(z.T)
+    assert np.abs(c - np.eye(3)).max() < 5 / math.sqrt(ids.size)
+    lag = np.corrcoef(z[:-1, 0], z[1:, 0])[0, 1]
+    assert abs(lag) < 5 / math.sqrt(ids.size)
+    # different slots / steps give independent streams
+    z2 = philox.normals3(ids, 7, 1, seed=123)
+    z3 = philox.normals3(ids, 8, 0, seed=123)
+    assert abs(np.corrcoef(z[:, 0], z2[:, 0])[0, 1]) < 5 / math.sqrt(ids.size)
+    assert abs(np.corrcoef(z[:, 0], z3[:, 0])[0, 1]) < 5 / math.sqrt(ids.size)
+
+
+# ---------------------------------------------------------------------------
+# Stencils (Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+def _lams(n=200, seed=0):
+    lam = np.random.default_rng(seed).random((n, 3))
+    lam[0] = 0.0
+    lam[1] = [0.5, 0.5, 0.5]
+    lam[2] = [1 - 1e-12, 0.25, 0.0]
+    return lam
+
+
+@pytest.mark.parametrize("order,deg", [(2, 1), (4, 3)])
+def test_stencil_reproduces_polynomials(order, deg):
+    """I_eta is exact for polynomials of degree <= eta - 1 (proof of Lemma Thm:P2G)."""
+    lam = _lams()
+    F = stencil.weights(lam, order)
+    offs = stencil.offsets(order).astype(np.float64)
+    assert F.shape[1] == (8 if order == 2 else 32)
+    for a, b, c in itertools.product(range(deg + 1), repeat=3):
+        if a + b + c > deg:
+            continue
+        nodes = offs[:, 0] ** a * offs[:, 1] ** b * offs[:, 2] ** c      # p(gamma)
+        exact = lam[:, 0] ** a * lam[:, 1] ** b * lam[:, 2] ** c         # p(lambda)
+        assert np.allclose(F @ nodes, exact, atol=1e-13, rtol=0), (a, b, c)
+
+
+def test_order4_not_exact_for_degree4():
+    lam = _lams()
+    F = stencil.weights(lam, 4)
+    offs = stencil.offsets(4).astype(np.float64)
+    assert not np.allclose(F @ offs[:, 0] ** 4, lam[:, 0] ** 4, atol=1e-6)
+
+
+def test_order4_outer_cluster_identity():
+    """-(F_211 + F_121 + F_112) = l1 l2 l3 (3 - |l|^2) / 6 (proof of Lemma Thm:P2G)."""
+    lam = _lams()
+    F = stencil.weights(lam, 4)
+    offs = [tuple(o) for o in stencil.offsets(4)]
+    s = sum(F[:, offs.index(o)] for o in [(2, 1, 1), (1, 2, 1), (1, 1, 2)])
+    l1, l2, l3 = lam.T
+    assert np.allclose(-s, l1 * l2 * l3 * (3 - l1 ** 2 - l2 ** 2 - l3 ** 2) / 6, atol=1e-15)
+    # the 8 clusters (one per inner vertex) sum to <= 1/2 in magnitude
+    outer = F[:, 8:].sum(axis=1)
+    assert np.all(-outer <= 0.5 + 1e-15) and np.all(outer <= 1e-15)
+
+
+def test_order4_printed_axis1_rows():
+    """The two axis-1 outer rows printed in eq. 4ord, evaluated directly."""
+    lam = _lams()
+    F = stencil.weights(lam, 4)
+    offs = [tuple(o) for o in stencil.offsets(4)]
+    l1, l2, l3 = lam.T
+    for j2, j3 in itertools.product((0, 1), repeat=2):
+        t = (1 - j2 + (2 * j2 - 1) * l2) * (1 - j3 + (2 * j3 - 1) * l3)
+        assert np.allclose(F[:, offs.index((2, j2, j3))], -(1 + l1) * (1 - l1) * l1 * t / 6, atol=1e-15)
+        assert np.allclose(F[:, offs.index((-1, j2, j3))], -(2 - l1) * l1 * (1 - l1) * t / 6, atol=1e-15)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_stencil_derivatives_match_finite_differences(order):
+    lam = np.random.default_rng(3).uniform(0.05, 0.95, (50, 3))
+    d = stencil.dweights(lam, order)
+    e = 1e-6
+    for a in range(3):
+        lp, lm = lam.copy(), lam.copy()
+        lp[:, a] += e
+        lm[:, a] -= e
+        fd = (stencil.weights(lp, order) - stencil.weights(lm, order)) / (2 * e)
+        assert np.allclose(d[..., a], fd, atol=1e-8)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_deposit_continuous_across_cell_faces(order):
+    """The weights glue continuously across faces, so the deposit is continuous in X."""
+    H, L = 8, 2.0
+    h = L / H
+    rng = np.random.default_rng(5)
+    for axis in range(3):
+        X = rng.uniform(-0.5, 0.5, (1, 3))
+        X[0, axis] = 3 * h
+        lo, hi = X.copy(), X.copy()
+        lo[0, axis] -= 1e-12
+        a = sipf.deposit(lo, 1.0, H, L, order)
+        b = sipf.deposit(hi, 1.0, H, L, order)
+        assert np.abs(a - b).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Deposit / interpolation (Definitions particle2grid, grid2particle)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_deposit_conserves_mass(order):
+    """Sum of phi equals M0 for any particle set (Sec. 3.4 mass conservation)."""
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-1, 1, (5000, 3))
+    X[:10] = -1.0   # on the lower box face
+    X[10:20] = 1.0 - 1e-15
+    phi = sipf.deposit(X, 37.0 / X.shape[0], 16, 2.0, order)
+    assert abs(phi.sum() - 37.0) < 1e-12 * 37
+
+
+def test_deposit_translation_by_one_cell_is_a_roll():
+    """Shifting all particles by exactly h shifts phi by one index (node g at g mod H)."""
+    H, L = 16, 2.0
+    h = L / H
+    X = np.random.default_rng(2).uniform(-1, 1, (3000, 3))
+    for axis in range(3):
+        Xs = X.copy()
+        Xs[:, axis] = sipf.wrap(Xs[:, axis] + h, L)
+        a = np.roll(sipf.deposit(X, 1.0, H, L, 4), 1, axis=axis)
+        b = sipf.deposit(Xs, 1.0, H, L, 4)
+        assert np.abs(a - b).max() < 1e-13
+
+
+def test_single_particle_moments_about_its_position():
+    """Interior particle: sum_j phi_j p(x_j) = w p(X) for all cubic p (order 4)."""
+    H, L = 16, 2.0
+    h = L / H
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        X = rng.uniform(-0.4, 0.4, (1, 3))
+        phi = sipf.deposit(X, 1.0, H, L, 4)
+        q = sipf.freqs(H) * h        # node coordinate of array index k
+        x, y, z = np.meshgrid(q, q, q, indexing="ij")
+        for a, b, c in itertools.product(range(4), repeat=3):
+            if a + b + c > 3:
+                continue
+            lhs = (phi * x ** a * y ** b * z ** c).sum()
+            rhs = X[0, 0] ** a * X[0, 1] ** b * X[0, 2] ** c
+            assert abs(lhs - rhs) < 1e-13
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_p2g_g2p_adjoint_relation(order):
+    """<I rho, f> = <rho, I* f> (Sec. 3.1)."""
+    H, L = 8, 2.0
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (300, 3))
+    w = rng.random(300)
+    f = rng.standard_normal((H, H, H))
+    lhs = (sipf.deposit(X, w, H, L, order) * f).sum()
+    rhs = (w * sipf.interp(f, X, H, L, order)).sum()
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+# ---------------------------------------------------------------------------
+# Transforms (Sec. 3.1 F_H convention) against the naive DFT
+# ---------------------------------------------------------------------------
+
+def _naive_dft(f, sign):
+    H = f.shape[0]
+    j = np.arange(H)
+    out = np.zeros((H, H, H), dtype=np.complex128)
+    for a, b, c in itertools.product(range(H), repeat=3):
+        ph = np.exp(sign * 2j * np.pi * (a * j[:, None, None] + b * j[None, :, None] + c * j[None, None, :]) / H)
+        out[a, b, c] = (f * ph).sum()
+    return out
+
+
+@pytest.mark.parametrize("H", [4, 8])
+def test_transforms_equal_naive_dft(H):
+    L = 2.0
+    rng = np.random.default_rng(H)
+    phi = rng.standard_normal((H, H, H))
+    assert np.abs(sipf.forward_transform(phi, L) - _naive_dft(phi, -1) / L ** 3).max() < 1e-13 * H ** 3
+    a = rng.standard_normal((H, H, H)) + 1j * rng.standard_normal((H, H, H))
+    assert np.abs(sipf.inverse_transform(a) - _naive_dft(a, +1)).max() < 1e-12 * H ** 3
+
+
+def test_inverse_of_forward_on_grid_delta():
+    """F_H^{-1} F_H of a unit delta at a node is (H/L)^3 there and 0 elsewhere (Sec. 3.1)."""
+    H, L = 8, 2.0
+    h = L / H
+    d = np.zeros((H, H, H))
+    d[3, 5, 1] = 1.0 / h ** 3          # grid delta of unit mass as a cell density
+    rt = sipf.inverse_transform(sipf.forward_transform(d * h ** 3, L))
+    expect = np.zeros((H, H, H))
+    expect[3, 5, 1] = (H / L) ** 3
+    assert np.abs(rt - expect).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Error bounds of Lemmas Thm:P2G and Thm:G2P against the direct SIPF sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order,C", [(2, 9 / 2), (4, 513 / 16)])
+def test_p2g_spectral_error_bound(order, C):
+    L, M0 = 2.0, 5.0
+    X = np.random.default_rng(11).uniform(-1, 1, (40, 3))
+    prev = None
+    for H in (8, 16, 32):
+        h = L / H
+        beta_pic = sipf.forward_transform(sipf.deposit(X, M0 / 40, H, L, order), L)
+        beta_dir = sipf.direct_beta(X, M0, H, L)
+        xi = sipf.wavevectors(H, L)
+        y = np.sqrt((xi ** 2).sum(axis=0))
+        err = np.abs(beta_pic - beta_dir)
+        bound = C * M0 * L ** -3 * y ** order * h ** order
+        assert np.all(err <= bound + 1e-13)
+        # at the fixed mode q = (1, 1, 0) the error falls like h^order
+        e = err[1, 1, 0]
+        if prev is not None:
+            assert e < prev / (2 ** order) * 1.6
+        prev = e
+
+
+@pytest.mark.parametrize("order,C", [(2, 9 / 2), (4, 513 / 16)])
+def test_g2p_error_bound(order, C):
+    H, L = 16, 2.0
+    h = L / H
+    q = np.array([1.0, 2.0, -1.0]) * 2 * np.pi / L
+    nodes = sipf.freqs(H) * h
+    x, y, z = np.meshgrid(nodes, nodes, nodes, indexing="ij")
+    f = np.sin(q[0] * x + q[1] * y + q[2] * z + 0.3)
+    X = np.random.default_rng(6).uniform(-1, 1, (500, 3))
+    exact = np.sin(X @ q + 0.3)
+    err = np.abs(sipf.interp(f, X, H, L, order) - exact)
+    Dmax = np.abs(q).max() ** order    # max over |k| = order of |D_k f|
+    assert err.max() <= C * Dmax * h ** order
+
+
+# ---------------------------------------------------------------------------
+# Closed forms of the spectral update (eq. alpha_hat_update)
+# ---------------------------------------------------------------------------
+
+def test_zero_mode_closed_form():
+    """alpha_0^(n) = (tau M0 / (eps L^3)) sum_{s=1}^n (1 + tau k^2 / eps)^-s for any trajectory."""
+    prm = sipf.Params(L=2.0, chi=1.0, mu=1.0, eps=0.5, k=2.0, M0=60.0, dt=1e-3, H=8)
+    X0 = np.random.default_rng(0).normal(0, 0.1, (300, 3))
+    n = 15
+    _, alpha = sipf.run(X0, prm, n)
+    r = 1.0 / (1.0 + prm.dt * prm.k ** 2 / prm.eps)
+    expect = prm.dt * prm.M0 / (prm.eps * prm.L ** 3) * r * (1 - r ** n) / (1 - r)
+    assert abs(alpha[0, 0, 0].real - expect) < 1e-14 * expect * n
+    assert abs(alpha[0, 0, 0].imag) < 1e-15
+    # integral of c equals L^3 alpha_0 (Sec. 3.4 total-concentration statement, implicit form)
+    c = sipf.inverse_transform(alpha).real
+    assert abs(c.mean() - expect) < 1e-13
+
+
+def test_zero_mode_value_at_config1():
+    """The q = 0 coefficient after 100 steps of the H=32, P=1e4 FP64 workload."""
+    tau, M0, L, eps, k = 1e-4, 60.0, 2.0, 1.0, 1.0
+    r = 1 / (1 + tau * k ** 2 / eps)
+    val = tau * M0 / (eps * L ** 3) * r * (1 - r ** 100) / (1 - r)
+    assert abs(val - 0.0746225344409289) < 1e-15
+
+
+def _single_mode(prm, qs, amp):
+    H = prm.H
+    a = np.zeros((H, H, H), dtype=np.complex128)
+    idx = tuple(q % H for q in qs)
+    nidx = tuple((-q) % H for q in qs)
+    a[idx] = amp
+    a[nidx] = np.conj(amp)
+    return a
+
+
+def test_single_mode_decay_and_gradient():
+    """M0 = 0: alpha_q^(n) = A_q^n alpha_q^(0); grid gradient = Phi_q grad c exactly."""
+    prm = sipf.Params(L=2.0, chi=0.0, mu=0.0, eps=1.0, k=1.0, M0=0.0, dt=1e-4, H=16)
+    qs = (1, 2, -3)
+    amp = 0.3 - 0.2j
+    a0 = _single_mode(prm, qs, amp)
+    X0 = np.zeros((4, 3))
+    _, a = sipf.run(X0, prm, 100, alpha0=a0)
+    xi = np.array(qs) * 2 * np.pi / prm.L
+    A = 1 / (1 + prm.dt / prm.eps * ((xi ** 2).sum() + prm.k ** 2))
+    assert abs(a[tuple(q % 16 for q in qs)] - amp * A ** 100) < 1e-15
+    # continuous analogue exp(-(|xi|^2 + k^2) t), within implicit Euler's n (a tau)^2 / 2
+    at = prm.dt * ((xi ** 2).sum() + 1)
+    assert abs(A ** 100 - math.exp(-100 * at)) < 100 * at ** 2 / 2
+    # c(x) = 2 Re(amp e^{i xi.x});  grad c = -2 xi Im(amp e^{i xi.x})... computed by calculus
+    G = sipf.gradient_grid(a0, prm)
+    h = prm.L / prm.H
+    nodes = sipf.freqs(prm.H) * h
+    x, y, z = np.meshgrid(nodes, nodes, nodes, indexing="ij")
+    th = xi[0] * x + xi[1] * y + xi[2] * z
+    Phi = math.exp(-2 * math.pi ** 2 * sum(q * q for q in qs) / prm.h0() ** 2)
+    # d/dx_d [2 (Re amp cos th - Im amp sin th)] = -2 xi_d (Re amp sin th + Im amp cos th)
+    for d in range(3):
+        expect = -2 * xi[d] * (amp.real * np.sin(th) + amp.imag * np.cos(th)) * Phi
+        assert np.abs(G[d] - expect).max() < 1e-12
+
+
+def test_filter_scale_rule():
+    """H0 = ceil(8 H^(8/13) L^(5/13)) (Sec. 5.1) at L = 2."""
+    vals = [sipf.Params(H=H, L=2.0).h0() for H in (32, 64, 128)]
+    assert vals == [89.0, 136.0, 207.0]
+    assert sipf.Params(H=8, L=8.0).h0() == math.ceil(8 * 8 ** (8 / 13) * 8 ** (5 / 13))
+
+
+# ---------------------------------------------------------------------------
+# Particle branch (Algorithm 4, eq. rho_hat_update)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", ["strang", "em"])
+def test_brownian_variance_at_zero_chemotaxis(scheme):
+    """chi = 0: each coordinate of X^(n) - X^(0) has variance 2 mu n tau."""
+    prm = sipf.Params(L=2.0, chi=0.0, mu=0.7, eps=1.0, k=1.0, M0=1.0, dt=2e-4, H=8, scheme=scheme)
+    P, n = 40_000, 6
+    X0 = np.random.default_rng(1).uniform(-1, 1, (P, 3))
+    X, _ = sipf.run(X0, prm, n)
+    D = sipf.min_image(X - X0, prm.L)
+    var = 2 * prm.mu * n * prm.dt
+    assert np.all(np.abs(D.mean(axis=0)) < 5 * math.sqrt(var / P))
+    assert np.all(np.abs(D.var(axis=0) - var) < 5 * var * math.sqrt(2.0 / P))
+
+
+def test_first_step_has_no_drift():
+    """alpha^(0) = 0: step 1 gathers grad c^(0) = 0, so X^(1) - X^(0) is pure noise."""
+    prm = sipf.Params(L=2.0, chi=5.0, mu=1.0, eps=1.0, k=1.0, M0=80.0, dt=1e-4, H=16)
+    X0 = np.random.default_rng(2).normal(0, 0.1, (500, 3))
+    X1, _ = sipf.run(X0, prm, 1)
+    ids = np.arange(500, dtype=np.uint64)
+    Z = philox.normals3(ids, 1, 0, 0) + philox.normals3(ids, 1, 1, 0)
+    assert np.abs(sipf.min_image(X1 - X0 - math.sqrt(prm.mu * prm.dt) * Z, 2.0)).max() < 1e-15
+    X2, _ = sipf.run(X0, prm, 2)
+    ids2 = philox.normals3(ids, 2, 0, 0) + philox.normals3(ids, 2, 1, 0)
+    pure = sipf.min_image(X2 - X1 - math.sqrt(prm.mu * prm.dt) * ids2, 2.0)
+    assert np.abs(pure).max() > 1e-8   # the second step does feel the field
+
+
+def test_drift_follows_the_filtered_gradient():
+    """mu = 0: one step moves a particle by chi tau I*(Phi grad c)(X), within the G2P bound."""
+    prm = sipf.Params(L=2.0, chi=2.0, mu=0.0, eps=1.0, k=1.0, M0=0.0, dt=1e-3, H=32)
+    qs = (1, 0, 2)
+    amp = 0.5 + 0.1j
+    a0 = _single_mode(prm, qs, amp)
+    X0 = np.random.default_rng(3).uniform(-1, 1, (200, 3))
+    X1, _ = sipf.run(X0, prm, 2, alpha0=a0)
+    # step 1 uses grad c^(0); step 2 uses grad c^(1) = A_q * grad c^(0)
+    xi = np.array(qs) * 2 * np.pi / prm.L
+    A = 1 / (1 + prm.dt * ((xi ** 2).sum() + 1))
+    Phi = math.exp(-2 * math.pi ** 2 * sum(q * q for q in qs) / prm.h0() ** 2)
+    def grad(X):
+        th = X @ xi
+        return (-2 * (amp.real * np.sin(th) + amp.imag * np.cos(th)))[:, None] * xi[None] * Phi
+    Xa = X0 + prm.chi * prm.dt * grad(X0)
+    Xb = Xa + prm.chi * prm.dt * A * grad(Xa)
+    h = prm.L / prm.H
+    K2 = 4.5 * 2 * abs(amp) * np.abs(xi).max() ** 3
+    assert np.abs(sipf.min_image(X1 - Xb, 2.0)).max() < 2 * prm.chi * prm.dt * K2 * h ** 2
+
+
+def test_sipf_pic_approaches_direct_sipf():
+    """With the same noise and a fixed filter scale H0 (so the field is resolved at
+    every H), SIPF-PIC positions approach those of the direct O(PH^3) SIPF sums
+    at second order in h (the G2P order; Lemmas Thm:P2G and Thm:G2P)."""
+    rng = np.random.default_rng(8)
+    X0 = rng.normal(0, 0.25, (60, 3))
+    errs = []
+    for H in (8, 16, 32):
+        prm = sipf.Params(L=2.0, chi=1.0, mu=0.2, eps=1.0, k=1.0, M0=200.0, dt=2e-3, H=H, H0=5.0)
+        Xp, ap = X0.copy(), np.zeros((H, H, H), complex)
+        Xd, ad = X0.copy(), np.zeros((H, H, H), complex)
+        for n in range(1, 4):
+            Xp, ap = sipf.step(Xp, ap, n, prm)
+            Xd, ad = sipf.sipf_direct_step(Xd, ad, n, prm, use_filter=True)
+        errs.append(np.abs(sipf.min_image(Xp - Xd, 2.0)).max())
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+
+
+def test_half_spectrum_round_trip():
+    H = 8
+    phi = np.random.default_rng(0).standard_normal((H, H, H))
+    full = np.fft.fftn(phi)
+    assert np.abs(sipf.full_spectrum(sipf.half_spectrum(full)) - full).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Pathwise adjoint against central finite differences
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", ["strang", "em"])
+def test_adjoint_matches_finite_differences(scheme):
+    prm = sipf.Params(L=2.0, chi=1.5, mu=0.8, eps=1.0, k=1.0, M0=80.0, dt=2e-3, H=8, scheme=scheme)
+    rng = np.random.default_rng(21)
+    X0 = rng.normal(0, 0.2, (48, 3))
+    N = 3
+    loss, gX, gchi, gmu = adjoint.loss_and_grad(X0, prm, N)
+    assert abs(loss - adjoint.loss_only(X0, prm, N)) < 1e-12 * loss
+    e = 1e-6
+    def fd_param(name):
+        p1 = sipf.Params(**{**prm.__dict__, name: getattr(prm, name) + e})
+        p0 = sipf.Params(**{**prm.__dict__, name: getattr(prm, name) - e})
+        return (adjoint.loss_only(X0, p1, N) - adjoint.loss_only(X0, p0, N)) / (2 * e)
+    assert abs(gchi - fd_param("chi")) < 1e-5 * max(1.0, abs(gchi))
+    assert abs(gmu - fd_param("mu")) < 1e-5 * max(1.0, abs(gmu))
+    for p, a in [(0, 0), (5, 1), (17, 2), (33, 0), (47, 1)]:
+        Xp, Xm = X0.copy(), X0.copy()
+        Xp[p, a] += e
+        Xm[p, a] -= e
+        fd = (adjoint.loss_only(Xp, prm, N) - adjoint.loss_only(Xm, prm, N)) / (2 * e)
+        assert abs(gX[p, a] - fd) < 1e-5 * max(1.0, np.abs(gX).max())
+
+
+def test_adjoint_linear_functional_cotangent():
+    """With a given phi_bar the loss is linear in phi^(N); checked by finite differences."""
+    prm = sipf.Params(L=2.0, chi=1.0, mu=1.0, eps=1.0, k=1.0, M0=40.0, dt=1e-3, H=8)
+    rng = np.random.default_rng(22)
+    X0 = rng.normal(0, 0.2, (32, 3))
+    pb = rng.standard_normal((8, 8, 8))
+    _, gX, gchi, _ = adjoint.loss_and_grad(X0, prm, 2, phi_bar=pb)
+    e = 1e-6
+    p1 = sipf.Params(**{**prm.__dict__, "chi": prm.chi + e})
+    p0 = sipf.Params(**{**prm.__dict__, "chi": prm.chi - e})
+    fd = (adjoint.loss_only(X0, p1, 2, phi_bar=pb) - adjoint.loss_only(X0, p0, 2, phi_bar=pb)) / (2 * e)
+    assert abs(gchi - fd) < 1e-6 * max(1.0, abs(fd))
