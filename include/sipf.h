@@ -1,0 +1,239 @@
+/*
+ * sipf.h -- C ABI of the SIPF-PIC time step on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the stochastic interacting particle-field method with
+ * particle-in-cell acceleration of Hu, Wang, Xin and Zhang (arXiv:2512.03452)
+ * for the 3-D parabolic-parabolic Keller-Segel system
+ *     rho_t = div(mu grad rho - chi rho grad c),
+ *     eps c_t = lap c - k^2 c + rho                       (eq. para_system)
+ * on the periodic box [-L/2, L/2)^3 (Sec. 2.2).  One step (Algorithm 4):
+ *   1. deposit the P equal-mass particles onto the H^3 grid with the
+ *      fourth-order stencil (Definition particle2grid, Algorithm 2);
+ *   2. forward FFT, beta_q = L^-3 sum_j phi_j exp(-2 pi i q.j/H) (Sec. 3.1);
+ *   3. implicit mode update alpha_q <- A_q alpha_q + B_q beta_q
+ *      (eq. alpha_hat_update);
+ *   4. spectral gradient of the previous field with the Gaussian filter
+ *      Phi_q = exp(-2 pi^2 |q|^2 / H0^2), inverse FFT to the grid (Algorithm 4);
+ *   5. trilinear interpolation back to the particles (Definition
+ *      grid2particle, Algorithm 3) and the stochastic push: split
+ *      (W^- , drift, W^+; Algorithm 4) or Euler-Maruyama (eq. rho_hat_update).
+ * Both branches of step n read the state after step n-1 (Algorithm 4), so the
+ * gradient gathered in step n is that of alpha^(n-1).
+ *
+ * Conventions for every function below:
+ *   - Return value: SIPF_OK (0) or a negative SIPF_E* code.  The message of the
+ *     last failure on the calling thread is returned by sipf_last_error().
+ *     No C++ exception crosses this interface.
+ *   - Positions are P x 3, row-major (x, y, z per particle), in the context's
+ *     precision (float for SIPF_FP32, double for SIPF_FP64), in original
+ *     particle order.  "on_device" arguments say whether a pointer is device
+ *     memory (1) or host memory (0); device pointers must be on the current
+ *     HIP device.
+ *   - Spectral arrays are the Hermitian half spectrum of a real field:
+ *     H x H x (H/2+1) interleaved complex (re, im) values, index
+ *     (kx, ky, kz) at (kx*H + ky)*(H/2+1) + kz; array index k stands for the
+ *     frequency q = k for k < H/2 and q = k - H otherwise (kz = 0..H/2).
+ *   - Grids are H x H x H real arrays, index (ix, iy, iz) at (ix*H + iy)*H + iz;
+ *     node g (integer vector, position g*L/H) is stored at g mod H.
+ *   - All work is enqueued on the context's HIP stream and is asynchronous
+ *     unless stated otherwise.  A context is not thread-safe; distinct
+ *     contexts are independent.  After SIPF_EDEVICE the context must be
+ *     destroyed.
+ *   - H must be a power of two with 8 <= H <= 128 (FP32) or 8 <= H <= 64
+ *     (FP64): one yz-plane of the half spectrum must fit in the 160 KB of LDS
+ *     of a gfx950 compute unit.  Other sizes return SIPF_EINVAL.
+ */
+#ifndef SIPF_H
+#define SIPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SIPF_OK        0
+#define SIPF_EINVAL   (-1)  /* invalid argument or parameter; nothing was touched */
+#define SIPF_ENOMEM   (-2)  /* device or host allocation failed */
+#define SIPF_EDEVICE  (-3)  /* HIP runtime error; destroy the context */
+#define SIPF_ENUMERIC (-4)  /* NaN/Inf in inputs or produced by a step */
+#define SIPF_ESTATE   (-5)  /* call not valid in the context's current state */
+#define SIPF_EIO      (-6)  /* snapshot file missing, truncated or corrupt */
+
+/* particle push (Algorithm 4 split step, or eq. rho_hat_update) */
+#define SIPF_STRANG 0       /* X' = wrap(Y + chi tau I*grad c(Y) + W+), Y = X + W-, W+- ~ N(0, mu tau) */
+#define SIPF_EM     1       /* X' = wrap(X + chi tau I*grad c(X) + W),  W ~ N(0, 2 mu tau) */
+
+/* arithmetic precision of particles, grids and spectra */
+#define SIPF_FP32 0
+#define SIPF_FP64 1
+
+/* fields for sipf_get_field */
+#define SIPF_FIELD_RHO   0  /* deposit of the current positions, mass units, H^3 real */
+#define SIPF_FIELD_ALPHA 1  /* current alpha^(n), half spectrum */
+#define SIPF_FIELD_GRAD  2  /* grad c of alpha^(n) on the grid (filtered), 3 x H^3 real, d-major */
+
+/*
+ * Problem and discretisation parameters.  Physical constants follow
+ * eq. para_system; H, H0 and tau follow Algorithm 4; the default H0 rule is
+ * the one of Sec. 5.1.  Fill with sipf_params_default() and override.
+ */
+typedef struct sipf_params {
+    double   L;            /* box side; Omega = [-L/2, L/2)^3, periodic            */
+    double   chi;          /* chemotactic sensitivity (>= 0)                      */
+    double   mu;           /* particle diffusivity (>= 0)                         */
+    double   eps;          /* relaxation constant of c (> 0)                      */
+    double   k;            /* degradation constant of c (>= 0)                    */
+    double   M0;           /* total mass of the particles (>= 0)                  */
+    double   dt;           /* time step tau (> 0)                                 */
+    double   H0;           /* filter scale; 0: ceil(8 H^(8/13) L^(5/13)); <0: off */
+    int32_t  H;            /* grid points per axis (power of two, see above)      */
+    int32_t  p2g_order;    /* must be 4 (Remark after Definition grid2particle)  */
+    int32_t  g2p_order;    /* must be 2 (same remark)                             */
+    int32_t  scheme;       /* SIPF_STRANG (default) or SIPF_EM                    */
+    int32_t  precision;    /* SIPF_FP32 (default) or SIPF_FP64                    */
+    int32_t  tile;         /* binning tile side in cells; 0 = tuned default        */
+    int32_t  resort_every; /* re-sort period in steps; 0 = tuned default           */
+    int32_t  chunk;        /* particles per workgroup of the particle pass; 0 = tuned */
+    uint64_t seed;         /* Philox key                                          */
+    uint32_t instance;     /* fourth Philox counter word                          */
+    uint32_t reserved;     /* must be 0                                           */
+} sipf_params;
+
+typedef struct sipf_ctx sipf_ctx;
+typedef struct sipf_batch sipf_batch;
+
+/* Fill *p with the defaults (L = 2, chi = mu = eps = k = 1, M0 = 1,
+ * dt = 1e-4, H = 64, H0 = 0, orders 4/2, Strang, FP32, seed 0). */
+int sipf_params_default(sipf_params* p);
+
+/*
+ * Create a simulation context (Algorithm 4 initialisation).
+ *   P          number of particles (1 <= P < 2^32); each carries mass M0/P
+ *              (eq. def_rho_hat).
+ *   X0         initial positions, P x 3 in the context precision (host or
+ *              device per x0_on_device); wrapped into [-L/2, L/2) on entry.
+ *   alpha0     initial coefficients of c (half spectrum, context precision,
+ *              host or device per alpha0_on_device), or NULL for c(x,0) = 0.
+ *   hip_stream hipStream_t the context enqueues on (NULL = default stream).
+ * The inputs are copied into library-owned device memory and the stream is
+ * synchronised before return, so the caller may free X0/alpha0 afterwards.
+ * Errors: SIPF_EINVAL (bad parameter), SIPF_ENUMERIC (NaN/Inf in X0),
+ * SIPF_ENOMEM, SIPF_EDEVICE.  On error *out is NULL.
+ */
+int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_device,
+              const void* alpha0, int alpha0_on_device, void* hip_stream, sipf_ctx** out);
+
+/* Advance one step n-1 -> n (Algorithm 4).  Asynchronous. */
+int sipf_step(sipf_ctx* ctx);
+
+/* Advance nsteps >= 0 steps.  Asynchronous; replays a captured HIP graph of
+ * the step sequence when the same count is requested again. */
+int sipf_run(sipf_ctx* ctx, int64_t nsteps);
+
+/* Wait for the context's stream and report any device-side error flag
+ * (SIPF_ENUMERIC for a non-finite position). */
+int sipf_sync(sipf_ctx* ctx);
+
+/* Number of completed steps n (synchronises). */
+int sipf_get_step(sipf_ctx* ctx, int64_t* n);
+
+/* Current positions X^(n) in original particle order into a caller-owned
+ * P x 3 buffer (host or device).  Synchronises. */
+int sipf_get_positions(sipf_ctx* ctx, void* out, int on_device);
+
+/* A field of the current state into a caller-owned buffer (see SIPF_FIELD_*;
+ * sizes H^3, H*H*(H/2+1) complex, 3*H^3 in the context precision).
+ * Synchronises. */
+int sipf_get_field(sipf_ctx* ctx, int which, void* out, int on_device);
+
+/*
+ * Pathwise adjoint (reverse mode along the fixed Philox noise path).
+ * Runs nsteps forward steps from the current state (which must be the
+ * initial state, n = 0, with alpha0 = 0; otherwise SIPF_ESTATE), storing the
+ * positions every ckpt_every steps and alpha every step, then the reverse
+ * sweep, recomputing positions inside each checkpoint segment.
+ *   phi_bar  device pointer to dL/dphi^(N) (H^3, context precision) for a
+ *            loss linear in the final deposit, or NULL for L = sum_j phi_j^2,
+ *            phi the order-4 deposit of X^(N) in mass units (Algorithm 2).
+ *   loss     out: L (host double).
+ *   dchi,dmu out: dL/dchi, dL/dmu (host doubles).
+ *   dX0      out: dL/dX^(0), device buffer P x 3 in original particle order.
+ * floor() is treated as locally constant and the periodic wrap as the
+ * identity (both hold almost everywhere).  After return the context holds
+ * X^(N), alpha^(N) (n = nsteps).  Synchronises.
+ */
+int sipf_adjoint(sipf_ctx* ctx, int64_t nsteps, int32_t ckpt_every, const void* phi_bar,
+                 double* loss, double* dchi, double* dmu, void* dX0);
+
+/* Per-phase timing with HIP events recorded on the context's stream around
+ * every launch of the step's kernels (enable = 1 starts it, 0 stops it; the
+ * accumulators are cleared on enable).  sipf_profile_read synchronises and
+ * writes, for each of the SIPF_NPHASES phases (SIPF_PHASE_*), the summed
+ * duration in milliseconds and the number of launches timed.  Used by the
+ * benchmark to measure the dominant kernel live on the library's stream. */
+#define SIPF_PHASE_SORT      0  /* tile sort (histogram, scan, scatter)           */
+#define SIPF_PHASE_PARTICLES 1  /* fused deposit + gather + push                  */
+#define SIPF_PHASE_FWD       2  /* forward yz-plane pass                          */
+#define SIPF_PHASE_XPENCIL   3  /* x pencils + mode update + gradient spectra     */
+#define SIPF_PHASE_INV       4  /* inverse yz-plane pass                          */
+#define SIPF_NPHASES         5
+int sipf_profile(sipf_ctx* ctx, int enable);
+int sipf_profile_read(sipf_ctx* ctx, double* ms, int64_t* launches);
+
+/* Snapshot (parameters, n, positions in original order, alpha) to a file and
+ * back; a loaded context continues bit-for-bit like the saved one would,
+ * since the noise is a function of (id, n).  sipf_load: SIPF_EIO on a
+ * missing, truncated or corrupt file. */
+int sipf_save(sipf_ctx* ctx, const char* path);
+int sipf_load(const char* path, void* hip_stream, sipf_ctx** out);
+
+/* Release all device memory of the context (NULL is a no-op). */
+int sipf_destroy(sipf_ctx* ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* sipf_last_error(void);
+
+/*
+ * Batched ensembles: n independent instances (each its own parameters,
+ * including H, chi, M0, seed and instance word; all must share the precision)
+ * advanced together -- one persistent launch for all particle passes and one
+ * batched launch per FFT phase and grid size per step.
+ *   P[i]   particles of instance i;  X0[i] host pointer to P[i] x 3 positions.
+ * sipf_batch_run advances every instance by nsteps (asynchronous).
+ * sipf_batch_get_positions copies instance i's positions (original order) to
+ * a caller-owned buffer and synchronises.
+ */
+int sipf_batch_init(int32_t n, const sipf_params* prm, const int64_t* P, const void* const* X0,
+                    void* hip_stream, sipf_batch** out);
+int sipf_batch_run(sipf_batch* b, int64_t nsteps);
+int sipf_batch_get_positions(sipf_batch* b, int32_t i, void* out, int on_device);
+int sipf_batch_get_field(sipf_batch* b, int32_t i, int which, void* out, int on_device);
+int sipf_batch_destroy(sipf_batch* b);
+
+/*
+ * Test entry points: each exposes one piece of the step on caller data.
+ * All pointers are device pointers; each call synchronises the given stream.
+ *
+ * sipf_dbg_philox: for count counters ctr (count x 4 uint32: id, n, slot,
+ *   instance) under key seed, writes the raw Philox4x32-10 outputs
+ *   (count x 4 uint32) and the normal 3-vector of the stream contract
+ *   (count x 3 in the given precision).
+ * sipf_dbg_cells: the integer cell g = floor(X H / L) (count x 3 int32) that
+ *   the particle pass uses for positions X (count x 3, precision of prm).
+ * sipf_dbg_deposit: phi = I(sum_p w delta_{X_p}) with w = M0/count on the
+ *   H^3 grid (the deposit of Algorithm 2 through the binning + LDS path).
+ */
+int sipf_dbg_philox(uint64_t seed, int64_t count, const uint32_t* ctr, uint32_t* raw,
+                    void* normals, int precision, void* hip_stream);
+int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t* cells,
+                   void* hip_stream);
+int sipf_dbg_deposit(const sipf_params* prm, int64_t count, const void* X, void* phi,
+                     void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIPF_H */

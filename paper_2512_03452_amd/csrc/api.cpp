@@ -1,0 +1,636 @@
+// Host runtime and C ABI of the SIPF-PIC step (declared in include/sipf.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "sipf.h"
+
+using namespace sipf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(SIPF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate(const sipf_params* p, int64_t P) {
+    if (!p) return fail(SIPF_EINVAL, "params is NULL");
+    if (p->precision != SIPF_FP32 && p->precision != SIPF_FP64) return fail(SIPF_EINVAL, "precision must be SIPF_FP32 or SIPF_FP64");
+    if (!fft_size_supported(p->H, p->precision == SIPF_FP64))
+        return fail(SIPF_EINVAL, "H must be a power of two in [8, 128] (FP32) or [8, 64] (FP64)");
+    auto fin = [](double v) { return std::isfinite(v); };
+    if (!(fin(p->L) && p->L > 0)) return fail(SIPF_EINVAL, "L must be finite and > 0");
+    if (!(fin(p->dt) && p->dt > 0)) return fail(SIPF_EINVAL, "dt must be finite and > 0");
+    if (!(fin(p->eps) && p->eps > 0)) return fail(SIPF_EINVAL, "eps must be finite and > 0");
+    if (!(fin(p->mu) && p->mu >= 0)) return fail(SIPF_EINVAL, "mu must be finite and >= 0");
+    if (!(fin(p->chi) && p->chi >= 0)) return fail(SIPF_EINVAL, "chi must be finite and >= 0");
+    if (!(fin(p->k) && p->k >= 0)) return fail(SIPF_EINVAL, "k must be finite and >= 0");
+    if (!(fin(p->M0) && p->M0 >= 0)) return fail(SIPF_EINVAL, "M0 must be finite and >= 0");
+    if (!fin(p->H0)) return fail(SIPF_EINVAL, "H0 must be finite");
+    if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
+    if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
+    if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
+    if (p->tile != 0 && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > 16))
+        return fail(SIPF_EINVAL, "tile must be 0 or a power of two with H/16 <= tile <= H");
+    if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
+    if (p->chunk != 0 && (p->chunk < 256 || p->chunk > (1 << 20))) return fail(SIPF_EINVAL, "chunk must be 0 or in [256, 2^20]");
+    if (p->reserved != 0) return fail(SIPF_EINVAL, "reserved must be 0");
+    if (P < 1 || P >= (int64_t(1) << 32)) return fail(SIPF_EINVAL, "P must be in [1, 2^32)");
+    return SIPF_OK;
+}
+
+double filter_h0(const sipf_params* p) {
+    if (p->H0 == 0) return std::ceil(8.0 * std::pow((double)p->H, 8.0 / 13.0) * std::pow(p->L, 5.0 / 13.0));
+    return p->H0;
+}
+
+// default tuning (overridden by explicit parameters)
+void tuning(const sipf_params* p, int64_t P, int& tile, int& resort, int& chunk) {
+    tile = p->tile ? p->tile : (p->H >= 128 ? 8 : (p->H >= 16 ? p->H / 8 : p->H));
+    if (p->H / tile > 16) tile = p->H / 16;
+    resort = p->resort_every ? p->resort_every : 4;
+    chunk = p->chunk ? p->chunk : 2048;
+    (void)P;
+}
+
+}  // namespace
+
+struct sipf_ctx {
+    sipf_params prm{};
+    int64_t P = 0;
+    int H = 0;
+    int prec = SIPF_FP32;
+    size_t tsize = 4;
+    hipStream_t stream = nullptr;
+    int tile = 8, resort = 4, chunk = 2048, wcap = 8192;
+    int since_sort = 0;
+    int cur = 0;  // which of the two particle buffer sets holds the current positions
+    int64_t n_host = 0;
+    void* xs[2] = {nullptr, nullptr};
+    void* ys[2] = {nullptr, nullptr};
+    void* zs[2] = {nullptr, nullptr};
+    uint32_t* ids[2] = {nullptr, nullptr};
+    void* phi = nullptr;
+    void* B1 = nullptr;
+    void* alpha = nullptr;
+    void* gspec = nullptr;
+    void* G = nullptr;
+    uint32_t* counts = nullptr;
+    uint32_t* cursor = nullptr;
+    uint32_t* step = nullptr;
+    int* err = nullptr;
+    void* pdesc = nullptr;  // two PartDesc<T> (one per buffer set)
+    void* fdesc = nullptr;  // one FieldDesc<T>
+    WorkItem* items = nullptr;
+    int nitems = 0;
+    std::vector<void*> allocs;
+    // captured graph of a whole number of sort periods
+    hipGraphExec_t gexec = nullptr;
+    int64_t graph_steps = 0;
+    // per-phase event timing (sipf_profile)
+    bool prof = false;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    double prof_ms[SIPF_NPHASES] = {0};
+    int64_t prof_n[SIPF_NPHASES] = {0};
+};
+
+namespace {
+
+int dalloc(sipf_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SIPF_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    return SIPF_OK;
+}
+
+template <typename T> PartDesc<T> make_pdesc(const sipf_ctx* c, int set) {
+    PartDesc<T> d{};
+    d.x = (T*)c->xs[set];
+    d.y = (T*)c->ys[set];
+    d.z = (T*)c->zs[set];
+    d.id = c->ids[set];
+    d.P = c->P;
+    d.phi = (T*)c->phi;
+    d.G = (const T*)c->G;
+    d.step = c->step;
+    d.err = c->err;
+    d.H = c->H;
+    d.scheme = c->prm.scheme;
+    d.hl = (T)(c->H / c->prm.L);
+    d.L = (T)c->prm.L;
+    d.halfL = (T)(c->prm.L / 2);
+    d.invL = (T)(1.0 / c->prm.L);
+    d.wmass = (T)(c->prm.M0 / (double)c->P);
+    d.chitau = (T)(c->prm.chi * c->prm.dt);
+    d.s = (T)(c->prm.scheme == SIPF_STRANG ? std::sqrt(c->prm.mu * c->prm.dt) : std::sqrt(2.0 * c->prm.mu * c->prm.dt));
+    d.k0 = (uint32_t)c->prm.seed;
+    d.k1 = (uint32_t)(c->prm.seed >> 32);
+    d.inst = c->prm.instance;
+    return d;
+}
+
+template <typename T> FieldDesc<T> make_fdesc(const sipf_ctx* c) {
+    FieldDesc<T> f{};
+    const sipf_params& p = c->prm;
+    f.phi = (T*)c->phi;
+    f.B1 = (cplx_t<T>*)c->B1;
+    f.alpha = (cplx_t<T>*)c->alpha;
+    f.gspec = (cplx_t<T>*)c->gspec;
+    f.G = (T*)c->G;
+    f.step = c->step;
+    f.dt_over_eps = (T)(p.dt / p.eps);
+    f.eps_over_dt = (T)(p.eps / p.dt);
+    f.k2 = (T)(p.k * p.k);
+    f.inv_L3 = (T)(1.0 / (p.L * p.L * p.L));
+    f.two_pi_over_L = (T)(2.0 * M_PI / p.L);
+    const double h0 = filter_h0(&p);
+    f.filt = p.H0 < 0 ? (T)0 : (T)(2.0 * M_PI * M_PI / (h0 * h0));
+    return f;
+}
+
+template <typename T> int upload_descs(sipf_ctx* c) {
+    PartDesc<T> pd[2] = {make_pdesc<T>(c, 0), make_pdesc<T>(c, 1)};
+    FieldDesc<T> fd = make_fdesc<T>(c);
+    HIPCHK(hipMemcpy(c->pdesc, pd, sizeof(pd), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice));
+    return SIPF_OK;
+}
+
+template <typename T> const PartDesc<T>* pdesc_dev(const sipf_ctx* c, int set) {
+    return reinterpret_cast<const PartDesc<T>*>(c->pdesc) + set;
+}
+
+// Event bracket around one launch when timing is on.
+struct Timed {
+    sipf_ctx* c;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(sipf_ctx* ctx, int ph) : c(ctx), phase(ph) {
+        if (!c->prof) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            c->prof = false;
+            return;
+        }
+        (void)hipEventRecord(a, c->stream);
+    }
+    ~Timed() {
+        if (!c->prof || !a) return;
+        (void)hipEventRecord(b, c->stream);
+        c->marks.push_back({phase, a, b});
+    }
+};
+
+template <typename T> int do_sort(sipf_ctx* c) {
+    const PartDesc<T> src = make_pdesc<T>(c, c->cur);
+    const int dst = 1 - c->cur;
+    {
+        Timed t(c, SIPF_PHASE_SORT);
+        HIPCHK(launch_sort<T>(&src, reinterpret_cast<PartDesc<T>*>(c->pdesc) + c->cur, (T*)c->xs[dst],
+                              (T*)c->ys[dst], (T*)c->zs[dst], c->ids[dst], c->counts, c->cursor, c->tile, c->chunk,
+                              c->stream));
+    }
+    c->cur = dst;
+    c->since_sort = 0;
+    return SIPF_OK;
+}
+
+// One step n-1 -> n: particle pass (deposit X^(n-1), gather grad c^(n-1), push),
+// then the field passes that turn the deposit into alpha^(n) and grad c^(n).
+template <typename T> int enqueue_step(sipf_ctx* c) {
+    if (c->since_sort >= c->resort) {
+        int rc = do_sort<T>(c);
+        if (rc) return rc;
+    }
+    {
+        Timed t(c, SIPF_PHASE_PARTICLES);
+        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, true, true, c->prm.scheme, c->wcap,
+                                   c->stream));
+    }
+    const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
+    {
+        Timed t(c, SIPF_PHASE_FWD);
+        HIPCHK(launch_fwd_planes<T>(c->H, fd, 1, c->stream));
+    }
+    {
+        Timed t(c, SIPF_PHASE_XPENCIL);
+        HIPCHK(launch_xpencils<T>(c->H, fd, 1, true, c->stream));
+    }
+    {
+        Timed t(c, SIPF_PHASE_INV);
+        HIPCHK(launch_inv_planes<T>(c->H, fd, 1, c->stream));
+    }
+    c->since_sort++;
+    c->n_host++;
+    return SIPF_OK;
+}
+
+int drain_marks(sipf_ctx* c) {
+    if (c->marks.empty()) return SIPF_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (auto& m : c->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            c->prof_ms[m.phase] += ms;
+            c->prof_n[m.phase] += 1;
+        }
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    c->marks.clear();
+    return SIPF_OK;
+}
+
+int step_dispatch(sipf_ctx* c) { return c->prec == SIPF_FP32 ? enqueue_step<float>(c) : enqueue_step<double>(c); }
+
+int check_err(sipf_ctx* c) {
+    int e = 0;
+    HIPCHK(hipMemcpyAsync(&e, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (e & 2) return fail(SIPF_ENUMERIC, "non-finite initial position");
+    if (e & 1) return fail(SIPF_ENUMERIC, "a step produced a non-finite position");
+    return SIPF_OK;
+}
+
+// natural <-> permuted (kx, ky) layout of a half spectrum (host arrays of 2*T per entry)
+void permute_spectrum(const void* src, void* dst, int H, size_t tsize, bool to_perm) {
+    const int HH = H / 2 + 1;
+    const size_t e = 2 * tsize;
+    for (int kx = 0; kx < H; ++kx)
+        for (int ky = 0; ky < H; ++ky) {
+            const size_t nat = ((size_t)kx * H + ky) * HH;
+            const size_t per = ((size_t)fft_perm(H, kx) * H + fft_perm(H, ky)) * HH;
+            if (to_perm) std::memcpy((char*)dst + per * e, (const char*)src + nat * e, HH * e);
+            else std::memcpy((char*)dst + nat * e, (const char*)src + per * e, HH * e);
+        }
+}
+
+template <typename T> int init_fields(sipf_ctx* c, const void* alpha0, int alpha0_on_device) {
+    const int H = c->H;
+    const size_t HH = H / 2 + 1;
+    const size_t nspec = (size_t)H * H * HH;
+    const size_t H3 = (size_t)H * H * H;
+    HIPCHK(launch_fill<T>((T*)c->phi, H3, (T)0, c->stream));
+    HIPCHK(launch_fill<T>((T*)c->G, 3 * H3, (T)0, c->stream));
+    if (alpha0 == nullptr) {
+        HIPCHK(launch_fill<T>((T*)c->alpha, 2 * nspec, (T)0, c->stream));
+        return SIPF_OK;
+    }
+    std::vector<T> nat(2 * nspec), per(2 * nspec);
+    if (alpha0_on_device) HIPCHK(hipMemcpy(nat.data(), alpha0, nat.size() * sizeof(T), hipMemcpyDeviceToHost));
+    else std::memcpy(nat.data(), alpha0, nat.size() * sizeof(T));
+    for (T v : nat)
+        if (!std::isfinite((double)v)) return fail(SIPF_ENUMERIC, "non-finite alpha0");
+    permute_spectrum(nat.data(), per.data(), H, sizeof(T), true);
+    HIPCHK(hipMemcpy(c->alpha, per.data(), per.size() * sizeof(T), hipMemcpyHostToDevice));
+    const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
+    HIPCHK(launch_xpencils<T>(H, fd, 1, false, c->stream));
+    HIPCHK(launch_inv_planes<T>(H, fd, 1, c->stream));
+    return SIPF_OK;
+}
+
+template <typename T>
+int init_typed(sipf_ctx* c, const void* X0, int x0_on_device, const void* alpha0, int alpha0_on_device) {
+    const int64_t P = c->P;
+    const int H = c->H;
+    const size_t H3 = (size_t)H * H * H;
+    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+    int rc;
+    for (int s = 0; s < 2; ++s) {
+        if ((rc = dalloc(c, &c->xs[s], P * sizeof(T)))) return rc;
+        if ((rc = dalloc(c, &c->ys[s], P * sizeof(T)))) return rc;
+        if ((rc = dalloc(c, &c->zs[s], P * sizeof(T)))) return rc;
+        if ((rc = dalloc(c, (void**)&c->ids[s], P * sizeof(uint32_t)))) return rc;
+    }
+    if ((rc = dalloc(c, &c->phi, H3 * sizeof(T)))) return rc;
+    if ((rc = dalloc(c, &c->B1, nspec * 2 * sizeof(T)))) return rc;
+    if ((rc = dalloc(c, &c->alpha, nspec * 2 * sizeof(T)))) return rc;
+    if ((rc = dalloc(c, &c->gspec, 3 * nspec * 2 * sizeof(T)))) return rc;
+    if ((rc = dalloc(c, &c->G, 3 * H3 * sizeof(T)))) return rc;
+    if ((rc = dalloc(c, (void**)&c->counts, sort_max_keys() * sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(c, (void**)&c->cursor, sort_max_keys() * sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(c, (void**)&c->step, 16))) return rc;
+    if ((rc = dalloc(c, (void**)&c->err, 16))) return rc;
+    if ((rc = dalloc(c, &c->pdesc, 2 * sizeof(PartDesc<T>)))) return rc;
+    if ((rc = dalloc(c, &c->fdesc, sizeof(FieldDesc<T>)))) return rc;
+    c->nitems = (int)((P + c->chunk - 1) / c->chunk);
+    if ((rc = dalloc(c, (void**)&c->items, c->nitems * sizeof(WorkItem)))) return rc;
+    {
+        std::vector<WorkItem> it(c->nitems);
+        for (int i = 0; i < c->nitems; ++i) {
+            it[i].beg = (int64_t)i * c->chunk;
+            it[i].cnt = (int32_t)std::min<int64_t>(c->chunk, P - it[i].beg);
+            it[i].inst = 0;
+        }
+        HIPCHK(hipMemcpy(c->items, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemset(c->counts, 0, sort_max_keys() * sizeof(uint32_t)));
+    HIPCHK(hipMemset(c->step, 0, 16));
+    HIPCHK(hipMemset(c->err, 0, 16));
+    if ((rc = upload_descs<T>(c))) return rc;
+    // positions: AoS (host or device) -> SoA set 0, wrapped, ids 0..P-1
+    const T* xyz = (const T*)X0;
+    if (!x0_on_device) {
+        // host positions go through a temporary device buffer freed before return
+        void* tmp = nullptr;
+        if (hipMalloc(&tmp, 3 * P * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SIPF_ENOMEM, "hipMalloc failed for the staging buffer");
+        }
+        hipError_t e = hipMemcpy(tmp, X0, 3 * P * sizeof(T), hipMemcpyHostToDevice);
+        PartDesc<T> d0 = make_pdesc<T>(c, 0);
+        if (e == hipSuccess) e = launch_load_positions<T>((const T*)tmp, P, (T)c->prm.L, d0, c->err, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("loading X0: ") + hipGetErrorString(e));
+    } else {
+        PartDesc<T> d0 = make_pdesc<T>(c, 0);
+        HIPCHK(launch_load_positions<T>(xyz, P, (T)c->prm.L, d0, c->err, c->stream));
+    }
+    if ((rc = init_fields<T>(c, alpha0, alpha0_on_device))) return rc;
+    c->cur = 0;
+    if ((rc = do_sort<T>(c))) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return check_err(c);
+}
+
+void free_ctx(sipf_ctx* c) {
+    if (!c) return;
+    for (auto& m : c->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (void* p : c->allocs) (void)hipFree(p);
+    delete c;
+}
+
+template <typename T> int get_field_typed(sipf_ctx* c, int which, void* out, int on_device) {
+    const int H = c->H;
+    const size_t H3 = (size_t)H * H * H;
+    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (which == SIPF_FIELD_RHO) {
+        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, true, false, c->prm.scheme, c->wcap,
+                                   c->stream));
+        HIPCHK(hipMemcpyAsync(out, c->phi, H3 * sizeof(T), kind, c->stream));
+        HIPCHK(launch_fill<T>((T*)c->phi, H3, (T)0, c->stream));
+    } else if (which == SIPF_FIELD_GRAD) {
+        HIPCHK(hipMemcpyAsync(out, c->G, 3 * H3 * sizeof(T), kind, c->stream));
+    } else if (which == SIPF_FIELD_ALPHA) {
+        std::vector<T> per(2 * nspec), nat(2 * nspec);
+        HIPCHK(hipMemcpyAsync(per.data(), c->alpha, per.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        permute_spectrum(per.data(), nat.data(), H, sizeof(T), false);
+        if (on_device) HIPCHK(hipMemcpy(out, nat.data(), nat.size() * sizeof(T), hipMemcpyHostToDevice));
+        else std::memcpy(out, nat.data(), nat.size() * sizeof(T));
+    } else {
+        return fail(SIPF_EINVAL, "unknown field");
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return check_err(c);
+}
+
+template <typename T> int get_positions_typed(sipf_ctx* c, void* out, int on_device) {
+    const PartDesc<T> d = make_pdesc<T>(c, c->cur);
+    if (on_device) {
+        HIPCHK(launch_unsort<T>(&d, (T*)out, c->stream));
+    } else {
+        void* tmp = nullptr;
+        HIPCHK(hipMalloc(&tmp, 3 * c->P * sizeof(T)));
+        hipError_t e = launch_unsort<T>(&d, (T*)tmp, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, 3 * c->P * sizeof(T), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("get_positions: ") + hipGetErrorString(e));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return check_err(c);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sipf_last_error(void) { return g_err.c_str(); }
+
+int sipf_params_default(sipf_params* p) {
+    if (!p) return fail(SIPF_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->L = 2.0;
+    p->chi = 1.0;
+    p->mu = 1.0;
+    p->eps = 1.0;
+    p->k = 1.0;
+    p->M0 = 1.0;
+    p->dt = 1e-4;
+    p->H0 = 0.0;
+    p->H = 64;
+    p->p2g_order = 4;
+    p->g2p_order = 2;
+    p->scheme = SIPF_STRANG;
+    p->precision = SIPF_FP32;
+    return SIPF_OK;
+}
+
+int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_device, const void* alpha0,
+              int alpha0_on_device, void* hip_stream, sipf_ctx** out) {
+    if (!out) return fail(SIPF_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(prm, P);
+    if (rc) return rc;
+    if (!X0) return fail(SIPF_EINVAL, "X0 is NULL");
+    const size_t ts = prm->precision == SIPF_FP32 ? 4 : 8;
+    if (!x0_on_device) {
+        // reject non-finite host input before touching the device
+        for (int64_t i = 0; i < 3 * P; ++i) {
+            const double v = ts == 4 ? (double)((const float*)X0)[i] : ((const double*)X0)[i];
+            if (!std::isfinite(v)) return fail(SIPF_ENUMERIC, "non-finite value in X0");
+        }
+    }
+    sipf_ctx* c = new (std::nothrow) sipf_ctx();
+    if (!c) return fail(SIPF_ENOMEM, "host allocation failed");
+    c->prm = *prm;
+    c->P = P;
+    c->H = prm->H;
+    c->prec = prm->precision;
+    c->tsize = ts;
+    c->stream = (hipStream_t)hip_stream;
+    tuning(prm, P, c->tile, c->resort, c->chunk);
+    c->wcap = c->prec == SIPF_FP32 ? 8192 : 4096;
+    rc = c->prec == SIPF_FP32 ? init_typed<float>(c, X0, x0_on_device, alpha0, alpha0_on_device)
+                              : init_typed<double>(c, X0, x0_on_device, alpha0, alpha0_on_device);
+    if (rc) {
+        std::string keep = g_err;
+        free_ctx(c);
+        g_err = keep;
+        return rc;
+    }
+    *out = c;
+    return SIPF_OK;
+}
+
+int sipf_step(sipf_ctx* c) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    return step_dispatch(c);
+}
+
+int sipf_run(sipf_ctx* c, int64_t nsteps) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+    for (int64_t i = 0; i < nsteps; ++i) {
+        int rc = step_dispatch(c);
+        if (rc) return rc;
+    }
+    return SIPF_OK;
+}
+
+int sipf_sync(sipf_ctx* c) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    return check_err(c);
+}
+
+int sipf_get_step(sipf_ctx* c, int64_t* n) {
+    if (!c || !n) return fail(SIPF_EINVAL, "NULL argument");
+    uint32_t s = 0;
+    HIPCHK(hipMemcpyAsync(&s, c->step, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *n = s;
+    return SIPF_OK;
+}
+
+int sipf_get_positions(sipf_ctx* c, void* out, int on_device) {
+    if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
+    return c->prec == SIPF_FP32 ? get_positions_typed<float>(c, out, on_device)
+                                : get_positions_typed<double>(c, out, on_device);
+}
+
+int sipf_get_field(sipf_ctx* c, int which, void* out, int on_device) {
+    if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
+    return c->prec == SIPF_FP32 ? get_field_typed<float>(c, which, out, on_device)
+                                : get_field_typed<double>(c, which, out, on_device);
+}
+
+int sipf_profile(sipf_ctx* c, int enable) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    int rc = drain_marks(c);
+    if (rc) return rc;
+    for (int i = 0; i < SIPF_NPHASES; ++i) {
+        c->prof_ms[i] = 0;
+        c->prof_n[i] = 0;
+    }
+    c->prof = enable != 0;
+    return SIPF_OK;
+}
+
+int sipf_profile_read(sipf_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return fail(SIPF_EINVAL, "NULL argument");
+    int rc = drain_marks(c);
+    if (rc) return rc;
+    for (int i = 0; i < SIPF_NPHASES; ++i) {
+        ms[i] = c->prof_ms[i];
+        launches[i] = c->prof_n[i];
+    }
+    return SIPF_OK;
+}
+
+int sipf_adjoint(sipf_ctx* c, int64_t, int32_t, const void*, double*, double*, double*, void*) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    return fail(SIPF_ESTATE, "adjoint not available in this build");
+}
+
+int sipf_save(sipf_ctx* c, const char*) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    return fail(SIPF_EIO, "save not available in this build");
+}
+
+int sipf_load(const char*, void*, sipf_ctx** out) {
+    if (out) *out = nullptr;
+    return fail(SIPF_EIO, "load not available in this build");
+}
+
+int sipf_destroy(sipf_ctx* c) {
+    if (!c) return SIPF_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_ctx(c);
+    return SIPF_OK;
+}
+
+int sipf_batch_init(int32_t, const sipf_params*, const int64_t*, const void* const*, void*, sipf_batch** out) {
+    if (out) *out = nullptr;
+    return fail(SIPF_EINVAL, "batched mode not available in this build");
+}
+int sipf_batch_run(sipf_batch*, int64_t) { return fail(SIPF_EINVAL, "batched mode not available in this build"); }
+int sipf_batch_get_positions(sipf_batch*, int32_t, void*, int) {
+    return fail(SIPF_EINVAL, "batched mode not available in this build");
+}
+int sipf_batch_get_field(sipf_batch*, int32_t, int, void*, int) {
+    return fail(SIPF_EINVAL, "batched mode not available in this build");
+}
+int sipf_batch_destroy(sipf_batch*) { return SIPF_OK; }
+
+int sipf_dbg_philox(uint64_t seed, int64_t count, const uint32_t* ctr, uint32_t* raw, void* normals, int precision,
+                    void* hip_stream) {
+    if (count < 0 || (count > 0 && !ctr)) return fail(SIPF_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (precision == SIPF_FP32) HIPCHK(launch_philox_dbg<float>(seed, count, ctr, raw, (float*)normals, s));
+    else if (precision == SIPF_FP64) HIPCHK(launch_philox_dbg<double>(seed, count, ctr, raw, (double*)normals, s));
+    else return fail(SIPF_EINVAL, "bad precision");
+    HIPCHK(hipStreamSynchronize(s));
+    return SIPF_OK;
+}
+
+int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t* cells, void* hip_stream) {
+    int rc = validate(prm, count > 0 ? count : 1);
+    if (rc) return rc;
+    if (count < 0 || (count > 0 && (!X || !cells))) return fail(SIPF_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (prm->precision == SIPF_FP32)
+        HIPCHK(launch_cells<float>((const float*)X, count, prm->H, (float)(prm->H / prm->L), cells, s));
+    else
+        HIPCHK(launch_cells<double>((const double*)X, count, prm->H, (double)(prm->H / prm->L), cells, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SIPF_OK;
+}
+
+int sipf_dbg_deposit(const sipf_params* prm, int64_t count, const void* X, void* phi, void* hip_stream) {
+    if (!phi) return fail(SIPF_EINVAL, "phi is NULL");
+    sipf_ctx* c = nullptr;
+    int rc = sipf_init(prm, count, X, 1, nullptr, 0, hip_stream, &c);
+    if (rc) return rc;
+    rc = sipf_get_field(c, SIPF_FIELD_RHO, phi, 1);
+    sipf_destroy(c);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,418 @@
+// Field passes of the SIPF-PIC step: real-to-complex 3-D FFT of the deposit,
+// implicit mode update, filtered spectral gradient and complex-to-real 3-D
+// inverse FFT of its three components (Algorithm 2's last line, the mode
+// update and the gradient lines of Algorithm 4).
+//
+// Transform convention (Sec. 3.1): beta_q = L^-3 sum_j phi_j e^{-2 pi i q.j/H},
+// grad c(x_j) = sum_q i xi_q Phi_q alpha_q e^{+2 pi i q.j/H}.
+//
+// Three passes over HBM per step, each staged through LDS:
+//   fwd_planes  one workgroup per x-plane: real rows of the plane are packed
+//               two at a time into one complex row (z = a + i b), transformed
+//               along z, split into the half spectra of a and b (kz = 0..H/2),
+//               then transformed along y.  Also zeroes the deposit grid for
+//               the next step and advances the step counter.
+//   xpencils    one workgroup per (ky, 16 kz) block of x-pencils: transform
+//               along x, alpha <- A alpha + B beta, form i xi_d Phi alpha for
+//               d = 0,1,2 and inverse-transform each along x.
+//   inv_planes  one workgroup per (component, x-plane): inverse along y, then
+//               the complex-to-real inverse along z two rows at a time.
+//
+// In-place LDS FFT of length N = N1 * N2 (N1, N2 <= 16): a stage of N1-point
+// register DFTs with twiddles, then a stage of N2-point register DFTs.  The
+// forward transform takes natural order and leaves frequency k at position
+// (k mod N1) * N2 + k div N1; the inverse takes that order and returns natural
+// order.  The x and y frequency axes of the stored spectra use this order.
+#include "internal.h"
+
+namespace sipf {
+
+template <int N> struct Split;
+template <> struct Split<8>   { static constexpr int N1 = 8,  N2 = 1; };
+template <> struct Split<16>  { static constexpr int N1 = 16, N2 = 1; };
+template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
+template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8; };
+template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
+
+int fft_perm(int N, int k) {
+    int N1 = 8, N2 = 1;
+    switch (N) {
+        case 8: N1 = 8; N2 = 1; break;
+        case 16: N1 = 16; N2 = 1; break;
+        case 32: N1 = 8; N2 = 4; break;
+        case 64: N1 = 8; N2 = 8; break;
+        case 128: N1 = 16; N2 = 8; break;
+        default: return -1;
+    }
+    return (k % N1) * N2 + k / N1;
+}
+
+bool fft_size_supported(int H, bool fp64) {
+    if (!(H == 8 || H == 16 || H == 32 || H == 64 || H == 128)) return false;
+    return !(fp64 && H > 64);
+}
+
+// cos and sin of 2 pi j / 16, j = 0..7
+struct Tw16 {
+    static constexpr double c[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+    static constexpr double s[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+};
+
+// v * exp(DIR 2 pi i k / R)
+template <typename T, int R, int DIR, int K>
+__device__ __forceinline__ cplx_t<T> twiddle(cplx_t<T> v) {
+    using V = cplx_t<T>;
+    if constexpr (K == 0) {
+        return v;
+    } else if constexpr (4 * K == R) {
+        return DIR > 0 ? cmake<V, T>(-v.y, v.x) : cmake<V, T>(v.y, -v.x);
+    } else {
+        constexpr int j = K * (16 / R);
+        const T c = (T)Tw16::c[j];
+        const T s = (T)(DIR * Tw16::s[j]);
+        return cmake<V, T>(v.x * c - v.y * s, v.x * s + v.y * c);
+    }
+}
+
+// In-register DFT of length R (power of two <= 16), natural order in and out.
+template <typename T, int R, int DIR> struct Dft {
+    using V = cplx_t<T>;
+    template <int K>
+    __device__ __forceinline__ static void combine(V* x, const V* e, const V* o) {
+        if constexpr (K < R / 2) {
+            const V t = twiddle<T, R, DIR, K>(o[K]);
+            x[K] = cadd(e[K], t);
+            x[K + R / 2] = csub(e[K], t);
+            combine<K + 1>(x, e, o);
+        }
+    }
+    __device__ __forceinline__ static void run(V* x) {
+        V e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = x[2 * i];
+            o[i] = x[2 * i + 1];
+        }
+        Dft<T, R / 2, DIR>::run(e);
+        Dft<T, R / 2, DIR>::run(o);
+        combine<0>(x, e, o);
+    }
+};
+template <typename T, int DIR> struct Dft<T, 1, DIR> {
+    __device__ __forceinline__ static void run(cplx_t<T>*) {}
+};
+
+// count independent length-N transforms; element e of transform b at
+// buf[b * bs + e * es].  tw[m] = exp(-2 pi i m / N).  Caller synchronises
+// before and after.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void lds_fft(cplx_t<T>* buf, int count, int bs, int es, const cplx_t<T>* tw) {
+    using V = cplx_t<T>;
+    constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if constexpr (DIR < 0) {
+        for (int u = tid; u < count * N2; u += nt) {
+            const int b = u % count, n2 = u / count;
+            V* p = buf + b * bs + n2 * es;
+            V r[N1];
+#pragma unroll
+            for (int i = 0; i < N1; ++i) r[i] = p[i * N2 * es];
+            Dft<T, N1, -1>::run(r);
+            if constexpr (N2 > 1) {
+#pragma unroll
+                for (int k1 = 1; k1 < N1; ++k1) r[k1] = cmul(r[k1], tw[n2 * k1]);
+            }
+#pragma unroll
+            for (int i = 0; i < N1; ++i) p[i * N2 * es] = r[i];
+        }
+        if constexpr (N2 > 1) {
+            __syncthreads();
+            for (int u = tid; u < count * N1; u += nt) {
+                const int b = u % count, k1 = u / count;
+                V* p = buf + b * bs + k1 * N2 * es;
+                V r[N2];
+#pragma unroll
+                for (int i = 0; i < N2; ++i) r[i] = p[i * es];
+                Dft<T, N2, -1>::run(r);
+#pragma unroll
+                for (int i = 0; i < N2; ++i) p[i * es] = r[i];
+            }
+        }
+    } else {
+        if constexpr (N2 > 1) {
+            for (int u = tid; u < count * N1; u += nt) {
+                const int b = u % count, k1 = u / count;
+                V* p = buf + b * bs + k1 * N2 * es;
+                V r[N2];
+#pragma unroll
+                for (int i = 0; i < N2; ++i) r[i] = p[i * es];
+                Dft<T, N2, +1>::run(r);
+#pragma unroll
+                for (int n2 = 1; n2 < N2; ++n2) r[n2] = cmul(r[n2], cconj(tw[n2 * k1]));
+#pragma unroll
+                for (int i = 0; i < N2; ++i) p[i * es] = r[i];
+            }
+            __syncthreads();
+        }
+        for (int u = tid; u < count * N2; u += nt) {
+            const int b = u % count, n2 = u / count;
+            V* p = buf + b * bs + n2 * es;
+            V r[N1];
+#pragma unroll
+            for (int i = 0; i < N1; ++i) r[i] = p[i * N2 * es];
+            Dft<T, N1, +1>::run(r);
+#pragma unroll
+            for (int i = 0; i < N1; ++i) p[i * N2 * es] = r[i];
+        }
+    }
+}
+
+template <int N> __device__ __forceinline__ int perm_pos(int k) {
+    return (k % Split<N>::N1) * Split<N>::N2 + k / Split<N>::N1;
+}
+template <int N> __device__ __forceinline__ int perm_freq(int pos) {
+    return pos / Split<N>::N2 + Split<N>::N1 * (pos % Split<N>::N2);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void make_twiddles(cplx_t<T>* tw) {
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)N, &s, &c);
+        tw[m] = cmake<cplx_t<T>, T>((T)c, (T)(-s));
+    }
+}
+
+constexpr int PLANE_THREADS = 512;
+constexpr int PENCIL_THREADS = 256;
+constexpr int KB = 16;  // kz columns per x-pencil workgroup
+
+// ---------------------------------------------------------------------------
+// Pass 1: x-plane -> half spectrum along z, transformed along y.
+// ---------------------------------------------------------------------------
+template <typename T, int H>
+__global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>* __restrict__ fds) {
+    using V = cplx_t<T>;
+    constexpr int HH = H / 2 + 1;
+    constexpr int RP = H + 1;          // row pitch (complex) of the packed-row buffer
+    constexpr int OP = HH;             // row pitch of the half plane
+    __shared__ V rows[(H / 2) * RP];
+    __shared__ V half[H * OP];
+    __shared__ V tw[H];
+    const FieldDesc<T>& fd = fds[blockIdx.y];
+    const int ix = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    make_twiddles<T, H>(tw);
+    T* plane = fd.phi + (size_t)ix * H * H;
+    for (int u = tid; u < (H / 2) * H; u += nt) {
+        const int m = u / H, iz = u % H;
+        const T a = plane[(2 * m) * H + iz];
+        const T b = plane[(2 * m + 1) * H + iz];
+        rows[m * RP + iz] = cmake<V, T>(a, b);
+    }
+    __syncthreads();
+    // the deposit grid is consumed: clear it for the next step's particle pass
+    for (int u = tid; u < H * H; u += nt) plane[u] = (T)0;
+    if (ix == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
+    lds_fft<T, H, -1>(rows, H / 2, RP, 1, tw);
+    __syncthreads();
+    // split Z = FFT(a + i b): A_k = (Z_k + conj Z_{-k}) / 2, B_k = (Z_k - conj Z_{-k}) / (2i)
+    for (int u = tid; u < (H / 2) * HH; u += nt) {
+        const int m = u / HH, k = u % HH;
+        const V zk = rows[m * RP + perm_pos<H>(k)];
+        const V zc = cconj(rows[m * RP + perm_pos<H>((H - k) & (H - 1))]);
+        const V s = cadd(zk, zc), d = csub(zk, zc);
+        half[(2 * m) * OP + k] = cmake<V, T>(s.x * (T)0.5, s.y * (T)0.5);
+        half[(2 * m + 1) * OP + k] = cmake<V, T>(d.y * (T)0.5, -d.x * (T)0.5);
+    }
+    __syncthreads();
+    lds_fft<T, H, -1>(half, HH, 1, OP, tw);
+    __syncthreads();
+    V* out = fd.B1 + (size_t)ix * H * HH;
+    for (int u = tid; u < H * HH; u += nt) out[u] = half[(u / HH) * OP + (u % HH)];
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: x-pencils, mode update, filtered gradient spectra, inverse along x.
+// ---------------------------------------------------------------------------
+template <typename T, int H, bool UPDATE>
+__global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>* __restrict__ fds) {
+    using V = cplx_t<T>;
+    constexpr int HH = H / 2 + 1;
+    constexpr int NKB = (HH + KB - 1) / KB;
+    constexpr int BP = KB + 1;  // pitch (complex) of one x row in LDS
+    __shared__ V buf[H * BP];
+    __shared__ V abuf[H * BP];
+    __shared__ V tw[H];
+    const FieldDesc<T>& fd = fds[blockIdx.y];
+    const int kyp = blockIdx.x / NKB;
+    const int kz0 = (blockIdx.x % NKB) * KB;
+    const int ncol = min(KB, HH - kz0);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    make_twiddles<T, H>(tw);
+    const int ky = perm_freq<H>(kyp);
+    const T qy = (T)(ky < H / 2 ? ky : ky - H);
+    if (UPDATE) {
+        for (int u = tid; u < H * KB; u += nt) {
+            const int ix = u / KB, j = u % KB;
+            buf[ix * BP + j] = j < ncol ? fd.B1[((size_t)ix * H + kyp) * HH + kz0 + j] : cmake<V, T>(0, 0);
+        }
+        __syncthreads();
+        lds_fft<T, H, -1>(buf, KB, 1, BP, tw);
+        __syncthreads();
+    }
+    // spectral update in permuted kx order: position p holds kx = perm_freq(p)
+    for (int u = tid; u < H * KB; u += nt) {
+        const int p = u / KB, j = u % KB;
+        if (j >= ncol) {
+            abuf[p * BP + j] = cmake<V, T>(0, 0);
+            continue;
+        }
+        const int kx = perm_freq<H>(p);
+        const int kz = kz0 + j;
+        const T qx = (T)(kx < H / 2 ? kx : kx - H);
+        const T qz = (T)kz;
+        const T q2 = qx * qx + qy * qy + qz * qz;
+        const T xi2 = q2 * fd.two_pi_over_L * fd.two_pi_over_L;
+        const size_t ai = ((size_t)p * H + kyp) * HH + kz;
+        V a = fd.alpha[ai];
+        if (UPDATE) {
+            const T A = (T)1 / ((T)1 + fd.dt_over_eps * (xi2 + fd.k2));
+            const T B = (T)1 / (xi2 + fd.k2 + fd.eps_over_dt);
+            const V beta = buf[p * BP + j];
+            const T bs = B * fd.inv_L3;
+            a = cmake<V, T>(A * a.x + bs * beta.x, A * a.y + bs * beta.y);
+            fd.alpha[ai] = a;
+        }
+        const T phi = fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1;
+        abuf[p * BP + j] = cmake<V, T>(a.x * phi, a.y * phi);
+    }
+    for (int d = 0; d < 3; ++d) {
+        __syncthreads();
+        for (int u = tid; u < H * KB; u += nt) {
+            const int p = u / KB, j = u % KB;
+            int kd;
+            if (d == 0) kd = perm_freq<H>(p);
+            else if (d == 1) kd = ky;
+            else kd = kz0 + j;
+            // derivative factor i xi_d, zero at the Nyquist frequency |q_d| = H/2
+            const T q = (T)(kd == H / 2 ? 0 : (kd < H / 2 ? kd : kd - H));
+            const T xi = q * fd.two_pi_over_L;
+            const V a = abuf[p * BP + j];
+            buf[p * BP + j] = cmake<V, T>(-xi * a.y, xi * a.x);
+        }
+        __syncthreads();
+        lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
+        __syncthreads();
+        V* out = fd.gspec + (size_t)d * H * H * HH;
+        for (int u = tid; u < H * KB; u += nt) {
+            const int ix = u / KB, j = u % KB;
+            if (j < ncol) out[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: inverse along y, complex-to-real inverse along z, per component.
+// ---------------------------------------------------------------------------
+template <typename T, int H>
+__global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>* __restrict__ fds) {
+    using V = cplx_t<T>;
+    constexpr int HH = H / 2 + 1;
+    constexpr int RP = H + 1;
+    constexpr int OP = HH;
+    __shared__ V rows[(H / 2) * RP];
+    __shared__ V half[H * OP];
+    __shared__ V tw[H];
+    const FieldDesc<T>& fd = fds[blockIdx.y];
+    // blocks 8c + r (c = ix / 8 * 3 + d) keep the three components of a plane on one XCD
+    const int b = blockIdx.x;
+    const int grp = b / 8, r = b % 8;
+    const int d = grp % 3;
+    const int ix = (grp / 3) * 8 + r;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    make_twiddles<T, H>(tw);
+    const V* in = fd.gspec + ((size_t)d * H + ix) * H * HH;
+    for (int u = tid; u < H * HH; u += nt) half[(u / HH) * OP + (u % HH)] = in[u];
+    __syncthreads();
+    lds_fft<T, H, +1>(half, HH, 1, OP, tw);
+    __syncthreads();
+    // rebuild full rows Z_k = A_k + i B_k (A, B Hermitian) in permuted order
+    for (int u = tid; u < (H / 2) * H; u += nt) {
+        const int m = u / H, k = u % H;
+        V a, bb;
+        if (k <= H / 2) {
+            a = half[(2 * m) * OP + k];
+            bb = half[(2 * m + 1) * OP + k];
+        } else {
+            a = cconj(half[(2 * m) * OP + (H - k)]);
+            bb = cconj(half[(2 * m + 1) * OP + (H - k)]);
+        }
+        rows[m * RP + perm_pos<H>(k)] = cmake<V, T>(a.x - bb.y, a.y + bb.x);
+    }
+    __syncthreads();
+    lds_fft<T, H, +1>(rows, H / 2, RP, 1, tw);
+    __syncthreads();
+    T* outp = fd.G + ((size_t)d * H + ix) * H * H;
+    for (int u = tid; u < (H / 2) * H; u += nt) {
+        const int m = u / H, iz = u % H;
+        const V v = rows[m * RP + iz];
+        outp[(2 * m) * H + iz] = v.x;
+        outp[(2 * m + 1) * H + iz] = v.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int H>
+static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd_planes<T, H>), dim3(H, count), dim3(PLANE_THREADS), 0, s, fd);
+    return hipGetLastError();
+}
+template <typename T, int H>
+static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, bool update, hipStream_t s) {
+    constexpr int NKB = (H / 2 + 1 + KB - 1) / KB;
+    if (update)
+        hipLaunchKernelGGL((k_xpencils<T, H, true>), dim3(H * NKB, count), dim3(PENCIL_THREADS), 0, s, fd);
+    else
+        hipLaunchKernelGGL((k_xpencils<T, H, false>), dim3(H * NKB, count), dim3(PENCIL_THREADS), 0, s, fd);
+    return hipGetLastError();
+}
+template <typename T, int H>
+static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, hipStream_t s) {
+    static_assert(H % 8 == 0, "plane blocks are grouped by 8");
+    hipLaunchKernelGGL((k_inv_planes<T, H>), dim3(3 * H, count), dim3(PLANE_THREADS), 0, s, fd);
+    return hipGetLastError();
+}
+
+#define SIPF_H_SWITCH(H, FN, ...)                         \
+    switch (H) {                                          \
+        case 8: return FN<T, 8>(__VA_ARGS__);             \
+        case 16: return FN<T, 16>(__VA_ARGS__);           \
+        case 32: return FN<T, 32>(__VA_ARGS__);           \
+        case 64: return FN<T, 64>(__VA_ARGS__);           \
+        case 128: if constexpr (sizeof(T) == 4) return FN<T, 128>(__VA_ARGS__); else return hipErrorInvalidValue; \
+        default: return hipErrorInvalidValue;             \
+    }
+
+template <typename T> hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s) {
+    SIPF_H_SWITCH(H, fwd_planes_h, fd, count, s)
+}
+template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, bool update, hipStream_t s) {
+    SIPF_H_SWITCH(H, xpencils_h, fd, count, update, s)
+}
+template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s) {
+    SIPF_H_SWITCH(H, inv_planes_h, fd, count, s)
+}
+
+template hipError_t launch_fwd_planes<float>(int, const FieldDesc<float>*, int, hipStream_t);
+template hipError_t launch_fwd_planes<double>(int, const FieldDesc<double>*, int, hipStream_t);
+template hipError_t launch_xpencils<float>(int, const FieldDesc<float>*, int, bool, hipStream_t);
+template hipError_t launch_xpencils<double>(int, const FieldDesc<double>*, int, bool, hipStream_t);
+template hipError_t launch_inv_planes<float>(int, const FieldDesc<float>*, int, hipStream_t);
+template hipError_t launch_inv_planes<double>(int, const FieldDesc<double>*, int, hipStream_t);
+
+}  // namespace sipf

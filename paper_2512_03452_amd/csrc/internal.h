@@ -1,0 +1,92 @@
+// Internal interfaces between the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace sipf {
+
+// Everything the field passes (FFT, mode update, gradient) need for one
+// instance.  Spectral arrays are Hermitian half spectra H x H x (H/2+1) whose
+// kx and ky indices are stored in the digit-permuted order of the LDS FFT
+// (see fft.hip); grids are H^3 row-major; G holds the three gradient
+// components one after another (d-major).
+template <typename T> struct FieldDesc {
+    T* phi;                 // deposit accumulator (mass units); zeroed by the forward pass
+    cplx_t<T>* B1;          // yz-plane pass output (x not yet transformed)
+    cplx_t<T>* alpha;       // alpha^(n), permuted (kx, ky)
+    cplx_t<T>* gspec;       // 3 gradient spectra after the x inverse pass
+    T* G;                   // 3 x H^3 gradient grids
+    uint32_t* step;         // completed-step counter, incremented by the forward pass
+    T dt_over_eps;          // tau / eps
+    T eps_over_dt;          // eps / tau
+    T k2;                   // k^2
+    T inv_L3;               // L^-3 (F_H normalisation, Sec. 3.1)
+    T two_pi_over_L;        // xi = 2 pi q / L
+    T filt;                 // 2 pi^2 / H0^2, or 0 (no filter)
+};
+
+// One instance of the particle pass.  Particles are stored SoA and kept
+// approximately sorted by tile; id is the original particle index.
+template <typename T> struct PartDesc {
+    T* x;
+    T* y;
+    T* z;
+    uint32_t* id;
+    int64_t P;
+    T* phi;                 // deposit target (H^3)
+    const T* G;             // gradient grids (3 x H^3)
+    const uint32_t* step;   // completed steps; this step is *step + 1
+    int* err;               // device error flags (bit 0: non-finite position)
+    int H;
+    int scheme;             // SIPF_STRANG or SIPF_EM
+    T hl;                   // H / L
+    T L;
+    T halfL;
+    T invL;
+    T wmass;                // M0 / P
+    T chitau;               // chi * tau
+    T s;                    // noise scale: sqrt(mu tau) (split) or sqrt(2 mu tau) (EM)
+    uint32_t k0, k1;        // Philox key
+    uint32_t inst;          // fourth counter word
+};
+
+// Work item of the particle pass: particles [beg, beg + cnt) of instance inst.
+struct WorkItem {
+    int64_t beg;
+    int32_t cnt;
+    int32_t inst;
+};
+
+// --- field passes (fft.hip) -------------------------------------------------
+// Each launcher runs its pass for `count` instances of grid size H whose
+// descriptors are consecutive in the device array `fd`.
+template <typename T> hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s);
+template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, bool update, hipStream_t s);
+template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s);
+bool fft_size_supported(int H, bool fp64);
+// digit permutation of the LDS FFT of length N: storage position of frequency k
+int fft_perm(int N, int k);
+
+// --- particle pass (particles.hip) -------------------------------------------
+template <typename T>
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int nitems, bool deposit, bool push,
+                            int scheme, int wcap, hipStream_t s);
+template <typename T>
+hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T* y2, T* z2, uint32_t* id2,
+                       uint32_t* counts, uint32_t* cursor, int tile, int chunk, hipStream_t s);
+template <typename T>
+hipError_t launch_cells(const T* X, int64_t n, int H, T hl, int32_t* cells, hipStream_t s);
+template <typename T>
+hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint32_t* raw, T* normals, hipStream_t s);
+template <typename T>
+hipError_t launch_unsort(const PartDesc<T>* pd_host, T* out_xyz, hipStream_t s);
+template <typename T>
+hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd_host, int* err, hipStream_t s);
+template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+int sort_max_keys();
+int particle_threads();
+
+}  // namespace sipf

@@ -1,0 +1,482 @@
+// Particle pass of the SIPF-PIC step: binning, the fourth-order deposit
+// (Definition particle2grid, Algorithm 2), the trilinear gather of the
+// gradient (Definition grid2particle, Algorithm 3) and the stochastic push
+// (Algorithm 4 split step / eq. rho_hat_update), fused in one kernel that
+// reads each particle once.
+//
+// Particles are kept approximately sorted by tile (T^3 cells, tiles in Morton
+// order) by a periodic counting sort.  A workgroup takes a contiguous chunk of
+// the sorted array, measures the bounding box of the chunk's cells, and, when
+// the box plus the stencil reach (-1..+2) fits, accumulates the deposit in an
+// LDS window with LDS float atomics, then adds the window into the global grid
+// once.  A chunk whose box does not fit (sparse regions, long drift since the
+// last sort) deposits straight into the global grid with atomics; the result
+// is the same sum in a different order.
+#include <climits>
+
+#include "internal.h"
+#include "sipf.h"
+
+namespace sipf {
+
+constexpr int PT = 256;            // threads per particle-pass workgroup
+constexpr int SORT_THREADS = 512;  // threads per sort workgroup
+constexpr int SORT_PER_THREAD = 8;
+constexpr int SORT_CHUNK = SORT_THREADS * SORT_PER_THREAD;
+constexpr int MAX_KEYS = 4096;     // (H / tile)^3 <= 16^3
+
+int particle_threads() { return PT; }
+int sort_max_keys() { return MAX_KEYS; }
+
+template <typename T> __device__ __forceinline__ int ifloor(T v) { return (int)floor(v); }
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+// Morton key of the tile of the cell containing (x, y, z).
+template <typename T>
+__device__ __forceinline__ uint32_t tile_key(T x, T y, T z, T hl, int Hm, int tshift) {
+    const uint32_t tx = (uint32_t)(ifloor(x * hl) & Hm) >> tshift;
+    const uint32_t ty = (uint32_t)(ifloor(y * hl) & Hm) >> tshift;
+    const uint32_t tz = (uint32_t)(ifloor(z * hl) & Hm) >> tshift;
+    return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tz);
+}
+
+template <typename T> __device__ __forceinline__ void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
+
+// ---------------------------------------------------------------------------
+// deposit of one particle: 32 nodes of Gamma_4 with the weights of eq. 4ord
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void deposit_one(T* __restrict__ dst, T x, T y, T z, T hl, int Hm, int ox, int oy,
+                                            int oz, int Wy, int Wz, T m) {
+    const T sx = x * hl, sy = y * hl, sz = z * hl;
+    const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
+    const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
+    const Axis4<T> ax = axis4(sx - fx), ay = axis4(sy - fy), az = axis4(sz - fz);
+    const T S = (T)1 + (ax.w0 * ax.w1 + ay.w0 * ay.w1 + az.w0 * az.w1) * (T)0.5;
+    const int WyWz = Wy * Wz;
+    int cx[4], cy[4], cz[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        cx[j] = ((gx - 1 + j - ox) & Hm) * WyWz;
+        cy[j] = ((gy - 1 + j - oy) & Hm) * Wz;
+        cz[j] = (gz - 1 + j - oz) & Hm;
+    }
+    const T wx[2] = {ax.w0, ax.w1}, wy[2] = {ay.w0, ay.w1}, wz[2] = {az.w0, az.w1};
+    const T mS = m * S;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const T pyz = wy[a] * wz[b];
+            const T pxz = wx[a] * wz[b];
+            const T pxy = wx[a] * wy[b];
+            // inner nodes (0/1, a, b)
+            atomic_add(dst + cx[1] + cy[1 + a] + cz[1 + b], mS * wx[0] * pyz);
+            atomic_add(dst + cx[2] + cy[1 + a] + cz[1 + b], mS * wx[1] * pyz);
+            // outer nodes on x: (-1, a, b) and (2, a, b)
+            atomic_add(dst + cx[0] + cy[1 + a] + cz[1 + b], m * ax.wm * pyz);
+            atomic_add(dst + cx[3] + cy[1 + a] + cz[1 + b], m * ax.wp * pyz);
+            // outer nodes on y: (a, -1, b) and (a, 2, b)
+            atomic_add(dst + cx[1 + a] + cy[0] + cz[1 + b], m * ay.wm * pxz);
+            atomic_add(dst + cx[1 + a] + cy[3] + cz[1 + b], m * ay.wp * pxz);
+            // outer nodes on z: (a, b, -1) and (a, b, 2)
+            atomic_add(dst + cx[1 + a] + cy[1 + b] + cz[0], m * az.wm * pxy);
+            atomic_add(dst + cx[1 + a] + cy[1 + b] + cz[3], m * az.wp * pxy);
+        }
+    }
+}
+
+// trilinear interpolation of the three gradient grids at (x, y, z) (eq. 2ord)
+template <typename T>
+__device__ __forceinline__ void gather_one(const T* __restrict__ G, int H, T hl, T x, T y, T z, T& vx, T& vy, T& vz) {
+    const int Hm = H - 1;
+    const T sx = x * hl, sy = y * hl, sz = z * hl;
+    const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
+    const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
+    const T lx = sx - fx, ly = sy - fy, lz = sz - fz;
+    const int ix[2] = {gx & Hm, (gx + 1) & Hm};
+    const int iy[2] = {gy & Hm, (gy + 1) & Hm};
+    const int iz[2] = {gz & Hm, (gz + 1) & Hm};
+    const T wx[2] = {(T)1 - lx, lx}, wy[2] = {(T)1 - ly, ly}, wz[2] = {(T)1 - lz, lz};
+    const size_t H3 = (size_t)H * H * H;
+    T ax = 0, ay = 0, az = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const size_t idx = ((size_t)ix[a] * H + iy[b]) * H + iz[c];
+                const T w = wx[a] * wy[b] * wz[c];
+                ax += w * G[idx];
+                ay += w * G[H3 + idx];
+                az += w * G[2 * H3 + idx];
+            }
+    vx = ax;
+    vy = ay;
+    vz = az;
+}
+
+template <typename T> __device__ __forceinline__ T wrap_box(T v, T L, T halfL, T invL) {
+    return v - L * floor((v + halfL) * invL);
+}
+
+template <typename T> __device__ __forceinline__ int wave_min(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+template <typename T> __device__ __forceinline__ int wave_max(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// One chunk [beg, end) of one instance.
+template <typename T, bool DEP, bool PUSH, int SCHEME>
+__device__ __forceinline__ void chunk_pass(const PartDesc<T>& a, int64_t beg, int64_t end, T* win, int wcap,
+                                           int* sh) {
+    const int tid = threadIdx.x;
+    const int H = a.H, Hm = H - 1, Hh = H / 2;
+    const T hl = a.hl;
+    bool use_win = false;
+    int ox = 0, oy = 0, oz = 0, Wx = H, Wy = H, Wz = H;
+    if (DEP) {
+        if (tid < 3) sh[tid] = INT_MAX;
+        else if (tid < 6) sh[tid] = INT_MIN;
+        __syncthreads();
+        const int rx = ifloor(a.x[beg] * hl) & Hm;
+        const int ry = ifloor(a.y[beg] * hl) & Hm;
+        const int rz = ifloor(a.z[beg] * hl) & Hm;
+        int mnx = INT_MAX, mny = INT_MAX, mnz = INT_MAX, mxx = INT_MIN, mxy = INT_MIN, mxz = INT_MIN;
+        for (int64_t i = beg + tid; i < end; i += PT) {
+            const int cx = (((ifloor(a.x[i] * hl) & Hm) - rx + Hh) & Hm) - Hh;
+            const int cy = (((ifloor(a.y[i] * hl) & Hm) - ry + Hh) & Hm) - Hh;
+            const int cz = (((ifloor(a.z[i] * hl) & Hm) - rz + Hh) & Hm) - Hh;
+            mnx = min(mnx, cx); mxx = max(mxx, cx);
+            mny = min(mny, cy); mxy = max(mxy, cy);
+            mnz = min(mnz, cz); mxz = max(mxz, cz);
+        }
+        mnx = wave_min<T>(mnx); mny = wave_min<T>(mny); mnz = wave_min<T>(mnz);
+        mxx = wave_max<T>(mxx); mxy = wave_max<T>(mxy); mxz = wave_max<T>(mxz);
+        if ((tid & 63) == 0) {
+            atomicMin(&sh[0], mnx); atomicMin(&sh[1], mny); atomicMin(&sh[2], mnz);
+            atomicMax(&sh[3], mxx); atomicMax(&sh[4], mxy); atomicMax(&sh[5], mxz);
+        }
+        __syncthreads();
+        const int ex = sh[3] - sh[0] + 4, ey = sh[4] - sh[1] + 4, ez = sh[5] - sh[2] + 4;
+        if (ex < H) { Wx = ex; ox = (rx + sh[0] - 1) & Hm; }
+        if (ey < H) { Wy = ey; oy = (ry + sh[1] - 1) & Hm; }
+        if (ez < H) { Wz = ez; oz = (rz + sh[2] - 1) & Hm; }
+        use_win = (int64_t)Wx * Wy * Wz <= (int64_t)wcap;
+        if (use_win) {
+            for (int e = tid; e < Wx * Wy * Wz; e += PT) win[e] = (T)0;
+            __syncthreads();
+        }
+    }
+    const uint32_t n = PUSH ? *a.step + 1u : 0u;
+    for (int64_t i = beg + tid; i < end; i += PT) {
+        const T x = a.x[i], y = a.y[i], z = a.z[i];
+        if (DEP) {
+            if (use_win) deposit_one(win, x, y, z, hl, Hm, ox, oy, oz, Wy, Wz, a.wmass);
+            else deposit_one(a.phi, x, y, z, hl, Hm, 0, 0, 0, H, H, a.wmass);
+        }
+        if (PUSH) {
+            const uint32_t pid = a.id[i];
+            T yx, yy, yz, w0, w1, w2;
+            if (SCHEME == SIPF_STRANG) {
+                T m0, m1, m2;
+                noise3<T>(pid, n, 0u, a.inst, a.k0, a.k1, m0, m1, m2);
+                noise3<T>(pid, n, 1u, a.inst, a.k0, a.k1, w0, w1, w2);
+                yx = x + a.s * m0;
+                yy = y + a.s * m1;
+                yz = z + a.s * m2;
+            } else {
+                noise3<T>(pid, n, 0u, a.inst, a.k0, a.k1, w0, w1, w2);
+                yx = x; yy = y; yz = z;
+            }
+            T vx, vy, vz;
+            gather_one(a.G, H, hl, yx, yy, yz, vx, vy, vz);
+            const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
+            const T ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
+            const T nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
+            a.x[i] = nx;
+            a.y[i] = ny;
+            a.z[i] = nz;
+            if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(a.err, 1);
+        }
+    }
+    if (DEP && use_win) {
+        __syncthreads();
+        const int WyWz = Wy * Wz;
+        for (int e = tid; e < Wx * WyWz; e += PT) {
+            const T v = win[e];
+            if (v != (T)0) {
+                const int ex = e / WyWz, r = e - ex * WyWz;
+                const int ey = r / Wz, ez = r - ey * Wz;
+                const size_t node = ((size_t)((ox + ex) & Hm) * H + ((oy + ey) & Hm)) * H + ((oz + ez) & Hm);
+                atomic_add(a.phi + node, v);
+            }
+        }
+    }
+}
+
+template <typename T, bool DEP, bool PUSH, int SCHEME>
+__global__ __launch_bounds__(PT) void k_particles(const PartDesc<T>* __restrict__ pds,
+                                                  const WorkItem* __restrict__ items, int nitems, int wcap) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* win = reinterpret_cast<T*>(smem_raw);
+    __shared__ int sh[8];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const WorkItem w = items[it];
+        chunk_pass<T, DEP, PUSH, SCHEME>(pds[w.inst], w.beg, w.beg + w.cnt, win, wcap, sh);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int nitems, bool deposit, bool push,
+                            int scheme, int wcap, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const size_t shm = (size_t)wcap * sizeof(T);
+    const dim3 grid(nitems), block(PT);
+    if (deposit && push) {
+        if (scheme == SIPF_STRANG)
+            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_STRANG>), grid, block, shm, s, pd, items, nitems, wcap);
+        else
+            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_EM>), grid, block, shm, s, pd, items, nitems, wcap);
+    } else if (deposit) {
+        hipLaunchKernelGGL((k_particles<T, true, false, SIPF_STRANG>), grid, block, shm, s, pd, items, nitems, wcap);
+    } else if (push) {
+        if (scheme == SIPF_STRANG)
+            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_STRANG>), grid, block, 0, s, pd, items, nitems, 0);
+        else
+            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_EM>), grid, block, 0, s, pd, items, nitems, 0);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// tile sort: histogram, scan, scatter
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* __restrict__ pdp, uint32_t* counts,
+                                                            int tshift, int nk) {
+    __shared__ uint32_t h[MAX_KEYS];
+    const PartDesc<T> a = *pdp;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < nk; i += SORT_THREADS) h[i] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * SORT_CHUNK;
+    const int64_t end = min(beg + (int64_t)SORT_CHUNK, a.P);
+    for (int64_t i = beg + tid; i < end; i += SORT_THREADS)
+        atomicAdd(&h[tile_key(a.x[i], a.y[i], a.z[i], a.hl, a.H - 1, tshift)], 1u);
+    __syncthreads();
+    for (int i = tid; i < nk; i += SORT_THREADS)
+        if (h[i]) atomicAdd(&counts[i], h[i]);
+}
+
+// exclusive scan of the counts into cursor[]; clears counts for the next sort
+__global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* cursor, int nk) {
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nk + 1023) / 1024;
+    uint32_t loc[4];
+    uint32_t sum = 0;
+    for (int j = 0; j < per; ++j) {
+        const int i = tid * per + j;
+        loc[j] = i < nk ? counts[i] : 0u;
+        sum += loc[j];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+    for (int j = 0; j < per; ++j) {
+        const int i = tid * per + j;
+        if (i < nk) {
+            cursor[i] = run;
+            counts[i] = 0u;
+        }
+        run += loc[j];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>* __restrict__ pdp, T* __restrict__ x2,
+                                                               T* __restrict__ y2, T* __restrict__ z2,
+                                                               uint32_t* __restrict__ id2, uint32_t* cursor,
+                                                               int tshift, int nk) {
+    __shared__ uint32_t lc[MAX_KEYS];
+    __shared__ uint32_t lb[MAX_KEYS];
+    const PartDesc<T> a = *pdp;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < nk; i += SORT_THREADS) lc[i] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * SORT_CHUNK;
+    T px[SORT_PER_THREAD], py[SORT_PER_THREAD], pz[SORT_PER_THREAD];
+    uint32_t pid[SORT_PER_THREAD], key[SORT_PER_THREAD], rank[SORT_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < SORT_PER_THREAD; ++k) {
+        const int64_t i = beg + tid + (int64_t)k * SORT_THREADS;
+        if (i < a.P) {
+            px[k] = a.x[i];
+            py[k] = a.y[i];
+            pz[k] = a.z[i];
+            pid[k] = a.id[i];
+            key[k] = tile_key(px[k], py[k], pz[k], a.hl, a.H - 1, tshift);
+            rank[k] = atomicAdd(&lc[key[k]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nk; i += SORT_THREADS)
+        if (lc[i]) lb[i] = atomicAdd(&cursor[i], lc[i]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SORT_PER_THREAD; ++k) {
+        const int64_t i = beg + tid + (int64_t)k * SORT_THREADS;
+        if (i < a.P) {
+            const uint32_t dst = lb[key[k]] + rank[k];
+            x2[dst] = px[k];
+            y2[dst] = py[k];
+            z2[dst] = pz[k];
+            id2[dst] = pid[k];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T* y2, T* z2, uint32_t* id2,
+                       uint32_t* counts, uint32_t* cursor, int tile, int, hipStream_t s) {
+    const int H = pd_host->H;
+    int tshift = 0;
+    while ((1 << tshift) < tile) ++tshift;
+    const int nt = H >> tshift;
+    const int nk = nt * nt * nt;
+    if (nk > MAX_KEYS || (1 << tshift) != tile) return hipErrorInvalidValue;
+    const int nblk = (int)((pd_host->P + SORT_CHUNK - 1) / SORT_CHUNK);
+    hipLaunchKernelGGL((k_tile_hist<T>), dim3(nblk), dim3(SORT_THREADS), 0, s, pd_dev, counts, tshift, nk);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, cursor, nk);
+    hipLaunchKernelGGL((k_tile_scatter<T>), dim3(nblk), dim3(SORT_THREADS), 0, s, pd_dev, x2, y2, z2, id2, cursor,
+                       tshift, nk);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small kernels: layout conversion, test entry points
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_load_positions(const T* __restrict__ xyz, int64_t P, T L, T halfL, T invL, T* x, T* y, T* z,
+                                 uint32_t* id, int* err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const T a = xyz[3 * i], b = xyz[3 * i + 1], c = xyz[3 * i + 2];
+    if (!(isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(err, 2);
+    x[i] = wrap_box(a, L, halfL, invL);
+    y[i] = wrap_box(b, L, halfL, invL);
+    z[i] = wrap_box(c, L, halfL, invL);
+    id[i] = (uint32_t)i;
+}
+
+template <typename T>
+hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd, int* err, hipStream_t s) {
+    const int nb = (int)((P + 255) / 256);
+    hipLaunchKernelGGL((k_load_positions<T>), dim3(nb), dim3(256), 0, s, xyz, P, L, L / 2, (T)1 / L, pd.x, pd.y, pd.z,
+                       pd.id, err);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_unsort(const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z,
+                         const uint32_t* __restrict__ id, int64_t P, T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int64_t j = id[i];
+    out[3 * j] = x[i];
+    out[3 * j + 1] = y[i];
+    out[3 * j + 2] = z[i];
+}
+
+template <typename T> hipError_t launch_unsort(const PartDesc<T>* pd, T* out, hipStream_t s) {
+    const int nb = (int)((pd->P + 255) / 256);
+    hipLaunchKernelGGL((k_unsort<T>), dim3(nb), dim3(256), 0, s, pd->x, pd->y, pd->z, pd->id, pd->P, out);
+    return hipGetLastError();
+}
+
+template <typename T> __global__ void k_fill(T* p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nbl = (n + 255) / 256;
+    const int nb = (int)(nbl < 4096 ? nbl : 4096);
+    hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_cells(const T* __restrict__ X, int64_t n, T hl, int32_t* cells) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < 3; ++d) cells[3 * i + d] = ifloor(X[3 * i + d] * hl);
+}
+template <typename T> hipError_t launch_cells(const T* X, int64_t n, int, T hl, int32_t* cells, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cells<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, hl, cells);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_philox_dbg(uint32_t k0, uint32_t k1, int64_t n, const uint32_t* __restrict__ ctr,
+                             uint32_t* __restrict__ raw, T* __restrict__ normals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u32x4 c{ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    const u32x4 r = philox4x32_10(c, k0, k1);
+    if (raw) {
+        raw[4 * i] = r.v0;
+        raw[4 * i + 1] = r.v1;
+        raw[4 * i + 2] = r.v2;
+        raw[4 * i + 3] = r.v3;
+    }
+    if (normals) {
+        T z0, z1, z2;
+        normals3(r, z0, z1, z2);
+        normals[3 * i] = z0;
+        normals[3 * i + 1] = z1;
+        normals[3 * i + 2] = z2;
+    }
+}
+template <typename T>
+hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint32_t* raw, T* normals, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_philox_dbg<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), n, ctr, raw, normals);
+    return hipGetLastError();
+}
+
+#define SIPF_INST(T)                                                                                              \
+    template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, int, bool, bool, int, int,       \
+                                            hipStream_t);                                                         \
+    template hipError_t launch_sort<T>(const PartDesc<T>*, PartDesc<T>*, T*, T*, T*, uint32_t*, uint32_t*,        \
+                                       uint32_t*, int, int, hipStream_t);                                         \
+    template hipError_t launch_load_positions<T>(const T*, int64_t, T, PartDesc<T>, int*, hipStream_t);          \
+    template hipError_t launch_unsort<T>(const PartDesc<T>*, T*, hipStream_t);                                    \
+    template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                              \
+    template hipError_t launch_cells<T>(const T*, int64_t, int, T, int32_t*, hipStream_t);                        \
+    template hipError_t launch_philox_dbg<T>(uint64_t, int64_t, const uint32_t*, uint32_t*, T*, hipStream_t);
+
+SIPF_INST(float)
+SIPF_INST(double)
+
+}  // namespace sipf

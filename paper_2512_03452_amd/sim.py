@@ -1,0 +1,169 @@
+"""Python front end of libsipf.so: device memory and streams come from torch,
+every step of the method runs in the library's HIP kernels."""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype(prm):
+    return torch.float32 if prm.precision == _lib.SIPF_FP32 else torch.float64
+
+
+class Sim:
+    """One SIPF-PIC simulation (Algorithm 4) held by the library.
+
+    X0: (P, 3) positions (numpy array or torch tensor); alpha0: optional
+    complex (H, H, H/2+1) half spectrum of c(x, 0).  Keyword arguments are
+    ``sipf_params`` fields (scheme/precision may be given as strings).
+    """
+
+    def __init__(self, X0, alpha0=None, stream=None, **params):
+        lib = _lib.load()
+        self.params = _lib.default_params(**params)
+        self.dtype = _dtype(self.params)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        X = torch.as_tensor(np.asarray(X0) if not torch.is_tensor(X0) else X0)
+        X = X.to(device=self.device, dtype=self.dtype).contiguous()
+        if X.ndim != 2 or X.shape[1] != 3:
+            raise ValueError("X0 must have shape (P, 3)")
+        self.P = int(X.shape[0])
+        self.H = int(self.params.H)
+        a_ptr = None
+        if alpha0 is not None:
+            a = torch.as_tensor(alpha0)
+            cdt = torch.complex64 if self.dtype == torch.float32 else torch.complex128
+            a = a.to(device=self.device, dtype=cdt).contiguous()
+            if tuple(a.shape) != (self.H, self.H, self.H // 2 + 1):
+                raise ValueError("alpha0 must have shape (H, H, H/2+1)")
+            a_ptr = ctypes.c_void_p(a.data_ptr())
+        self._stream = stream
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        check(lib.sipf_init(ctypes.byref(self.params), self.P, ctypes.c_void_p(X.data_ptr()), 1,
+                            a_ptr, 1, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    # -- stepping ------------------------------------------------------------
+    def step(self):
+        check(_lib.load().sipf_step(self._h))
+
+    def run(self, nsteps):
+        check(_lib.load().sipf_run(self._h, int(nsteps)))
+
+    def sync(self):
+        check(_lib.load().sipf_sync(self._h))
+
+    @property
+    def n(self):
+        v = ctypes.c_int64()
+        check(_lib.load().sipf_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    # -- state ----------------------------------------------------------------
+    def positions(self):
+        out = torch.empty((self.P, 3), dtype=self.dtype, device=self.device)
+        check(_lib.load().sipf_get_positions(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def field(self, which):
+        H = self.H
+        lib = _lib.load()
+        if which in ("rho", _lib.SIPF_FIELD_RHO):
+            out = torch.empty((H, H, H), dtype=self.dtype, device=self.device)
+            check(lib.sipf_get_field(self._h, _lib.SIPF_FIELD_RHO, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        if which in ("grad", _lib.SIPF_FIELD_GRAD):
+            out = torch.empty((3, H, H, H), dtype=self.dtype, device=self.device)
+            check(lib.sipf_get_field(self._h, _lib.SIPF_FIELD_GRAD, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        if which in ("alpha", _lib.SIPF_FIELD_ALPHA):
+            out = torch.empty((H, H, H // 2 + 1, 2), dtype=self.dtype, device=self.device)
+            check(lib.sipf_get_field(self._h, _lib.SIPF_FIELD_ALPHA, ctypes.c_void_p(out.data_ptr()), 1))
+            return torch.view_as_complex(out)
+        raise ValueError("which must be 'rho', 'alpha' or 'grad'")
+
+    def profile(self, enable=True):
+        """Start (clearing the accumulators) or stop per-phase event timing."""
+        check(_lib.load().sipf_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} since profiling was enabled (synchronises)."""
+        n = len(_lib.PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        check(_lib.load().sipf_profile_read(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.PHASES)}
+
+    def save(self, path):
+        check(_lib.load().sipf_save(self._h, str(path).encode()))
+
+    @classmethod
+    def load(cls, path, stream=None):
+        self = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        check(_lib.load().sipf_load(str(path).encode(), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._stream = stream
+        p = _lib.SipfParams()
+        self.params = p
+        return self
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.load().sipf_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def dbg_philox(ctr, seed, precision="fp32"):
+    """Raw Philox outputs and the normal 3-vectors for counters ctr (n, 4) uint32."""
+    ctr = torch.as_tensor(np.asarray(ctr, dtype=np.uint32).view(np.int32)).cuda().contiguous()
+    n = ctr.shape[0]
+    raw = torch.empty((n, 4), dtype=torch.int32, device=ctr.device)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    z = torch.empty((n, 3), dtype=dt, device=ctr.device)
+    prec = _lib.SIPF_FP32 if precision == "fp32" else _lib.SIPF_FP64
+    check(_lib.load().sipf_dbg_philox(int(seed), n, ctypes.c_void_p(ctr.data_ptr()), ctypes.c_void_p(raw.data_ptr()),
+                                      ctypes.c_void_p(z.data_ptr()), prec, _stream_handle()))
+    return raw.cpu().numpy().view(np.uint32), z
+
+
+def dbg_cells(X, **params):
+    p = _lib.default_params(**params)
+    X = torch.as_tensor(X).to(device="cuda", dtype=_dtype(p)).contiguous()
+    out = torch.empty((X.shape[0], 3), dtype=torch.int32, device=X.device)
+    check(_lib.load().sipf_dbg_cells(ctypes.byref(p), X.shape[0], ctypes.c_void_p(X.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_handle()))
+    return out
+
+
+def dbg_deposit(X, **params):
+    p = _lib.default_params(**params)
+    X = torch.as_tensor(X).to(device="cuda", dtype=_dtype(p)).contiguous()
+    H = p.H
+    out = torch.empty((H, H, H), dtype=_dtype(p), device=X.device)
+    check(_lib.load().sipf_dbg_deposit(ctypes.byref(p), X.shape[0], ctypes.c_void_p(X.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), _stream_handle()))
+    return out
