@@ -95,7 +95,7 @@ typedef struct sipf_params {
     int32_t  precision;    /* SIPF_FP32 (default) or SIPF_FP64                    */
     int32_t  tile;         /* binning tile side in cells; 0 = tuned default        */
     int32_t  resort_every; /* re-sort period in steps; 0 = tuned default           */
-    int32_t  chunk;        /* particles per workgroup of the particle pass; 0 = tuned */
+    int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = tuned */
     uint64_t seed;         /* Philox key                                          */
     uint32_t instance;     /* fourth Philox counter word                          */
     uint32_t reserved;     /* must be 0                                           */

@@ -50,7 +50,7 @@ int validate(const sipf_params* p, int64_t P) {
     if (p->tile != 0 && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > 16))
         return fail(SIPF_EINVAL, "tile must be 0 or a power of two with H/16 <= tile <= H");
     if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
-    if (p->chunk != 0 && (p->chunk < 256 || p->chunk > (1 << 20))) return fail(SIPF_EINVAL, "chunk must be 0 or in [256, 2^20]");
+    if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 4096)) return fail(SIPF_EINVAL, "chunk must be 0 or in [256, 4096]");
     if (p->reserved != 0) return fail(SIPF_EINVAL, "reserved must be 0");
     if (P < 1 || P >= (int64_t(1) << 32)) return fail(SIPF_EINVAL, "P must be in [1, 2^32)");
     return SIPF_OK;
@@ -66,7 +66,7 @@ void tuning(const sipf_params* p, int64_t P, int& tile, int& resort, int& chunk)
     tile = p->tile ? p->tile : (p->H >= 128 ? 8 : (p->H >= 16 ? p->H / 8 : p->H));
     if (p->H / tile > 16) tile = p->H / 16;
     resort = p->resort_every ? p->resort_every : 4;
-    chunk = p->chunk ? p->chunk : 2048;
+    chunk = p->chunk ? p->chunk : 4096;
     (void)P;
 }
 
@@ -79,7 +79,7 @@ struct sipf_ctx {
     int prec = SIPF_FP32;
     size_t tsize = 4;
     hipStream_t stream = nullptr;
-    int tile = 8, resort = 4, chunk = 2048, wcap = 8192;
+    int tile = 8, resort = 4, chunk = 4096, win_bytes = 65536, pgrid = 1024;
     int since_sort = 0;
     int cur = 0;  // which of the two particle buffer sets holds the current positions
     int64_t n_host = 0;
@@ -98,8 +98,9 @@ struct sipf_ctx {
     int* err = nullptr;
     void* pdesc = nullptr;  // two PartDesc<T> (one per buffer set)
     void* fdesc = nullptr;  // one FieldDesc<T>
-    WorkItem* items = nullptr;
-    int nitems = 0;
+    WorkItem* items = nullptr;  // work items of the particle pass, rebuilt by every sort
+    int* nitems = nullptr;      // device count of items
+    int items_cap = 0;
     std::vector<void*> allocs;
     // captured graph of a whole number of sort periods
     hipGraphExec_t gexec = nullptr;
@@ -153,6 +154,8 @@ template <typename T> PartDesc<T> make_pdesc(const sipf_ctx* c, int set) {
     d.k0 = (uint32_t)c->prm.seed;
     d.k1 = (uint32_t)(c->prm.seed >> 32);
     d.inst = c->prm.instance;
+    // |W^-| <= s max|z| with max|z| = sqrt(-2 ln 2^-24) (uniforms are >= 2^-24)
+    d.gmargin = c->prm.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.7677 * (double)d.hl) : 0;
     return d;
 }
 
@@ -214,7 +217,7 @@ template <typename T> int do_sort(sipf_ctx* c) {
         Timed t(c, SIPF_PHASE_SORT);
         HIPCHK(launch_sort<T>(&src, reinterpret_cast<PartDesc<T>*>(c->pdesc) + c->cur, (T*)c->xs[dst],
                               (T*)c->ys[dst], (T*)c->zs[dst], c->ids[dst], c->counts, c->cursor, c->tile, c->chunk,
-                              c->stream));
+                              c->items, c->nitems, 0, c->stream));
     }
     c->cur = dst;
     c->since_sort = 0;
@@ -230,8 +233,8 @@ template <typename T> int enqueue_step(sipf_ctx* c) {
     }
     {
         Timed t(c, SIPF_PHASE_PARTICLES);
-        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, true, true, c->prm.scheme, c->wcap,
-                                   c->stream));
+        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, true,
+                                   c->prm.scheme, c->win_bytes, c->stream));
     }
     const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
     {
@@ -339,17 +342,11 @@ int init_typed(sipf_ctx* c, const void* X0, int x0_on_device, const void* alpha0
     if ((rc = dalloc(c, (void**)&c->err, 16))) return rc;
     if ((rc = dalloc(c, &c->pdesc, 2 * sizeof(PartDesc<T>)))) return rc;
     if ((rc = dalloc(c, &c->fdesc, sizeof(FieldDesc<T>)))) return rc;
-    c->nitems = (int)((P + c->chunk - 1) / c->chunk);
-    if ((rc = dalloc(c, (void**)&c->items, c->nitems * sizeof(WorkItem)))) return rc;
-    {
-        std::vector<WorkItem> it(c->nitems);
-        for (int i = 0; i < c->nitems; ++i) {
-            it[i].beg = (int64_t)i * c->chunk;
-            it[i].cnt = (int32_t)std::min<int64_t>(c->chunk, P - it[i].beg);
-            it[i].inst = 0;
-        }
-        HIPCHK(hipMemcpy(c->items, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-    }
+    c->items_cap = (int)((P + particle_chunk() - 1) / particle_chunk()) + sort_max_keys();
+    if ((rc = dalloc(c, (void**)&c->items, c->items_cap * sizeof(WorkItem)))) return rc;
+    if ((rc = dalloc(c, (void**)&c->nitems, 16))) return rc;
+    HIPCHK(hipMemset(c->nitems, 0, 16));
+    c->pgrid = std::min(c->items_cap, 1024);
     HIPCHK(hipMemset(c->counts, 0, sort_max_keys() * sizeof(uint32_t)));
     HIPCHK(hipMemset(c->step, 0, 16));
     HIPCHK(hipMemset(c->err, 0, 16));
@@ -397,8 +394,8 @@ template <typename T> int get_field_typed(sipf_ctx* c, int which, void* out, int
     const size_t nspec = (size_t)H * H * (H / 2 + 1);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (which == SIPF_FIELD_RHO) {
-        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, true, false, c->prm.scheme, c->wcap,
-                                   c->stream));
+        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false,
+                                   c->prm.scheme, c->win_bytes, c->stream));
         HIPCHK(hipMemcpyAsync(out, c->phi, H3 * sizeof(T), kind, c->stream));
         HIPCHK(launch_fill<T>((T*)c->phi, H3, (T)0, c->stream));
     } else if (which == SIPF_FIELD_GRAD) {
@@ -486,7 +483,7 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
     c->tsize = ts;
     c->stream = (hipStream_t)hip_stream;
     tuning(prm, P, c->tile, c->resort, c->chunk);
-    c->wcap = c->prec == SIPF_FP32 ? 8192 : 4096;
+    c->win_bytes = 65536;
     rc = c->prec == SIPF_FP32 ? init_typed<float>(c, X0, x0_on_device, alpha0, alpha0_on_device)
                               : init_typed<double>(c, X0, x0_on_device, alpha0, alpha0_on_device);
     if (rc) {

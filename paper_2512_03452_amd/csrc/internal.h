@@ -51,6 +51,7 @@ template <typename T> struct PartDesc {
     T s;                    // noise scale: sqrt(mu tau) (split) or sqrt(2 mu tau) (EM)
     uint32_t k0, k1;        // Philox key
     uint32_t inst;          // fourth counter word
+    int gmargin;            // cells the W^- displacement can reach (gradient window margin)
 };
 
 // Work item of the particle pass: particles [beg, beg + cnt) of instance inst.
@@ -72,11 +73,12 @@ int fft_perm(int N, int k);
 
 // --- particle pass (particles.hip) -------------------------------------------
 template <typename T>
-hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int nitems, bool deposit, bool push,
-                            int scheme, int wcap, hipStream_t s);
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+                            bool push, int scheme, int win_bytes, hipStream_t s);
 template <typename T>
 hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T* y2, T* z2, uint32_t* id2,
-                       uint32_t* counts, uint32_t* cursor, int tile, int chunk, hipStream_t s);
+                       uint32_t* counts, uint32_t* cursor, int tile, int chunk, WorkItem* items, int* nitems,
+                       int inst, hipStream_t s);
 template <typename T>
 hipError_t launch_cells(const T* X, int64_t n, int H, T hl, int32_t* cells, hipStream_t s);
 template <typename T>
@@ -88,5 +90,6 @@ hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd_ho
 template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
 int sort_max_keys();
 int particle_threads();
+int particle_chunk();
 
 }  // namespace sipf

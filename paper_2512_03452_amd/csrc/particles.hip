@@ -19,14 +19,25 @@
 
 namespace sipf {
 
-constexpr int PT = 256;            // threads per particle-pass workgroup
+constexpr int PT = 512;            // threads per particle-pass workgroup
+constexpr int PPT = 8;             // particles held in registers per thread
+constexpr int CH = PT * PPT;       // particles per work item at most
 constexpr int SORT_THREADS = 512;  // threads per sort workgroup
 constexpr int SORT_PER_THREAD = 8;
 constexpr int SORT_CHUNK = SORT_THREADS * SORT_PER_THREAD;
 constexpr int MAX_KEYS = 4096;     // (H / tile)^3 <= 16^3
+constexpr int MIN_WINDOW_ITEM = 64;  // smaller items deposit and gather straight from global memory
 
 int particle_threads() { return PT; }
+int particle_chunk() { return CH; }
 int sort_max_keys() { return MAX_KEYS; }
+
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GLOBAL T* gp(T* p) { return (GLOBAL T*)p; }
+template <typename T> __device__ __forceinline__ const GLOBAL T* gp(const T* p) { return (const GLOBAL T*)p; }
+
+__device__ __forceinline__ void gatomic_add(float* p, float v) { __builtin_amdgcn_global_atomic_fadd_f32(gp(p), v); }
+__device__ __forceinline__ void gatomic_add(double* p, double v) { __builtin_amdgcn_global_atomic_fadd_f64(gp(p), v); }
 
 template <typename T> __device__ __forceinline__ int ifloor(T v) { return (int)floor(v); }
 
@@ -46,14 +57,32 @@ __device__ __forceinline__ uint32_t tile_key(T x, T y, T z, T hl, int Hm, int ts
     return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tz);
 }
 
-template <typename T> __device__ __forceinline__ void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
+// Fixed-point accumulator of the LDS deposit window.  Float atomic adds on
+// LDS run ~25x slower than integer ones on gfx950, so weights are rounded to
+// integers at a power-of-two scale 2^S chosen per work item so that no node
+// sum can overflow, summed exactly with integer LDS atomics, and converted
+// back once when the window is added to the grid.
+template <typename T> struct Fixed;
+template <> struct Fixed<float> {
+    using I = int32_t;
+    using U = uint32_t;
+    static constexpr int BITS = 30;
+    __device__ static I quant(float v) { return (I)rintf(v); }
+};
+template <> struct Fixed<double> {
+    using I = long long;
+    using U = unsigned long long;
+    static constexpr int BITS = 62;
+    __device__ static I quant(double v) { return (I)rint(v); }
+};
 
 // ---------------------------------------------------------------------------
-// deposit of one particle: 32 nodes of Gamma_4 with the weights of eq. 4ord
+// deposit of one particle: 32 nodes of Gamma_4 with the weights of eq. 4ord.
+// sink(index, F) receives the window index and the weight F (without mass).
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void deposit_one(T* __restrict__ dst, T x, T y, T z, T hl, int Hm, int ox, int oy,
-                                            int oz, int Wy, int Wz, T m) {
+template <typename T, typename Sink>
+__device__ __forceinline__ void deposit_one(Sink& sink, T x, T y, T z, T hl, int Hm, int ox, int oy, int oz, int Wy,
+                                            int Wz) {
     const T sx = x * hl, sy = y * hl, sz = z * hl;
     const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
     const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
@@ -68,7 +97,6 @@ __device__ __forceinline__ void deposit_one(T* __restrict__ dst, T x, T y, T z, 
         cz[j] = (gz - 1 + j - oz) & Hm;
     }
     const T wx[2] = {ax.w0, ax.w1}, wy[2] = {ay.w0, ay.w1}, wz[2] = {az.w0, az.w1};
-    const T mS = m * S;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
@@ -76,35 +104,42 @@ __device__ __forceinline__ void deposit_one(T* __restrict__ dst, T x, T y, T z, 
             const T pyz = wy[a] * wz[b];
             const T pxz = wx[a] * wz[b];
             const T pxy = wx[a] * wy[b];
+            const T Spyz = S * pyz;
             // inner nodes (0/1, a, b)
-            atomic_add(dst + cx[1] + cy[1 + a] + cz[1 + b], mS * wx[0] * pyz);
-            atomic_add(dst + cx[2] + cy[1 + a] + cz[1 + b], mS * wx[1] * pyz);
+            sink(cx[1] + cy[1 + a] + cz[1 + b], wx[0] * Spyz);
+            sink(cx[2] + cy[1 + a] + cz[1 + b], wx[1] * Spyz);
             // outer nodes on x: (-1, a, b) and (2, a, b)
-            atomic_add(dst + cx[0] + cy[1 + a] + cz[1 + b], m * ax.wm * pyz);
-            atomic_add(dst + cx[3] + cy[1 + a] + cz[1 + b], m * ax.wp * pyz);
+            sink(cx[0] + cy[1 + a] + cz[1 + b], ax.wm * pyz);
+            sink(cx[3] + cy[1 + a] + cz[1 + b], ax.wp * pyz);
             // outer nodes on y: (a, -1, b) and (a, 2, b)
-            atomic_add(dst + cx[1 + a] + cy[0] + cz[1 + b], m * ay.wm * pxz);
-            atomic_add(dst + cx[1 + a] + cy[3] + cz[1 + b], m * ay.wp * pxz);
+            sink(cx[1 + a] + cy[0] + cz[1 + b], ay.wm * pxz);
+            sink(cx[1 + a] + cy[3] + cz[1 + b], ay.wp * pxz);
             // outer nodes on z: (a, b, -1) and (a, b, 2)
-            atomic_add(dst + cx[1 + a] + cy[1 + b] + cz[0], m * az.wm * pxy);
-            atomic_add(dst + cx[1 + a] + cy[1 + b] + cz[3], m * az.wp * pxy);
+            sink(cx[1 + a] + cy[1 + b] + cz[0], az.wm * pxy);
+            sink(cx[1 + a] + cy[1 + b] + cz[3], az.wp * pxy);
         }
     }
 }
 
-// trilinear interpolation of the three gradient grids at (x, y, z) (eq. 2ord)
-template <typename T>
-__device__ __forceinline__ void gather_one(const T* __restrict__ G, int H, T hl, T x, T y, T z, T& vx, T& vy, T& vz) {
-    const int Hm = H - 1;
-    const T sx = x * hl, sy = y * hl, sz = z * hl;
-    const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
-    const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
-    const T lx = sx - fx, ly = sy - fy, lz = sz - fz;
-    const int ix[2] = {gx & Hm, (gx + 1) & Hm};
-    const int iy[2] = {gy & Hm, (gy + 1) & Hm};
-    const int iz[2] = {gz & Hm, (gz + 1) & Hm};
+template <typename T> struct LdsSink {
+    typename Fixed<T>::I* win;
+    T scale;  // 2^S
+    __device__ __forceinline__ void operator()(int idx, T F) const {
+        atomicAdd(reinterpret_cast<typename Fixed<T>::U*>(win + idx), (typename Fixed<T>::U)Fixed<T>::quant(F * scale));
+    }
+};
+template <typename T> struct GlobalSink {
+    T* phi;
+    T m;
+    __device__ __forceinline__ void operator()(int idx, T F) const { gatomic_add(phi + idx, F * m); }
+};
+
+// trilinear interpolation (eq. 2ord) of three planar grids of node pitch n3,
+// nodes (ix[a], iy[b], iz[c]) with row strides (Wy, Wz)
+template <typename T, typename P>
+__device__ __forceinline__ void trilinear3(P G, size_t n3, int Wy, int Wz, const int* ix, const int* iy, const int* iz,
+                                           T lx, T ly, T lz, T& vx, T& vy, T& vz) {
     const T wx[2] = {(T)1 - lx, lx}, wy[2] = {(T)1 - ly, ly}, wz[2] = {(T)1 - lz, lz};
-    const size_t H3 = (size_t)H * H * H;
     T ax = 0, ay = 0, az = 0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -112,11 +147,11 @@ __device__ __forceinline__ void gather_one(const T* __restrict__ G, int H, T hl,
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const size_t idx = ((size_t)ix[a] * H + iy[b]) * H + iz[c];
+                const size_t idx = ((size_t)ix[a] * Wy + iy[b]) * Wz + iz[c];
                 const T w = wx[a] * wy[b] * wz[c];
                 ax += w * G[idx];
-                ay += w * G[H3 + idx];
-                az += w * G[2 * H3 + idx];
+                ay += w * G[n3 + idx];
+                az += w * G[2 * n3 + idx];
             }
     vx = ax;
     vy = ay;
@@ -127,135 +162,235 @@ template <typename T> __device__ __forceinline__ T wrap_box(T v, T L, T halfL, T
     return v - L * floor((v + halfL) * invL);
 }
 
-template <typename T> __device__ __forceinline__ int wave_min(int v) {
+__device__ __forceinline__ int wave_min(int v) {
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
     return v;
 }
-template <typename T> __device__ __forceinline__ int wave_max(int v) {
+__device__ __forceinline__ int wave_max(int v) {
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
     return v;
 }
 
-// One chunk [beg, end) of one instance.
+// Window along one axis covering relative cells [lo, hi] of a chunk whose
+// reference cell is r: origin and width, or the whole axis when it would wrap.
+__device__ __forceinline__ void axis_window(int r, int lo, int hi, int H, int& o, int& W) {
+    const int w = hi - lo + 1;
+    if (w >= H) {
+        o = 0;
+        W = H;
+    } else {
+        o = (r + lo) & (H - 1);
+        W = w;
+    }
+}
+
+// One work item: particles [beg, beg + cnt) of one instance, held in registers.
 template <typename T, bool DEP, bool PUSH, int SCHEME>
-__device__ __forceinline__ void chunk_pass(const PartDesc<T>& a, int64_t beg, int64_t end, T* win, int wcap,
-                                           int* sh) {
+__device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int cnt, unsigned char* lds,
+                                          int win_bytes, int* sh) {
+    using I = typename Fixed<T>::I;
     const int tid = threadIdx.x;
     const int H = a.H, Hm = H - 1, Hh = H / 2;
     const T hl = a.hl;
-    bool use_win = false;
-    int ox = 0, oy = 0, oz = 0, Wx = H, Wy = H, Wz = H;
-    if (DEP) {
+    T px[PPT], py[PPT], pz[PPT];
+    uint32_t pid[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int j = tid + k * PT;
+        if (j < cnt) {
+            px[k] = gp(a.x)[beg + j];
+            py[k] = gp(a.y)[beg + j];
+            pz[k] = gp(a.z)[beg + j];
+            if (PUSH) pid[k] = gp(a.id)[beg + j];
+        }
+    }
+    const bool windows = cnt >= MIN_WINDOW_ITEM;
+    int rx = 0, ry = 0, rz = 0;
+    if (windows) {
+        // bounding box of the item's cells, relative to the first particle's cell
         if (tid < 3) sh[tid] = INT_MAX;
         else if (tid < 6) sh[tid] = INT_MIN;
         __syncthreads();
-        const int rx = ifloor(a.x[beg] * hl) & Hm;
-        const int ry = ifloor(a.y[beg] * hl) & Hm;
-        const int rz = ifloor(a.z[beg] * hl) & Hm;
+        rx = ifloor(gp(a.x)[beg] * hl) & Hm;
+        ry = ifloor(gp(a.y)[beg] * hl) & Hm;
+        rz = ifloor(gp(a.z)[beg] * hl) & Hm;
         int mnx = INT_MAX, mny = INT_MAX, mnz = INT_MAX, mxx = INT_MIN, mxy = INT_MIN, mxz = INT_MIN;
-        for (int64_t i = beg + tid; i < end; i += PT) {
-            const int cx = (((ifloor(a.x[i] * hl) & Hm) - rx + Hh) & Hm) - Hh;
-            const int cy = (((ifloor(a.y[i] * hl) & Hm) - ry + Hh) & Hm) - Hh;
-            const int cz = (((ifloor(a.z[i] * hl) & Hm) - rz + Hh) & Hm) - Hh;
-            mnx = min(mnx, cx); mxx = max(mxx, cx);
-            mny = min(mny, cy); mxy = max(mxy, cy);
-            mnz = min(mnz, cz); mxz = max(mxz, cz);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (tid + k * PT < cnt) {
+                const int cx = (((ifloor(px[k] * hl) & Hm) - rx + Hh) & Hm) - Hh;
+                const int cy = (((ifloor(py[k] * hl) & Hm) - ry + Hh) & Hm) - Hh;
+                const int cz = (((ifloor(pz[k] * hl) & Hm) - rz + Hh) & Hm) - Hh;
+                mnx = min(mnx, cx); mxx = max(mxx, cx);
+                mny = min(mny, cy); mxy = max(mxy, cy);
+                mnz = min(mnz, cz); mxz = max(mxz, cz);
+            }
         }
-        mnx = wave_min<T>(mnx); mny = wave_min<T>(mny); mnz = wave_min<T>(mnz);
-        mxx = wave_max<T>(mxx); mxy = wave_max<T>(mxy); mxz = wave_max<T>(mxz);
+        mnx = wave_min(mnx); mny = wave_min(mny); mnz = wave_min(mnz);
+        mxx = wave_max(mxx); mxy = wave_max(mxy); mxz = wave_max(mxz);
         if ((tid & 63) == 0) {
             atomicMin(&sh[0], mnx); atomicMin(&sh[1], mny); atomicMin(&sh[2], mnz);
             atomicMax(&sh[3], mxx); atomicMax(&sh[4], mxy); atomicMax(&sh[5], mxz);
         }
         __syncthreads();
-        const int ex = sh[3] - sh[0] + 4, ey = sh[4] - sh[1] + 4, ez = sh[5] - sh[2] + 4;
-        if (ex < H) { Wx = ex; ox = (rx + sh[0] - 1) & Hm; }
-        if (ey < H) { Wy = ey; oy = (ry + sh[1] - 1) & Hm; }
-        if (ez < H) { Wz = ez; oz = (rz + sh[2] - 1) & Hm; }
-        use_win = (int64_t)Wx * Wy * Wz <= (int64_t)wcap;
+    }
+
+    if (DEP) {
+        int ox = 0, oy = 0, oz = 0, Wx = H, Wy = H, Wz = H;
+        bool use_win = false;
+        if (windows) {
+            // nodes -1..+2 around every cell of the box
+            axis_window(rx, sh[0] - 1, sh[3] + 2, H, ox, Wx);
+            axis_window(ry, sh[1] - 1, sh[4] + 2, H, oy, Wy);
+            axis_window(rz, sh[2] - 1, sh[5] + 2, H, oz, Wz);
+            use_win = (int64_t)Wx * Wy * Wz * (int64_t)sizeof(I) <= win_bytes;
+        }
         if (use_win) {
-            for (int e = tid; e < Wx * Wy * Wz; e += PT) win[e] = (T)0;
+            I* win = reinterpret_cast<I*>(lds);
+            const int nw = Wx * Wy * Wz;
+            for (int e = tid; e < nw; e += PT) win[e] = 0;
+            // 2^S with S = BITS - bitlength(ceil(11 cnt / 8)): |sum of F| <= 1.375 cnt per node
+            const int need = (11 * cnt + 7) / 8;
+            const int S = Fixed<T>::BITS - (32 - __clz(need));
+            const T scale = (T)ldexp(1.0, S);
             __syncthreads();
+            LdsSink<T> sink{win, scale};
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (tid + k * PT < cnt) deposit_one(sink, px[k], py[k], pz[k], hl, Hm, ox, oy, oz, Wy, Wz);
+            __syncthreads();
+            const T back = a.wmass * (T)ldexp(1.0, -S);
+            const int WyWz = Wy * Wz;
+            for (int e = tid; e < nw; e += PT) {
+                const I v = win[e];
+                if (v != 0) {
+                    const int ex = e / WyWz, r = e - ex * WyWz;
+                    const int ey = r / Wz, ez = r - ey * Wz;
+                    const size_t node = ((size_t)((ox + ex) & Hm) * H + ((oy + ey) & Hm)) * H + ((oz + ez) & Hm);
+                    gatomic_add(a.phi + node, (T)v * back);
+                }
+            }
+            __syncthreads();  // the window memory is reused below
+        } else {
+            GlobalSink<T> sink{a.phi, a.wmass};
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (tid + k * PT < cnt) deposit_one(sink, px[k], py[k], pz[k], hl, Hm, 0, 0, 0, H, H);
         }
     }
-    const uint32_t n = PUSH ? *a.step + 1u : 0u;
-    for (int64_t i = beg + tid; i < end; i += PT) {
-        const T x = a.x[i], y = a.y[i], z = a.z[i];
-        if (DEP) {
-            if (use_win) deposit_one(win, x, y, z, hl, Hm, ox, oy, oz, Wy, Wz, a.wmass);
-            else deposit_one(a.phi, x, y, z, hl, Hm, 0, 0, 0, H, H, a.wmass);
+
+    if (PUSH) {
+        // gradient window: cells of the box (+ margin for the W^- displacement) and +1 for the trilinear reach
+        int ox = 0, oy = 0, oz = 0, Wx = H, Wy = H, Wz = H;
+        bool use_win = false;
+        const T* Gl = reinterpret_cast<const T*>(lds);
+        size_t n3 = 0;
+        if (windows) {
+            for (int m = a.gmargin; m >= 0 && !use_win; --m) {
+                axis_window(rx, sh[0] - m, sh[3] + 1 + m, H, ox, Wx);
+                axis_window(ry, sh[1] - m, sh[4] + 1 + m, H, oy, Wy);
+                axis_window(rz, sh[2] - m, sh[5] + 1 + m, H, oz, Wz);
+                use_win = 3 * (int64_t)Wx * Wy * Wz * (int64_t)sizeof(T) <= win_bytes;
+            }
+            if (use_win) {
+                T* Gw = reinterpret_cast<T*>(lds);
+                const int nw = Wx * Wy * Wz;
+                n3 = (size_t)nw;
+                const size_t H3 = (size_t)H * H * H;
+                const int WyWz = Wy * Wz;
+                for (int e = tid; e < nw; e += PT) {
+                    const int ex = e / WyWz, r = e - ex * WyWz;
+                    const int ey = r / Wz, ez = r - ey * Wz;
+                    const size_t node = ((size_t)((ox + ex) & Hm) * H + ((oy + ey) & Hm)) * H + ((oz + ez) & Hm);
+                    Gw[e] = gp(a.G)[node];
+                    Gw[nw + e] = gp(a.G)[H3 + node];
+                    Gw[2 * nw + e] = gp(a.G)[2 * H3 + node];
+                }
+                __syncthreads();
+            }
         }
-        if (PUSH) {
-            const uint32_t pid = a.id[i];
+        const uint32_t n = *a.step + 1u;
+        const size_t H3 = (size_t)H * H * H;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int j = tid + k * PT;
+            if (j >= cnt) continue;
+            const T x = px[k], y = py[k], z = pz[k];
             T yx, yy, yz, w0, w1, w2;
             if (SCHEME == SIPF_STRANG) {
                 T m0, m1, m2;
-                noise3<T>(pid, n, 0u, a.inst, a.k0, a.k1, m0, m1, m2);
-                noise3<T>(pid, n, 1u, a.inst, a.k0, a.k1, w0, w1, w2);
+                noise3<T>(pid[k], n, 0u, a.inst, a.k0, a.k1, m0, m1, m2);
+                noise3<T>(pid[k], n, 1u, a.inst, a.k0, a.k1, w0, w1, w2);
                 yx = x + a.s * m0;
                 yy = y + a.s * m1;
                 yz = z + a.s * m2;
             } else {
-                noise3<T>(pid, n, 0u, a.inst, a.k0, a.k1, w0, w1, w2);
-                yx = x; yy = y; yz = z;
+                noise3<T>(pid[k], n, 0u, a.inst, a.k0, a.k1, w0, w1, w2);
+                yx = x;
+                yy = y;
+                yz = z;
             }
+            const T sx = yx * hl, sy = yy * hl, sz = yz * hl;
+            const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
+            const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
+            int ix[2] = {(gx - ox) & Hm, (gx + 1 - ox) & Hm};
+            int iy[2] = {(gy - oy) & Hm, (gy + 1 - oy) & Hm};
+            int iz[2] = {(gz - oz) & Hm, (gz + 1 - oz) & Hm};
             T vx, vy, vz;
-            gather_one(a.G, H, hl, yx, yy, yz, vx, vy, vz);
+            const bool inside = use_win && (Wx == H || ix[0] <= Wx - 2) && (Wy == H || iy[0] <= Wy - 2) &&
+                                (Wz == H || iz[0] <= Wz - 2);
+            if (inside) {
+                trilinear3<T>(Gl, n3, Wy, Wz, ix, iy, iz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
+            } else {
+                ix[0] = gx & Hm; ix[1] = (gx + 1) & Hm;
+                iy[0] = gy & Hm; iy[1] = (gy + 1) & Hm;
+                iz[0] = gz & Hm; iz[1] = (gz + 1) & Hm;
+                trilinear3<T>(gp(a.G), H3, H, H, ix, iy, iz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
+            }
             const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
             const T ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
             const T nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
-            a.x[i] = nx;
-            a.y[i] = ny;
-            a.z[i] = nz;
+            gp(a.x)[beg + j] = nx;
+            gp(a.y)[beg + j] = ny;
+            gp(a.z)[beg + j] = nz;
             if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(a.err, 1);
-        }
-    }
-    if (DEP && use_win) {
-        __syncthreads();
-        const int WyWz = Wy * Wz;
-        for (int e = tid; e < Wx * WyWz; e += PT) {
-            const T v = win[e];
-            if (v != (T)0) {
-                const int ex = e / WyWz, r = e - ex * WyWz;
-                const int ey = r / Wz, ez = r - ey * Wz;
-                const size_t node = ((size_t)((ox + ex) & Hm) * H + ((oy + ey) & Hm)) * H + ((oz + ez) & Hm);
-                atomic_add(a.phi + node, v);
-            }
         }
     }
 }
 
+// Persistent over the work items listed by the last sort (count in *nitems).
 template <typename T, bool DEP, bool PUSH, int SCHEME>
 __global__ __launch_bounds__(PT) void k_particles(const PartDesc<T>* __restrict__ pds,
-                                                  const WorkItem* __restrict__ items, int nitems, int wcap) {
+                                                  const WorkItem* __restrict__ items, const int* __restrict__ nitems,
+                                                  int win_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* win = reinterpret_cast<T*>(smem_raw);
     __shared__ int sh[8];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int n = *nitems;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const WorkItem w = items[it];
-        chunk_pass<T, DEP, PUSH, SCHEME>(pds[w.inst], w.beg, w.beg + w.cnt, win, wcap, sh);
+        item_pass<T, DEP, PUSH, SCHEME>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
         __syncthreads();
     }
 }
 
 template <typename T>
-hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int nitems, bool deposit, bool push,
-                            int scheme, int wcap, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    const size_t shm = (size_t)wcap * sizeof(T);
-    const dim3 grid(nitems), block(PT);
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+                            bool push, int scheme, int win_bytes, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    const size_t shm = (size_t)win_bytes;
+    const dim3 g(grid), b(PT);
     if (deposit && push) {
         if (scheme == SIPF_STRANG)
-            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_STRANG>), grid, block, shm, s, pd, items, nitems, wcap);
+            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
         else
-            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_EM>), grid, block, shm, s, pd, items, nitems, wcap);
+            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (deposit) {
-        hipLaunchKernelGGL((k_particles<T, true, false, SIPF_STRANG>), grid, block, shm, s, pd, items, nitems, wcap);
+        hipLaunchKernelGGL((k_particles<T, true, false, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (push) {
         if (scheme == SIPF_STRANG)
-            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_STRANG>), grid, block, 0, s, pd, items, nitems, 0);
+            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
         else
-            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_EM>), grid, block, 0, s, pd, items, nitems, 0);
+            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
     }
     return hipGetLastError();
 }
@@ -280,35 +415,62 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* _
         if (h[i]) atomicAdd(&counts[i], h[i]);
 }
 
-// exclusive scan of the counts into cursor[]; clears counts for the next sort
-__global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* cursor, int nk) {
+// Block-wide exclusive scan of one value per thread (1024 threads).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* part, uint32_t& total) {
+    const int tid = threadIdx.x;
+    part[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t u = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += u;
+        __syncthreads();
+    }
+    total = part[1023];
+    const uint32_t r = part[tid] - v;
+    __syncthreads();
+    return r;
+}
+
+// Exclusive scan of the tile counts into cursor[] (tile starts), and the list
+// of work items: each non-empty tile is split into ceil(count / chunk)
+// contiguous items of near-equal size.  Clears counts for the next sort.
+__global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* cursor, int nk, WorkItem* items,
+                                                    int* nitems, int inst, int chunk) {
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
     const int per = (nk + 1023) / 1024;
-    uint32_t loc[4];
-    uint32_t sum = 0;
+    uint32_t loc[4], nit[4];
+    uint32_t sum = 0, isum = 0;
     for (int j = 0; j < per; ++j) {
         const int i = tid * per + j;
         loc[j] = i < nk ? counts[i] : 0u;
+        nit[j] = (loc[j] + chunk - 1) / chunk;
         sum += loc[j];
+        isum += nit[j];
     }
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - sum;
+    uint32_t total, itotal;
+    uint32_t run = block_exclusive_scan(sum, part, total);
+    uint32_t irun = block_exclusive_scan(isum, part, itotal);
     for (int j = 0; j < per; ++j) {
         const int i = tid * per + j;
         if (i < nk) {
             cursor[i] = run;
             counts[i] = 0u;
+            for (uint32_t k = 0; k < nit[j]; ++k) {
+                const uint32_t b0 = (uint32_t)(((uint64_t)k * loc[j]) / nit[j]);
+                const uint32_t b1 = (uint32_t)(((uint64_t)(k + 1) * loc[j]) / nit[j]);
+                WorkItem w;
+                w.beg = (int64_t)run + b0;
+                w.cnt = (int32_t)(b1 - b0);
+                w.inst = inst;
+                items[irun + k] = w;
+            }
         }
         run += loc[j];
+        irun += nit[j];
     }
+    if (tid == 0) *nitems = (int)itotal;
 }
 
 template <typename T>
@@ -356,7 +518,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>
 
 template <typename T>
 hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T* y2, T* z2, uint32_t* id2,
-                       uint32_t* counts, uint32_t* cursor, int tile, int, hipStream_t s) {
+                       uint32_t* counts, uint32_t* cursor, int tile, int chunk, WorkItem* items, int* nitems,
+                       int inst, hipStream_t s) {
+    if (chunk <= 0 || chunk > CH) chunk = CH;
     const int H = pd_host->H;
     int tshift = 0;
     while ((1 << tshift) < tile) ++tshift;
@@ -365,7 +529,7 @@ hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T
     if (nk > MAX_KEYS || (1 << tshift) != tile) return hipErrorInvalidValue;
     const int nblk = (int)((pd_host->P + SORT_CHUNK - 1) / SORT_CHUNK);
     hipLaunchKernelGGL((k_tile_hist<T>), dim3(nblk), dim3(SORT_THREADS), 0, s, pd_dev, counts, tshift, nk);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, cursor, nk);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, cursor, nk, items, nitems, inst, chunk);
     hipLaunchKernelGGL((k_tile_scatter<T>), dim3(nblk), dim3(SORT_THREADS), 0, s, pd_dev, x2, y2, z2, id2, cursor,
                        tshift, nk);
     return hipGetLastError();
@@ -466,10 +630,10 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 }
 
 #define SIPF_INST(T)                                                                                              \
-    template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, int, bool, bool, int, int,       \
-                                            hipStream_t);                                                         \
+    template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, const int*, int, bool, bool, int, \
+                                            int, hipStream_t);                                                    \
     template hipError_t launch_sort<T>(const PartDesc<T>*, PartDesc<T>*, T*, T*, T*, uint32_t*, uint32_t*,        \
-                                       uint32_t*, int, int, hipStream_t);                                         \
+                                       uint32_t*, int, int, WorkItem*, int*, int, hipStream_t);                        \
     template hipError_t launch_load_positions<T>(const T*, int64_t, T, PartDesc<T>, int*, hipStream_t);          \
     template hipError_t launch_unsort<T>(const PartDesc<T>*, T*, hipStream_t);                                    \
     template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                              \
