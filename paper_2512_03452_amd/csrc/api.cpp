@@ -483,7 +483,8 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
     c->tsize = ts;
     c->stream = (hipStream_t)hip_stream;
     tuning(prm, P, c->tile, c->resort, c->chunk);
-    c->win_bytes = 65536;
+    // LDS per particle-pass workgroup: the larger of the two fast windows
+    c->win_bytes = particle_window_bytes(c->prec == SIPF_FP64);
     rc = c->prec == SIPF_FP32 ? init_typed<float>(c, X0, x0_on_device, alpha0, alpha0_on_device)
                               : init_typed<double>(c, X0, x0_on_device, alpha0, alpha0_on_device);
     if (rc) {

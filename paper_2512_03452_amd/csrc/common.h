@@ -59,16 +59,18 @@ template <typename T> __device__ __forceinline__ T u01(uint32_t r) {
 
 // Box-Muller: (z0, z1) = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
 //             z2       = sqrt(-2 ln u2) cos 2 pi u3.
+// float: the hardware transcendentals (v_log_f32 is log2; v_sin/v_cos take
+// revolutions, so cos 2 pi u is one instruction); u in [2^-24, 1) keeps every
+// argument in range.
 __device__ __forceinline__ void normals3(u32x4 r, float& z0, float& z1, float& z2) {
     const float u0 = u01<float>(r.v0), u1 = u01<float>(r.v1);
     const float u2 = u01<float>(r.v2), u3 = u01<float>(r.v3);
-    const float a = sqrtf(-2.0f * logf(u0));
-    const float b = sqrtf(-2.0f * logf(u2));
-    float s1, c1;
-    sincospif(2.0f * u1, &s1, &c1);
-    z0 = a * c1;
-    z1 = a * s1;
-    z2 = b * cospif(2.0f * u3);
+    constexpr float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+    const float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+    const float b = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+    z0 = a * __builtin_amdgcn_cosf(u1);
+    z1 = a * __builtin_amdgcn_sinf(u1);
+    z2 = b * __builtin_amdgcn_cosf(u3);
 }
 __device__ __forceinline__ void normals3(u32x4 r, double& z0, double& z1, double& z2) {
     const double u0 = u01<double>(r.v0), u1 = u01<double>(r.v1);

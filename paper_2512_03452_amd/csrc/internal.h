@@ -91,5 +91,6 @@ template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s
 int sort_max_keys();
 int particle_threads();
 int particle_chunk();
+int particle_window_bytes(bool fp64);
 
 }  // namespace sipf

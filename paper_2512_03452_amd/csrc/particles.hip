@@ -158,6 +158,149 @@ __device__ __forceinline__ void trilinear3(P G, size_t n3, int Wy, int Wz, const
     vz = az;
 }
 
+// Exact round-to-nearest integer of |v| < 2^22 (float) or 2^51 (double): in
+// v + 1.5 2^23 (resp. 1.5 2^52) the unit in the last place is 1, so the low
+// mantissa bits of the sum hold round(v) offset by the magic constant.
+template <typename T> struct Magic;
+template <> struct Magic<float> {
+    static constexpr float M = 12582912.0f;
+    static constexpr int MAXS = 21;
+    __device__ static int32_t take(float v) { return __float_as_int(v) - 0x4B400000; }
+};
+template <> struct Magic<double> {
+    static constexpr double M = 6755399441055744.0;
+    static constexpr int MAXS = 50;
+    __device__ static long long take(double v) { return __double_as_longlong(v) - 0x4338000000000000LL; }
+};
+
+// Fixed widths of the fast windows (cells per axis): the deposit window holds
+// the item's cells plus the stencil reach, the gradient window the cells plus
+// the trilinear reach and the W^- margin.  With compile-time strides every
+// stencil node is an immediate offset from one LDS address.
+template <typename T> struct Win;
+// Odd widths keep all three axes in the LDS bank index (a power-of-two
+// stride would drop the slowest axis from it).
+#ifndef SIPF_WIN_D
+#define SIPF_WIN_D 19
+#endif
+#ifndef SIPF_WIN_G
+#define SIPF_WIN_G 15
+#endif
+template <> struct Win<float> { static constexpr int D = SIPF_WIN_D, G = SIPF_WIN_G; };
+template <> struct Win<double> { static constexpr int D = 15, G = 11; };
+
+// LDS bytes the particle pass needs per workgroup (the larger fast window)
+int particle_window_bytes(bool fp64) {
+    const int d32 = Win<float>::D * Win<float>::D * Win<float>::D * 4;
+    const int g32 = 3 * Win<float>::G * Win<float>::G * Win<float>::G * 4;
+    const int d64 = Win<double>::D * Win<double>::D * Win<double>::D * 8;
+    const int g64 = 3 * Win<double>::G * Win<double>::G * Win<double>::G * 8;
+    const int b = fp64 ? (d64 > g64 ? d64 : g64) : (d32 > g32 ? d32 : g32);
+    return (b + 255) / 256 * 256;
+}
+
+// q = e / d, r = e % d for 0 <= e < 2^20, 0 < d < 2^10: float reciprocal
+// estimate, corrected by one step.
+__device__ __forceinline__ void divmod_small(int e, int d, float inv_d, int& q, int& r) {
+    q = (int)((float)e * inv_d);
+    r = e - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+}
+// (i, j, k) of flat index e in a box of sizes (., ey, ez), row-major
+__device__ __forceinline__ void unflatten3(int e, int ey, int ez, float inv_ez, float inv_ey, int& i, int& j, int& k) {
+    int r;
+    divmod_small(e, ez, inv_ez, r, k);
+    divmod_small(r, ey, inv_ey, i, j);
+}
+
+// Deposit of one particle into a fixed-stride fixed-point window whose node
+// (i, j, k) is at (i D + j) D + k, origin (ox, oy, oz).  The scale 2^S is
+// folded into the x factors (every Gamma_4 weight has exactly one).
+template <typename T>
+__device__ __forceinline__ void deposit_fast(typename Fixed<T>::I* win, T x, T y, T z, T hl, int Hm, int ox, int oy,
+                                             int oz, T scale) {
+    constexpr int D = Win<T>::D;
+    using U = typename Fixed<T>::U;
+    const T sx = x * hl, sy = y * hl, sz = z * hl;
+    const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
+    const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
+    const Axis4<T> ax = axis4(sx - fx), ay = axis4(sy - fy), az = axis4(sz - fz);
+    const T S = (T)1 + (ax.w0 * ax.w1 + ay.w0 * ay.w1 + az.w0 * az.w1) * (T)0.5;
+    const int base = (((gx - 1 - ox) & Hm) * D + ((gy - 1 - oy) & Hm)) * D + ((gz - 1 - oz) & Hm);
+    U* w = reinterpret_cast<U*>(win) + base;
+    const T X[4] = {ax.wm * scale, ax.w0 * scale, ax.w1 * scale, ax.wp * scale};
+    const T Y[4] = {ay.wm, ay.w0, ay.w1, ay.wp};
+    const T Z[4] = {az.wm, az.w0, az.w1, az.wp};
+#define SIPF_ADD(i, j, k, a, b) atomicAdd(w + ((i) * D + (j)) * D + (k), (U)Magic<T>::take(fma(a, b, Magic<T>::M)))
+#pragma unroll
+    for (int j = 1; j <= 2; ++j)
+#pragma unroll
+        for (int k = 1; k <= 2; ++k) {
+            const T yz = Y[j] * Z[k];
+            const T Syz = S * yz;
+            SIPF_ADD(1, j, k, X[1], Syz);  // inner nodes
+            SIPF_ADD(2, j, k, X[2], Syz);
+            SIPF_ADD(0, j, k, X[0], yz);   // outer nodes on x
+            SIPF_ADD(3, j, k, X[3], yz);
+        }
+#pragma unroll
+    for (int i = 1; i <= 2; ++i)
+#pragma unroll
+        for (int k = 1; k <= 2; ++k) {
+            const T xz = X[i] * Z[k];
+            SIPF_ADD(i, 0, k, Y[0], xz);   // outer nodes on y
+            SIPF_ADD(i, 3, k, Y[3], xz);
+        }
+#pragma unroll
+    for (int i = 1; i <= 2; ++i)
+#pragma unroll
+        for (int j = 1; j <= 2; ++j) {
+            const T xy = X[i] * Y[j];
+            SIPF_ADD(i, j, 0, Z[0], xy);   // outer nodes on z
+            SIPF_ADD(i, j, 3, Z[3], xy);
+        }
+#undef SIPF_ADD
+}
+
+// Trilinear gather from a fixed-stride window (node (i, j, k) at (i G + j) G + k,
+// three planes of G^3); false if the cell is not covered by the loaded part
+// (ex, ey, ez) of the window.
+template <typename T>
+__device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz, T lx, T ly, T lz, int Hm, int ox,
+                                            int oy, int oz, int ex, int ey, int ez, T& vx, T& vy, T& vz) {
+    constexpr int G = Win<T>::G;
+    constexpr int G3 = G * G * G;
+    const int ix = (gx - ox) & Hm, iy = (gy - oy) & Hm, iz = (gz - oz) & Hm;
+    if (ix > ex - 2 || iy > ey - 2 || iz > ez - 2) return false;
+    const T* p = Gw + (ix * G + iy) * G + iz;
+    const T wx[2] = {(T)1 - lx, lx}, wy[2] = {(T)1 - ly, ly}, wz[2] = {(T)1 - lz, lz};
+    T ax = 0, ay = 0, az = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const T wab = wx[a] * wy[b];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T w = wab * wz[c];
+                const int o = (a * G + b) * G + c;
+                ax += w * p[o];
+                ay += w * p[G3 + o];
+                az += w * p[2 * G3 + o];
+            }
+        }
+    vx = ax;
+    vy = ay;
+    vz = az;
+    return true;
+}
+
 template <typename T> __device__ __forceinline__ T wrap_box(T v, T L, T halfL, T invL) {
     return v - L * floor((v + halfL) * invL);
 }
@@ -235,7 +378,40 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         __syncthreads();
     }
 
-    if (DEP) {
+    if (DEP && windows && H > Win<T>::D && sh[3] - sh[0] + 4 <= Win<T>::D && sh[4] - sh[1] + 4 <= Win<T>::D &&
+        sh[5] - sh[2] + 4 <= Win<T>::D) {
+        // fast path: fixed-stride window, nodes -1..+2 around the box
+        constexpr int D = Win<T>::D;
+        I* win = reinterpret_cast<I*>(lds);
+        const int ox = (rx + sh[0] - 1) & Hm, oy = (ry + sh[1] - 1) & Hm, oz = (rz + sh[2] - 1) & Hm;
+        const int ex = sh[3] - sh[0] + 4, ey = sh[4] - sh[1] + 4, ez = sh[5] - sh[2] + 4;
+        const int ne = ex * ey * ez;
+        const float inv_ey = 1.0f / (float)ey, inv_ez = 1.0f / (float)ez;
+        for (int e = tid; e < ne; e += PT) {
+            int i, j, k;
+            unflatten3(e, ey, ez, inv_ez, inv_ey, i, j, k);
+            win[(i * D + j) * D + k] = 0;
+        }
+        const int need = (11 * cnt + 7) / 8;
+        const int S = min(Magic<T>::MAXS, Fixed<T>::BITS - (32 - __clz(need)));
+        const T scale = (T)ldexp(1.0, S);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (tid + k * PT < cnt) deposit_fast<T>(win, px[k], py[k], pz[k], hl, Hm, ox, oy, oz, scale);
+        __syncthreads();
+        const T back = a.wmass * (T)ldexp(1.0, -S);
+        for (int e = tid; e < ne; e += PT) {
+            int i, j, k;
+            unflatten3(e, ey, ez, inv_ez, inv_ey, i, j, k);
+            const I v = win[(i * D + j) * D + k];
+            if (v != 0) {
+                const int node = ((((ox + i) & Hm) * H) + ((oy + j) & Hm)) * H + ((oz + k) & Hm);
+                gatomic_add(a.phi + node, (T)v * back);
+            }
+        }
+        __syncthreads();  // the window memory is reused below
+    } else if (DEP) {
         int ox = 0, oy = 0, oz = 0, Wx = H, Wy = H, Wz = H;
         bool use_win = false;
         if (windows) {
@@ -282,10 +458,41 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
     if (PUSH) {
         // gradient window: cells of the box (+ margin for the W^- displacement) and +1 for the trilinear reach
         int ox = 0, oy = 0, oz = 0, Wx = H, Wy = H, Wz = H;
-        bool use_win = false;
+        bool use_win = false, fast = false;
         const T* Gl = reinterpret_cast<const T*>(lds);
         size_t n3 = 0;
-        if (windows) {
+        if (windows && H > Win<T>::G) {
+            constexpr int G = Win<T>::G;
+            constexpr int G3 = G * G * G;
+            for (int m = a.gmargin; m >= 0 && !fast; --m)
+                fast = sh[3] - sh[0] + 2 + 2 * m <= G && sh[4] - sh[1] + 2 + 2 * m <= G &&
+                       sh[5] - sh[2] + 2 + 2 * m <= G;
+            if (fast) {
+                int m = a.gmargin;
+                while (sh[3] - sh[0] + 2 + 2 * m > G || sh[4] - sh[1] + 2 + 2 * m > G || sh[5] - sh[2] + 2 + 2 * m > G) --m;
+                ox = (rx + sh[0] - m) & Hm;
+                oy = (ry + sh[1] - m) & Hm;
+                oz = (rz + sh[2] - m) & Hm;
+                Wx = sh[3] - sh[0] + 2 + 2 * m;
+                Wy = sh[4] - sh[1] + 2 + 2 * m;
+                Wz = sh[5] - sh[2] + 2 + 2 * m;
+                T* Gw = reinterpret_cast<T*>(lds);
+                const int H3 = H * H * H;
+                const int ne = Wx * Wy * Wz;
+                const float inv_ey = 1.0f / (float)Wy, inv_ez = 1.0f / (float)Wz;
+                for (int e = tid; e < ne; e += PT) {
+                    int i, j, k;
+                    unflatten3(e, Wy, Wz, inv_ez, inv_ey, i, j, k);
+                    const int node = ((((ox + i) & Hm) * H) + ((oy + j) & Hm)) * H + ((oz + k) & Hm);
+                    const int o = (i * G + j) * G + k;
+                    Gw[o] = gp(a.G)[node];
+                    Gw[G3 + o] = gp(a.G)[H3 + node];
+                    Gw[2 * G3 + o] = gp(a.G)[2 * H3 + node];
+                }
+                __syncthreads();
+            }
+        }
+        if (windows && !fast) {
             for (int m = a.gmargin; m >= 0 && !use_win; --m) {
                 axis_window(rx, sh[0] - m, sh[3] + 1 + m, H, ox, Wx);
                 axis_window(ry, sh[1] - m, sh[4] + 1 + m, H, oy, Wy);
@@ -337,9 +544,12 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             int iy[2] = {(gy - oy) & Hm, (gy + 1 - oy) & Hm};
             int iz[2] = {(gz - oz) & Hm, (gz + 1 - oz) & Hm};
             T vx, vy, vz;
-            const bool inside = use_win && (Wx == H || ix[0] <= Wx - 2) && (Wy == H || iy[0] <= Wy - 2) &&
+            const bool inside = !fast && use_win && (Wx == H || ix[0] <= Wx - 2) && (Wy == H || iy[0] <= Wy - 2) &&
                                 (Wz == H || iz[0] <= Wz - 2);
-            if (inside) {
+            if (fast && gather_fast<T>(Gl, gx, gy, gz, sx - fx, sy - fy, sz - fz, Hm, ox, oy, oz, Wx, Wy, Wz, vx, vy,
+                                       vz)) {
+                // gathered from the fixed-stride window
+            } else if (inside) {
                 trilinear3<T>(Gl, n3, Wy, Wz, ix, iy, iz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
             } else {
                 ix[0] = gx & Hm; ix[1] = (gx + 1) & Hm;
@@ -440,7 +650,7 @@ __global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* 
     __shared__ uint32_t part[1024];
     const int tid = threadIdx.x;
     const int per = (nk + 1023) / 1024;
-    uint32_t loc[4], nit[4];
+    uint32_t loc[MAX_KEYS / 1024], nit[MAX_KEYS / 1024];
     uint32_t sum = 0, isum = 0;
     for (int j = 0; j < per; ++j) {
         const int i = tid * per + j;
