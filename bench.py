@@ -61,6 +61,34 @@ def cpu_baseline(cfg, sample_P, steps):
                        f"{wall:.1f} s wall")
 
 
+def adjoint_ratio(pkg, workloads, np, torch):
+    """fwd+adjoint time over forward time on the adjoint workload (same GPU)."""
+    cfg = workloads.CONFIGS["fp32_adjoint_h64"]
+    P, N, K = cfg["P"], cfg["steps"], 10
+    X0 = cfg["init"](P).astype(np.float32)
+    sim = pkg.Sim(X0, **cfg["params"])
+    sim.run(5)
+    sim.sync()
+    sim.close()
+    sim = pkg.Sim(X0, **cfg["params"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(N)
+    sim.sync()
+    t_fwd = time.perf_counter() - t0
+    sim.close()
+    sim = pkg.Sim(X0, **cfg["params"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, dchi, dmu, dX0 = sim.adjoint(N, K)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    sim.close()
+    return {"workload": "fp32_adjoint_h64", "P": P, "H": cfg["params"]["H"], "steps": N, "ckpt_every": K,
+            "fwd_ms": 1e3 * t_fwd, "fwd_adj_ms": 1e3 * t_adj, "ratio": t_adj / t_fwd,
+            "grad_finite": bool(np.isfinite(dchi) and np.isfinite(dmu) and torch.isfinite(dX0).all().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +99,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -146,6 +175,9 @@ def main():
         "phases": phases,
     }
     sim.close()
+    if not args.no_adjoint:
+        print("# fwd+adjoint vs fwd on the adjoint workload", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_ratio(pkg, workloads, np, torch)
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, P), args.cpu_steps)

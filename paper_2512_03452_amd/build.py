@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsipf.so")
-SOURCES = ["fft.hip", "particles.hip", "api.cpp"]
+SOURCES = ["fft.hip", "particles.hip", "adjoint.hip", "api.cpp"]
 ARCH = os.environ.get("SIPF_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [
@@ -48,7 +48,7 @@ def _compile(src):
 def build(verbose=False):
     """Compile every source and link libsipf.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -239,15 +239,15 @@ template <typename T> int enqueue_step(sipf_ctx* c) {
     const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
     {
         Timed t(c, SIPF_PHASE_FWD);
-        HIPCHK(launch_fwd_planes<T>(c->H, fd, 1, c->stream));
+        HIPCHK(launch_fwd_planes<T>(c->H, fd, 1, 1, true, c->stream));
     }
     {
         Timed t(c, SIPF_PHASE_XPENCIL);
-        HIPCHK(launch_xpencils<T>(c->H, fd, 1, true, c->stream));
+        HIPCHK(launch_xpencils<T>(c->H, fd, 1, XP_STEP, c->stream));
     }
     {
         Timed t(c, SIPF_PHASE_INV);
-        HIPCHK(launch_inv_planes<T>(c->H, fd, 1, c->stream));
+        HIPCHK(launch_inv_planes<T>(c->H, fd, 1, 3, c->stream));
     }
     c->since_sort++;
     c->n_host++;
@@ -313,8 +313,8 @@ template <typename T> int init_fields(sipf_ctx* c, const void* alpha0, int alpha
     permute_spectrum(nat.data(), per.data(), H, sizeof(T), true);
     HIPCHK(hipMemcpy(c->alpha, per.data(), per.size() * sizeof(T), hipMemcpyHostToDevice));
     const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
-    HIPCHK(launch_xpencils<T>(H, fd, 1, false, c->stream));
-    HIPCHK(launch_inv_planes<T>(H, fd, 1, c->stream));
+    HIPCHK(launch_xpencils<T>(H, fd, 1, XP_GRAD, c->stream));
+    HIPCHK(launch_inv_planes<T>(H, fd, 1, 3, c->stream));
     return SIPF_OK;
 }
 
@@ -428,6 +428,253 @@ template <typename T> int get_positions_typed(sipf_ctx* c, void* out, int on_dev
         if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("get_positions: ") + hipGetErrorString(e));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
+    return check_err(c);
+}
+
+// Device buffer freed when it goes out of scope (adjoint temporaries).
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n) { return hipMalloc(&p, n ? n : 16); }
+};
+
+template <typename T> PartDesc<T> pdesc_on(const sipf_ctx* c, T* x, T* y, T* z, uint32_t* id) {
+    PartDesc<T> d = make_pdesc<T>(c, 0);
+    d.x = x;
+    d.y = y;
+    d.z = z;
+    d.id = id;
+    return d;
+}
+
+// Gradient grids of alpha (the context's alpha buffer) into the context's G.
+template <typename T> int recompute_grad(sipf_ctx* c) {
+    const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
+    HIPCHK(launch_xpencils<T>(c->H, fd, 1, XP_GRAD, c->stream));
+    HIPCHK(launch_inv_planes<T>(c->H, fd, 1, 3, c->stream));
+    return SIPF_OK;
+}
+
+template <typename T>
+int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* loss_out, double* dchi_out,
+                  double* dmu_out, T* dX0) {
+    using V = cplx_t<T>;
+    int64_t n0 = 0;
+    {
+        uint32_t s = 0;
+        HIPCHK(hipMemcpyAsync(&s, c->step, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        n0 = s;
+    }
+    if (n0 != 0 || c->n_host != 0) return fail(SIPF_ESTATE, "sipf_adjoint needs a context at step 0");
+    if (K > N) K = (int)N;
+    const int H = c->H;
+    const int64_t P = c->P;
+    const size_t H3 = (size_t)H * H * H;
+    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+    const int64_t nseg = (N + K - 1) / K;
+    const size_t pos_bytes = (size_t)P * (3 * sizeof(T) + sizeof(uint32_t));
+    auto need = [&](DevBuf& b, size_t n) -> int {
+        if (b.alloc(n) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SIPF_ENOMEM, "adjoint: device allocation failed");
+        }
+        return SIPF_OK;
+    };
+    DevBuf tape, ckpt, seg, xbar, Gbar, phibar, abar, aN, scr, gs1, fdS, fdA, acc, pds, items, nit;
+    int rc;
+    if ((rc = need(tape, (size_t)N * nspec * sizeof(V)))) return rc;
+    if ((rc = need(ckpt, (size_t)nseg * pos_bytes))) return rc;
+    if ((rc = need(seg, (size_t)K * pos_bytes))) return rc;
+    if ((rc = need(xbar, (size_t)P * 3 * sizeof(T)))) return rc;
+    if ((rc = need(Gbar, 3 * H3 * sizeof(T)))) return rc;
+    if ((rc = need(phibar, H3 * sizeof(T)))) return rc;
+    if ((rc = need(abar, nspec * sizeof(V)))) return rc;
+    if ((rc = need(aN, nspec * sizeof(V)))) return rc;
+    if ((rc = need(scr, 3 * nspec * sizeof(V)))) return rc;
+    if ((rc = need(gs1, nspec * sizeof(V)))) return rc;
+    if ((rc = need(fdS, sizeof(FieldDesc<T>)))) return rc;
+    if ((rc = need(fdA, sizeof(FieldDesc<T>)))) return rc;
+    if ((rc = need(acc, 4 * sizeof(double)))) return rc;
+    if ((rc = need(pds, (size_t)K * sizeof(PartDesc<T>)))) return rc;
+    const int nu = (int)((P + particle_chunk() - 1) / particle_chunk());
+    if ((rc = need(items, (size_t)nu * sizeof(WorkItem)))) return rc;
+    if ((rc = need(nit, 16))) return rc;
+    // position slot j of a buffer: x, y, z, id
+    auto slot = [&](void* base, int64_t j, T*& x, T*& y, T*& z, uint32_t*& id) {
+        char* b = (char*)base + (size_t)j * pos_bytes;
+        x = (T*)b;
+        y = x + P;
+        z = y + P;
+        id = (uint32_t*)(z + P);
+    };
+    {
+        // adjoint field descriptors: source (abar -> phibar) and accumulation (Gbar -> abar)
+        FieldDesc<T> f = make_fdesc<T>(c);
+        f.alpha = (V*)abar.p;
+        f.gspec = (V*)gs1.p;
+        f.G = (T*)phibar.p;
+        f.step = nullptr;
+        HIPCHK(hipMemcpy(fdS.p, &f, sizeof(f), hipMemcpyHostToDevice));
+        f = make_fdesc<T>(c);
+        f.phi = (T*)Gbar.p;
+        f.B1 = (V*)scr.p;
+        f.alpha = (V*)abar.p;
+        f.step = nullptr;
+        HIPCHK(hipMemcpy(fdA.p, &f, sizeof(f), hipMemcpyHostToDevice));
+        std::vector<PartDesc<T>> pd(K);
+        for (int j = 0; j < K; ++j) {
+            T *x, *y, *z;
+            uint32_t* id;
+            slot(seg.p, j, x, y, z, id);
+            pd[j] = pdesc_on<T>(c, x, y, z, id);
+        }
+        HIPCHK(hipMemcpy(pds.p, pd.data(), pd.size() * sizeof(PartDesc<T>), hipMemcpyHostToDevice));
+        std::vector<WorkItem> it(nu);
+        for (int i = 0; i < nu; ++i) {
+            it[i].beg = (int64_t)i * particle_chunk();
+            it[i].cnt = (int32_t)std::min<int64_t>(particle_chunk(), P - it[i].beg);
+            it[i].inst = 0;
+        }
+        HIPCHK(hipMemcpy(items.p, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(nit.p, &nu, sizeof(int), hipMemcpyHostToDevice));
+    }
+    const FieldDesc<T>* fdc = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
+    auto copy_positions = [&](T* x, T* y, T* z, uint32_t* id, const T* sx, const T* sy, const T* sz,
+                              const uint32_t* sid) -> int {
+        HIPCHK(hipMemcpyAsync(x, sx, P * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(y, sy, P * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(z, sz, P * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(id, sid, P * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+        return SIPF_OK;
+    };
+
+    // ---- forward with tape: alpha^(n-1) every step, X^(n-1) every K steps
+    for (int64_t n = 1; n <= N; ++n) {
+        if ((n - 1) % K == 0) {
+            T *x, *y, *z;
+            uint32_t* id;
+            slot(ckpt.p, (n - 1) / K, x, y, z, id);
+            if ((rc = copy_positions(x, y, z, id, (const T*)c->xs[c->cur], (const T*)c->ys[c->cur],
+                                     (const T*)c->zs[c->cur], c->ids[c->cur])))
+                return rc;
+        }
+        HIPCHK(hipMemcpyAsync((V*)tape.p + (size_t)(n - 1) * nspec, c->alpha, nspec * sizeof(V),
+                              hipMemcpyDeviceToDevice, c->stream));
+        if ((rc = enqueue_step<T>(c))) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(aN.p, c->alpha, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
+
+    // ---- loss and its cotangent phibar^(N)
+    HIPCHK(launch_zero_f64((double*)acc.p, 4, c->stream));
+    HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false, c->prm.scheme,
+                               c->win_bytes, c->stream));
+    if (phibar_in) {
+        HIPCHK(launch_dot<T>(phibar_in, (const T*)c->phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
+        HIPCHK(hipMemcpyAsync(phibar.p, phibar_in, H3 * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        HIPCHK(launch_dot<T>((const T*)c->phi, (const T*)c->phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
+        HIPCHK(launch_fill<T>((T*)phibar.p, (int64_t)H3, (T)0, c->stream));
+        HIPCHK(launch_axpby<T>((T*)phibar.p, (const T*)c->phi, (T)2, (T)0, (int64_t)H3, c->stream));
+    }
+    HIPCHK(launch_fill<T>((T*)c->phi, (int64_t)H3, (T)0, c->stream));
+
+    AdjDesc<T> ad{};
+    ad.P = P;
+    ad.H = H;
+    ad.scheme = c->prm.scheme;
+    const PartDesc<T> ref = make_pdesc<T>(c, c->cur);
+    ad.hl = ref.hl;
+    ad.wmass = ref.wmass;
+    ad.chitau = ref.chitau;
+    ad.tau = (T)c->prm.dt;
+    ad.s = ref.s;
+    ad.k0 = ref.k0;
+    ad.k1 = ref.k1;
+    ad.inst = ref.inst;
+    ad.xbar = (T*)xbar.p;
+    ad.Gbar = (T*)Gbar.p;
+    ad.acc = (double*)acc.p;
+    ad.G = (const T*)c->G;
+    // seed: Xbar^(N) from phibar^(N) at X^(N)
+    ad.x = (const T*)c->xs[c->cur];
+    ad.y = (const T*)c->ys[c->cur];
+    ad.z = (const T*)c->zs[c->cur];
+    ad.id = c->ids[c->cur];
+    ad.phibar = (const T*)phibar.p;
+    HIPCHK(launch_adj_seed<T>(ad, c->stream));
+    HIPCHK(launch_fill<T>((T*)abar.p, (int64_t)(2 * nspec), (T)0, c->stream));
+
+    // ---- reverse sweep, one checkpoint segment at a time
+    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int64_t base = sgi * K;
+        const int len = (int)std::min<int64_t>(K, N - base);
+        {
+            T *x, *y, *z, *cx, *cy, *cz;
+            uint32_t *id, *cid;
+            slot(seg.p, 0, x, y, z, id);
+            slot(ckpt.p, sgi, cx, cy, cz, cid);
+            if ((rc = copy_positions(x, y, z, id, cx, cy, cz, cid))) return rc;
+        }
+        for (int m = 1; m < len; ++m) {
+            // X^(base+m) = push of X^(base+m-1) with the gradient of alpha^(base+m-1), step base+m
+            HIPCHK(hipMemcpyAsync(c->alpha, (V*)tape.p + (size_t)(base + m - 1) * nspec, nspec * sizeof(V),
+                                  hipMemcpyDeviceToDevice, c->stream));
+            if ((rc = recompute_grad<T>(c))) return rc;
+            T *x, *y, *z, *px, *py, *pz;
+            uint32_t *id, *pid;
+            slot(seg.p, m, x, y, z, id);
+            slot(seg.p, m - 1, px, py, pz, pid);
+            if ((rc = copy_positions(x, y, z, id, px, py, pz, pid))) return rc;
+            HIPCHK(launch_set_u32(c->step, (uint32_t)(base + m - 1), c->stream));
+            HIPCHK(launch_particles<T>(reinterpret_cast<const PartDesc<T>*>(pds.p) + m, (const WorkItem*)items.p,
+                                       (const int*)nit.p, std::min(nu, 1024), false, true, c->prm.scheme,
+                                       c->win_bytes, c->stream));
+        }
+        for (int64_t n = base + len; n > base; --n) {
+            // (a) phibar^(n-1) = L^-3 C2R(B abar^(n)); zero at n = N (abar^(N) = 0)
+            const bool src = n < N;
+            if (src) {
+                HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdS.p, 1, XP_ADJ_SRC, c->stream));
+                HIPCHK(launch_inv_planes<T>(H, (const FieldDesc<T>*)fdS.p, 1, 1, c->stream));
+            }
+            // (b) G^(n-1)
+            HIPCHK(hipMemcpyAsync(c->alpha, (V*)tape.p + (size_t)(n - 1) * nspec, nspec * sizeof(V),
+                                  hipMemcpyDeviceToDevice, c->stream));
+            if ((rc = recompute_grad<T>(c))) return rc;
+            // (c) particles of X^(n-1)
+            HIPCHK(launch_fill<T>((T*)Gbar.p, (int64_t)(3 * H3), (T)0, c->stream));
+            T *x, *y, *z;
+            uint32_t* id;
+            slot(seg.p, n - 1 - base, x, y, z, id);
+            ad.x = x;
+            ad.y = y;
+            ad.z = z;
+            ad.id = id;
+            ad.phibar = src ? (const T*)phibar.p : nullptr;
+            ad.n = (uint32_t)n;
+            HIPCHK(launch_adj_step<T>(ad, c->stream));
+            // (d) abar^(n-1) = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d)
+            HIPCHK(launch_fwd_planes<T>(H, (const FieldDesc<T>*)fdA.p, 1, 3, false, c->stream));
+            HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdA.p, 1, XP_ADJ_ACC, c->stream));
+        }
+    }
+    // ---- results and restoration of the context state (X^(N), alpha^(N), G^(N), n = N)
+    double hacc[4];
+    HIPCHK(hipMemcpyAsync(hacc, acc.p, sizeof(hacc), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(dX0, xbar.p, (size_t)P * 3 * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->alpha, aN.p, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = recompute_grad<T>(c))) return rc;
+    HIPCHK(launch_set_u32(c->step, (uint32_t)N, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    (void)fdc;
+    const double tau = c->prm.dt, mu = c->prm.mu;
+    const double dsdmu = c->prm.scheme == SIPF_STRANG ? tau / (2.0 * std::sqrt(mu * tau)) : tau / std::sqrt(2.0 * mu * tau);
+    *loss_out = hacc[2];
+    *dchi_out = hacc[0];
+    *dmu_out = mu > 0 ? hacc[1] * dsdmu : 0.0;
     return check_err(c);
 }
 
@@ -561,9 +808,14 @@ int sipf_profile_read(sipf_ctx* c, double* ms, int64_t* launches) {
     return SIPF_OK;
 }
 
-int sipf_adjoint(sipf_ctx* c, int64_t, int32_t, const void*, double*, double*, double*, void*) {
-    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
-    return fail(SIPF_ESTATE, "adjoint not available in this build");
+int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* phi_bar, double* loss, double* dchi,
+                 double* dmu, void* dX0) {
+    if (!c || !loss || !dchi || !dmu || !dX0) return fail(SIPF_EINVAL, "NULL argument");
+    if (nsteps < 1 || nsteps > (int64_t)1 << 30) return fail(SIPF_EINVAL, "nsteps must be >= 1");
+    if (ckpt_every < 1) return fail(SIPF_EINVAL, "ckpt_every must be >= 1");
+    return c->prec == SIPF_FP32
+               ? adjoint_typed<float>(c, nsteps, ckpt_every, (const float*)phi_bar, loss, dchi, dmu, (float*)dX0)
+               : adjoint_typed<double>(c, nsteps, ckpt_every, (const double*)phi_bar, loss, dchi, dmu, (double*)dX0);
 }
 
 int sipf_save(sipf_ctx* c, const char*) {

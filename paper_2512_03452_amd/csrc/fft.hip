@@ -193,7 +193,7 @@ constexpr int KB = 16;  // kz columns per x-pencil workgroup
 // Pass 1: x-plane -> half spectrum along z, transformed along y.
 // ---------------------------------------------------------------------------
 template <typename T, int H>
-__global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>* __restrict__ fds) {
+__global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>* __restrict__ fds, int consume) {
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
     constexpr int RP = H + 1;          // row pitch (complex) of the packed-row buffer
@@ -202,10 +202,11 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>
     __shared__ V half[H * OP];
     __shared__ V tw[H];
     const FieldDesc<T>& fd = fds[blockIdx.y];
-    const int ix = blockIdx.x;
+    const int ix = blockIdx.x % H;
+    const int comp = blockIdx.x / H;  // component of a multi-grid input (phi + comp H^3)
     const int tid = threadIdx.x, nt = blockDim.x;
     make_twiddles<T, H>(tw);
-    T* plane = fd.phi + (size_t)ix * H * H;
+    T* plane = fd.phi + ((size_t)comp * H + ix) * H * H;
     for (int u = tid; u < (H / 2) * H; u += nt) {
         const int m = u / H, iz = u % H;
         const T a = plane[(2 * m) * H + iz];
@@ -213,9 +214,11 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>
         rows[m * RP + iz] = cmake<V, T>(a, b);
     }
     __syncthreads();
-    // the deposit grid is consumed: clear it for the next step's particle pass
-    for (int u = tid; u < H * H; u += nt) plane[u] = (T)0;
-    if (ix == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
+    if (consume) {
+        // the deposit grid is consumed: clear it for the next step's particle pass
+        for (int u = tid; u < H * H; u += nt) plane[u] = (T)0;
+        if (ix == 0 && comp == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
+    }
     lds_fft<T, H, -1>(rows, H / 2, RP, 1, tw);
     __syncthreads();
     // split Z = FFT(a + i b): A_k = (Z_k + conj Z_{-k}) / 2, B_k = (Z_k - conj Z_{-k}) / (2i)
@@ -230,15 +233,29 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>
     __syncthreads();
     lds_fft<T, H, -1>(half, HH, 1, OP, tw);
     __syncthreads();
-    V* out = fd.B1 + (size_t)ix * H * HH;
+    V* out = fd.B1 + ((size_t)comp * H + ix) * H * HH;
     for (int u = tid; u < H * HH; u += nt) out[u] = half[(u / HH) * OP + (u % HH)];
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2: x-pencils, mode update, filtered gradient spectra, inverse along x.
 // ---------------------------------------------------------------------------
-template <typename T, int H, bool UPDATE>
+template <typename T, int H, int MODE>
+__device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp, int kz0, int ncol, T qy, int ky,
+                                                cplx_t<T>* buf, cplx_t<T>* abuf, const cplx_t<T>* tw);
+
+// MODE_STEP: forward x of B1, mode update of alpha, three gradient spectra
+//            i xi_d Phi alpha, inverse x into gspec.
+// MODE_GRAD: the three gradient spectra of alpha (no update).
+// MODE_ADJ_SRC: adjoint of the source term: L^-3 B abar (abar in alpha), inverse x
+//            into gspec component 0.
+// MODE_ADJ_ACC: adjoint of the gradient and of the propagation: forward x of the
+//            three transformed grids in B1, abar <- A abar + sum_d (-i xi_d Phi) B1_d.
+enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3 };
+
+template <typename T, int H, int MODE>
 __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>* __restrict__ fds) {
+    constexpr bool UPDATE = MODE == MODE_STEP;
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
     constexpr int NKB = (HH + KB - 1) / KB;
@@ -254,6 +271,10 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
     make_twiddles<T, H>(tw);
     const int ky = perm_freq<H>(kyp);
     const T qy = (T)(ky < H / 2 ? ky : ky - H);
+    if constexpr (MODE == MODE_ADJ_SRC || MODE == MODE_ADJ_ACC) {
+        adjoint_pencils<T, H, MODE>(fd, kyp, kz0, ncol, qy, ky, buf, abuf, tw);
+        return;
+    }
     if (UPDATE) {
         for (int u = tid; u < H * KB; u += nt) {
             const int ix = u / KB, j = u % KB;
@@ -314,11 +335,95 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
     }
 }
 
+template <typename T, int H, int MODE>
+__device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp, int kz0, int ncol, T qy, int ky,
+                                                cplx_t<T>* buf, cplx_t<T>* abuf, const cplx_t<T>* tw) {
+    using V = cplx_t<T>;
+    constexpr int HH = H / 2 + 1;
+    constexpr int BP = KB + 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    auto factors = [&](int p, int j, T& A, T& B, T& phi, T (&xi)[3]) {
+        const int kx = perm_freq<H>(p);
+        const int kz = kz0 + j;
+        const T qx = (T)(kx < H / 2 ? kx : kx - H);
+        const T qz = (T)kz;
+        const T q2 = qx * qx + qy * qy + qz * qz;
+        const T xi2 = q2 * fd.two_pi_over_L * fd.two_pi_over_L;
+        A = (T)1 / ((T)1 + fd.dt_over_eps * (xi2 + fd.k2));
+        B = (T)1 / (xi2 + fd.k2 + fd.eps_over_dt);
+        phi = fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1;
+        const int kd[3] = {kx, ky, kz};
+        for (int d = 0; d < 3; ++d) {
+            const T q = (T)(kd[d] == H / 2 ? 0 : (kd[d] < H / 2 ? kd[d] : kd[d] - H));
+            xi[d] = q * fd.two_pi_over_L;
+        }
+    };
+    if constexpr (MODE == MODE_ADJ_SRC) {
+        for (int u = tid; u < H * KB; u += nt) {
+            const int p = u / KB, j = u % KB;
+            V v = cmake<V, T>(0, 0);
+            if (j < ncol) {
+                T A, B, phi, xi[3];
+                factors(p, j, A, B, phi, xi);
+                const V a = fd.alpha[((size_t)p * H + kyp) * HH + kz0 + j];
+                const T s = B * fd.inv_L3;
+                v = cmake<V, T>(a.x * s, a.y * s);
+            }
+            buf[p * BP + j] = v;
+        }
+        __syncthreads();
+        lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
+        __syncthreads();
+        for (int u = tid; u < H * KB; u += nt) {
+            const int ix = u / KB, j = u % KB;
+            if (j < ncol) fd.gspec[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
+        }
+    } else {
+        // accumulate sum_d (-i xi_d Phi) F(Gbar_d) in abuf
+        for (int u = tid; u < H * KB; u += nt) abuf[(u / KB) * BP + (u % KB)] = cmake<V, T>(0, 0);
+        for (int d = 0; d < 3; ++d) {
+            __syncthreads();
+            const V* in = fd.B1 + (size_t)d * H * H * HH;
+            for (int u = tid; u < H * KB; u += nt) {
+                const int ix = u / KB, j = u % KB;
+                buf[ix * BP + j] = j < ncol ? in[((size_t)ix * H + kyp) * HH + kz0 + j] : cmake<V, T>(0, 0);
+            }
+            __syncthreads();
+            lds_fft<T, H, -1>(buf, KB, 1, BP, tw);
+            __syncthreads();
+            for (int u = tid; u < H * KB; u += nt) {
+                const int p = u / KB, j = u % KB;
+                if (j >= ncol) continue;
+                T A, B, phi, xi[3];
+                factors(p, j, A, B, phi, xi);
+                const V g = buf[p * BP + j];
+                const T c = xi[d] * phi;
+                V acc = abuf[p * BP + j];
+                // (-i c) g = (c g.y, -c g.x)
+                acc.x += c * g.y;
+                acc.y -= c * g.x;
+                abuf[p * BP + j] = acc;
+            }
+        }
+        __syncthreads();
+        for (int u = tid; u < H * KB; u += nt) {
+            const int p = u / KB, j = u % KB;
+            if (j >= ncol) continue;
+            T A, B, phi, xi[3];
+            factors(p, j, A, B, phi, xi);
+            const size_t ai = ((size_t)p * H + kyp) * HH + kz0 + j;
+            const V a = fd.alpha[ai];
+            const V acc = abuf[p * BP + j];
+            fd.alpha[ai] = cmake<V, T>(A * a.x + acc.x, A * a.y + acc.y);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pass 3: inverse along y, complex-to-real inverse along z, per component.
 // ---------------------------------------------------------------------------
 template <typename T, int H>
-__global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>* __restrict__ fds) {
+__global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>* __restrict__ fds, int ncomp) {
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
     constexpr int RP = H + 1;
@@ -327,11 +432,11 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
     __shared__ V half[H * OP];
     __shared__ V tw[H];
     const FieldDesc<T>& fd = fds[blockIdx.y];
-    // blocks 8c + r (c = ix / 8 * 3 + d) keep the three components of a plane on one XCD
+    // blocks 8c + r (c = (ix / 8) ncomp + d) keep the components of a plane on one XCD
     const int b = blockIdx.x;
     const int grp = b / 8, r = b % 8;
-    const int d = grp % 3;
-    const int ix = (grp / 3) * 8 + r;
+    const int d = grp % ncomp;
+    const int ix = (grp / ncomp) * 8 + r;
     const int tid = threadIdx.x, nt = blockDim.x;
     make_twiddles<T, H>(tw);
     const V* in = fd.gspec + ((size_t)d * H + ix) * H * HH;
@@ -368,23 +473,27 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T, int H>
-static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd_planes<T, H>), dim3(H, count), dim3(PLANE_THREADS), 0, s, fd);
+static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(PLANE_THREADS), 0, s, fd, consume ? 1 : 0);
     return hipGetLastError();
 }
 template <typename T, int H>
-static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, bool update, hipStream_t s) {
+static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStream_t s) {
     constexpr int NKB = (H / 2 + 1 + KB - 1) / KB;
-    if (update)
-        hipLaunchKernelGGL((k_xpencils<T, H, true>), dim3(H * NKB, count), dim3(PENCIL_THREADS), 0, s, fd);
-    else
-        hipLaunchKernelGGL((k_xpencils<T, H, false>), dim3(H * NKB, count), dim3(PENCIL_THREADS), 0, s, fd);
+    const dim3 g(H * NKB, count), b(PENCIL_THREADS);
+    switch (mode) {
+        case MODE_STEP: hipLaunchKernelGGL((k_xpencils<T, H, MODE_STEP>), g, b, 0, s, fd); break;
+        case MODE_GRAD: hipLaunchKernelGGL((k_xpencils<T, H, MODE_GRAD>), g, b, 0, s, fd); break;
+        case MODE_ADJ_SRC: hipLaunchKernelGGL((k_xpencils<T, H, MODE_ADJ_SRC>), g, b, 0, s, fd); break;
+        case MODE_ADJ_ACC: hipLaunchKernelGGL((k_xpencils<T, H, MODE_ADJ_ACC>), g, b, 0, s, fd); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 template <typename T, int H>
-static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, hipStream_t s) {
+static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s) {
     static_assert(H % 8 == 0, "plane blocks are grouped by 8");
-    hipLaunchKernelGGL((k_inv_planes<T, H>), dim3(3 * H, count), dim3(PLANE_THREADS), 0, s, fd);
+    hipLaunchKernelGGL((k_inv_planes<T, H>), dim3(ncomp * H, count), dim3(PLANE_THREADS), 0, s, fd, ncomp);
     return hipGetLastError();
 }
 
@@ -398,21 +507,22 @@ static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, hipStream_t s)
         default: return hipErrorInvalidValue;             \
     }
 
-template <typename T> hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s) {
-    SIPF_H_SWITCH(H, fwd_planes_h, fd, count, s)
+template <typename T>
+hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s) {
+    SIPF_H_SWITCH(H, fwd_planes_h, fd, count, ncomp, consume, s)
 }
-template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, bool update, hipStream_t s) {
-    SIPF_H_SWITCH(H, xpencils_h, fd, count, update, s)
+template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, int mode, hipStream_t s) {
+    SIPF_H_SWITCH(H, xpencils_h, fd, count, mode, s)
 }
-template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s) {
-    SIPF_H_SWITCH(H, inv_planes_h, fd, count, s)
+template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s) {
+    SIPF_H_SWITCH(H, inv_planes_h, fd, count, ncomp, s)
 }
 
-template hipError_t launch_fwd_planes<float>(int, const FieldDesc<float>*, int, hipStream_t);
-template hipError_t launch_fwd_planes<double>(int, const FieldDesc<double>*, int, hipStream_t);
-template hipError_t launch_xpencils<float>(int, const FieldDesc<float>*, int, bool, hipStream_t);
-template hipError_t launch_xpencils<double>(int, const FieldDesc<double>*, int, bool, hipStream_t);
-template hipError_t launch_inv_planes<float>(int, const FieldDesc<float>*, int, hipStream_t);
-template hipError_t launch_inv_planes<double>(int, const FieldDesc<double>*, int, hipStream_t);
+template hipError_t launch_fwd_planes<float>(int, const FieldDesc<float>*, int, int, bool, hipStream_t);
+template hipError_t launch_fwd_planes<double>(int, const FieldDesc<double>*, int, int, bool, hipStream_t);
+template hipError_t launch_xpencils<float>(int, const FieldDesc<float>*, int, int, hipStream_t);
+template hipError_t launch_xpencils<double>(int, const FieldDesc<double>*, int, int, hipStream_t);
+template hipError_t launch_inv_planes<float>(int, const FieldDesc<float>*, int, int, hipStream_t);
+template hipError_t launch_inv_planes<double>(int, const FieldDesc<double>*, int, int, hipStream_t);
 
 }  // namespace sipf

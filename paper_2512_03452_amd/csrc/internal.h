@@ -54,6 +54,28 @@ template <typename T> struct PartDesc {
     int gmargin;            // cells the W^- displacement can reach (gradient window margin)
 };
 
+// One reverse step of the particle branch (adjoint.hip).
+template <typename T> struct AdjDesc {
+    const T* x;             // X^(n-1), any order
+    const T* y;
+    const T* z;
+    const uint32_t* id;
+    int64_t P;
+    const T* G;             // gradient grids of alpha^(n-1)
+    const T* phibar;        // cotangent of the deposit of X^(n-1), or null
+    T* xbar;                // P x 3 by particle id: in Xbar^(n), out Xbar^(n-1)
+    T* Gbar;                // 3 x H^3 cotangent of G (accumulated)
+    double* acc;            // [0] chibar, [1] sbar (accumulated)
+    int H;
+    int scheme;
+    T hl;
+    T wmass;
+    T chitau;
+    T tau;
+    T s;
+    uint32_t k0, k1, inst, n;
+};
+
 // Work item of the particle pass: particles [beg, beg + cnt) of instance inst.
 struct WorkItem {
     int64_t beg;
@@ -64,9 +86,15 @@ struct WorkItem {
 // --- field passes (fft.hip) -------------------------------------------------
 // Each launcher runs its pass for `count` instances of grid size H whose
 // descriptors are consecutive in the device array `fd`.
-template <typename T> hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s);
-template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, bool update, hipStream_t s);
-template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, hipStream_t s);
+// fwd_planes: R2C of ncomp grids (phi + c H^3 -> B1 + c spectrum); consume = clear
+//             the input and advance the step counter (the step's deposit).
+// xpencils:   mode MODE_STEP / MODE_GRAD / MODE_ADJ_SRC / MODE_ADJ_ACC (fft.hip).
+// inv_planes: C2R of ncomp spectra (gspec + c spectrum -> G + c H^3).
+enum { XP_STEP = 0, XP_GRAD = 1, XP_ADJ_SRC = 2, XP_ADJ_ACC = 3 };
+template <typename T>
+hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s);
+template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, int mode, hipStream_t s);
+template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s);
 bool fft_size_supported(int H, bool fp64);
 // digit permutation of the LDS FFT of length N: storage position of frequency k
 int fft_perm(int N, int k);
@@ -88,6 +116,12 @@ hipError_t launch_unsort(const PartDesc<T>* pd_host, T* out_xyz, hipStream_t s);
 template <typename T>
 hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd_host, int* err, hipStream_t s);
 template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+template <typename T> hipError_t launch_adj_seed(const AdjDesc<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_adj_step(const AdjDesc<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_dot(const T* u, const T* v, int64_t n, double* out, hipStream_t s);
+template <typename T> hipError_t launch_axpby(T* y, const T* x, T a, T b, int64_t n, hipStream_t s);
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 int sort_max_keys();
 int particle_threads();
 int particle_chunk();

@@ -104,6 +104,26 @@ class Sim:
         check(_lib.load().sipf_profile_read(self._h, ms, cnt))
         return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.PHASES)}
 
+    def adjoint(self, nsteps, ckpt_every=10, phi_bar=None):
+        """Pathwise gradient of a final-density loss (the context must be at step 0).
+
+        Runs nsteps forward steps, then the reverse sweep.  With phi_bar None the
+        loss is sum(phi^2) for phi the deposit of X^(N); otherwise it is
+        sum(phi_bar * phi).  Returns (loss, dL/dchi, dL/dmu, dL/dX0) with dX0 a
+        (P, 3) device tensor in original particle order.
+        """
+        loss, dchi, dmu = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        dX0 = torch.empty((self.P, 3), dtype=self.dtype, device=self.device)
+        pb = None
+        if phi_bar is not None:
+            phi_bar = torch.as_tensor(phi_bar).to(device=self.device, dtype=self.dtype).contiguous()
+            if tuple(phi_bar.shape) != (self.H, self.H, self.H):
+                raise ValueError("phi_bar must have shape (H, H, H)")
+            pb = ctypes.c_void_p(phi_bar.data_ptr())
+        check(_lib.load().sipf_adjoint(self._h, int(nsteps), int(ckpt_every), pb, ctypes.byref(loss),
+                                       ctypes.byref(dchi), ctypes.byref(dmu), ctypes.c_void_p(dX0.data_ptr())))
+        return loss.value, dchi.value, dmu.value, dX0
+
     def save(self, path):
         check(_lib.load().sipf_save(self._h, str(path).encode()))
 
@@ -167,3 +187,38 @@ def dbg_deposit(X, **params):
     check(_lib.load().sipf_dbg_deposit(ctypes.byref(p), X.shape[0], ctypes.c_void_p(X.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), _stream_handle()))
     return out
+
+
+class Rollout(torch.autograd.Function):
+    """phi^(N) = deposit of the positions after N SIPF-PIC steps from X0.
+
+    Differentiable in X0, chi and mu along the fixed Philox noise path; the
+    backward pass runs the library's adjoint (sipf_adjoint) with the incoming
+    gradient as phi_bar, checkpointing positions every ``ckpt_every`` steps.
+    ``params`` holds the other sipf_params fields.
+    """
+
+    @staticmethod
+    def forward(ctx, X0, chi, mu, params, nsteps, ckpt_every=10):
+        p = dict(params, chi=float(chi), mu=float(mu))
+        sim = Sim(X0.detach(), **p)
+        sim.run(int(nsteps))
+        phi = sim.field("rho")
+        sim.close()
+        ctx.save_for_backward(X0)
+        ctx.p = p
+        ctx.nsteps = int(nsteps)
+        ctx.ckpt = int(ckpt_every)
+        ctx.chi_like = torch.as_tensor(chi)
+        ctx.mu_like = torch.as_tensor(mu)
+        return phi
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        (X0,) = ctx.saved_tensors
+        sim = Sim(X0.detach(), **ctx.p)
+        _, dchi, dmu, dX0 = sim.adjoint(ctx.nsteps, ctx.ckpt, phi_bar=grad_phi)
+        sim.close()
+        gchi = torch.full_like(ctx.chi_like, dchi, dtype=torch.float64)
+        gmu = torch.full_like(ctx.mu_like, dmu, dtype=torch.float64)
+        return dX0.to(X0.dtype), gchi.to(ctx.chi_like.dtype), gmu.to(ctx.mu_like.dtype), None, None, None
