@@ -62,31 +62,81 @@ def cpu_baseline(cfg, sample_P, steps):
 
 
 def adjoint_ratio(pkg, workloads, np, torch):
-    """fwd+adjoint time over forward time on the adjoint workload (same GPU)."""
+    """fwd+adjoint time over forward time on the adjoint workload (same GPU),
+    in the workload's FP32 and in FP64.  Each adjoint runs twice from the same
+    inputs: the relative difference of the two dL/dX0 shows how far rounding
+    (summation order of the deposit) is amplified along the trajectory."""
     cfg = workloads.CONFIGS["fp32_adjoint_h64"]
     P, N, K = cfg["P"], cfg["steps"], 10
-    X0 = cfg["init"](P).astype(np.float32)
-    sim = pkg.Sim(X0, **cfg["params"])
-    sim.run(5)
-    sim.sync()
-    sim.close()
-    sim = pkg.Sim(X0, **cfg["params"])
+    out = {"workload": "fp32_adjoint_h64", "P": P, "H": cfg["params"]["H"], "steps": N, "ckpt_every": K}
+    for prec in ("fp32", "fp64"):
+        params = dict(cfg["params"], precision=prec)
+        X0 = cfg["init"](P).astype(np.float32 if prec == "fp32" else np.float64)
+        sim = pkg.Sim(X0, **params)
+        sim.run(9)
+        sim.sync()
+        sim.close()
+        sim = pkg.Sim(X0, **params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(N)
+        sim.sync()
+        t_fwd = time.perf_counter() - t0
+        sim.close()
+        runs = []
+        for rep in range(2):
+            sim = pkg.Sim(X0, **params)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loss, dchi, dmu, dX0 = sim.adjoint(N, K)
+            torch.cuda.synchronize()
+            runs.append((time.perf_counter() - t0, loss, dchi, dmu, dX0.double()))
+            sim.close()
+        t_adj = min(r[0] for r in runs)
+        a, b = runs[0][4], runs[1][4]
+        out[prec] = {"fwd_ms": 1e3 * t_fwd, "fwd_adj_ms": 1e3 * t_adj, "ratio": t_adj / t_fwd,
+                     "loss": runs[0][1], "dchi": [runs[0][2], runs[1][2]], "dmu": [runs[0][3], runs[1][3]],
+                     "dX0_rel_diff_between_runs": float(torch.linalg.norm(a - b) / torch.linalg.norm(a)),
+                     "grad_finite": bool(np.isfinite(runs[0][2]) and torch.isfinite(a).all().item())}
+    out["ratio"] = out["fp32"]["ratio"]
+    return out
+
+
+def ensemble_throughput(pkg, workloads, np, torch, steps=40):
+    """64-instance ensemble (uneven P, H, chi): one batch versus the same
+    instances advanced one context after another (same GPU, same steps)."""
+    ens = workloads.ensemble(64, seed=0)
+    inst = [dict(params=e["params"], X0=e["X0"].astype(np.float32)) for e in ens]
+    total_P = sum(e["P"] for e in ens)
+    b = pkg.Batch(inst)
+    b.run(9)
+    b.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.run(N)
-    sim.sync()
-    t_fwd = time.perf_counter() - t0
-    sim.close()
-    sim = pkg.Sim(X0, **cfg["params"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss, dchi, dmu, dX0 = sim.adjoint(N, K)
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
-    sim.close()
-    return {"workload": "fp32_adjoint_h64", "P": P, "H": cfg["params"]["H"], "steps": N, "ckpt_every": K,
-            "fwd_ms": 1e3 * t_fwd, "fwd_adj_ms": 1e3 * t_adj, "ratio": t_adj / t_fwd,
-            "grad_finite": bool(np.isfinite(dchi) and np.isfinite(dmu) and torch.isfinite(dX0).all().item())}
+    b.run(steps)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    b.profile(True)
+    b.run(8)
+    prof = b.profile_read()
+    b.profile(False)
+    b.close()
+    del b
+    t_seq = 0.0
+    for it in inst:
+        sim = pkg.Sim(it["X0"], **it["params"])
+        sim.run(9)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.run(steps)
+        sim.sync()
+        t_seq += time.perf_counter() - t0
+        sim.close()
+    return {"workload": "ensemble64_h32_h64", "instances": 64, "total_P": total_P, "steps": steps,
+            "batched_ms_per_step": 1e3 * t_batch / steps, "batched_particle_steps_per_s": total_P * steps / t_batch,
+            "sequential_ms_per_step": 1e3 * t_seq / steps, "sequential_particle_steps_per_s": total_P * steps / t_seq,
+            "speedup": t_seq / t_batch,
+            "phases_us_per_step": {k: 1e3 * v[0] / 8 for k, v in prof.items() if v[1]}}
 
 
 def main():
@@ -100,6 +150,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -178,6 +229,9 @@ def main():
     if not args.no_adjoint:
         print("# fwd+adjoint vs fwd on the adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(pkg, workloads, np, torch)
+    if not args.no_ensemble:
+        print("# batched 64-instance ensemble vs one context at a time", file=sys.stderr, flush=True)
+        out["ensemble"] = ensemble_throughput(pkg, workloads, np, torch)
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, P), args.cpu_steps)

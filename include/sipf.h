@@ -128,13 +128,22 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
 /* Advance one step n-1 -> n (Algorithm 4).  Asynchronous. */
 int sipf_step(sipf_ctx* ctx);
 
-/* Advance nsteps >= 0 steps.  Asynchronous; replays a captured HIP graph of
- * the step sequence when the same count is requested again. */
+/* Advance nsteps >= 0 steps.  Asynchronous.  Whole runs of two re-sort
+ * periods replay a HIP graph captured on first use (kernels only, no memset
+ * or copy nodes); the remaining steps are enqueued one by one.  Graph replay
+ * and eager stepping enqueue the same kernels with the same arguments. */
 int sipf_run(sipf_ctx* ctx, int64_t nsteps);
+
+/* Switch graph replay in sipf_run on (1, the default) or off (0). */
+int sipf_use_graphs(sipf_ctx* ctx, int enable);
 
 /* Wait for the context's stream and report any device-side error flag
  * (SIPF_ENUMERIC for a non-finite position). */
 int sipf_sync(sipf_ctx* ctx);
+
+/* The parameters the context was created with (tuning fields as given,
+ * 0 where left to the defaults) and its particle count. */
+int sipf_get_params(sipf_ctx* ctx, sipf_params* prm, int64_t* P);
 
 /* Number of completed steps n (synchronises). */
 int sipf_get_step(sipf_ctx* ctx, int64_t* n);
@@ -182,10 +191,15 @@ int sipf_adjoint(sipf_ctx* ctx, int64_t nsteps, int32_t ckpt_every, const void* 
 int sipf_profile(sipf_ctx* ctx, int enable);
 int sipf_profile_read(sipf_ctx* ctx, double* ms, int64_t* launches);
 
-/* Snapshot (parameters, n, positions in original order, alpha) to a file and
- * back; a loaded context continues bit-for-bit like the saved one would,
- * since the noise is a function of (id, n).  sipf_load: SIPF_EIO on a
- * missing, truncated or corrupt file. */
+/* Snapshot (parameters, n, positions in original order, alpha^(n) in
+ * natural order) to a file and back.  The noise is a function of
+ * (seed, instance, particle id, n), so a loaded context draws the same
+ * increments as the saved one would; its results agree with an uninterrupted
+ * run up to the rounding of summation order (the deposit accumulates in an
+ * order that depends on scheduling and on the particle sort).  The file is
+ * native-endian; sipf_save: SIPF_EIO if the file cannot be written;
+ * sipf_load: SIPF_EIO on a missing, truncated, oversized or corrupt file,
+ * otherwise the errors of sipf_init. */
 int sipf_save(sipf_ctx* ctx, const char* path);
 int sipf_load(const char* path, void* hip_stream, sipf_ctx** out);
 
@@ -196,20 +210,48 @@ int sipf_destroy(sipf_ctx* ctx);
 const char* sipf_last_error(void);
 
 /*
- * Batched ensembles: n independent instances (each its own parameters,
- * including H, chi, M0, seed and instance word; all must share the precision)
- * advanced together -- one persistent launch for all particle passes and one
- * batched launch per FFT phase and grid size per step.
- *   P[i]   particles of instance i;  X0[i] host pointer to P[i] x 3 positions.
- * sipf_batch_run advances every instance by nsteps (asynchronous).
- * sipf_batch_get_positions copies instance i's positions (original order) to
- * a caller-owned buffer and synchronises.
+ * Tile / chunk / re-sort autotuner.  Times nsteps steps (after a warm-up that
+ * includes graph capture) of fresh contexts built from prm, P and X0 (same
+ * meaning as in sipf_init), searching one axis at a time: the binning tile
+ * (powers of two from 4 to 32 within the limits of sipf_params.tile), the
+ * work-item size (1024, 2048, 4096) and the re-sort period (2, 4, 8, 16),
+ * starting from the defaults.  *best receives prm with tile, chunk and
+ * resort_every set to the fastest combination found, *ms_per_step its time.
+ * Every trial context is destroyed before return; each needs the memory of
+ * one sipf_init.  Synchronises.  Errors: those of sipf_init.
+ */
+int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_device, int32_t nsteps,
+                  void* hip_stream, sipf_params* best, double* ms_per_step);
+
+/*
+ * Batched ensembles: n (1..1024) independent instances advanced together.
+ * Each has its own parameters (H, chi, mu, M0, dt, seed, instance word, tile
+ * ...); all must share the precision and the scheme (SIPF_EINVAL otherwise).
+ * The group's chunk and re-sort period are those of prm[0].  Per step the
+ * batch issues one persistent particle launch over the work items of every
+ * instance and one launch per FFT phase and distinct grid size H; every
+ * re-sort period one sort of every instance (four launches).
+ *   prm[i], P[i]  parameters and particle count of instance i;
+ *   X0[i]         its P[i] x 3 positions (host or device per x0_on_device).
+ * Inputs are copied; the caller keeps ownership.  Instance i of a batch
+ * computes what a context created by sipf_init with prm[i], P[i], X0[i]
+ * computes (same noise, same arithmetic), up to summation order.
+ * sipf_batch_run advances every instance by nsteps (asynchronous, graph
+ * replay as in sipf_run); the get functions address instance i and
+ * synchronise; sipf_batch_profile/_read time the batch's phases as
+ * sipf_profile does.  Errors as for the single-instance calls, plus
+ * SIPF_EINVAL for an instance index out of range.
  */
 int sipf_batch_init(int32_t n, const sipf_params* prm, const int64_t* P, const void* const* X0,
-                    void* hip_stream, sipf_batch** out);
+                    int x0_on_device, void* hip_stream, sipf_batch** out);
 int sipf_batch_run(sipf_batch* b, int64_t nsteps);
+int sipf_batch_use_graphs(sipf_batch* b, int enable);
+int sipf_batch_sync(sipf_batch* b);
+int sipf_batch_get_step(sipf_batch* b, int32_t i, int64_t* n);
 int sipf_batch_get_positions(sipf_batch* b, int32_t i, void* out, int on_device);
 int sipf_batch_get_field(sipf_batch* b, int32_t i, int which, void* out, int on_device);
+int sipf_batch_profile(sipf_batch* b, int enable);
+int sipf_batch_profile_read(sipf_batch* b, double* ms, int64_t* launches);
 int sipf_batch_destroy(sipf_batch* b);
 
 /*

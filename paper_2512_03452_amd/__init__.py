@@ -12,7 +12,7 @@ from . import workloads  # noqa: F401
 
 def __getattr__(name):
     # torch-dependent front end, imported on first use
-    if name in ("Sim", "Rollout", "dbg_philox", "dbg_cells", "dbg_deposit"):
+    if name in ("Sim", "Batch", "Rollout", "autotune", "dbg_philox", "dbg_cells", "dbg_deposit"):
         from . import sim
         return getattr(sim, name)
     raise AttributeError(name)

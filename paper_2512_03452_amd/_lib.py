@@ -73,10 +73,19 @@ SIGNATURES = {
     "sipf_load": [ctypes.c_char_p, _vp, ctypes.POINTER(_vp)],
     "sipf_destroy": [_vp],
     "sipf_last_error": [],
-    "sipf_batch_init": [_i32, _pp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp)],
+    "sipf_use_graphs": [_vp, ctypes.c_int],
+    "sipf_get_params": [_vp, _pp, ctypes.POINTER(_i64)],
+    "sipf_autotune": [_pp, _i64, _vp, ctypes.c_int, _i32, _vp, _pp, _dp],
+    "sipf_batch_init": [_i32, _pp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.c_int, _vp,
+                        ctypes.POINTER(_vp)],
     "sipf_batch_run": [_vp, _i64],
+    "sipf_batch_use_graphs": [_vp, ctypes.c_int],
+    "sipf_batch_sync": [_vp],
+    "sipf_batch_get_step": [_vp, _i32, ctypes.POINTER(_i64)],
     "sipf_batch_get_positions": [_vp, _i32, _vp, ctypes.c_int],
     "sipf_batch_get_field": [_vp, _i32, ctypes.c_int, _vp, ctypes.c_int],
+    "sipf_batch_profile": [_vp, ctypes.c_int],
+    "sipf_batch_profile_read": [_vp, _dp, ctypes.POINTER(_i64)],
     "sipf_batch_destroy": [_vp],
     "sipf_dbg_philox": [_u64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp],
     "sipf_dbg_cells": [_pp, _i64, _vp, _vp, _vp],

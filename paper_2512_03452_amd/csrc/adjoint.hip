@@ -10,25 +10,25 @@
 //   Xbar   = Ybar + (M0/P)(H/L) sum_gamma phibar[g + gamma] dF_gamma/dlambda.
 // Euler-Maruyama (eq. rho_hat_update): Y = X, sbar += Xbar'.Z.
 // Cotangents of positions are stored by original particle id.
+#include <climits>
+
 #include "internal.h"
+#include "pass_common.h"
 #include "sipf.h"
 
 namespace sipf {
 
-#define GLOBAL __attribute__((address_space(1)))
-
-__device__ __forceinline__ void adj_atomic_add(float* p, float v) {
-    __builtin_amdgcn_global_atomic_fadd_f32((GLOBAL float*)p, v);
-}
-__device__ __forceinline__ void adj_atomic_add(double* p, double v) {
-    __builtin_amdgcn_global_atomic_fadd_f64((GLOBAL double*)p, v);
-}
-
 // sum over the 32 nodes of Gamma_4 of phibar[node] * dF/dlambda (eq. 4ord)
+// Nodes are read from P at ((i - ox) mod H, (j - oy) mod H, (k - oz) mod H) with
+// row strides (Wy, Wz): the whole grid for o = 0, W = H, or a window of it.
 template <typename T>
 __device__ __forceinline__ void deposit_grad(const T* __restrict__ phibar, T x, T y, T z, T hl, int H, T& gx_, T& gy_,
-                                             T& gz_) {
+                                             T& gz_, int ox = 0, int oy = 0, int oz = 0, int Wy = 0, int Wz = 0) {
     const int Hm = H - 1;
+    if (Wy == 0) {
+        Wy = H;
+        Wz = H;
+    }
     const T s[3] = {x * hl, y * hl, z * hl};
     int g[3];
     T F[3][4], D[3][4], dS[3], S = (T)1;
@@ -50,8 +50,8 @@ __device__ __forceinline__ void deposit_grad(const T* __restrict__ phibar, T x, 
         dS[a] = ((T)1 - (T)2 * l) * (T)0.5;
     }
     auto node = [&](int i, int j, int k) -> T {
-        const int ix = (g[0] - 1 + i) & Hm, iy = (g[1] - 1 + j) & Hm, iz = (g[2] - 1 + k) & Hm;
-        return phibar[((size_t)ix * H + iy) * H + iz];
+        const int ix = (g[0] - 1 + i - ox) & Hm, iy = (g[1] - 1 + j - oy) & Hm, iz = (g[2] - 1 + k - oz) & Hm;
+        return phibar[((size_t)ix * Wy + iy) * Wz + iz];
     };
     T ax = 0, ay = 0, az = 0;
     // inner nodes: F = X Y Z S
@@ -119,65 +119,212 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
+// ---------------------------------------------------------------------------
+// Reverse particle pass over the work items of a tile sort (one item = up to
+// ACH particles of one tile, consecutive in the segment's order).  Per item,
+// the cells of X bound a window of the grid that covers the trilinear stencil
+// at Y = X + W^- (margin gmargin) and the deposit stencil at X:
+//   G window     the gradient grids, staged once from HBM (gather of v, J);
+//   Gbar window  fixed-point accumulators of the transpose of the gather,
+//                added to the grid once per item instead of once per particle;
+//   phibar window the deposit cotangent (derivative of the deposit).
+// A particle whose Y cell leaves the window, or an item whose window does not
+// fit, goes straight to HBM (gathers, float atomics).
+// ---------------------------------------------------------------------------
+constexpr int APT = 512;  // threads per workgroup
+constexpr int APPT = 8;   // particles per thread
+constexpr int ACH = APT * APPT;
+
+// Gbar accumulator: a term t (already scaled by 2^S) is added as round(t); S is
+// chosen per item so that every node sum stays below 2^E in magnitude.
+template <typename T> struct AdjFixed;
+template <> struct AdjFixed<float> {
+    using I = int32_t;
+    using U = uint32_t;
+    static constexpr int E = 30;
+    __device__ static U q(float t) { return (U)(int32_t)rintf(t); }
+};
+template <> struct AdjFixed<double> {
+    using I = long long;
+    using U = unsigned long long;
+    static constexpr int E = 50;
+    __device__ static U q(double t) { return (U)Magic<double>::take(t + Magic<double>::M); }
+};
+
+int adj_window_bytes(bool fp64) { return fp64 ? 150 * 1024 : 76 * 1024; }
+
 template <typename T, int SCHEME>
-__global__ __launch_bounds__(256) void k_adj_step(AdjDesc<T> a) {
-    __shared__ double sh[8];
-    const int H = a.H, Hm = H - 1;
-    const size_t H3 = (size_t)H * H * H;
+__device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int cnt, unsigned char* lds, int lds_bytes,
+                                         int* sh, double& chib, double& sb) {
+    using I = typename AdjFixed<T>::I;
+    using U = typename AdjFixed<T>::U;
+    const int tid = threadIdx.x;
+    const int H = a.H, Hm = H - 1, Hh = H / 2;
     const T hl = a.hl;
-    double chib = 0, sb = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.P; i += (int64_t)gridDim.x * blockDim.x) {
-        const T X[3] = {a.x[i], a.y[i], a.z[i]};
-        const uint32_t pid = a.id[i];
+    const size_t H3 = (size_t)H * H * H;
+    T px[APPT], py[APPT], pz[APPT], qx[APPT], qy[APPT], qz[APPT];
+    uint32_t pid[APPT];
+    if (tid < 3) sh[tid] = INT_MAX;
+    else if (tid < 6) sh[tid] = INT_MIN;
+    else if (tid == 6) sh[6] = 0;
+    __syncthreads();
+    const int rx = ifloor(a.x[beg] * hl) & Hm, ry = ifloor(a.y[beg] * hl) & Hm, rz = ifloor(a.z[beg] * hl) & Hm;
+    int mnx = INT_MAX, mny = INT_MAX, mnz = INT_MAX, mxx = INT_MIN, mxy = INT_MIN, mxz = INT_MIN;
+    float bmax = 0.f;
+#pragma unroll
+    for (int k = 0; k < APPT; ++k) {
+        const int j = tid + k * APT;
+        if (j < cnt) {
+            px[k] = gp(a.x)[beg + j];
+            py[k] = gp(a.y)[beg + j];
+            pz[k] = gp(a.z)[beg + j];
+            pid[k] = gp(a.id)[beg + j];
+            qx[k] = gp(a.xbx)[beg + j];
+            qy[k] = gp(a.xby)[beg + j];
+            qz[k] = gp(a.xbz)[beg + j];
+            const int cx = (((ifloor(px[k] * hl) & Hm) - rx + Hh) & Hm) - Hh;
+            const int cy = (((ifloor(py[k] * hl) & Hm) - ry + Hh) & Hm) - Hh;
+            const int cz = (((ifloor(pz[k] * hl) & Hm) - rz + Hh) & Hm) - Hh;
+            mnx = min(mnx, cx); mxx = max(mxx, cx);
+            mny = min(mny, cy); mxy = max(mxy, cy);
+            mnz = min(mnz, cz); mxz = max(mxz, cz);
+            // |x| rounded up to float (values beyond float range give +inf)
+            const float m3 = (float)fmax(fmax(fabs((double)qx[k]), fabs((double)qy[k])), fabs((double)qz[k]));
+            bmax = fmaxf(bmax, m3 * 1.0000002f);
+        }
+    }
+    mnx = wave_min(mnx); mny = wave_min(mny); mnz = wave_min(mnz);
+    mxx = wave_max(mxx); mxy = wave_max(mxy); mxz = wave_max(mxz);
+    int bm = __float_as_int(bmax);  // non-negative floats order like their bit patterns
+    bm = wave_max(bm);
+    if ((tid & 63) == 0) {
+        atomicMin(&sh[0], mnx); atomicMin(&sh[1], mny); atomicMin(&sh[2], mnz);
+        atomicMax(&sh[3], mxx); atomicMax(&sh[4], mxy); atomicMax(&sh[5], mxz);
+        atomicMax(&sh[6], bm);
+    }
+    __syncthreads();
+
+    // window geometry (uniform across the workgroup)
+    const double bound = (double)cnt * (double)a.chitau * (double)__int_as_float(sh[6]);
+    int gox = 0, goy = 0, goz = 0, gWx = H, gWy = H, gWz = H;
+    bool gwin = false;
+    if (bound < 1e300) {
+        for (int m = a.gmargin; m >= 0 && !gwin; --m) {
+            axis_window(rx, sh[0] - m, sh[3] + 1 + m, H, gox, gWx);
+            axis_window(ry, sh[1] - m, sh[4] + 1 + m, H, goy, gWy);
+            axis_window(rz, sh[2] - m, sh[5] + 1 + m, H, goz, gWz);
+            gwin = 3 * (int64_t)gWx * gWy * gWz * (int64_t)(sizeof(I) + sizeof(T)) <= lds_bytes;
+        }
+    }
+    const int gn = gwin ? gWx * gWy * gWz : 0;
+    const size_t used = (size_t)3 * gn * (sizeof(I) + sizeof(T));
+    int dox = 0, doy = 0, doz = 0, dWx = H, dWy = H, dWz = H;
+    bool dwin = false;
+    if (a.phibar != nullptr) {
+        axis_window(rx, sh[0] - 1, sh[3] + 2, H, dox, dWx);
+        axis_window(ry, sh[1] - 1, sh[4] + 2, H, doy, dWy);
+        axis_window(rz, sh[2] - 1, sh[5] + 2, H, doz, dWz);
+        dwin = used + (size_t)dWx * dWy * dWz * sizeof(T) <= (size_t)lds_bytes;
+    }
+    I* Gb = reinterpret_cast<I*>(lds);
+    T* Gw = reinterpret_cast<T*>(lds + (size_t)3 * gn * sizeof(I));
+    T* Pw = reinterpret_cast<T*>(lds + used);
+    if (gwin) {
+        const float inv_y = 1.0f / (float)gWy, inv_z = 1.0f / (float)gWz;
+        for (int e = tid; e < gn; e += APT) {
+            int i, j, k;
+            unflatten3(e, gWy, gWz, inv_z, inv_y, i, j, k);
+            const size_t node = ((size_t)((gox + i) & Hm) * H + ((goy + j) & Hm)) * H + ((goz + k) & Hm);
+            Gw[e] = gp(a.G)[node];
+            Gw[gn + e] = gp(a.G)[H3 + node];
+            Gw[2 * gn + e] = gp(a.G)[2 * H3 + node];
+            Gb[e] = 0;
+            Gb[gn + e] = 0;
+            Gb[2 * gn + e] = 0;
+        }
+    }
+    if (dwin) {
+        const int dn = dWx * dWy * dWz;
+        const float inv_y = 1.0f / (float)dWy, inv_z = 1.0f / (float)dWz;
+        for (int e = tid; e < dn; e += APT) {
+            int i, j, k;
+            unflatten3(e, dWy, dWz, inv_z, inv_y, i, j, k);
+            Pw[e] = gp(a.phibar)[((size_t)((dox + i) & Hm) * H + ((doy + j) & Hm)) * H + ((doz + k) & Hm)];
+        }
+    }
+    int e2 = 0;
+    if (bound > 0 && gwin) (void)frexp(bound, &e2);  // bound < 2^e2
+    const T scale = (T)ldexp(1.0, AdjFixed<T>::E - e2);
+    const T back = (T)ldexp(1.0, e2 - AdjFixed<T>::E);
+    __syncthreads();
+
+    const T c = a.wmass * hl;
+#pragma unroll
+    for (int k = 0; k < APPT; ++k) {
+        const int j = tid + k * APT;
+        if (j >= cnt) continue;
+        const T X[3] = {px[k], py[k], pz[k]};
+        const T xb[3] = {qx[k], qy[k], qz[k]};
         T zm[3], zp[3], Y[3];
         if (SCHEME == SIPF_STRANG) {
-            noise3<T>(pid, a.n, 0u, a.inst, a.k0, a.k1, zm[0], zm[1], zm[2]);
-            noise3<T>(pid, a.n, 1u, a.inst, a.k0, a.k1, zp[0], zp[1], zp[2]);
+            noise3<T>(pid[k], a.n, 0u, a.inst, a.k0, a.k1, zm[0], zm[1], zm[2]);
+            noise3<T>(pid[k], a.n, 1u, a.inst, a.k0, a.k1, zp[0], zp[1], zp[2]);
             for (int d = 0; d < 3; ++d) Y[d] = X[d] + a.s * zm[d];
         } else {
-            noise3<T>(pid, a.n, 0u, a.inst, a.k0, a.k1, zp[0], zp[1], zp[2]);
+            noise3<T>(pid[k], a.n, 0u, a.inst, a.k0, a.k1, zp[0], zp[1], zp[2]);
             for (int d = 0; d < 3; ++d) {
                 zm[d] = 0;
                 Y[d] = X[d];
             }
         }
-        // trilinear value and Jacobian at Y
-        int gi[3][2];
-        T w[3][2], dw[3][2];
+        int gc[3];
+        T w[3][2];
         for (int d = 0; d < 3; ++d) {
             const T sv = Y[d] * hl;
             const T f = floor(sv);
-            const int g = (int)f;
-            const T l = sv - f;
-            gi[d][0] = g & Hm;
-            gi[d][1] = (g + 1) & Hm;
-            w[d][0] = (T)1 - l;
-            w[d][1] = l;
-            dw[d][0] = -hl;
-            dw[d][1] = hl;
+            gc[d] = (int)f;
+            w[d][1] = sv - f;
+            w[d][0] = (T)1 - w[d][1];
         }
-        T v[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        size_t idx[8];
-        T wt[8];
-        int q = 0;
-        for (int ia = 0; ia < 2; ++ia)
-            for (int ib = 0; ib < 2; ++ib)
-                for (int ic = 0; ic < 2; ++ic, ++q) {
-                    idx[q] = ((size_t)gi[0][ia] * H + gi[1][ib]) * H + gi[2][ic];
-                    wt[q] = w[0][ia] * w[1][ib] * w[2][ic];
-                    const T dx = dw[0][ia] * w[1][ib] * w[2][ic];
-                    const T dy = w[0][ia] * dw[1][ib] * w[2][ic];
-                    const T dz = w[0][ia] * w[1][ib] * dw[2][ic];
-                    for (int d = 0; d < 3; ++d) {
-                        const T gv = a.G[d * H3 + idx[q]];
-                        v[d] += wt[q] * gv;
-                        J[d][0] += dx * gv;
-                        J[d][1] += dy * gv;
-                        J[d][2] += dz * gv;
+        const int i0 = (gc[0] - gox) & Hm, j0 = (gc[1] - goy) & Hm, k0 = (gc[2] - goz) & Hm;
+        const bool inside = gwin && (gWx == H || i0 <= gWx - 2) && (gWy == H || j0 <= gWy - 2) &&
+                            (gWz == H || k0 <= gWz - 2);
+        // node offsets: in the window, or in the whole grid
+        int off[8];
+        {
+            int q = 0;
+            for (int ia = 0; ia < 2; ++ia)
+                for (int ib = 0; ib < 2; ++ib)
+                    for (int ic = 0; ic < 2; ++ic, ++q) {
+                        if (inside)
+                            off[q] = (((gc[0] + ia - gox) & Hm) * gWy + ((gc[1] + ib - goy) & Hm)) * gWz +
+                                     ((gc[2] + ic - goz) & Hm);
+                        else
+                            off[q] = (((gc[0] + ia) & Hm) * H + ((gc[1] + ib) & Hm)) * H + ((gc[2] + ic) & Hm);
                     }
-                }
-        T xb[3];
-        for (int d = 0; d < 3; ++d) xb[d] = a.xbar[3 * (size_t)pid + d];
+        }
+        const T* Gs = inside ? Gw : a.G;
+        const size_t pitch = inside ? (size_t)gn : H3;
+        T v[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, wt[8];
+        {
+            int q = 0;
+            for (int ia = 0; ia < 2; ++ia)
+                for (int ib = 0; ib < 2; ++ib)
+                    for (int ic = 0; ic < 2; ++ic, ++q) {
+                        const T wyz = w[1][ib] * w[2][ic], wxz = w[0][ia] * w[2][ic], wxy = w[0][ia] * w[1][ib];
+                        wt[q] = w[0][ia] * wyz;
+                        const T dx = (ia ? hl : -hl) * wyz;
+                        const T dy = (ib ? hl : -hl) * wxz;
+                        const T dz = (ic ? hl : -hl) * wxy;
+                        for (int d = 0; d < 3; ++d) {
+                            const T gv = Gs[d * pitch + off[q]];
+                            v[d] += wt[q] * gv;
+                            J[d][0] += dx * gv;
+                            J[d][1] += dy * gv;
+                            J[d][2] += dz * gv;
+                        }
+                    }
+        }
         chib += (double)(a.tau * (xb[0] * v[0] + xb[1] * v[1] + xb[2] * v[2]));
         T vb[3], yb[3];
         for (int d = 0; d < 3; ++d) vb[d] = a.chitau * xb[d];
@@ -187,26 +334,108 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjDesc<T> a) {
                            yb[2] * zm[2]);
         else
             sb += (double)(xb[0] * zp[0] + xb[1] * zp[1] + xb[2] * zp[2]);
-        // transpose of the gather: scatter vbar with the trilinear weights at Y
-        for (int k = 0; k < 8; ++k)
-            for (int d = 0; d < 3; ++d) adj_atomic_add(a.Gbar + d * H3 + idx[k], wt[k] * vb[d]);
+        // transpose of the gather: vbar spread with the trilinear weights at Y
+        if (inside) {
+            const T vs[3] = {vb[0] * scale, vb[1] * scale, vb[2] * scale};
+            for (int q = 0; q < 8; ++q)
+                for (int d = 0; d < 3; ++d)
+                    atomicAdd(reinterpret_cast<U*>(Gb + d * gn + off[q]), AdjFixed<T>::q(wt[q] * vs[d]));
+        } else {
+            for (int q = 0; q < 8; ++q)
+                for (int d = 0; d < 3; ++d) gatomic_add(a.Gbar + d * H3 + off[q], wt[q] * vb[d]);
+        }
         // transpose of the deposit at X
         if (a.phibar != nullptr) {
             T gx, gy, gz;
-            deposit_grad(a.phibar, X[0], X[1], X[2], hl, H, gx, gy, gz);
-            const T c = a.wmass * hl;
+            if (dwin) deposit_grad(Pw, X[0], X[1], X[2], hl, H, gx, gy, gz, dox, doy, doz, dWy, dWz);
+            else deposit_grad(a.phibar, X[0], X[1], X[2], hl, H, gx, gy, gz);
             yb[0] += c * gx;
             yb[1] += c * gy;
             yb[2] += c * gz;
         }
-        for (int d = 0; d < 3; ++d) a.xbar[3 * (size_t)pid + d] = yb[d];
+        gp(a.xbx)[beg + j] = yb[0];
+        gp(a.xby)[beg + j] = yb[1];
+        gp(a.xbz)[beg + j] = yb[2];
     }
-    const double tc = block_sum(chib, sh);
-    const double ts = block_sum(sb, sh);
+    __syncthreads();
+    if (gwin) {
+        const float inv_y = 1.0f / (float)gWy, inv_z = 1.0f / (float)gWz;
+        for (int e = tid; e < 3 * gn; e += APT) {
+            const I val = Gb[e];
+            if (val != 0) {
+                const int d = e >= 2 * gn ? 2 : (e >= gn ? 1 : 0);
+                int i, j, k;
+                unflatten3(e - d * gn, gWy, gWz, inv_z, inv_y, i, j, k);
+                const size_t node = ((size_t)((gox + i) & Hm) * H + ((goy + j) & Hm)) * H + ((goz + k) & Hm);
+                gatomic_add(a.Gbar + d * H3 + node, (T)val * back);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double block_sum_n(double v, double* sh, int nthreads) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nthreads / 64; ++i) t += sh[i];
+    return t;
+}
+
+template <typename T, int SCHEME>
+__global__ __launch_bounds__(APT) void k_adj_items(AdjDesc<T> a, const WorkItem* __restrict__ items,
+                                                   const int* __restrict__ nitems, int lds_bytes) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int sh[8];
+    __shared__ double shd[APT / 64];
+    const int n = *nitems;
+    double chib = 0, sb = 0;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const WorkItem w = items[it];
+        adj_item<T, SCHEME>(a, w.beg, w.cnt, lds, lds_bytes, sh, chib, sb);
+        __syncthreads();
+    }
+    const double tc = block_sum_n(chib, shd, APT);
+    const double ts = block_sum_n(sb, shd, APT);
     if (threadIdx.x == 0) {
         atomicAdd(a.acc, tc);
         atomicAdd(a.acc + 1, ts);
     }
+}
+
+template <typename T>
+__global__ void k_copy_positions(T* x, T* y, T* z, uint32_t* id, const T* __restrict__ sx, const T* __restrict__ sy,
+                                 const T* __restrict__ sz, const uint32_t* __restrict__ sid, int64_t P) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = sx[i];
+        y[i] = sy[i];
+        z[i] = sz[i];
+        id[i] = sid[i];
+    }
+}
+
+template <typename T>
+__global__ void k_xbar_order(T* xbar, T* bx, T* by, T* bz, const uint32_t* __restrict__ id, int64_t P, int to_order) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const size_t p = id[i];
+        if (to_order) {
+            bx[i] = xbar[3 * p];
+            by[i] = xbar[3 * p + 1];
+            bz[i] = xbar[3 * p + 2];
+        } else {
+            xbar[3 * p] = bx[i];
+            xbar[3 * p + 1] = by[i];
+            xbar[3 * p + 2] = bz[i];
+        }
+    }
+}
+
+__global__ void k_iota_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
 }
 
 template <typename T>
@@ -238,11 +467,37 @@ template <typename T> hipError_t launch_adj_seed(const AdjDesc<T>& a, hipStream_
     hipLaunchKernelGGL((k_adj_seed<T>), dim3(grid_for(a.P)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
-template <typename T> hipError_t launch_adj_step(const AdjDesc<T>& a, hipStream_t s) {
-    if (a.scheme == SIPF_STRANG)
-        hipLaunchKernelGGL((k_adj_step<T, SIPF_STRANG>), dim3(grid_for(a.P)), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_adj_step<T, SIPF_EM>), dim3(grid_for(a.P)), dim3(256), 0, s, a);
+template <typename T>
+hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, const int* nitems, int grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (particle_chunk() > ACH) return hipErrorInvalidValue;  // a work item must fit one workgroup
+    const int lds = adj_window_bytes(sizeof(T) == 8);
+    if (a.scheme == SIPF_STRANG) {
+        (void)hipFuncSetAttribute((const void*)k_adj_items<T, SIPF_STRANG>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        hipLaunchKernelGGL((k_adj_items<T, SIPF_STRANG>), dim3(grid), dim3(APT), lds, s, a, items, nitems, lds);
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_adj_items<T, SIPF_EM>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds);
+        hipLaunchKernelGGL((k_adj_items<T, SIPF_EM>), dim3(grid), dim3(APT), lds, s, a, items, nitems, lds);
+    }
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_copy_positions(T* x, T* y, T* z, uint32_t* id, const T* sx, const T* sy, const T* sz,
+                                 const uint32_t* sid, int64_t P, hipStream_t s) {
+    hipLaunchKernelGGL((k_copy_positions<T>), dim3(grid_for(P)), dim3(256), 0, s, x, y, z, id, sx, sy, sz, sid, P);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_xbar_order(T* xbar, T* bx, T* by, T* bz, const uint32_t* id, int64_t P, bool to_order,
+                             hipStream_t s) {
+    hipLaunchKernelGGL((k_xbar_order<T>), dim3(grid_for(P)), dim3(256), 0, s, xbar, bx, by, bz, id, P,
+                       to_order ? 1 : 0);
+    return hipGetLastError();
+}
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 template <typename T> hipError_t launch_dot(const T* u, const T* v, int64_t n, double* out, hipStream_t s) {
@@ -264,7 +519,10 @@ hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
 
 #define SIPF_ADJ_INST(T)                                                                \
     template hipError_t launch_adj_seed<T>(const AdjDesc<T>&, hipStream_t);            \
-    template hipError_t launch_adj_step<T>(const AdjDesc<T>&, hipStream_t);            \
+    template hipError_t launch_adj_items<T>(const AdjDesc<T>&, const WorkItem*, const int*, int, hipStream_t); \
+    template hipError_t launch_copy_positions<T>(T*, T*, T*, uint32_t*, const T*, const T*, const T*,          \
+                                                 const uint32_t*, int64_t, hipStream_t);                       \
+    template hipError_t launch_xbar_order<T>(T*, T*, T*, T*, const uint32_t*, int64_t, bool, hipStream_t);     \
     template hipError_t launch_dot<T>(const T*, const T*, int64_t, double*, hipStream_t); \
     template hipError_t launch_axpby<T>(T*, const T*, T, T, int64_t, hipStream_t);
 SIPF_ADJ_INST(float)

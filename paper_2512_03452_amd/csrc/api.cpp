@@ -1,6 +1,20 @@
 // Host runtime and C ABI of the SIPF-PIC step (declared in include/sipf.h).
+//
+// The runtime advances a *group* of independent instances together.  One step
+// of a group is one persistent particle launch over the work items of every
+// instance, then three field launches (forward planes, x pencils, inverse
+// planes) per distinct grid size H, each covering all instances of that size
+// (blockIdx.y selects the instance).  Every resort_every steps one sort of all
+// instances (four launches) re-bins the particles and rebuilds the work list.
+// A simulation context is a group of one; a batch is a group of many.
+//
+// Stepping replays a captured HIP graph of two sort periods (the sort swaps
+// between two particle buffer sets, so two periods return to the starting
+// set); steps that do not fill a whole graph run eagerly.  No memset node is
+// ever recorded: every buffer the step clears is cleared by a kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +43,12 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int v) {
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
 
 int validate(const sipf_params* p, int64_t P) {
     if (!p) return fail(SIPF_EINVAL, "params is NULL");
@@ -61,51 +81,72 @@ double filter_h0(const sipf_params* p) {
     return p->H0;
 }
 
-// default tuning (overridden by explicit parameters)
-void tuning(const sipf_params* p, int64_t P, int& tile, int& resort, int& chunk) {
-    tile = p->tile ? p->tile : (p->H >= 128 ? 8 : (p->H >= 16 ? p->H / 8 : p->H));
-    if (p->H / tile > 16) tile = p->H / 16;
-    resort = p->resort_every ? p->resort_every : 4;
-    chunk = p->chunk ? p->chunk : 4096;
-    (void)P;
+// Defaults where the parameters leave the tuning open (0): an 8-cell tile at
+// H = 128 and H/8 below, a re-sort every 4 steps, items of up to 4096.
+int default_tile(const sipf_params* p) {
+    int t = p->tile ? p->tile : (p->H >= 128 ? 8 : (p->H >= 16 ? p->H / 8 : p->H));
+    if (p->H / t > 16) t = p->H / 16;
+    return t;
 }
+int default_resort(const sipf_params* p) { return p->resort_every ? p->resort_every : 4; }
+int default_chunk(const sipf_params* p) { return p->chunk ? p->chunk : 4096; }
 
 }  // namespace
 
-struct sipf_ctx {
+// One instance: its parameters and device buffers.
+struct Inst {
     sipf_params prm{};
     int64_t P = 0;
     int H = 0;
-    int prec = SIPF_FP32;
-    size_t tsize = 4;
-    hipStream_t stream = nullptr;
-    int tile = 8, resort = 4, chunk = 4096, win_bytes = 65536, pgrid = 1024;
-    int since_sort = 0;
-    int cur = 0;  // which of the two particle buffer sets holds the current positions
-    int64_t n_host = 0;
+    int tile = 8;
     void* xs[2] = {nullptr, nullptr};
     void* ys[2] = {nullptr, nullptr};
     void* zs[2] = {nullptr, nullptr};
     uint32_t* ids[2] = {nullptr, nullptr};
-    void* phi = nullptr;
-    void* B1 = nullptr;
-    void* alpha = nullptr;
-    void* gspec = nullptr;
-    void* G = nullptr;
-    uint32_t* counts = nullptr;
-    uint32_t* cursor = nullptr;
-    uint32_t* step = nullptr;
-    int* err = nullptr;
-    void* pdesc = nullptr;  // two PartDesc<T> (one per buffer set)
-    void* fdesc = nullptr;  // one FieldDesc<T>
-    WorkItem* items = nullptr;  // work items of the particle pass, rebuilt by every sort
-    int* nitems = nullptr;      // device count of items
+    void* phi = nullptr;    // H^3 deposit
+    void* B1 = nullptr;     // half spectrum after the yz pass
+    void* alpha = nullptr;  // alpha^(n), permuted (kx, ky)
+    void* gspec = nullptr;  // 3 gradient spectra
+    void* G = nullptr;      // 3 x H^3 gradient grids
+};
+
+// Instances of one grid size: FieldDesc slots [first, first + count).
+struct HClass {
+    int H, first, count;
+};
+
+struct Group {
+    int prec = SIPF_FP32;
+    size_t tsize = 4;
+    int scheme = SIPF_STRANG;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;  // private stream used only to capture graphs
+    int resort = 4, chunk = 4096, win_bytes = 65536, pgrid = 1024;
+    int since_sort = 0;
+    int cur = 0;  // which of the two particle buffer sets holds the current positions
+    int64_t n_host = 0;
+    std::vector<Inst> in;
+    std::vector<HClass> classes;
+    std::vector<int> fslot;  // FieldDesc slot of instance i
+    uint32_t* steps = nullptr;  // per-instance completed-step counters
+    int* errs = nullptr;        // per-instance error flags
+    uint32_t* counts = nullptr;  // n x MAX_KEYS tile counts (zero between sorts)
+    uint32_t* cursor = nullptr;  // n x MAX_KEYS tile starts / scatter cursors
+    void* pdesc = nullptr;       // 2n PartDesc<T>: set s of instance i at s*n + i
+    void* fdesc = nullptr;       // n FieldDesc<T>, grouped by H class
+    SortChunk* chunks = nullptr;
+    int nchunks = 0;
+    WorkItem* seg = nullptr;  // per-instance item segments written by the scan
+    int* seg_off = nullptr;
+    int* seg_n = nullptr;
+    WorkItem* items = nullptr;  // concatenated work items of the particle pass
+    int* nitems = nullptr;
     int items_cap = 0;
     std::vector<void*> allocs;
-    // captured graph of a whole number of sort periods
-    hipGraphExec_t gexec = nullptr;
-    int64_t graph_steps = 0;
-    // per-phase event timing (sipf_profile)
+    // captured graphs of two sort periods, by starting buffer set
+    bool graphs = true;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // per-phase event timing
     bool prof = false;
     struct Mark {
         int phase;
@@ -116,9 +157,12 @@ struct sipf_ctx {
     int64_t prof_n[SIPF_NPHASES] = {0};
 };
 
+struct sipf_ctx : Group {};
+struct sipf_batch : Group {};
+
 namespace {
 
-int dalloc(sipf_ctx* c, void** p, size_t bytes) {
+int dalloc(Group* g, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(p, bytes);
@@ -127,47 +171,53 @@ int dalloc(sipf_ctx* c, void** p, size_t bytes) {
         (void)hipGetLastError();
         return fail(SIPF_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
     }
-    c->allocs.push_back(*p);
+    g->allocs.push_back(*p);
     return SIPF_OK;
 }
 
-template <typename T> PartDesc<T> make_pdesc(const sipf_ctx* c, int set) {
+template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
+    const Inst& I = g->in[i];
+    const sipf_params& p = I.prm;
     PartDesc<T> d{};
-    d.x = (T*)c->xs[set];
-    d.y = (T*)c->ys[set];
-    d.z = (T*)c->zs[set];
-    d.id = c->ids[set];
-    d.P = c->P;
-    d.phi = (T*)c->phi;
-    d.G = (const T*)c->G;
-    d.step = c->step;
-    d.err = c->err;
-    d.H = c->H;
-    d.scheme = c->prm.scheme;
-    d.hl = (T)(c->H / c->prm.L);
-    d.L = (T)c->prm.L;
-    d.halfL = (T)(c->prm.L / 2);
-    d.invL = (T)(1.0 / c->prm.L);
-    d.wmass = (T)(c->prm.M0 / (double)c->P);
-    d.chitau = (T)(c->prm.chi * c->prm.dt);
-    d.s = (T)(c->prm.scheme == SIPF_STRANG ? std::sqrt(c->prm.mu * c->prm.dt) : std::sqrt(2.0 * c->prm.mu * c->prm.dt));
-    d.k0 = (uint32_t)c->prm.seed;
-    d.k1 = (uint32_t)(c->prm.seed >> 32);
-    d.inst = c->prm.instance;
+    d.x = (T*)I.xs[set];
+    d.y = (T*)I.ys[set];
+    d.z = (T*)I.zs[set];
+    d.id = I.ids[set];
+    d.P = I.P;
+    d.phi = (T*)I.phi;
+    d.G = (const T*)I.G;
+    d.step = g->steps + i;
+    d.err = g->errs + i;
+    d.H = I.H;
+    d.scheme = p.scheme;
+    d.hl = (T)(I.H / p.L);
+    d.L = (T)p.L;
+    d.halfL = (T)(p.L / 2);
+    d.invL = (T)(1.0 / p.L);
+    d.wmass = (T)(p.M0 / (double)I.P);
+    d.chitau = (T)(p.chi * p.dt);
+    d.s = (T)(p.scheme == SIPF_STRANG ? std::sqrt(p.mu * p.dt) : std::sqrt(2.0 * p.mu * p.dt));
+    d.k0 = (uint32_t)p.seed;
+    d.k1 = (uint32_t)(p.seed >> 32);
+    d.inst = p.instance;
     // |W^-| <= s max|z| with max|z| = sqrt(-2 ln 2^-24) (uniforms are >= 2^-24)
-    d.gmargin = c->prm.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.7677 * (double)d.hl) : 0;
+    d.gmargin = p.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.7677 * (double)d.hl) : 0;
+    d.tshift = ilog2(I.tile);
+    const int nt = I.H / I.tile;
+    d.nkeys = nt * nt * nt;
     return d;
 }
 
-template <typename T> FieldDesc<T> make_fdesc(const sipf_ctx* c) {
+template <typename T> FieldDesc<T> make_fdesc(const Group* g, int i) {
+    const Inst& I = g->in[i];
+    const sipf_params& p = I.prm;
     FieldDesc<T> f{};
-    const sipf_params& p = c->prm;
-    f.phi = (T*)c->phi;
-    f.B1 = (cplx_t<T>*)c->B1;
-    f.alpha = (cplx_t<T>*)c->alpha;
-    f.gspec = (cplx_t<T>*)c->gspec;
-    f.G = (T*)c->G;
-    f.step = c->step;
+    f.phi = (T*)I.phi;
+    f.B1 = (cplx_t<T>*)I.B1;
+    f.alpha = (cplx_t<T>*)I.alpha;
+    f.gspec = (cplx_t<T>*)I.gspec;
+    f.G = (T*)I.G;
+    f.step = g->steps + i;
     f.dt_over_eps = (T)(p.dt / p.eps);
     f.eps_over_dt = (T)(p.eps / p.dt);
     f.k2 = (T)(p.k * p.k);
@@ -178,106 +228,178 @@ template <typename T> FieldDesc<T> make_fdesc(const sipf_ctx* c) {
     return f;
 }
 
-template <typename T> int upload_descs(sipf_ctx* c) {
-    PartDesc<T> pd[2] = {make_pdesc<T>(c, 0), make_pdesc<T>(c, 1)};
-    FieldDesc<T> fd = make_fdesc<T>(c);
-    HIPCHK(hipMemcpy(c->pdesc, pd, sizeof(pd), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->fdesc, &fd, sizeof(fd), hipMemcpyHostToDevice));
+template <typename T> int upload_descs(Group* g) {
+    const int n = (int)g->in.size();
+    std::vector<PartDesc<T>> pd(2 * n);
+    std::vector<FieldDesc<T>> fd(n);
+    for (int i = 0; i < n; ++i) {
+        pd[i] = make_pdesc<T>(g, i, 0);
+        pd[n + i] = make_pdesc<T>(g, i, 1);
+        fd[g->fslot[i]] = make_fdesc<T>(g, i);
+    }
+    HIPCHK(hipMemcpy(g->pdesc, pd.data(), pd.size() * sizeof(PartDesc<T>), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->fdesc, fd.data(), fd.size() * sizeof(FieldDesc<T>), hipMemcpyHostToDevice));
     return SIPF_OK;
 }
 
-template <typename T> const PartDesc<T>* pdesc_dev(const sipf_ctx* c, int set) {
-    return reinterpret_cast<const PartDesc<T>*>(c->pdesc) + set;
+template <typename T> const PartDesc<T>* pdesc_dev(const Group* g, int set) {
+    return reinterpret_cast<const PartDesc<T>*>(g->pdesc) + (size_t)set * g->in.size();
+}
+template <typename T> const FieldDesc<T>* fdesc_dev(const Group* g, int slot) {
+    return reinterpret_cast<const FieldDesc<T>*>(g->fdesc) + slot;
 }
 
-// Event bracket around one launch when timing is on.
+// Event bracket around one phase when timing is on.
 struct Timed {
-    sipf_ctx* c;
+    Group* g;
     int phase;
     hipEvent_t a = nullptr, b = nullptr;
-    Timed(sipf_ctx* ctx, int ph) : c(ctx), phase(ph) {
-        if (!c->prof) return;
+    Timed(Group* grp, int ph) : g(grp), phase(ph) {
+        if (!g->prof) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-            c->prof = false;
+            g->prof = false;
             return;
         }
-        (void)hipEventRecord(a, c->stream);
+        (void)hipEventRecord(a, g->stream);
     }
     ~Timed() {
-        if (!c->prof || !a) return;
-        (void)hipEventRecord(b, c->stream);
-        c->marks.push_back({phase, a, b});
+        if (!g->prof || !a) return;
+        (void)hipEventRecord(b, g->stream);
+        g->marks.push_back({phase, a, b});
     }
 };
 
-template <typename T> int do_sort(sipf_ctx* c) {
-    const PartDesc<T> src = make_pdesc<T>(c, c->cur);
-    const int dst = 1 - c->cur;
+template <typename T> int do_sort(Group* g) {
+    const int dst = 1 - g->cur;
     {
-        Timed t(c, SIPF_PHASE_SORT);
-        HIPCHK(launch_sort<T>(&src, reinterpret_cast<PartDesc<T>*>(c->pdesc) + c->cur, (T*)c->xs[dst],
-                              (T*)c->ys[dst], (T*)c->zs[dst], c->ids[dst], c->counts, c->cursor, c->tile, c->chunk,
-                              c->items, c->nitems, 0, c->stream));
+        Timed t(g, SIPF_PHASE_SORT);
+        HIPCHK(launch_sort<T>(pdesc_dev<T>(g, g->cur), pdesc_dev<T>(g, dst), g->chunks, g->nchunks, (int)g->in.size(),
+                              g->counts, g->cursor, g->seg, g->seg_off, g->seg_n, g->items, g->nitems, g->chunk,
+                              g->stream));
     }
-    c->cur = dst;
-    c->since_sort = 0;
+    g->cur = dst;
+    g->since_sort = 0;
     return SIPF_OK;
 }
 
-// One step n-1 -> n: particle pass (deposit X^(n-1), gather grad c^(n-1), push),
-// then the field passes that turn the deposit into alpha^(n) and grad c^(n).
-template <typename T> int enqueue_step(sipf_ctx* c) {
-    if (c->since_sort >= c->resort) {
-        int rc = do_sort<T>(c);
+// One step n-1 -> n of every instance: particle pass (deposit X^(n-1), gather
+// grad c^(n-1), push), then the field passes that turn the deposit into
+// alpha^(n) and grad c^(n).
+template <typename T> int enqueue_step(Group* g) {
+    if (g->since_sort >= g->resort) {
+        int rc = do_sort<T>(g);
         if (rc) return rc;
     }
     {
-        Timed t(c, SIPF_PHASE_PARTICLES);
-        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, true,
-                                   c->prm.scheme, c->win_bytes, c->stream));
-    }
-    const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
-    {
-        Timed t(c, SIPF_PHASE_FWD);
-        HIPCHK(launch_fwd_planes<T>(c->H, fd, 1, 1, true, c->stream));
+        Timed t(g, SIPF_PHASE_PARTICLES);
+        HIPCHK(launch_particles<T>(pdesc_dev<T>(g, g->cur), g->items, g->nitems, g->pgrid, true, true, g->scheme,
+                                   g->win_bytes, g->stream));
     }
     {
-        Timed t(c, SIPF_PHASE_XPENCIL);
-        HIPCHK(launch_xpencils<T>(c->H, fd, 1, XP_STEP, c->stream));
+        Timed t(g, SIPF_PHASE_FWD);
+        for (const HClass& h : g->classes)
+            HIPCHK(launch_fwd_planes<T>(h.H, fdesc_dev<T>(g, h.first), h.count, 1, true, g->stream));
     }
     {
-        Timed t(c, SIPF_PHASE_INV);
-        HIPCHK(launch_inv_planes<T>(c->H, fd, 1, 3, c->stream));
+        Timed t(g, SIPF_PHASE_XPENCIL);
+        for (const HClass& h : g->classes)
+            HIPCHK(launch_xpencils<T>(h.H, fdesc_dev<T>(g, h.first), h.count, XP_STEP, g->stream));
     }
-    c->since_sort++;
-    c->n_host++;
+    {
+        Timed t(g, SIPF_PHASE_INV);
+        for (const HClass& h : g->classes)
+            HIPCHK(launch_inv_planes<T>(h.H, fdesc_dev<T>(g, h.first), h.count, 3, g->stream));
+    }
+    g->since_sort++;
+    g->n_host++;
     return SIPF_OK;
 }
 
-int drain_marks(sipf_ctx* c) {
-    if (c->marks.empty()) return SIPF_OK;
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (auto& m : c->marks) {
+// Capture two sort periods (starting at a due sort from buffer set g->cur) on
+// the private stream.  Nothing runs during capture; the host-side stepping
+// state is put back afterwards.
+template <typename T> int capture_graph(Group* g, hipGraphExec_t* out) {
+    *out = nullptr;
+    if (!g->cap) HIPCHK(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    const int since = g->since_sort, cur = g->cur;
+    const int64_t nh = g->n_host;
+    hipStream_t user = g->stream;
+    g->stream = g->cap;
+    HIPCHK(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    int rc = SIPF_OK;
+    for (int k = 0; k < 2 * g->resort && rc == SIPF_OK; ++k) rc = enqueue_step<T>(g);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g->cap, &graph);
+    g->stream = user;
+    g->since_sort = since;
+    g->cur = cur;
+    g->n_host = nh;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(SIPF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return SIPF_OK;
+}
+
+template <typename T> int run_typed(Group* g, int64_t nsteps) {
+    int64_t left = nsteps;
+    const int period = 2 * g->resort;
+    while (left > 0) {
+        if (g->graphs && !g->prof && g->n_host > 0 && g->since_sort >= g->resort && left >= period) {
+            hipGraphExec_t& ge = g->gexec[g->cur];
+            if (!ge) {
+                int rc = capture_graph<T>(g, &ge);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(ge, g->stream));
+            g->n_host += period;  // the graph ends where it started: set cur, sort due
+            left -= period;
+            continue;
+        }
+        int rc = enqueue_step<T>(g);
+        if (rc) return rc;
+        --left;
+    }
+    return SIPF_OK;
+}
+
+int run_group(Group* g, int64_t nsteps) {
+    return g->prec == SIPF_FP32 ? run_typed<float>(g, nsteps) : run_typed<double>(g, nsteps);
+}
+
+int drain_marks(Group* g) {
+    if (g->marks.empty()) return SIPF_OK;
+    HIPCHK(hipStreamSynchronize(g->stream));
+    for (auto& m : g->marks) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
-            c->prof_ms[m.phase] += ms;
-            c->prof_n[m.phase] += 1;
+            g->prof_ms[m.phase] += ms;
+            g->prof_n[m.phase] += 1;
         }
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);
     }
-    c->marks.clear();
+    g->marks.clear();
     return SIPF_OK;
 }
 
-int step_dispatch(sipf_ctx* c) { return c->prec == SIPF_FP32 ? enqueue_step<float>(c) : enqueue_step<double>(c); }
-
-int check_err(sipf_ctx* c) {
-    int e = 0;
-    HIPCHK(hipMemcpyAsync(&e, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (e & 2) return fail(SIPF_ENUMERIC, "non-finite initial position");
-    if (e & 1) return fail(SIPF_ENUMERIC, "a step produced a non-finite position");
+int check_err(Group* g) {
+    const int n = (int)g->in.size();
+    std::vector<int> e(n, 0);
+    HIPCHK(hipMemcpyAsync(e.data(), g->errs, n * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    for (int i = 0; i < n; ++i) {
+        const std::string who = n > 1 ? " (instance " + std::to_string(i) + ")" : std::string();
+        if (e[i] & 2) return fail(SIPF_ENUMERIC, "non-finite initial position" + who);
+        if (e[i] & 1) return fail(SIPF_ENUMERIC, "a step produced a non-finite position" + who);
+    }
     return SIPF_OK;
 }
 
@@ -294,15 +416,111 @@ void permute_spectrum(const void* src, void* dst, int H, size_t tsize, bool to_p
         }
 }
 
-template <typename T> int init_fields(sipf_ctx* c, const void* alpha0, int alpha0_on_device) {
-    const int H = c->H;
-    const size_t HH = H / 2 + 1;
-    const size_t nspec = (size_t)H * H * HH;
+// Set up the group's instances (parameters already in g->in): tuning, H
+// classes, device buffers and descriptors.
+template <typename T> int alloc_group(Group* g) {
+    const int n = (int)g->in.size();
+    const int mk = sort_max_keys();
+    int rc;
+    // H classes in ascending H; FieldDesc slots grouped by class
+    std::vector<int> hs;
+    for (const Inst& I : g->in) hs.push_back(I.H);
+    std::sort(hs.begin(), hs.end());
+    hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
+    g->fslot.assign(n, 0);
+    int slot = 0;
+    for (int H : hs) {
+        HClass c{H, slot, 0};
+        for (int i = 0; i < n; ++i)
+            if (g->in[i].H == H) {
+                g->fslot[i] = slot++;
+                c.count++;
+            }
+        g->classes.push_back(c);
+    }
+    std::vector<SortChunk> chunks;
+    std::vector<int> seg_off(n);
+    int64_t cap = 0;
+    const int sc = sort_chunk();
+    for (int i = 0; i < n; ++i) {
+        Inst& I = g->in[i];
+        const int64_t P = I.P;
+        const size_t H3 = (size_t)I.H * I.H * I.H;
+        const size_t nspec = (size_t)I.H * I.H * (I.H / 2 + 1);
+        for (int s = 0; s < 2; ++s) {
+            if ((rc = dalloc(g, &I.xs[s], P * sizeof(T)))) return rc;
+            if ((rc = dalloc(g, &I.ys[s], P * sizeof(T)))) return rc;
+            if ((rc = dalloc(g, &I.zs[s], P * sizeof(T)))) return rc;
+            if ((rc = dalloc(g, (void**)&I.ids[s], P * sizeof(uint32_t)))) return rc;
+        }
+        if ((rc = dalloc(g, &I.phi, H3 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.B1, nspec * 2 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.alpha, nspec * 2 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.gspec, 3 * nspec * 2 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.G, 3 * H3 * sizeof(T)))) return rc;
+        for (int64_t b = 0; b < P; b += sc) chunks.push_back(SortChunk{b, i, 0});
+        const int nt = I.H / I.tile;
+        seg_off[i] = (int)cap;
+        cap += (P + g->chunk - 1) / g->chunk + (int64_t)nt * nt * nt;
+    }
+    if (cap >= (int64_t(1) << 31) || chunks.size() >= (size_t(1) << 31))
+        return fail(SIPF_EINVAL, "too many particles in one group");
+    g->items_cap = (int)cap;
+    g->nchunks = (int)chunks.size();
+    if ((rc = dalloc(g, (void**)&g->counts, (size_t)n * mk * sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->cursor, (size_t)n * mk * sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->steps, n * sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->errs, n * sizeof(int)))) return rc;
+    if ((rc = dalloc(g, &g->pdesc, 2 * n * sizeof(PartDesc<T>)))) return rc;
+    if ((rc = dalloc(g, &g->fdesc, n * sizeof(FieldDesc<T>)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->chunks, chunks.size() * sizeof(SortChunk)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->seg, cap * sizeof(WorkItem)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->seg_off, n * sizeof(int)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->seg_n, n * sizeof(int)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->items, cap * sizeof(WorkItem)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->nitems, 16))) return rc;
+    HIPCHK(hipMemcpy(g->chunks, chunks.data(), chunks.size() * sizeof(SortChunk), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->seg_off, seg_off.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(g->nitems, 0, 16));
+    HIPCHK(hipMemset(g->counts, 0, (size_t)n * mk * sizeof(uint32_t)));
+    HIPCHK(hipMemset(g->steps, 0, n * sizeof(uint32_t)));
+    HIPCHK(hipMemset(g->errs, 0, n * sizeof(int)));
+    g->pgrid = std::min(g->items_cap, 1024);
+    return upload_descs<T>(g);
+}
+
+// Positions of instance i (AoS, host or device) -> SoA set 0, wrapped, ids 0..P-1.
+template <typename T> int load_positions(Group* g, int i, const void* X0, int on_device) {
+    const int64_t P = g->in[i].P;
+    const PartDesc<T> d0 = make_pdesc<T>(g, i, 0);
+    const T L = (T)g->in[i].prm.L;
+    if (on_device) {
+        HIPCHK(launch_load_positions<T>((const T*)X0, P, L, d0, g->errs + i, g->stream));
+        return SIPF_OK;
+    }
+    // host positions go through a temporary device buffer freed before return
+    void* tmp = nullptr;
+    if (hipMalloc(&tmp, 3 * P * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SIPF_ENOMEM, "hipMalloc failed for the staging buffer");
+    }
+    hipError_t e = hipMemcpyAsync(tmp, X0, 3 * P * sizeof(T), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = launch_load_positions<T>((const T*)tmp, P, L, d0, g->errs + i, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("loading X0: ") + hipGetErrorString(e));
+    return SIPF_OK;
+}
+
+template <typename T> int init_fields(Group* g, int i, const void* alpha0, int alpha0_on_device) {
+    const Inst& I = g->in[i];
+    const int H = I.H;
+    const size_t nspec = (size_t)H * H * (H / 2 + 1);
     const size_t H3 = (size_t)H * H * H;
-    HIPCHK(launch_fill<T>((T*)c->phi, H3, (T)0, c->stream));
-    HIPCHK(launch_fill<T>((T*)c->G, 3 * H3, (T)0, c->stream));
+    HIPCHK(launch_fill<T>((T*)I.phi, H3, (T)0, g->stream));
+    HIPCHK(launch_fill<T>((T*)I.G, 3 * H3, (T)0, g->stream));
     if (alpha0 == nullptr) {
-        HIPCHK(launch_fill<T>((T*)c->alpha, 2 * nspec, (T)0, c->stream));
+        HIPCHK(launch_fill<T>((T*)I.alpha, 2 * nspec, (T)0, g->stream));
         return SIPF_OK;
     }
     std::vector<T> nat(2 * nspec), per(2 * nspec);
@@ -311,125 +529,177 @@ template <typename T> int init_fields(sipf_ctx* c, const void* alpha0, int alpha
     for (T v : nat)
         if (!std::isfinite((double)v)) return fail(SIPF_ENUMERIC, "non-finite alpha0");
     permute_spectrum(nat.data(), per.data(), H, sizeof(T), true);
-    HIPCHK(hipMemcpy(c->alpha, per.data(), per.size() * sizeof(T), hipMemcpyHostToDevice));
-    const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
-    HIPCHK(launch_xpencils<T>(H, fd, 1, XP_GRAD, c->stream));
-    HIPCHK(launch_inv_planes<T>(H, fd, 1, 3, c->stream));
+    HIPCHK(hipMemcpyAsync(I.alpha, per.data(), per.size() * sizeof(T), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(launch_xpencils<T>(H, fdesc_dev<T>(g, g->fslot[i]), 1, XP_GRAD, g->stream));
+    HIPCHK(launch_inv_planes<T>(H, fdesc_dev<T>(g, g->fslot[i]), 1, 3, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
     return SIPF_OK;
 }
 
+// Full initialisation of a group whose g->in holds validated parameters.
 template <typename T>
-int init_typed(sipf_ctx* c, const void* X0, int x0_on_device, const void* alpha0, int alpha0_on_device) {
-    const int64_t P = c->P;
-    const int H = c->H;
-    const size_t H3 = (size_t)H * H * H;
-    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+int init_group(Group* g, const void* const* X0, int x0_on_device, const void* alpha0, int alpha0_on_device) {
     int rc;
-    for (int s = 0; s < 2; ++s) {
-        if ((rc = dalloc(c, &c->xs[s], P * sizeof(T)))) return rc;
-        if ((rc = dalloc(c, &c->ys[s], P * sizeof(T)))) return rc;
-        if ((rc = dalloc(c, &c->zs[s], P * sizeof(T)))) return rc;
-        if ((rc = dalloc(c, (void**)&c->ids[s], P * sizeof(uint32_t)))) return rc;
+    if ((rc = alloc_group<T>(g))) return rc;
+    for (int i = 0; i < (int)g->in.size(); ++i) {
+        if ((rc = load_positions<T>(g, i, X0[i], x0_on_device))) return rc;
+        if ((rc = init_fields<T>(g, i, i == 0 ? alpha0 : nullptr, alpha0_on_device))) return rc;
     }
-    if ((rc = dalloc(c, &c->phi, H3 * sizeof(T)))) return rc;
-    if ((rc = dalloc(c, &c->B1, nspec * 2 * sizeof(T)))) return rc;
-    if ((rc = dalloc(c, &c->alpha, nspec * 2 * sizeof(T)))) return rc;
-    if ((rc = dalloc(c, &c->gspec, 3 * nspec * 2 * sizeof(T)))) return rc;
-    if ((rc = dalloc(c, &c->G, 3 * H3 * sizeof(T)))) return rc;
-    if ((rc = dalloc(c, (void**)&c->counts, sort_max_keys() * sizeof(uint32_t)))) return rc;
-    if ((rc = dalloc(c, (void**)&c->cursor, sort_max_keys() * sizeof(uint32_t)))) return rc;
-    if ((rc = dalloc(c, (void**)&c->step, 16))) return rc;
-    if ((rc = dalloc(c, (void**)&c->err, 16))) return rc;
-    if ((rc = dalloc(c, &c->pdesc, 2 * sizeof(PartDesc<T>)))) return rc;
-    if ((rc = dalloc(c, &c->fdesc, sizeof(FieldDesc<T>)))) return rc;
-    c->items_cap = (int)((P + particle_chunk() - 1) / particle_chunk()) + sort_max_keys();
-    if ((rc = dalloc(c, (void**)&c->items, c->items_cap * sizeof(WorkItem)))) return rc;
-    if ((rc = dalloc(c, (void**)&c->nitems, 16))) return rc;
-    HIPCHK(hipMemset(c->nitems, 0, 16));
-    c->pgrid = std::min(c->items_cap, 1024);
-    HIPCHK(hipMemset(c->counts, 0, sort_max_keys() * sizeof(uint32_t)));
-    HIPCHK(hipMemset(c->step, 0, 16));
-    HIPCHK(hipMemset(c->err, 0, 16));
-    if ((rc = upload_descs<T>(c))) return rc;
-    // positions: AoS (host or device) -> SoA set 0, wrapped, ids 0..P-1
-    const T* xyz = (const T*)X0;
-    if (!x0_on_device) {
-        // host positions go through a temporary device buffer freed before return
-        void* tmp = nullptr;
-        if (hipMalloc(&tmp, 3 * P * sizeof(T)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(SIPF_ENOMEM, "hipMalloc failed for the staging buffer");
-        }
-        hipError_t e = hipMemcpy(tmp, X0, 3 * P * sizeof(T), hipMemcpyHostToDevice);
-        PartDesc<T> d0 = make_pdesc<T>(c, 0);
-        if (e == hipSuccess) e = launch_load_positions<T>((const T*)tmp, P, (T)c->prm.L, d0, c->err, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(tmp);
-        if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("loading X0: ") + hipGetErrorString(e));
-    } else {
-        PartDesc<T> d0 = make_pdesc<T>(c, 0);
-        HIPCHK(launch_load_positions<T>(xyz, P, (T)c->prm.L, d0, c->err, c->stream));
-    }
-    if ((rc = init_fields<T>(c, alpha0, alpha0_on_device))) return rc;
-    c->cur = 0;
-    if ((rc = do_sort<T>(c))) return rc;
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return check_err(c);
+    g->cur = 0;
+    if ((rc = do_sort<T>(g))) return rc;
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return check_err(g);
 }
 
-void free_ctx(sipf_ctx* c) {
-    if (!c) return;
-    for (auto& m : c->marks) {
+void free_group(Group* g) {
+    if (!g) return;
+    for (auto& m : g->marks) {
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);
     }
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    for (void* p : c->allocs) (void)hipFree(p);
-    delete c;
+    for (auto& ge : g->gexec)
+        if (ge) (void)hipGraphExecDestroy(ge);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    for (void* p : g->allocs) (void)hipFree(p);
 }
 
-template <typename T> int get_field_typed(sipf_ctx* c, int which, void* out, int on_device) {
-    const int H = c->H;
+// Shared set-up of contexts and batches: validation, host checks, tuning.
+int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, const void* const* X0,
+                int x0_on_device, void* hip_stream) {
+    if (n < 1 || n > 1024) return fail(SIPF_EINVAL, "instance count must be in [1, 1024]");
+    if (!prm || !P || !X0) return fail(SIPF_EINVAL, "NULL argument");
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(&prm[i], P[i]);
+        if (rc) return n > 1 ? fail(rc, "instance " + std::to_string(i) + ": " + g_err) : rc;
+        if (!X0[i]) return fail(SIPF_EINVAL, "X0 is NULL");
+        if (prm[i].precision != prm[0].precision) return fail(SIPF_EINVAL, "all instances must share the precision");
+        if (prm[i].scheme != prm[0].scheme) return fail(SIPF_EINVAL, "all instances must share the scheme");
+    }
+    const size_t ts = prm[0].precision == SIPF_FP32 ? 4 : 8;
+    if (!x0_on_device) {
+        // reject non-finite host input before touching the device
+        for (int i = 0; i < n; ++i)
+            for (int64_t j = 0; j < 3 * P[i]; ++j) {
+                const double v = ts == 4 ? (double)((const float*)X0[i])[j] : ((const double*)X0[i])[j];
+                if (!std::isfinite(v)) return fail(SIPF_ENUMERIC, "non-finite value in X0");
+            }
+    }
+    g->prec = prm[0].precision;
+    g->tsize = ts;
+    g->scheme = prm[0].scheme;
+    g->stream = (hipStream_t)hip_stream;
+    g->resort = default_resort(&prm[0]);
+    g->chunk = default_chunk(&prm[0]);
+    g->win_bytes = particle_window_bytes(g->prec == SIPF_FP64);
+    g->in.resize(n);
+    for (int i = 0; i < n; ++i) {
+        Inst& I = g->in[i];
+        I.prm = prm[i];
+        I.P = P[i];
+        I.H = prm[i].H;
+        I.tile = default_tile(&prm[i]);
+    }
+    return SIPF_OK;
+}
+
+int init_any(Group* g, const void* const* X0, int x0_on_device, const void* alpha0, int alpha0_on_device) {
+    return g->prec == SIPF_FP32 ? init_group<float>(g, X0, x0_on_device, alpha0, alpha0_on_device)
+                                : init_group<double>(g, X0, x0_on_device, alpha0, alpha0_on_device);
+}
+
+template <typename T> int get_field_typed(Group* g, int i, int which, void* out, int on_device) {
+    const Inst& I = g->in[i];
+    const int H = I.H;
     const size_t H3 = (size_t)H * H * H;
     const size_t nspec = (size_t)H * H * (H / 2 + 1);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (which == SIPF_FIELD_RHO) {
-        HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false,
-                                   c->prm.scheme, c->win_bytes, c->stream));
-        HIPCHK(hipMemcpyAsync(out, c->phi, H3 * sizeof(T), kind, c->stream));
-        HIPCHK(launch_fill<T>((T*)c->phi, H3, (T)0, c->stream));
+        // deposit-only pass over every instance, then clear every deposit again
+        HIPCHK(launch_particles<T>(pdesc_dev<T>(g, g->cur), g->items, g->nitems, g->pgrid, true, false, g->scheme,
+                                   g->win_bytes, g->stream));
+        HIPCHK(hipMemcpyAsync(out, I.phi, H3 * sizeof(T), kind, g->stream));
+        for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)J.H * J.H * J.H, (T)0, g->stream));
     } else if (which == SIPF_FIELD_GRAD) {
-        HIPCHK(hipMemcpyAsync(out, c->G, 3 * H3 * sizeof(T), kind, c->stream));
+        HIPCHK(hipMemcpyAsync(out, I.G, 3 * H3 * sizeof(T), kind, g->stream));
     } else if (which == SIPF_FIELD_ALPHA) {
         std::vector<T> per(2 * nspec), nat(2 * nspec);
-        HIPCHK(hipMemcpyAsync(per.data(), c->alpha, per.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpyAsync(per.data(), I.alpha, per.size() * sizeof(T), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
         permute_spectrum(per.data(), nat.data(), H, sizeof(T), false);
         if (on_device) HIPCHK(hipMemcpy(out, nat.data(), nat.size() * sizeof(T), hipMemcpyHostToDevice));
         else std::memcpy(out, nat.data(), nat.size() * sizeof(T));
     } else {
         return fail(SIPF_EINVAL, "unknown field");
     }
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return check_err(c);
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return check_err(g);
 }
 
-template <typename T> int get_positions_typed(sipf_ctx* c, void* out, int on_device) {
-    const PartDesc<T> d = make_pdesc<T>(c, c->cur);
+template <typename T> int get_positions_typed(Group* g, int i, void* out, int on_device) {
+    const PartDesc<T> d = make_pdesc<T>(g, i, g->cur);
     if (on_device) {
-        HIPCHK(launch_unsort<T>(&d, (T*)out, c->stream));
+        HIPCHK(launch_unsort<T>(&d, (T*)out, g->stream));
     } else {
         void* tmp = nullptr;
-        HIPCHK(hipMalloc(&tmp, 3 * c->P * sizeof(T)));
-        hipError_t e = launch_unsort<T>(&d, (T*)tmp, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, 3 * c->P * sizeof(T), hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        HIPCHK(hipMalloc(&tmp, 3 * d.P * sizeof(T)));
+        hipError_t e = launch_unsort<T>(&d, (T*)tmp, g->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, 3 * d.P * sizeof(T), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         (void)hipFree(tmp);
         if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("get_positions: ") + hipGetErrorString(e));
     }
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return check_err(c);
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return check_err(g);
 }
+
+int get_field_any(Group* g, int i, int which, void* out, int on_device) {
+    return g->prec == SIPF_FP32 ? get_field_typed<float>(g, i, which, out, on_device)
+                                : get_field_typed<double>(g, i, which, out, on_device);
+}
+int get_positions_any(Group* g, int i, void* out, int on_device) {
+    return g->prec == SIPF_FP32 ? get_positions_typed<float>(g, i, out, on_device)
+                                : get_positions_typed<double>(g, i, out, on_device);
+}
+
+int get_step_any(Group* g, int i, int64_t* n) {
+    uint32_t s = 0;
+    HIPCHK(hipMemcpyAsync(&s, g->steps + i, sizeof(s), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *n = s;
+    return SIPF_OK;
+}
+
+int profile_any(Group* g, int enable) {
+    int rc = drain_marks(g);
+    if (rc) return rc;
+    for (int i = 0; i < SIPF_NPHASES; ++i) {
+        g->prof_ms[i] = 0;
+        g->prof_n[i] = 0;
+    }
+    g->prof = enable != 0;
+    return SIPF_OK;
+}
+
+int profile_read_any(Group* g, double* ms, int64_t* launches) {
+    int rc = drain_marks(g);
+    if (rc) return rc;
+    for (int i = 0; i < SIPF_NPHASES; ++i) {
+        ms[i] = g->prof_ms[i];
+        launches[i] = g->prof_n[i];
+    }
+    return SIPF_OK;
+}
+
+int destroy_any(Group* g) {
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    else (void)hipDeviceSynchronize();
+    free_group(g);
+    return SIPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pathwise adjoint of a single-instance context
+// ---------------------------------------------------------------------------
 
 // Device buffer freed when it goes out of scope (adjoint temporaries).
 struct DevBuf {
@@ -440,8 +710,8 @@ struct DevBuf {
     hipError_t alloc(size_t n) { return hipMalloc(&p, n ? n : 16); }
 };
 
-template <typename T> PartDesc<T> pdesc_on(const sipf_ctx* c, T* x, T* y, T* z, uint32_t* id) {
-    PartDesc<T> d = make_pdesc<T>(c, 0);
+template <typename T> PartDesc<T> pdesc_on(const Group* g, T* x, T* y, T* z, uint32_t* id) {
+    PartDesc<T> d = make_pdesc<T>(g, 0, 0);
     d.x = x;
     d.y = y;
     d.z = z;
@@ -449,29 +719,38 @@ template <typename T> PartDesc<T> pdesc_on(const sipf_ctx* c, T* x, T* y, T* z, 
     return d;
 }
 
-// Gradient grids of alpha (the context's alpha buffer) into the context's G.
-template <typename T> int recompute_grad(sipf_ctx* c) {
-    const FieldDesc<T>* fd = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
-    HIPCHK(launch_xpencils<T>(c->H, fd, 1, XP_GRAD, c->stream));
-    HIPCHK(launch_inv_planes<T>(c->H, fd, 1, 3, c->stream));
+// Gradient grids of alpha (the instance's alpha buffer) into its G.
+template <typename T> int recompute_grad(Group* g) {
+    const FieldDesc<T>* fd = fdesc_dev<T>(g, 0);
+    HIPCHK(launch_xpencils<T>(g->in[0].H, fd, 1, XP_GRAD, g->stream));
+    HIPCHK(launch_inv_planes<T>(g->in[0].H, fd, 1, 3, g->stream));
     return SIPF_OK;
 }
 
+// Reverse mode of N steps of a single-instance context along its noise path.
+//   forward:  the usual steps, taping alpha^(n-1) every step and X^(n-1) every
+//             K steps;
+//   per segment [base, base + len), last segment first:
+//     sort X^(base) into tile order (this rebuilds the work items; later
+//     positions of the segment keep that order), recompute X^(base+m) and the
+//     gradient grids G^(base+m) of the segment, then for n = base+len .. base+1
+//       phibar^(n-1) = L^-3 C2R(B abar^(n))              (n < N)
+//       reverse particle pass at X^(n-1) with G^(n-1): Xbar, Gbar, chibar, sbar
+//       abar^(n-1)   = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d).
+// Position cotangents live in segment order during a segment and by particle
+// id between segments.
 template <typename T>
-int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* loss_out, double* dchi_out,
+int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_out, double* dchi_out,
                   double* dmu_out, T* dX0) {
     using V = cplx_t<T>;
+    Inst& I = c->in[0];
     int64_t n0 = 0;
-    {
-        uint32_t s = 0;
-        HIPCHK(hipMemcpyAsync(&s, c->step, sizeof(s), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        n0 = s;
-    }
+    int rc;
+    if ((rc = get_step_any(c, 0, &n0))) return rc;
     if (n0 != 0 || c->n_host != 0) return fail(SIPF_ESTATE, "sipf_adjoint needs a context at step 0");
     if (K > N) K = (int)N;
-    const int H = c->H;
-    const int64_t P = c->P;
+    const int H = I.H;
+    const int64_t P = I.P;
     const size_t H3 = (size_t)H * H * H;
     const size_t nspec = (size_t)H * H * (H / 2 + 1);
     const int64_t nseg = (N + K - 1) / K;
@@ -483,12 +762,13 @@ int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* los
         }
         return SIPF_OK;
     };
-    DevBuf tape, ckpt, seg, xbar, Gbar, phibar, abar, aN, scr, gs1, fdS, fdA, acc, pds, items, nit;
-    int rc;
+    DevBuf tape, ckpt, seg, Gseg, xbar, xbs, Gbar, phibar, abar, aN, scr, gs1, fdS, fdA, fdR, pdR, pdS, consts, acc;
     if ((rc = need(tape, (size_t)N * nspec * sizeof(V)))) return rc;
     if ((rc = need(ckpt, (size_t)nseg * pos_bytes))) return rc;
     if ((rc = need(seg, (size_t)K * pos_bytes))) return rc;
+    if ((rc = need(Gseg, (size_t)K * 3 * H3 * sizeof(T)))) return rc;
     if ((rc = need(xbar, (size_t)P * 3 * sizeof(T)))) return rc;
+    if ((rc = need(xbs, (size_t)P * 3 * sizeof(T)))) return rc;
     if ((rc = need(Gbar, 3 * H3 * sizeof(T)))) return rc;
     if ((rc = need(phibar, H3 * sizeof(T)))) return rc;
     if ((rc = need(abar, nspec * sizeof(V)))) return rc;
@@ -497,11 +777,11 @@ int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* los
     if ((rc = need(gs1, nspec * sizeof(V)))) return rc;
     if ((rc = need(fdS, sizeof(FieldDesc<T>)))) return rc;
     if ((rc = need(fdA, sizeof(FieldDesc<T>)))) return rc;
+    if ((rc = need(fdR, (size_t)N * sizeof(FieldDesc<T>)))) return rc;
+    if ((rc = need(pdR, (size_t)N * sizeof(PartDesc<T>)))) return rc;
+    if ((rc = need(pdS, (size_t)(nseg + 1) * sizeof(PartDesc<T>)))) return rc;
+    if ((rc = need(consts, (size_t)N * sizeof(uint32_t)))) return rc;
     if ((rc = need(acc, 4 * sizeof(double)))) return rc;
-    if ((rc = need(pds, (size_t)K * sizeof(PartDesc<T>)))) return rc;
-    const int nu = (int)((P + particle_chunk() - 1) / particle_chunk());
-    if ((rc = need(items, (size_t)nu * sizeof(WorkItem)))) return rc;
-    if ((rc = need(nit, 16))) return rc;
     // position slot j of a buffer: x, y, z, id
     auto slot = [&](void* base, int64_t j, T*& x, T*& y, T*& z, uint32_t*& id) {
         char* b = (char*)base + (size_t)j * pos_bytes;
@@ -510,44 +790,56 @@ int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* los
         z = y + P;
         id = (uint32_t*)(z + P);
     };
+    T* gseg = (T*)Gseg.p;
     {
         // adjoint field descriptors: source (abar -> phibar) and accumulation (Gbar -> abar)
-        FieldDesc<T> f = make_fdesc<T>(c);
+        FieldDesc<T> f = make_fdesc<T>(c, 0);
         f.alpha = (V*)abar.p;
         f.gspec = (V*)gs1.p;
         f.G = (T*)phibar.p;
         f.step = nullptr;
         HIPCHK(hipMemcpy(fdS.p, &f, sizeof(f), hipMemcpyHostToDevice));
-        f = make_fdesc<T>(c);
+        f = make_fdesc<T>(c, 0);
         f.phi = (T*)Gbar.p;
         f.B1 = (V*)scr.p;
         f.alpha = (V*)abar.p;
         f.step = nullptr;
         HIPCHK(hipMemcpy(fdA.p, &f, sizeof(f), hipMemcpyHostToDevice));
-        std::vector<PartDesc<T>> pd(K);
-        for (int j = 0; j < K; ++j) {
+        // per step t: gradient grids of the taped alpha^(t) into the segment store,
+        // and the push of step t + 1 in place on segment slot (t mod K) + 1
+        std::vector<FieldDesc<T>> fr(N);
+        std::vector<PartDesc<T>> pr(N);
+        for (int64_t t = 0; t < N; ++t) {
+            fr[t] = make_fdesc<T>(c, 0);
+            fr[t].alpha = (V*)tape.p + (size_t)t * nspec;
+            fr[t].gspec = (V*)scr.p;
+            fr[t].G = gseg + (size_t)(t % K) * 3 * H3;
+            fr[t].step = nullptr;
+            const int sl = (int)(t % K) + 1 < K ? (int)(t % K) + 1 : 0;
             T *x, *y, *z;
             uint32_t* id;
-            slot(seg.p, j, x, y, z, id);
-            pd[j] = pdesc_on<T>(c, x, y, z, id);
+            slot(seg.p, sl, x, y, z, id);
+            pr[t] = pdesc_on<T>(c, x, y, z, id);
+            pr[t].G = gseg + (size_t)(t % K) * 3 * H3;
+            pr[t].step = (const uint32_t*)consts.p + t;
         }
-        HIPCHK(hipMemcpy(pds.p, pd.data(), pd.size() * sizeof(PartDesc<T>), hipMemcpyHostToDevice));
-        std::vector<WorkItem> it(nu);
-        for (int i = 0; i < nu; ++i) {
-            it[i].beg = (int64_t)i * particle_chunk();
-            it[i].cnt = (int32_t)std::min<int64_t>(particle_chunk(), P - it[i].beg);
-            it[i].inst = 0;
+        HIPCHK(hipMemcpy(fdR.p, fr.data(), fr.size() * sizeof(FieldDesc<T>), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(pdR.p, pr.data(), pr.size() * sizeof(PartDesc<T>), hipMemcpyHostToDevice));
+        // sort descriptors: checkpoint j (source) and segment slot 0 (destination)
+        std::vector<PartDesc<T>> ps(nseg + 1);
+        for (int64_t j = 0; j <= nseg; ++j) {
+            T *x, *y, *z;
+            uint32_t* id;
+            slot(j < nseg ? ckpt.p : seg.p, j < nseg ? j : 0, x, y, z, id);
+            ps[j] = pdesc_on<T>(c, x, y, z, id);
         }
-        HIPCHK(hipMemcpy(items.p, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(nit.p, &nu, sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(pdS.p, ps.data(), ps.size() * sizeof(PartDesc<T>), hipMemcpyHostToDevice));
+        HIPCHK(launch_iota_u32((uint32_t*)consts.p, N, c->stream));
     }
-    const FieldDesc<T>* fdc = reinterpret_cast<const FieldDesc<T>*>(c->fdesc);
-    auto copy_positions = [&](T* x, T* y, T* z, uint32_t* id, const T* sx, const T* sy, const T* sz,
-                              const uint32_t* sid) -> int {
-        HIPCHK(hipMemcpyAsync(x, sx, P * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(y, sy, P * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(z, sz, P * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(id, sid, P * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+    const FieldDesc<T>* fr_dev = (const FieldDesc<T>*)fdR.p;
+    auto grad_of_tape = [&](int64_t t) -> int {
+        HIPCHK(launch_xpencils<T>(H, fr_dev + t, 1, XP_GRAD, c->stream));
+        HIPCHK(launch_inv_planes<T>(H, fr_dev + t, 1, 3, c->stream));
         return SIPF_OK;
     };
 
@@ -557,81 +849,83 @@ int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* los
             T *x, *y, *z;
             uint32_t* id;
             slot(ckpt.p, (n - 1) / K, x, y, z, id);
-            if ((rc = copy_positions(x, y, z, id, (const T*)c->xs[c->cur], (const T*)c->ys[c->cur],
-                                     (const T*)c->zs[c->cur], c->ids[c->cur])))
-                return rc;
+            HIPCHK(launch_copy_positions<T>(x, y, z, id, (const T*)I.xs[c->cur], (const T*)I.ys[c->cur],
+                                            (const T*)I.zs[c->cur], I.ids[c->cur], P, c->stream));
         }
-        HIPCHK(hipMemcpyAsync((V*)tape.p + (size_t)(n - 1) * nspec, c->alpha, nspec * sizeof(V),
+        HIPCHK(hipMemcpyAsync((V*)tape.p + (size_t)(n - 1) * nspec, I.alpha, nspec * sizeof(V),
                               hipMemcpyDeviceToDevice, c->stream));
         if ((rc = enqueue_step<T>(c))) return rc;
     }
-    HIPCHK(hipMemcpyAsync(aN.p, c->alpha, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(aN.p, I.alpha, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
 
     // ---- loss and its cotangent phibar^(N)
     HIPCHK(launch_zero_f64((double*)acc.p, 4, c->stream));
-    HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false, c->prm.scheme,
+    HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false, c->scheme,
                                c->win_bytes, c->stream));
     if (phibar_in) {
-        HIPCHK(launch_dot<T>(phibar_in, (const T*)c->phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
+        HIPCHK(launch_dot<T>(phibar_in, (const T*)I.phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
         HIPCHK(hipMemcpyAsync(phibar.p, phibar_in, H3 * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
     } else {
-        HIPCHK(launch_dot<T>((const T*)c->phi, (const T*)c->phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
+        HIPCHK(launch_dot<T>((const T*)I.phi, (const T*)I.phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
         HIPCHK(launch_fill<T>((T*)phibar.p, (int64_t)H3, (T)0, c->stream));
-        HIPCHK(launch_axpby<T>((T*)phibar.p, (const T*)c->phi, (T)2, (T)0, (int64_t)H3, c->stream));
+        HIPCHK(launch_axpby<T>((T*)phibar.p, (const T*)I.phi, (T)2, (T)0, (int64_t)H3, c->stream));
     }
-    HIPCHK(launch_fill<T>((T*)c->phi, (int64_t)H3, (T)0, c->stream));
+    HIPCHK(launch_fill<T>((T*)I.phi, (int64_t)H3, (T)0, c->stream));
 
     AdjDesc<T> ad{};
     ad.P = P;
     ad.H = H;
-    ad.scheme = c->prm.scheme;
-    const PartDesc<T> ref = make_pdesc<T>(c, c->cur);
+    ad.scheme = c->scheme;
+    const PartDesc<T> ref = make_pdesc<T>(c, 0, c->cur);
     ad.hl = ref.hl;
     ad.wmass = ref.wmass;
     ad.chitau = ref.chitau;
-    ad.tau = (T)c->prm.dt;
+    ad.tau = (T)I.prm.dt;
     ad.s = ref.s;
     ad.k0 = ref.k0;
     ad.k1 = ref.k1;
     ad.inst = ref.inst;
+    ad.gmargin = ref.gmargin;
     ad.xbar = (T*)xbar.p;
+    ad.xbx = (T*)xbs.p;
+    ad.xby = ad.xbx + P;
+    ad.xbz = ad.xby + P;
     ad.Gbar = (T*)Gbar.p;
     ad.acc = (double*)acc.p;
-    ad.G = (const T*)c->G;
-    // seed: Xbar^(N) from phibar^(N) at X^(N)
-    ad.x = (const T*)c->xs[c->cur];
-    ad.y = (const T*)c->ys[c->cur];
-    ad.z = (const T*)c->zs[c->cur];
-    ad.id = c->ids[c->cur];
+    // seed: Xbar^(N) (by id) from phibar^(N) at X^(N)
+    ad.x = (const T*)I.xs[c->cur];
+    ad.y = (const T*)I.ys[c->cur];
+    ad.z = (const T*)I.zs[c->cur];
+    ad.id = I.ids[c->cur];
+    ad.G = (const T*)I.G;
     ad.phibar = (const T*)phibar.p;
     HIPCHK(launch_adj_seed<T>(ad, c->stream));
     HIPCHK(launch_fill<T>((T*)abar.p, (int64_t)(2 * nspec), (T)0, c->stream));
 
     // ---- reverse sweep, one checkpoint segment at a time
+    const PartDesc<T>* ps_dev = (const PartDesc<T>*)pdS.p;
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
         const int64_t base = sgi * K;
         const int len = (int)std::min<int64_t>(K, N - base);
-        {
-            T *x, *y, *z, *cx, *cy, *cz;
-            uint32_t *id, *cid;
-            slot(seg.p, 0, x, y, z, id);
-            slot(ckpt.p, sgi, cx, cy, cz, cid);
-            if ((rc = copy_positions(x, y, z, id, cx, cy, cz, cid))) return rc;
-        }
+        HIPCHK(launch_sort<T>(ps_dev + sgi, ps_dev + nseg, c->chunks, c->nchunks, 1, c->counts, c->cursor, c->seg,
+                              c->seg_off, c->seg_n, c->items, c->nitems, c->chunk, c->stream));
+        if ((rc = grad_of_tape(base))) return rc;
         for (int m = 1; m < len; ++m) {
-            // X^(base+m) = push of X^(base+m-1) with the gradient of alpha^(base+m-1), step base+m
-            HIPCHK(hipMemcpyAsync(c->alpha, (V*)tape.p + (size_t)(base + m - 1) * nspec, nspec * sizeof(V),
-                                  hipMemcpyDeviceToDevice, c->stream));
-            if ((rc = recompute_grad<T>(c))) return rc;
+            // X^(base+m) = push of X^(base+m-1) with G^(base+m-1) (step base+m), then G^(base+m)
             T *x, *y, *z, *px, *py, *pz;
             uint32_t *id, *pid;
             slot(seg.p, m, x, y, z, id);
             slot(seg.p, m - 1, px, py, pz, pid);
-            if ((rc = copy_positions(x, y, z, id, px, py, pz, pid))) return rc;
-            HIPCHK(launch_set_u32(c->step, (uint32_t)(base + m - 1), c->stream));
-            HIPCHK(launch_particles<T>(reinterpret_cast<const PartDesc<T>*>(pds.p) + m, (const WorkItem*)items.p,
-                                       (const int*)nit.p, std::min(nu, 1024), false, true, c->prm.scheme,
-                                       c->win_bytes, c->stream));
+            HIPCHK(launch_copy_positions<T>(x, y, z, id, px, py, pz, pid, P, c->stream));
+            HIPCHK(launch_particles<T>((const PartDesc<T>*)pdR.p + (base + m - 1), c->items, c->nitems, c->pgrid,
+                                       false, true, c->scheme, c->win_bytes, c->stream));
+            if ((rc = grad_of_tape(base + m))) return rc;
+        }
+        {
+            T *x, *y, *z;
+            uint32_t* id;
+            slot(seg.p, 0, x, y, z, id);
+            HIPCHK(launch_xbar_order<T>((T*)xbar.p, ad.xbx, ad.xby, ad.xbz, id, P, true, c->stream));
         }
         for (int64_t n = base + len; n > base; --n) {
             // (a) phibar^(n-1) = L^-3 C2R(B abar^(n)); zero at n = N (abar^(N) = 0)
@@ -640,11 +934,7 @@ int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* los
                 HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdS.p, 1, XP_ADJ_SRC, c->stream));
                 HIPCHK(launch_inv_planes<T>(H, (const FieldDesc<T>*)fdS.p, 1, 1, c->stream));
             }
-            // (b) G^(n-1)
-            HIPCHK(hipMemcpyAsync(c->alpha, (V*)tape.p + (size_t)(n - 1) * nspec, nspec * sizeof(V),
-                                  hipMemcpyDeviceToDevice, c->stream));
-            if ((rc = recompute_grad<T>(c))) return rc;
-            // (c) particles of X^(n-1)
+            // (b) particles of X^(n-1) with G^(n-1)
             HIPCHK(launch_fill<T>((T*)Gbar.p, (int64_t)(3 * H3), (T)0, c->stream));
             T *x, *y, *z;
             uint32_t* id;
@@ -653,29 +943,142 @@ int adjoint_typed(sipf_ctx* c, int64_t N, int K, const T* phibar_in, double* los
             ad.y = y;
             ad.z = z;
             ad.id = id;
+            ad.G = gseg + (size_t)(n - 1 - base) * 3 * H3;
             ad.phibar = src ? (const T*)phibar.p : nullptr;
             ad.n = (uint32_t)n;
-            HIPCHK(launch_adj_step<T>(ad, c->stream));
-            // (d) abar^(n-1) = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d)
+            HIPCHK(launch_adj_items<T>(ad, c->items, c->nitems, c->pgrid, c->stream));
+            // (c) abar^(n-1) = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d)
             HIPCHK(launch_fwd_planes<T>(H, (const FieldDesc<T>*)fdA.p, 1, 3, false, c->stream));
             HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdA.p, 1, XP_ADJ_ACC, c->stream));
         }
+        {
+            T *x, *y, *z;
+            uint32_t* id;
+            slot(seg.p, 0, x, y, z, id);
+            HIPCHK(launch_xbar_order<T>((T*)xbar.p, ad.xbx, ad.xby, ad.xbz, id, P, false, c->stream));
+        }
     }
-    // ---- results and restoration of the context state (X^(N), alpha^(N), G^(N), n = N)
+    // ---- results and restoration of the context state (X^(N), alpha^(N), G^(N), n = N,
+    // work items of the current positions)
     double hacc[4];
     HIPCHK(hipMemcpyAsync(hacc, acc.p, sizeof(hacc), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(dX0, xbar.p, (size_t)P * 3 * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->alpha, aN.p, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(I.alpha, aN.p, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
     if ((rc = recompute_grad<T>(c))) return rc;
-    HIPCHK(launch_set_u32(c->step, (uint32_t)N, c->stream));
+    HIPCHK(launch_set_u32(c->steps, (uint32_t)N, c->stream));
+    if ((rc = do_sort<T>(c))) return rc;
     HIPCHK(hipStreamSynchronize(c->stream));
-    (void)fdc;
-    const double tau = c->prm.dt, mu = c->prm.mu;
-    const double dsdmu = c->prm.scheme == SIPF_STRANG ? tau / (2.0 * std::sqrt(mu * tau)) : tau / std::sqrt(2.0 * mu * tau);
+    const double tau = I.prm.dt, mu = I.prm.mu;
+    const double dsdmu = c->scheme == SIPF_STRANG ? tau / (2.0 * std::sqrt(mu * tau)) : tau / std::sqrt(2.0 * mu * tau);
     *loss_out = hacc[2];
     *dchi_out = hacc[0];
     *dmu_out = mu > 0 ? hacc[1] * dsdmu : 0.0;
     return check_err(c);
+}
+
+// ---------------------------------------------------------------------------
+// snapshots: header, positions in original order, alpha in natural order
+// ---------------------------------------------------------------------------
+const char kMagic[8] = {'S', 'I', 'P', 'F', 'S', 'N', 'A', 'P'};
+constexpr uint32_t kVersion = 1;
+
+struct SnapHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t tsize;
+    sipf_params prm;
+    int64_t P;
+    int64_t n;
+};
+
+int save_ctx(sipf_ctx* c, const char* path) {
+    const Inst& I = c->in[0];
+    const int H = I.H;
+    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+    SnapHeader h{};
+    std::memcpy(h.magic, kMagic, 8);
+    h.version = kVersion;
+    h.tsize = (uint32_t)c->tsize;
+    h.prm = I.prm;
+    h.P = I.P;
+    int rc;
+    if ((rc = get_step_any(c, 0, &h.n))) return rc;
+    std::vector<char> X((size_t)I.P * 3 * c->tsize), A(2 * nspec * c->tsize);
+    if ((rc = get_positions_any(c, 0, X.data(), 0))) return rc;
+    if ((rc = get_field_any(c, 0, SIPF_FIELD_ALPHA, A.data(), 0))) return rc;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(SIPF_EIO, std::string("cannot open ") + path + " for writing");
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(X.data(), 1, X.size(), f) == X.size() &&
+              std::fwrite(A.data(), 1, A.size(), f) == A.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(SIPF_EIO, std::string("writing ") + path + " failed");
+    return SIPF_OK;
+}
+
+int load_ctx(const char* path, void* hip_stream, sipf_ctx** out) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(SIPF_EIO, std::string("cannot open ") + path);
+    SnapHeader h{};
+    std::vector<char> X, A;
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 &&
+              h.version == kVersion && (h.tsize == 4 || h.tsize == 8) &&
+              h.tsize == (h.prm.precision == SIPF_FP32 ? 4u : 8u) && h.P >= 1 && h.P < (int64_t(1) << 32) &&
+              h.n >= 0 && h.n < (int64_t(1) << 32);
+    if (ok) ok = fft_size_supported(h.prm.H, h.prm.precision == SIPF_FP64);
+    if (ok) {
+        const size_t nspec = (size_t)h.prm.H * h.prm.H * (h.prm.H / 2 + 1);
+        X.resize((size_t)h.P * 3 * h.tsize);
+        A.resize(2 * nspec * h.tsize);
+        ok = std::fread(X.data(), 1, X.size(), f) == X.size() && std::fread(A.data(), 1, A.size(), f) == A.size();
+        char extra;
+        ok = ok && std::fread(&extra, 1, 1, f) == 0;
+    }
+    std::fclose(f);
+    if (!ok) return fail(SIPF_EIO, std::string(path) + ": not a complete snapshot");
+    sipf_ctx* c = nullptr;
+    int rc = sipf_init(&h.prm, h.P, X.data(), 0, A.data(), 0, hip_stream, &c);
+    if (rc) return rc;
+    if (h.n > 0) {
+        hipError_t e = launch_set_u32(c->steps, (uint32_t)h.n, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            sipf_destroy(c);
+            return fail(SIPF_EDEVICE, std::string("restoring the step counter: ") + hipGetErrorString(e));
+        }
+    }
+    *out = c;
+    return SIPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: coordinate search over (tile, chunk, resort period)
+// ---------------------------------------------------------------------------
+int time_config(const sipf_params* prm, int64_t P, const void* X0, int x0_on_device, int nsteps, void* hip_stream,
+                double* ms) {
+    sipf_ctx* c = nullptr;
+    int rc = sipf_init(prm, P, X0, x0_on_device, nullptr, 0, hip_stream, &c);
+    if (rc) return rc;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) {
+        rc = run_group(c, 2 * c->resort + 1);  // warm-up, including graph capture
+        if (!rc) e = hipEventRecord(a, c->stream);
+        if (!rc && e == hipSuccess) rc = run_group(c, nsteps);
+        if (!rc && e == hipSuccess) e = hipEventRecord(b, c->stream);
+        if (!rc && e == hipSuccess) e = hipEventSynchronize(b);
+        float f = 0.f;
+        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+        *ms = f / nsteps;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (!rc) rc = check_err(c);
+    std::string keep = g_err;
+    sipf_destroy(c);
+    g_err = keep;
+    if (!rc && e != hipSuccess) return fail(SIPF_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+    return rc;
 }
 
 }  // namespace
@@ -713,30 +1116,15 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
     int rc = validate(prm, P);
     if (rc) return rc;
     if (!X0) return fail(SIPF_EINVAL, "X0 is NULL");
-    const size_t ts = prm->precision == SIPF_FP32 ? 4 : 8;
-    if (!x0_on_device) {
-        // reject non-finite host input before touching the device
-        for (int64_t i = 0; i < 3 * P; ++i) {
-            const double v = ts == 4 ? (double)((const float*)X0)[i] : ((const double*)X0)[i];
-            if (!std::isfinite(v)) return fail(SIPF_ENUMERIC, "non-finite value in X0");
-        }
-    }
     sipf_ctx* c = new (std::nothrow) sipf_ctx();
     if (!c) return fail(SIPF_ENOMEM, "host allocation failed");
-    c->prm = *prm;
-    c->P = P;
-    c->H = prm->H;
-    c->prec = prm->precision;
-    c->tsize = ts;
-    c->stream = (hipStream_t)hip_stream;
-    tuning(prm, P, c->tile, c->resort, c->chunk);
-    // LDS per particle-pass workgroup: the larger of the two fast windows
-    c->win_bytes = particle_window_bytes(c->prec == SIPF_FP64);
-    rc = c->prec == SIPF_FP32 ? init_typed<float>(c, X0, x0_on_device, alpha0, alpha0_on_device)
-                              : init_typed<double>(c, X0, x0_on_device, alpha0, alpha0_on_device);
+    const void* xs[1] = {X0};
+    rc = setup_group(c, 1, prm, &P, xs, x0_on_device, hip_stream);
+    if (!rc) rc = init_any(c, xs, x0_on_device, alpha0, alpha0_on_device);
     if (rc) {
         std::string keep = g_err;
-        free_ctx(c);
+        free_group(c);
+        delete c;
         g_err = keep;
         return rc;
     }
@@ -746,16 +1134,25 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
 
 int sipf_step(sipf_ctx* c) {
     if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
-    return step_dispatch(c);
+    return c->prec == SIPF_FP32 ? enqueue_step<float>(c) : enqueue_step<double>(c);
 }
 
 int sipf_run(sipf_ctx* c, int64_t nsteps) {
     if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
-    for (int64_t i = 0; i < nsteps; ++i) {
-        int rc = step_dispatch(c);
-        if (rc) return rc;
-    }
+    return run_group(c, nsteps);
+}
+
+int sipf_use_graphs(sipf_ctx* c, int enable) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    c->graphs = enable != 0;
+    return SIPF_OK;
+}
+
+int sipf_get_params(sipf_ctx* c, sipf_params* prm, int64_t* P) {
+    if (!c || !prm || !P) return fail(SIPF_EINVAL, "NULL argument");
+    *prm = c->in[0].prm;
+    *P = c->in[0].P;
     return SIPF_OK;
 }
 
@@ -766,46 +1163,27 @@ int sipf_sync(sipf_ctx* c) {
 
 int sipf_get_step(sipf_ctx* c, int64_t* n) {
     if (!c || !n) return fail(SIPF_EINVAL, "NULL argument");
-    uint32_t s = 0;
-    HIPCHK(hipMemcpyAsync(&s, c->step, sizeof(s), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    *n = s;
-    return SIPF_OK;
+    return get_step_any(c, 0, n);
 }
 
 int sipf_get_positions(sipf_ctx* c, void* out, int on_device) {
     if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
-    return c->prec == SIPF_FP32 ? get_positions_typed<float>(c, out, on_device)
-                                : get_positions_typed<double>(c, out, on_device);
+    return get_positions_any(c, 0, out, on_device);
 }
 
 int sipf_get_field(sipf_ctx* c, int which, void* out, int on_device) {
     if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
-    return c->prec == SIPF_FP32 ? get_field_typed<float>(c, which, out, on_device)
-                                : get_field_typed<double>(c, which, out, on_device);
+    return get_field_any(c, 0, which, out, on_device);
 }
 
 int sipf_profile(sipf_ctx* c, int enable) {
     if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
-    int rc = drain_marks(c);
-    if (rc) return rc;
-    for (int i = 0; i < SIPF_NPHASES; ++i) {
-        c->prof_ms[i] = 0;
-        c->prof_n[i] = 0;
-    }
-    c->prof = enable != 0;
-    return SIPF_OK;
+    return profile_any(c, enable);
 }
 
 int sipf_profile_read(sipf_ctx* c, double* ms, int64_t* launches) {
     if (!c || !ms || !launches) return fail(SIPF_EINVAL, "NULL argument");
-    int rc = drain_marks(c);
-    if (rc) return rc;
-    for (int i = 0; i < SIPF_NPHASES; ++i) {
-        ms[i] = c->prof_ms[i];
-        launches[i] = c->prof_n[i];
-    }
-    return SIPF_OK;
+    return profile_read_any(c, ms, launches);
 }
 
 int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* phi_bar, double* loss, double* dchi,
@@ -818,36 +1196,134 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
                : adjoint_typed<double>(c, nsteps, ckpt_every, (const double*)phi_bar, loss, dchi, dmu, (double*)dX0);
 }
 
-int sipf_save(sipf_ctx* c, const char*) {
-    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
-    return fail(SIPF_EIO, "save not available in this build");
+int sipf_save(sipf_ctx* c, const char* path) {
+    if (!c || !path) return fail(SIPF_EINVAL, "NULL argument");
+    return save_ctx(c, path);
 }
 
-int sipf_load(const char*, void*, sipf_ctx** out) {
-    if (out) *out = nullptr;
-    return fail(SIPF_EIO, "load not available in this build");
+int sipf_load(const char* path, void* hip_stream, sipf_ctx** out) {
+    if (!out || !path) return fail(SIPF_EINVAL, "NULL argument");
+    *out = nullptr;
+    return load_ctx(path, hip_stream, out);
 }
 
 int sipf_destroy(sipf_ctx* c) {
     if (!c) return SIPF_OK;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    else (void)hipDeviceSynchronize();
-    free_ctx(c);
+    destroy_any(c);
+    delete c;
     return SIPF_OK;
 }
 
-int sipf_batch_init(int32_t, const sipf_params*, const int64_t*, const void* const*, void*, sipf_batch** out) {
-    if (out) *out = nullptr;
-    return fail(SIPF_EINVAL, "batched mode not available in this build");
+int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_device, int32_t nsteps,
+                  void* hip_stream, sipf_params* best, double* ms_per_step) {
+    if (!best || !ms_per_step) return fail(SIPF_EINVAL, "NULL argument");
+    int rc = validate(prm, P);
+    if (rc) return rc;
+    if (!X0) return fail(SIPF_EINVAL, "X0 is NULL");
+    if (nsteps < 1) return fail(SIPF_EINVAL, "nsteps must be >= 1");
+    sipf_params cur = *prm;
+    cur.tile = default_tile(prm);
+    cur.chunk = default_chunk(prm);
+    cur.resort_every = default_resort(prm);
+    double t_best = 0;
+    if ((rc = time_config(&cur, P, X0, x0_on_device, nsteps, hip_stream, &t_best))) return rc;
+    auto try_axis = [&](int32_t sipf_params::*field, const std::vector<int>& cands) -> int {
+        for (int v : cands) {
+            if (v == cur.*field) continue;
+            sipf_params p = cur;
+            p.*field = v;
+            if (validate(&p, P) != SIPF_OK) continue;
+            double t = 0;
+            int r = time_config(&p, P, X0, x0_on_device, nsteps, hip_stream, &t);
+            if (r) return r;
+            if (t < t_best) {
+                t_best = t;
+                cur = p;
+            }
+        }
+        return SIPF_OK;
+    };
+    std::vector<int> tiles;
+    for (int t = 4; t <= 32; t *= 2)
+        if (t <= prm->H && prm->H / t <= 16) tiles.push_back(t);
+    if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
+    if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 4096}))) return rc;
+    if ((rc = try_axis(&sipf_params::resort_every, {2, 4, 8, 16}))) return rc;
+    *best = cur;
+    *ms_per_step = t_best;
+    return SIPF_OK;
 }
-int sipf_batch_run(sipf_batch*, int64_t) { return fail(SIPF_EINVAL, "batched mode not available in this build"); }
-int sipf_batch_get_positions(sipf_batch*, int32_t, void*, int) {
-    return fail(SIPF_EINVAL, "batched mode not available in this build");
+
+int sipf_batch_init(int32_t n, const sipf_params* prm, const int64_t* P, const void* const* X0, int x0_on_device,
+                    void* hip_stream, sipf_batch** out) {
+    if (!out) return fail(SIPF_EINVAL, "out is NULL");
+    *out = nullptr;
+    sipf_batch* b = new (std::nothrow) sipf_batch();
+    if (!b) return fail(SIPF_ENOMEM, "host allocation failed");
+    int rc = setup_group(b, n, prm, P, X0, x0_on_device, hip_stream);
+    if (!rc) rc = init_any(b, X0, x0_on_device, nullptr, 0);
+    if (rc) {
+        std::string keep = g_err;
+        free_group(b);
+        delete b;
+        g_err = keep;
+        return rc;
+    }
+    *out = b;
+    return SIPF_OK;
 }
-int sipf_batch_get_field(sipf_batch*, int32_t, int, void*, int) {
-    return fail(SIPF_EINVAL, "batched mode not available in this build");
+
+int sipf_batch_run(sipf_batch* b, int64_t nsteps) {
+    if (!b) return fail(SIPF_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+    return run_group(b, nsteps);
 }
-int sipf_batch_destroy(sipf_batch*) { return SIPF_OK; }
+
+int sipf_batch_sync(sipf_batch* b) {
+    if (!b) return fail(SIPF_EINVAL, "batch is NULL");
+    return check_err(b);
+}
+
+int sipf_batch_get_step(sipf_batch* b, int32_t i, int64_t* n) {
+    if (!b || !n) return fail(SIPF_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int)b->in.size()) return fail(SIPF_EINVAL, "instance index out of range");
+    return get_step_any(b, i, n);
+}
+
+int sipf_batch_get_positions(sipf_batch* b, int32_t i, void* out, int on_device) {
+    if (!b || !out) return fail(SIPF_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int)b->in.size()) return fail(SIPF_EINVAL, "instance index out of range");
+    return get_positions_any(b, i, out, on_device);
+}
+
+int sipf_batch_get_field(sipf_batch* b, int32_t i, int which, void* out, int on_device) {
+    if (!b || !out) return fail(SIPF_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int)b->in.size()) return fail(SIPF_EINVAL, "instance index out of range");
+    return get_field_any(b, i, which, out, on_device);
+}
+
+int sipf_batch_profile(sipf_batch* b, int enable) {
+    if (!b) return fail(SIPF_EINVAL, "batch is NULL");
+    return profile_any(b, enable);
+}
+
+int sipf_batch_profile_read(sipf_batch* b, double* ms, int64_t* launches) {
+    if (!b || !ms || !launches) return fail(SIPF_EINVAL, "NULL argument");
+    return profile_read_any(b, ms, launches);
+}
+
+int sipf_batch_use_graphs(sipf_batch* b, int enable) {
+    if (!b) return fail(SIPF_EINVAL, "batch is NULL");
+    b->graphs = enable != 0;
+    return SIPF_OK;
+}
+
+int sipf_batch_destroy(sipf_batch* b) {
+    if (!b) return SIPF_OK;
+    destroy_any(b);
+    delete b;
+    return SIPF_OK;
+}
 
 int sipf_dbg_philox(uint64_t seed, int64_t count, const uint32_t* ctr, uint32_t* raw, void* normals, int precision,
                     void* hip_stream) {

@@ -52,6 +52,15 @@ template <typename T> struct PartDesc {
     uint32_t k0, k1;        // Philox key
     uint32_t inst;          // fourth counter word
     int gmargin;            // cells the W^- displacement can reach (gradient window margin)
+    int tshift;             // log2 of the sort tile side
+    int nkeys;              // (H / tile)^3 sort keys
+};
+
+// A run of sort-chunk particles of one instance (sort kernels).
+struct SortChunk {
+    int64_t beg;
+    int32_t inst;
+    int32_t pad;
 };
 
 // One reverse step of the particle branch (adjoint.hip).
@@ -63,7 +72,10 @@ template <typename T> struct AdjDesc {
     int64_t P;
     const T* G;             // gradient grids of alpha^(n-1)
     const T* phibar;        // cotangent of the deposit of X^(n-1), or null
-    T* xbar;                // P x 3 by particle id: in Xbar^(n), out Xbar^(n-1)
+    T* xbar;                // P x 3 by particle id (seed kernel output)
+    T* xbx;                 // cotangents in the order of x/y/z (SoA): in Xbar^(n), out Xbar^(n-1)
+    T* xby;
+    T* xbz;
     T* Gbar;                // 3 x H^3 cotangent of G (accumulated)
     double* acc;            // [0] chibar, [1] sbar (accumulated)
     int H;
@@ -74,6 +86,7 @@ template <typename T> struct AdjDesc {
     T tau;
     T s;
     uint32_t k0, k1, inst, n;
+    int gmargin;            // cells the W^- displacement can reach
 };
 
 // Work item of the particle pass: particles [beg, beg + cnt) of instance inst.
@@ -104,9 +117,10 @@ template <typename T>
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
                             bool push, int scheme, int win_bytes, hipStream_t s);
 template <typename T>
-hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T* y2, T* z2, uint32_t* id2,
-                       uint32_t* counts, uint32_t* cursor, int tile, int chunk, WorkItem* items, int* nitems,
-                       int inst, hipStream_t s);
+hipError_t launch_sort(const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks, int ninst,
+                       uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
+                       WorkItem* items, int* nitems, int chunk, hipStream_t s);
+int sort_chunk();
 template <typename T>
 hipError_t launch_cells(const T* X, int64_t n, int H, T hl, int32_t* cells, hipStream_t s);
 template <typename T>
@@ -117,7 +131,17 @@ template <typename T>
 hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd_host, int* err, hipStream_t s);
 template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T> hipError_t launch_adj_seed(const AdjDesc<T>& a, hipStream_t s);
-template <typename T> hipError_t launch_adj_step(const AdjDesc<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, const int* nitems, int grid, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_positions(T* x, T* y, T* z, uint32_t* id, const T* sx, const T* sy, const T* sz,
+                                 const uint32_t* sid, int64_t P, hipStream_t s);
+// by-id cotangents (P x 3) <-> cotangents in the order of the ids array (SoA)
+template <typename T>
+hipError_t launch_xbar_order(T* xbar, T* bx, T* by, T* bz, const uint32_t* id, int64_t P, bool to_order,
+                             hipStream_t s);
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+int adj_window_bytes(bool fp64);
 template <typename T> hipError_t launch_dot(const T* u, const T* v, int64_t n, double* out, hipStream_t s);
 template <typename T> hipError_t launch_axpby(T* y, const T* x, T a, T b, int64_t n, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);

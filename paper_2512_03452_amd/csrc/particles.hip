@@ -15,6 +15,7 @@
 #include <climits>
 
 #include "internal.h"
+#include "pass_common.h"
 #include "sipf.h"
 
 namespace sipf {
@@ -32,15 +33,6 @@ int particle_threads() { return PT; }
 int particle_chunk() { return CH; }
 int sort_max_keys() { return MAX_KEYS; }
 
-#define GLOBAL __attribute__((address_space(1)))
-template <typename T> __device__ __forceinline__ GLOBAL T* gp(T* p) { return (GLOBAL T*)p; }
-template <typename T> __device__ __forceinline__ const GLOBAL T* gp(const T* p) { return (const GLOBAL T*)p; }
-
-__device__ __forceinline__ void gatomic_add(float* p, float v) { __builtin_amdgcn_global_atomic_fadd_f32(gp(p), v); }
-__device__ __forceinline__ void gatomic_add(double* p, double v) { __builtin_amdgcn_global_atomic_fadd_f64(gp(p), v); }
-
-template <typename T> __device__ __forceinline__ int ifloor(T v) { return (int)floor(v); }
-
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     uint32_t r = 0;
 #pragma unroll
@@ -56,25 +48,6 @@ __device__ __forceinline__ uint32_t tile_key(T x, T y, T z, T hl, int Hm, int ts
     const uint32_t tz = (uint32_t)(ifloor(z * hl) & Hm) >> tshift;
     return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tz);
 }
-
-// Fixed-point accumulator of the LDS deposit window.  Float atomic adds on
-// LDS run ~25x slower than integer ones on gfx950, so weights are rounded to
-// integers at a power-of-two scale 2^S chosen per work item so that no node
-// sum can overflow, summed exactly with integer LDS atomics, and converted
-// back once when the window is added to the grid.
-template <typename T> struct Fixed;
-template <> struct Fixed<float> {
-    using I = int32_t;
-    using U = uint32_t;
-    static constexpr int BITS = 30;
-    __device__ static I quant(float v) { return (I)rintf(v); }
-};
-template <> struct Fixed<double> {
-    using I = long long;
-    using U = unsigned long long;
-    static constexpr int BITS = 62;
-    __device__ static I quant(double v) { return (I)rint(v); }
-};
 
 // ---------------------------------------------------------------------------
 // deposit of one particle: 32 nodes of Gamma_4 with the weights of eq. 4ord.
@@ -158,21 +131,6 @@ __device__ __forceinline__ void trilinear3(P G, size_t n3, int Wy, int Wz, const
     vz = az;
 }
 
-// Exact round-to-nearest integer of |v| < 2^22 (float) or 2^51 (double): in
-// v + 1.5 2^23 (resp. 1.5 2^52) the unit in the last place is 1, so the low
-// mantissa bits of the sum hold round(v) offset by the magic constant.
-template <typename T> struct Magic;
-template <> struct Magic<float> {
-    static constexpr float M = 12582912.0f;
-    static constexpr int MAXS = 21;
-    __device__ static int32_t take(float v) { return __float_as_int(v) - 0x4B400000; }
-};
-template <> struct Magic<double> {
-    static constexpr double M = 6755399441055744.0;
-    static constexpr int MAXS = 50;
-    __device__ static long long take(double v) { return __double_as_longlong(v) - 0x4338000000000000LL; }
-};
-
 // Fixed widths of the fast windows (cells per axis): the deposit window holds
 // the item's cells plus the stencil reach, the gradient window the cells plus
 // the trilinear reach and the W^- margin.  With compile-time strides every
@@ -197,26 +155,6 @@ int particle_window_bytes(bool fp64) {
     const int g64 = 3 * Win<double>::G * Win<double>::G * Win<double>::G * 8;
     const int b = fp64 ? (d64 > g64 ? d64 : g64) : (d32 > g32 ? d32 : g32);
     return (b + 255) / 256 * 256;
-}
-
-// q = e / d, r = e % d for 0 <= e < 2^20, 0 < d < 2^10: float reciprocal
-// estimate, corrected by one step.
-__device__ __forceinline__ void divmod_small(int e, int d, float inv_d, int& q, int& r) {
-    q = (int)((float)e * inv_d);
-    r = e - q * d;
-    if (r < 0) {
-        --q;
-        r += d;
-    } else if (r >= d) {
-        ++q;
-        r -= d;
-    }
-}
-// (i, j, k) of flat index e in a box of sizes (., ey, ez), row-major
-__device__ __forceinline__ void unflatten3(int e, int ey, int ez, float inv_ez, float inv_ey, int& i, int& j, int& k) {
-    int r;
-    divmod_small(e, ez, inv_ez, r, k);
-    divmod_small(r, ey, inv_ey, i, j);
 }
 
 // Deposit of one particle into a fixed-stride fixed-point window whose node
@@ -299,32 +237,6 @@ __device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz,
     vy = ay;
     vz = az;
     return true;
-}
-
-template <typename T> __device__ __forceinline__ T wrap_box(T v, T L, T halfL, T invL) {
-    return v - L * floor((v + halfL) * invL);
-}
-
-__device__ __forceinline__ int wave_min(int v) {
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Window along one axis covering relative cells [lo, hi] of a chunk whose
-// reference cell is r: origin and width, or the whole axis when it would wrap.
-__device__ __forceinline__ void axis_window(int r, int lo, int hi, int H, int& o, int& W) {
-    const int w = hi - lo + 1;
-    if (w >= H) {
-        o = 0;
-        W = H;
-    } else {
-        o = (r + lo) & (H - 1);
-        W = w;
-    }
 }
 
 // One work item: particles [beg, beg + cnt) of one instance, held in registers.
@@ -606,23 +518,32 @@ hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const 
 }
 
 // ---------------------------------------------------------------------------
-// tile sort: histogram, scan, scatter
+// tile sort: histogram, scan, combine, scatter -- for a group of instances
+//
+// The sort chunk table lists (instance, first particle) for every run of
+// SORT_CHUNK particles of every instance.  Counts and cursors hold MAX_KEYS
+// entries per instance.  The scan writes each instance's work items into its
+// own segment; the combine pass concatenates the segments into one list that
+// the (persistent) particle pass walks.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* __restrict__ pdp, uint32_t* counts,
-                                                            int tshift, int nk) {
+__global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* __restrict__ pds,
+                                                            const SortChunk* __restrict__ chunks,
+                                                            uint32_t* counts) {
     __shared__ uint32_t h[MAX_KEYS];
-    const PartDesc<T> a = *pdp;
+    const SortChunk ch = chunks[blockIdx.x];
+    const PartDesc<T> a = pds[ch.inst];
+    const int nk = a.nkeys;
     const int tid = threadIdx.x;
     for (int i = tid; i < nk; i += SORT_THREADS) h[i] = 0;
     __syncthreads();
-    const int64_t beg = (int64_t)blockIdx.x * SORT_CHUNK;
-    const int64_t end = min(beg + (int64_t)SORT_CHUNK, a.P);
-    for (int64_t i = beg + tid; i < end; i += SORT_THREADS)
-        atomicAdd(&h[tile_key(a.x[i], a.y[i], a.z[i], a.hl, a.H - 1, tshift)], 1u);
+    const int64_t end = min(ch.beg + (int64_t)SORT_CHUNK, a.P);
+    for (int64_t i = ch.beg + tid; i < end; i += SORT_THREADS)
+        atomicAdd(&h[tile_key(a.x[i], a.y[i], a.z[i], a.hl, a.H - 1, a.tshift)], 1u);
     __syncthreads();
+    uint32_t* cnt = counts + (size_t)ch.inst * MAX_KEYS;
     for (int i = tid; i < nk; i += SORT_THREADS)
-        if (h[i]) atomicAdd(&counts[i], h[i]);
+        if (h[i]) atomicAdd(&cnt[i], h[i]);
 }
 
 // Block-wide exclusive scan of one value per thread (1024 threads).
@@ -642,19 +563,27 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* p
     return r;
 }
 
-// Exclusive scan of the tile counts into cursor[] (tile starts), and the list
-// of work items: each non-empty tile is split into ceil(count / chunk)
-// contiguous items of near-equal size.  Clears counts for the next sort.
-__global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* cursor, int nk, WorkItem* items,
-                                                    int* nitems, int inst, int chunk) {
+// One workgroup per instance: exclusive scan of the tile counts into the
+// cursors (tile starts) and the instance's work items (each non-empty tile
+// split into ceil(count / chunk) contiguous items of near-equal size) into
+// its segment of `seg`.  Clears the counts for the next sort.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restrict__ pds, uint32_t* counts,
+                                                    uint32_t* cursor, WorkItem* seg, const int* __restrict__ seg_off,
+                                                    int* seg_n, int chunk) {
     __shared__ uint32_t part[1024];
+    const int inst = blockIdx.x;
+    const int nk = pds[inst].nkeys;
+    uint32_t* cnt = counts + (size_t)inst * MAX_KEYS;
+    uint32_t* cur = cursor + (size_t)inst * MAX_KEYS;
+    WorkItem* items = seg + seg_off[inst];
     const int tid = threadIdx.x;
     const int per = (nk + 1023) / 1024;
     uint32_t loc[MAX_KEYS / 1024], nit[MAX_KEYS / 1024];
     uint32_t sum = 0, isum = 0;
     for (int j = 0; j < per; ++j) {
         const int i = tid * per + j;
-        loc[j] = i < nk ? counts[i] : 0u;
+        loc[j] = i < nk ? cnt[i] : 0u;
         nit[j] = (loc[j] + chunk - 1) / chunk;
         sum += loc[j];
         isum += nit[j];
@@ -665,8 +594,8 @@ __global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* 
     for (int j = 0; j < per; ++j) {
         const int i = tid * per + j;
         if (i < nk) {
-            cursor[i] = run;
-            counts[i] = 0u;
+            cur[i] = run;
+            cnt[i] = 0u;
             for (uint32_t k = 0; k < nit[j]; ++k) {
                 const uint32_t b0 = (uint32_t)(((uint64_t)k * loc[j]) / nit[j]);
                 const uint32_t b1 = (uint32_t)(((uint64_t)(k + 1) * loc[j]) / nit[j]);
@@ -680,68 +609,87 @@ __global__ __launch_bounds__(1024) void k_tile_scan(uint32_t* counts, uint32_t* 
         run += loc[j];
         irun += nit[j];
     }
-    if (tid == 0) *nitems = (int)itotal;
+    if (tid == 0) seg_n[inst] = (int)itotal;
+}
+
+// Concatenate the instances' item segments into one list (one workgroup).
+__global__ __launch_bounds__(1024) void k_items_combine(const WorkItem* __restrict__ seg,
+                                                        const int* __restrict__ seg_off, const int* __restrict__ seg_n,
+                                                        int ninst, WorkItem* items, int* nitems) {
+    __shared__ uint32_t part[1024];
+    __shared__ int start[1024];
+    const int tid = threadIdx.x;
+    const uint32_t v = tid < ninst ? (uint32_t)seg_n[tid] : 0u;
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan(v, part, total);
+    if (tid < ninst) start[tid] = (int)off;
+    __syncthreads();
+    for (int i = 0; i < ninst; ++i) {
+        const int n = seg_n[i], o = seg_off[i], dst = start[i];
+        for (int k = tid; k < n; k += 1024) items[dst + k] = seg[o + k];
+    }
+    if (tid == 0) *nitems = (int)total;
 }
 
 template <typename T>
-__global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>* __restrict__ pdp, T* __restrict__ x2,
-                                                               T* __restrict__ y2, T* __restrict__ z2,
-                                                               uint32_t* __restrict__ id2, uint32_t* cursor,
-                                                               int tshift, int nk) {
+__global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>* __restrict__ src,
+                                                               const PartDesc<T>* __restrict__ dst,
+                                                               const SortChunk* __restrict__ chunks,
+                                                               uint32_t* cursor) {
     __shared__ uint32_t lc[MAX_KEYS];
     __shared__ uint32_t lb[MAX_KEYS];
-    const PartDesc<T> a = *pdp;
+    const SortChunk ch = chunks[blockIdx.x];
+    const PartDesc<T> a = src[ch.inst];
+    const PartDesc<T> b = dst[ch.inst];
+    const int nk = a.nkeys;
+    uint32_t* cur = cursor + (size_t)ch.inst * MAX_KEYS;
     const int tid = threadIdx.x;
     for (int i = tid; i < nk; i += SORT_THREADS) lc[i] = 0;
     __syncthreads();
-    const int64_t beg = (int64_t)blockIdx.x * SORT_CHUNK;
     T px[SORT_PER_THREAD], py[SORT_PER_THREAD], pz[SORT_PER_THREAD];
     uint32_t pid[SORT_PER_THREAD], key[SORT_PER_THREAD], rank[SORT_PER_THREAD];
 #pragma unroll
     for (int k = 0; k < SORT_PER_THREAD; ++k) {
-        const int64_t i = beg + tid + (int64_t)k * SORT_THREADS;
-        if (i < a.P) {
+        const int64_t i = ch.beg + tid + (int64_t)k * SORT_THREADS;
+        if (i < a.P && i < ch.beg + SORT_CHUNK) {
             px[k] = a.x[i];
             py[k] = a.y[i];
             pz[k] = a.z[i];
             pid[k] = a.id[i];
-            key[k] = tile_key(px[k], py[k], pz[k], a.hl, a.H - 1, tshift);
+            key[k] = tile_key(px[k], py[k], pz[k], a.hl, a.H - 1, a.tshift);
             rank[k] = atomicAdd(&lc[key[k]], 1u);
         }
     }
     __syncthreads();
     for (int i = tid; i < nk; i += SORT_THREADS)
-        if (lc[i]) lb[i] = atomicAdd(&cursor[i], lc[i]);
+        if (lc[i]) lb[i] = atomicAdd(&cur[i], lc[i]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < SORT_PER_THREAD; ++k) {
-        const int64_t i = beg + tid + (int64_t)k * SORT_THREADS;
-        if (i < a.P) {
-            const uint32_t dst = lb[key[k]] + rank[k];
-            x2[dst] = px[k];
-            y2[dst] = py[k];
-            z2[dst] = pz[k];
-            id2[dst] = pid[k];
+        const int64_t i = ch.beg + tid + (int64_t)k * SORT_THREADS;
+        if (i < a.P && i < ch.beg + SORT_CHUNK) {
+            const uint32_t d = lb[key[k]] + rank[k];
+            b.x[d] = px[k];
+            b.y[d] = py[k];
+            b.z[d] = pz[k];
+            b.id[d] = pid[k];
         }
     }
 }
 
+int sort_chunk() { return SORT_CHUNK; }
+
 template <typename T>
-hipError_t launch_sort(const PartDesc<T>* pd_host, PartDesc<T>* pd_dev, T* x2, T* y2, T* z2, uint32_t* id2,
-                       uint32_t* counts, uint32_t* cursor, int tile, int chunk, WorkItem* items, int* nitems,
-                       int inst, hipStream_t s) {
+hipError_t launch_sort(const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks, int ninst,
+                       uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
+                       WorkItem* items, int* nitems, int chunk, hipStream_t s) {
     if (chunk <= 0 || chunk > CH) chunk = CH;
-    const int H = pd_host->H;
-    int tshift = 0;
-    while ((1 << tshift) < tile) ++tshift;
-    const int nt = H >> tshift;
-    const int nk = nt * nt * nt;
-    if (nk > MAX_KEYS || (1 << tshift) != tile) return hipErrorInvalidValue;
-    const int nblk = (int)((pd_host->P + SORT_CHUNK - 1) / SORT_CHUNK);
-    hipLaunchKernelGGL((k_tile_hist<T>), dim3(nblk), dim3(SORT_THREADS), 0, s, pd_dev, counts, tshift, nk);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, cursor, nk, items, nitems, inst, chunk);
-    hipLaunchKernelGGL((k_tile_scatter<T>), dim3(nblk), dim3(SORT_THREADS), 0, s, pd_dev, x2, y2, z2, id2, cursor,
-                       tshift, nk);
+    if (ninst < 1 || ninst > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tile_hist<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+    hipLaunchKernelGGL((k_tile_scan<T>), dim3(ninst), dim3(1024), 0, s, src, counts, cursor, seg, seg_off, seg_n,
+                       chunk);
+    hipLaunchKernelGGL(k_items_combine, dim3(1), dim3(1024), 0, s, seg, seg_off, seg_n, ninst, items, nitems);
+    hipLaunchKernelGGL((k_tile_scatter<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
     return hipGetLastError();
 }
 
@@ -842,8 +790,9 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 #define SIPF_INST(T)                                                                                              \
     template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, const int*, int, bool, bool, int, \
                                             int, hipStream_t);                                                    \
-    template hipError_t launch_sort<T>(const PartDesc<T>*, PartDesc<T>*, T*, T*, T*, uint32_t*, uint32_t*,        \
-                                       uint32_t*, int, int, WorkItem*, int*, int, hipStream_t);                        \
+    template hipError_t launch_sort<T>(const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,        \
+                                       uint32_t*, uint32_t*, WorkItem*, const int*, int*, WorkItem*, int*, int,    \
+                                       hipStream_t);                                                               \
     template hipError_t launch_load_positions<T>(const T*, int64_t, T, PartDesc<T>, int*, hipStream_t);          \
     template hipError_t launch_unsort<T>(const PartDesc<T>*, T*, hipStream_t);                                    \
     template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                              \

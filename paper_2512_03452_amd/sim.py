@@ -129,14 +129,26 @@ class Sim:
 
     @classmethod
     def load(cls, path, stream=None):
+        """Context restored from a snapshot written by save()."""
+        lib = _lib.load()
         self = cls.__new__(cls)
         h = ctypes.c_void_p()
-        check(_lib.load().sipf_load(str(path).encode(), _stream_handle(stream), ctypes.byref(h)))
+        check(lib.sipf_load(str(path).encode(), _stream_handle(stream), ctypes.byref(h)))
         self._h = h
         self._stream = stream
         p = _lib.SipfParams()
+        P = ctypes.c_int64()
+        check(lib.sipf_get_params(h, ctypes.byref(p), ctypes.byref(P)))
         self.params = p
+        self.P = P.value
+        self.H = int(p.H)
+        self.dtype = _dtype(p)
+        self.device = torch.device("cuda", torch.cuda.current_device())
         return self
+
+    def use_graphs(self, enable=True):
+        """Replay captured HIP graphs in run() (default) or enqueue every step."""
+        check(_lib.load().sipf_use_graphs(self._h, 1 if enable else 0))
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -155,6 +167,112 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Independent SIPF-PIC instances advanced together (one persistent
+    particle launch and one launch per FFT phase and grid size per step).
+
+    instances: list of dicts with keys ``params`` (sipf_params fields),
+    ``X0`` ((P_i, 3) positions).  All instances share precision and scheme.
+    """
+
+    def __init__(self, instances, stream=None):
+        lib = _lib.load()
+        n = len(instances)
+        if n < 1:
+            raise ValueError("a batch needs at least one instance")
+        prm = (_lib.SipfParams * n)()
+        Ps = (ctypes.c_int64 * n)()
+        ptrs = (ctypes.c_void_p * n)()
+        self.params, self.P, self.H = [], [], []
+        keep = []
+        for i, inst in enumerate(instances):
+            p = _lib.default_params(**inst["params"])
+            prm[i] = p
+            self.params.append(p)
+            dt = _dtype(p)
+            X = inst["X0"]
+            X = torch.as_tensor(np.asarray(X) if not torch.is_tensor(X) else X)
+            X = X.to(device="cuda", dtype=dt).contiguous()
+            if X.ndim != 2 or X.shape[1] != 3:
+                raise ValueError(f"instance {i}: X0 must have shape (P, 3)")
+            keep.append(X)
+            Ps[i] = int(X.shape[0])
+            ptrs[i] = X.data_ptr()
+            self.P.append(int(X.shape[0]))
+            self.H.append(int(p.H))
+        self.dtype = _dtype(self.params[0])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n = n
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        check(lib.sipf_batch_init(n, prm, Ps, ptrs, 1, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, nsteps):
+        check(_lib.load().sipf_batch_run(self._h, int(nsteps)))
+
+    def use_graphs(self, enable=True):
+        check(_lib.load().sipf_batch_use_graphs(self._h, 1 if enable else 0))
+
+    def sync(self):
+        check(_lib.load().sipf_batch_sync(self._h))
+
+    def step_count(self, i):
+        v = ctypes.c_int64()
+        check(_lib.load().sipf_batch_get_step(self._h, int(i), ctypes.byref(v)))
+        return v.value
+
+    def positions(self, i):
+        out = torch.empty((self.P[i], 3), dtype=self.dtype, device=self.device)
+        check(_lib.load().sipf_batch_get_positions(self._h, int(i), ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def field(self, i, which):
+        H = self.H[i]
+        codes = {"rho": (_lib.SIPF_FIELD_RHO, (H, H, H)), "grad": (_lib.SIPF_FIELD_GRAD, (3, H, H, H)),
+                 "alpha": (_lib.SIPF_FIELD_ALPHA, (H, H, H // 2 + 1, 2))}
+        code, shape = codes[which]
+        out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        check(_lib.load().sipf_batch_get_field(self._h, int(i), code, ctypes.c_void_p(out.data_ptr()), 1))
+        return torch.view_as_complex(out) if which == "alpha" else out
+
+    def profile(self, enable=True):
+        check(_lib.load().sipf_batch_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        n = len(_lib.PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        check(_lib.load().sipf_batch_profile_read(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.PHASES)}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.load().sipf_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(X0, nsteps=8, stream=None, **params):
+    """Run the library's tile / chunk / re-sort search (sipf_autotune) for
+    positions X0 and parameters ``params``; returns (tuned params dict, ms/step)."""
+    p = _lib.default_params(**params)
+    X = torch.as_tensor(np.asarray(X0) if not torch.is_tensor(X0) else X0)
+    X = X.to(device="cuda", dtype=_dtype(p)).contiguous()
+    best = _lib.SipfParams()
+    ms = ctypes.c_double()
+    torch.cuda.synchronize()
+    check(_lib.load().sipf_autotune(ctypes.byref(p), int(X.shape[0]), ctypes.c_void_p(X.data_ptr()), 1,
+                                    int(nsteps), _stream_handle(stream), ctypes.byref(best), ctypes.byref(ms)))
+    return {"tile": best.tile, "chunk": best.chunk, "resort_every": best.resort_every}, ms.value
 
 
 def dbg_philox(ctr, seed, precision="fp32"):

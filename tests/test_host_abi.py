@@ -117,3 +117,99 @@ def test_load_of_missing_snapshot_is_eio(tmp_path):
     rc = L.load().sipf_load(str(tmp_path / "nope.bin").encode(), None, ctypes.byref(h))
     assert rc == L.SIPF_EIO
     assert h.value is None
+
+
+def _snap_header_type():
+    L = _lib()
+
+    class Hdr(ctypes.Structure):
+        _fields_ = [("magic", ctypes.c_char * 8), ("version", ctypes.c_uint32), ("tsize", ctypes.c_uint32),
+                    ("prm", L.SipfParams), ("P", ctypes.c_int64), ("n", ctypes.c_int64)]
+    return Hdr
+
+
+@pytest.mark.parametrize("damage", ["magic", "version", "truncated", "oversized", "tsize"])
+def test_load_of_corrupt_snapshot_is_eio(tmp_path, damage):
+    L = _lib()
+    Hdr = _snap_header_type()
+    p = L.default_params(H=8)
+    P = 10
+    h = Hdr(b"SIPFSNAP", 1, 4, p, P, 3)
+    payload = bytes(P * 3 * 4 + 8 * 8 * 5 * 2 * 4)
+    if damage == "magic":
+        h.magic = b"SIPFSNAQ"
+    elif damage == "version":
+        h.version = 2
+    elif damage == "tsize":
+        h.tsize = 8
+    elif damage == "truncated":
+        payload = payload[:-1]
+    elif damage == "oversized":
+        payload = payload + b"\0"
+    f = tmp_path / "snap.bin"
+    f.write_bytes(bytes(h) + payload)
+    out = ctypes.c_void_p()
+    rc = L.load().sipf_load(str(f).encode(), None, ctypes.byref(out))
+    assert rc == L.SIPF_EIO
+    assert out.value is None
+
+
+def _batch_init(L, prms, Ps, Xs, on_device=0):
+    n = len(prms)
+    arr = (L.SipfParams * max(n, 1))()
+    for i, p in enumerate(prms):
+        arr[i] = p
+    P = (ctypes.c_int64 * max(n, 1))(*Ps)
+    ptrs = (ctypes.c_void_p * max(n, 1))(*[X.ctypes.data for X in Xs])
+    h = ctypes.c_void_p()
+    rc = L.load().sipf_batch_init(n, arr, P, ptrs, on_device, None, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["empty", "mixed_precision", "mixed_scheme", "bad_instance", "bad_count",
+                                  "non_finite"])
+def test_batch_init_rejects_before_device(case):
+    L = _lib()
+    a = L.default_params(H=16)
+    b = L.default_params(H=32, chi=2.0, instance=1)
+    Xa = np.zeros((7, 3), np.float32)
+    Xb = np.zeros((9, 3), np.float32)
+    prms, Ps, Xs = [a, b], [7, 9], [Xa, Xb]
+    want = L.SIPF_EINVAL
+    if case == "empty":
+        prms, Ps, Xs = [], [], []
+    elif case == "mixed_precision":
+        prms[1] = L.default_params(H=32, precision="fp64")
+    elif case == "mixed_scheme":
+        prms[1] = L.default_params(H=32, scheme="em")
+    elif case == "bad_instance":
+        prms[1] = L.default_params(H=48)
+    elif case == "bad_count":
+        Ps[0] = 0
+    elif case == "non_finite":
+        Xb[4, 2] = np.inf
+        want = L.SIPF_ENUMERIC
+    rc, h = _batch_init(L, prms, Ps, Xs)
+    assert rc == want
+    assert h.value is None
+    assert L.load().sipf_last_error()
+
+
+def test_batch_and_tuning_null_handles():
+    L = _lib()
+    lib = L.load()
+    n = ctypes.c_int64()
+    assert lib.sipf_batch_run(None, 1) == L.SIPF_EINVAL
+    assert lib.sipf_batch_sync(None) == L.SIPF_EINVAL
+    assert lib.sipf_batch_get_step(None, 0, ctypes.byref(n)) == L.SIPF_EINVAL
+    assert lib.sipf_batch_get_positions(None, 0, None, 1) == L.SIPF_EINVAL
+    assert lib.sipf_batch_use_graphs(None, 1) == L.SIPF_EINVAL
+    assert lib.sipf_batch_destroy(None) == L.SIPF_OK
+    assert lib.sipf_use_graphs(None, 0) == L.SIPF_EINVAL
+    assert lib.sipf_get_params(None, None, None) == L.SIPF_EINVAL
+    p = L.default_params(H=12)
+    best = L.SipfParams()
+    ms = ctypes.c_double()
+    X = np.zeros((4, 3), np.float32)
+    assert lib.sipf_autotune(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, 4, None, ctypes.byref(best),
+                             ctypes.byref(ms)) == L.SIPF_EINVAL
