@@ -28,7 +28,8 @@ def algorithmic_bytes(phase, P, H, tsize):
     spec = 2 * tsize * H * H * (H // 2 + 1)   # one half spectrum
     grid = tsize * H ** 3
     if phase == "particles":
-        return 6 * tsize * P + grid + 3 * grid     # X read + write, deposit out, gradient in
+        # X read + write, particle id read (noise counter), deposit out, gradient in
+        return 6 * tsize * P + 4 * P + grid + 3 * grid
     if phase == "fwd_planes":
         return grid + spec                         # deposit in, y/z-transformed spectrum out
     if phase == "xpencils":
@@ -36,6 +37,31 @@ def algorithmic_bytes(phase, P, H, tsize):
     if phase == "inv_planes":
         return 3 * spec + 3 * grid                 # 3 spectra in, 3 gradient grids out
     return 0
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "particles_ring_h128_traffic.md")
+TRAFFIC_SOURCES = ["paper_2512_03452_amd/csrc/particles.hip", "paper_2512_03452_amd/csrc/pass_common.h",
+                   "paper_2512_03452_amd/csrc/common.h", "paper_2512_03452_amd/csrc/internal.h"]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of the particle pass from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary is missing or the kernel's sources changed since it was taken."""
+    if kernel != "particles" or workload != "fp32_ring_h128" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    import hashlib
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("TRAFFIC "):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("sources_sha256") == h.hexdigest():
+                    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
 
 
 def cpu_baseline(cfg, sample_P, steps):
@@ -139,6 +165,18 @@ def ensemble_throughput(pkg, workloads, np, torch, steps=40):
             "phases_us_per_step": {k: 1e3 * v[0] / 8 for k, v in prof.items() if v[1]}}
 
 
+def calibrate_copy(torch, nbytes=1 << 30, reps=5):
+    """A plain device copy of nbytes, reps times: the reference whose HBM
+    counters (FETCH_SIZE, WRITE_SIZE) scale those of the step's kernels."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -159,6 +199,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
 
     import paper_2512_03452_amd as pkg
     from paper_2512_03452_amd import workloads
@@ -218,7 +262,7 @@ def main():
                    "dt": params["dt"], "M0": params["M0"], "init": "torus R=0.5 sd=0.05"
                    if "ring" in args.workload else args.workload},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.workload),
                      "algorithmic_bytes_per_launch": abytes, "avg_launch_us": avg_s * 1e6},
         "step_roofline": {"algorithmic_bytes_per_step": sum(algorithmic_bytes(k, P, H, tsize) for k in phases),
                           "frac": sum(algorithmic_bytes(k, P, H, tsize) for k in phases) / (ms_per_step / 1e3)

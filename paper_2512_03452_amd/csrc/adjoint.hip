@@ -174,14 +174,19 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
 #pragma unroll
     for (int k = 0; k < APPT; ++k) {
         const int j = tid + k * APT;
+        const uint32_t jj = (uint32_t)(j < cnt ? j : cnt - 1);  // in-item index for every lane: branch-free loads
+        px[k] = gp(a.x + beg)[jj];
+        py[k] = gp(a.y + beg)[jj];
+        pz[k] = gp(a.z + beg)[jj];
+        pid[k] = gp(a.id + beg)[jj];
+        qx[k] = gp(a.xbx + beg)[jj];
+        qy[k] = gp(a.xby + beg)[jj];
+        qz[k] = gp(a.xbz + beg)[jj];
+    }
+#pragma unroll
+    for (int k = 0; k < APPT; ++k) {
+        const int j = tid + k * APT;
         if (j < cnt) {
-            px[k] = gp(a.x)[beg + j];
-            py[k] = gp(a.y)[beg + j];
-            pz[k] = gp(a.z)[beg + j];
-            pid[k] = gp(a.id)[beg + j];
-            qx[k] = gp(a.xbx)[beg + j];
-            qy[k] = gp(a.xby)[beg + j];
-            qz[k] = gp(a.xbz)[beg + j];
             const int cx = (((ifloor(px[k] * hl) & Hm) - rx + Hh) & Hm) - Hh;
             const int cy = (((ifloor(py[k] * hl) & Hm) - ry + Hh) & Hm) - Hh;
             const int cz = (((ifloor(pz[k] * hl) & Hm) - rz + Hh) & Hm) - Hh;
@@ -353,9 +358,9 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
             yb[1] += c * gy;
             yb[2] += c * gz;
         }
-        gp(a.xbx)[beg + j] = yb[0];
-        gp(a.xby)[beg + j] = yb[1];
-        gp(a.xbz)[beg + j] = yb[2];
+        gp(a.xbx + beg)[j] = yb[0];
+        gp(a.xby + beg)[j] = yb[1];
+        gp(a.xbz + beg)[j] = yb[2];
     }
     __syncthreads();
     if (gwin) {

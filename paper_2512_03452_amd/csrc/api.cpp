@@ -150,8 +150,10 @@ struct Group {
     bool prof = false;
     struct Mark {
         int phase;
-        hipEvent_t a, b;
+        hipEvent_t a, b;  // end of the previous phase (or a start marker), end of this phase
     };
+    std::vector<hipEvent_t> events;  // every event created for timing, released together
+    hipEvent_t last_stop = nullptr;  // end event of the last timed phase
     std::vector<Mark> marks;
     double prof_ms[SIPF_NPHASES] = {0};
     int64_t prof_n[SIPF_NPHASES] = {0};
@@ -249,23 +251,55 @@ template <typename T> const FieldDesc<T>* fdesc_dev(const Group* g, int slot) {
     return reinterpret_cast<const FieldDesc<T>*>(g->fdesc) + slot;
 }
 
-// Event bracket around one phase when timing is on.
+}  // namespace
+
+thread_local sipf::LaunchTiming* sipf::g_launch_timing = nullptr;
+
+namespace {
+
+// Events of one phase when timing is on.  Each phase's last kernel records
+// its end event as part of its dispatch (see launch_kernel); a phase is timed
+// from the end of the previous phase to its own end, so the interval holds
+// exactly the phase's kernels (kernels of one stream run back to back).  The
+// first phase after profiling starts, or after a read-out, begins at a marker.
 struct Timed {
     Group* g;
     int phase;
-    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTiming lt;
+    hipEvent_t a = nullptr;
     Timed(Group* grp, int ph) : g(grp), phase(ph) {
         if (!g->prof) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (hipEventCreate(&lt.stop) != hipSuccess) {
+            lt.stop = nullptr;
             g->prof = false;
             return;
         }
-        (void)hipEventRecord(a, g->stream);
+        g->events.push_back(lt.stop);
+        a = g->last_stop;
+        if (!a) {
+            if (hipEventCreate(&a) != hipSuccess) {
+                a = nullptr;
+                lt.stop = nullptr;
+                g->prof = false;
+                return;
+            }
+            g->events.push_back(a);
+            if (hipEventRecord(a, g->stream) != hipSuccess) {
+                lt.stop = nullptr;
+                g->prof = false;
+                return;
+            }
+            g->last_stop = a;
+        }
+        g_launch_timing = &lt;
     }
     ~Timed() {
-        if (!g->prof || !a) return;
-        (void)hipEventRecord(b, g->stream);
-        g->marks.push_back({phase, a, b});
+        if (!lt.stop) return;
+        g_launch_timing = nullptr;
+        if (lt.started) {
+            g->marks.push_back({phase, a, lt.stop});
+            g->last_stop = lt.stop;
+        }
     }
 };
 
@@ -374,8 +408,15 @@ int run_group(Group* g, int64_t nsteps) {
     return g->prec == SIPF_FP32 ? run_typed<float>(g, nsteps) : run_typed<double>(g, nsteps);
 }
 
+void release_marks(Group* g) {
+    for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+    g->events.clear();
+    g->last_stop = nullptr;
+    g->marks.clear();
+}
+
 int drain_marks(Group* g) {
-    if (g->marks.empty()) return SIPF_OK;
+    if (g->events.empty()) return SIPF_OK;
     HIPCHK(hipStreamSynchronize(g->stream));
     for (auto& m : g->marks) {
         float ms = 0.f;
@@ -383,10 +424,8 @@ int drain_marks(Group* g) {
             g->prof_ms[m.phase] += ms;
             g->prof_n[m.phase] += 1;
         }
-        (void)hipEventDestroy(m.a);
-        (void)hipEventDestroy(m.b);
     }
-    g->marks.clear();
+    release_marks(g);
     return SIPF_OK;
 }
 
@@ -485,7 +524,7 @@ template <typename T> int alloc_group(Group* g) {
     HIPCHK(hipMemset(g->counts, 0, (size_t)n * mk * sizeof(uint32_t)));
     HIPCHK(hipMemset(g->steps, 0, n * sizeof(uint32_t)));
     HIPCHK(hipMemset(g->errs, 0, n * sizeof(int)));
-    g->pgrid = std::min(g->items_cap, 1024);
+    g->pgrid = std::max(1, std::min(g->items_cap, particle_resident_blocks<T>(g->scheme, g->win_bytes)));
     return upload_descs<T>(g);
 }
 
@@ -553,10 +592,7 @@ int init_group(Group* g, const void* const* X0, int x0_on_device, const void* al
 
 void free_group(Group* g) {
     if (!g) return;
-    for (auto& m : g->marks) {
-        (void)hipEventDestroy(m.a);
-        (void)hipEventDestroy(m.b);
-    }
+    release_marks(g);
     for (auto& ge : g->gexec)
         if (ge) (void)hipGraphExecDestroy(ge);
     if (g->cap) (void)hipStreamDestroy(g->cap);

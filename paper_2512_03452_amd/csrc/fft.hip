@@ -474,7 +474,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
 // ---------------------------------------------------------------------------
 template <typename T, int H>
 static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(PLANE_THREADS), 0, s, fd, consume ? 1 : 0);
+    launch_kernel((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(PLANE_THREADS), 0, s, fd, consume ? 1 : 0);
     return hipGetLastError();
 }
 template <typename T, int H>
@@ -482,10 +482,10 @@ static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStr
     constexpr int NKB = (H / 2 + 1 + KB - 1) / KB;
     const dim3 g(H * NKB, count), b(PENCIL_THREADS);
     switch (mode) {
-        case MODE_STEP: hipLaunchKernelGGL((k_xpencils<T, H, MODE_STEP>), g, b, 0, s, fd); break;
-        case MODE_GRAD: hipLaunchKernelGGL((k_xpencils<T, H, MODE_GRAD>), g, b, 0, s, fd); break;
-        case MODE_ADJ_SRC: hipLaunchKernelGGL((k_xpencils<T, H, MODE_ADJ_SRC>), g, b, 0, s, fd); break;
-        case MODE_ADJ_ACC: hipLaunchKernelGGL((k_xpencils<T, H, MODE_ADJ_ACC>), g, b, 0, s, fd); break;
+        case MODE_STEP: launch_kernel((k_xpencils<T, H, MODE_STEP>), g, b, 0, s, fd); break;
+        case MODE_GRAD: launch_kernel((k_xpencils<T, H, MODE_GRAD>), g, b, 0, s, fd); break;
+        case MODE_ADJ_SRC: launch_kernel((k_xpencils<T, H, MODE_ADJ_SRC>), g, b, 0, s, fd); break;
+        case MODE_ADJ_ACC: launch_kernel((k_xpencils<T, H, MODE_ADJ_ACC>), g, b, 0, s, fd); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -493,7 +493,7 @@ static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStr
 template <typename T, int H>
 static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s) {
     static_assert(H % 8 == 0, "plane blocks are grouped by 8");
-    hipLaunchKernelGGL((k_inv_planes<T, H>), dim3(ncomp * H, count), dim3(PLANE_THREADS), 0, s, fd, ncomp);
+    launch_kernel((k_inv_planes<T, H>), dim3(ncomp * H, count), dim3(PLANE_THREADS), 0, s, fd, ncomp);
     return hipGetLastError();
 }
 

@@ -1,12 +1,36 @@
 // Internal interfaces between the host runtime and the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "common.h"
 
 namespace sipf {
+
+// Phase timing: while a LaunchTiming is installed on the calling thread, the
+// step's launches carry its events in their dispatch (the first launch records
+// `start` as it begins, every launch records `stop` as it ends), so the timed
+// interval holds the kernels and nothing else.
+struct LaunchTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    bool started = false;
+};
+extern thread_local LaunchTiming* g_launch_timing;
+
+template <typename F, typename... Args>
+inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args) {
+    LaunchTiming* t = g_launch_timing;
+    if (t) {
+        hipEvent_t first = t->started ? nullptr : t->start;
+        t->started = true;
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, first, t->stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+    }
+}
 
 // Everything the field passes (FFT, mode update, gradient) need for one
 // instance.  Spectral arrays are Hermitian half spectra H x H x (H/2+1) whose
@@ -150,5 +174,6 @@ int sort_max_keys();
 int particle_threads();
 int particle_chunk();
 int particle_window_bytes(bool fp64);
+template <typename T> int particle_resident_blocks(int scheme, int win_bytes);
 
 }  // namespace sipf

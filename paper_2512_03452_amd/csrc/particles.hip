@@ -249,15 +249,20 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
     const T hl = a.hl;
     T px[PPT], py[PPT], pz[PPT];
     uint32_t pid[PPT];
+    // uniform per-item bases and 32-bit offsets; lanes past the end load the
+    // item's last particle (cnt >= 1), so all loads issue without branches
+    const T* ix = a.x + beg;
+    const T* iy = a.y + beg;
+    const T* iz = a.z + beg;
+    const uint32_t* iid = a.id + beg;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int j = tid + k * PT;
-        if (j < cnt) {
-            px[k] = gp(a.x)[beg + j];
-            py[k] = gp(a.y)[beg + j];
-            pz[k] = gp(a.z)[beg + j];
-            if (PUSH) pid[k] = gp(a.id)[beg + j];
-        }
+        const uint32_t jj = (uint32_t)(j < cnt ? j : cnt - 1);
+        px[k] = gp(ix)[jj];
+        py[k] = gp(iy)[jj];
+        pz[k] = gp(iz)[jj];
+        if (PUSH) pid[k] = gp(iid)[jj];
     }
     const bool windows = cnt >= MIN_WINDOW_ITEM;
     int rx = 0, ry = 0, rz = 0;
@@ -472,9 +477,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
             const T ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
             const T nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
-            gp(a.x)[beg + j] = nx;
-            gp(a.y)[beg + j] = ny;
-            gp(a.z)[beg + j] = nz;
+            gp(a.x + beg)[j] = nx;
+            gp(a.y + beg)[j] = ny;
+            gp(a.z + beg)[j] = nz;
             if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(a.err, 1);
         }
     }
@@ -495,6 +500,26 @@ __global__ __launch_bounds__(PT) void k_particles(const PartDesc<T>* __restrict_
     }
 }
 
+// Workgroups of the fused particle pass that are resident on the whole device
+// at once (occupancy from its registers and its LDS window): the persistent
+// grid is sized to this, so that no workgroup waits for another to finish
+// before it can start its share of the work items.
+template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = scheme == SIPF_STRANG
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &per_cu, (const void*)k_particles<T, true, true, SIPF_STRANG>, PT, win_bytes)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &per_cu, (const void*)k_particles<T, true, true, SIPF_EM>, PT, win_bytes);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || per_cu < 1 || cus < 1) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return per_cu * cus;
+}
+
 template <typename T>
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
                             bool push, int scheme, int win_bytes, hipStream_t s) {
@@ -503,16 +528,16 @@ hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const 
     const dim3 g(grid), b(PT);
     if (deposit && push) {
         if (scheme == SIPF_STRANG)
-            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, true, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
         else
-            hipLaunchKernelGGL((k_particles<T, true, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, true, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (deposit) {
-        hipLaunchKernelGGL((k_particles<T, true, false, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
+        launch_kernel((k_particles<T, true, false, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (push) {
         if (scheme == SIPF_STRANG)
-            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, false, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
         else
-            hipLaunchKernelGGL((k_particles<T, false, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, false, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
     }
     return hipGetLastError();
 }
@@ -685,11 +710,11 @@ hipError_t launch_sort(const PartDesc<T>* src, const PartDesc<T>* dst, const Sor
                        WorkItem* items, int* nitems, int chunk, hipStream_t s) {
     if (chunk <= 0 || chunk > CH) chunk = CH;
     if (ninst < 1 || ninst > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_tile_hist<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
-    hipLaunchKernelGGL((k_tile_scan<T>), dim3(ninst), dim3(1024), 0, s, src, counts, cursor, seg, seg_off, seg_n,
+    launch_kernel((k_tile_hist<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+    launch_kernel((k_tile_scan<T>), dim3(ninst), dim3(1024), 0, s, src, counts, cursor, seg, seg_off, seg_n,
                        chunk);
-    hipLaunchKernelGGL(k_items_combine, dim3(1), dim3(1024), 0, s, seg, seg_off, seg_n, ninst, items, nitems);
-    hipLaunchKernelGGL((k_tile_scatter<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
+    launch_kernel(k_items_combine, dim3(1), dim3(1024), 0, s, seg, seg_off, seg_n, ninst, items, nitems);
+    launch_kernel((k_tile_scatter<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
     return hipGetLastError();
 }
 
@@ -788,6 +813,7 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 }
 
 #define SIPF_INST(T)                                                                                              \
+    template int particle_resident_blocks<T>(int, int);                                                           \
     template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, const int*, int, bool, bool, int, \
                                             int, hipStream_t);                                                    \
     template hipError_t launch_sort<T>(const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,        \
