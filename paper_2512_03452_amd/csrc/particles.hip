@@ -29,6 +29,26 @@ constexpr int SORT_CHUNK = SORT_THREADS * SORT_PER_THREAD;
 constexpr int MAX_KEYS = 4096;     // (H / tile)^3 <= 16^3
 constexpr int MIN_WINDOW_ITEM = 64;  // smaller items deposit and gather straight from global memory
 
+// Push phase: re-read each particle (1) or keep the item's particles in
+// registers from the load phase (0); unroll factor of the push loop.
+#ifndef SIPF_RELOAD
+#define SIPF_RELOAD 1
+#endif
+#ifndef SIPF_PUSH_UNROLL
+#define SIPF_PUSH_UNROLL 8
+#endif
+// Minimum waves per SIMD the register allocation must leave room for
+// (0: the compiler's choice).  Six waves per SIMD hold three 512-thread
+// workgroups per CU, which the LDS windows also allow.
+#ifndef SIPF_PART_WAVES
+#define SIPF_PART_WAVES 6
+#endif
+#if SIPF_PART_WAVES > 0
+#define SIPF_PART_ATTR __attribute__((amdgpu_waves_per_eu(SIPF_PART_WAVES)))
+#else
+#define SIPF_PART_ATTR
+#endif
+
 int particle_threads() { return PT; }
 int particle_chunk() { return CH; }
 int sort_max_keys() { return MAX_KEYS; }
@@ -146,6 +166,9 @@ template <typename T> struct Win;
 #endif
 template <> struct Win<float> { static constexpr int D = SIPF_WIN_D, G = SIPF_WIN_G; };
 template <> struct Win<double> { static constexpr int D = 15, G = 11; };
+// a window plane must fit one workgroup (plane_map)
+static_assert(Win<float>::D * Win<float>::D <= PT && Win<double>::D * Win<double>::D <= PT, "window plane");
+static_assert(Win<float>::G * Win<float>::G <= PT && Win<double>::G * Win<double>::G <= PT, "window plane");
 
 // LDS bytes the particle pass needs per workgroup (the larger fast window)
 int particle_window_bytes(bool fp64) {
@@ -155,6 +178,24 @@ int particle_window_bytes(bool fp64) {
     const int g64 = 3 * Win<double>::G * Win<double>::G * Win<double>::G * 8;
     const int b = fp64 ? (d64 > g64 ? d64 : g64) : (d32 > g32 ? d32 : g32);
     return (b + 255) / 256 * 256;
+}
+
+// Thread -> (i0, j, k) for walking a window of ey x ez columns along i with
+// stride nrep = PT / (ey ez) (ey ez <= PT); threads beyond nrep ey ez get
+// i0 = INT_MAX and do nothing.
+__device__ __forceinline__ void plane_map(int ey, int ez, int& i0, int& j, int& k, int& nrep) {
+    const int pl = ey * ez;
+    nrep = PT / pl;
+    const int t = threadIdx.x;
+    j = 0;
+    k = 0;
+    if (t < nrep * pl) {
+        int r;
+        divmod_small(t, pl, 1.0f / (float)pl, i0, r);
+        divmod_small(r, ez, 1.0f / (float)ez, j, k);
+    } else {
+        i0 = INT_MAX;
+    }
 }
 
 // Deposit of one particle into a fixed-stride fixed-point window whose node
@@ -262,7 +303,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         px[k] = gp(ix)[jj];
         py[k] = gp(iy)[jj];
         pz[k] = gp(iz)[jj];
+#if !SIPF_RELOAD
         if (PUSH) pid[k] = gp(iid)[jj];
+#endif
     }
     const bool windows = cnt >= MIN_WINDOW_ITEM;
     int rx = 0, ry = 0, rz = 0;
@@ -302,13 +345,10 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         I* win = reinterpret_cast<I*>(lds);
         const int ox = (rx + sh[0] - 1) & Hm, oy = (ry + sh[1] - 1) & Hm, oz = (rz + sh[2] - 1) & Hm;
         const int ex = sh[3] - sh[0] + 4, ey = sh[4] - sh[1] + 4, ez = sh[5] - sh[2] + 4;
-        const int ne = ex * ey * ez;
-        const float inv_ey = 1.0f / (float)ey, inv_ez = 1.0f / (float)ez;
-        for (int e = tid; e < ne; e += PT) {
-            int i, j, k;
-            unflatten3(e, ey, ez, inv_ez, inv_ey, i, j, k);
-            win[(i * D + j) * D + k] = 0;
-        }
+        // each thread owns one (j, k) column of the window and walks i
+        int i0, wj, wk, nrep;
+        plane_map(ey, ez, i0, wj, wk, nrep);
+        for (int i = i0; i < ex; i += nrep) win[(i * D + wj) * D + wk] = 0;
         const int need = (11 * cnt + 7) / 8;
         const int S = min(Magic<T>::MAXS, Fixed<T>::BITS - (32 - __clz(need)));
         const T scale = (T)ldexp(1.0, S);
@@ -318,13 +358,11 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             if (tid + k * PT < cnt) deposit_fast<T>(win, px[k], py[k], pz[k], hl, Hm, ox, oy, oz, scale);
         __syncthreads();
         const T back = a.wmass * (T)ldexp(1.0, -S);
-        for (int e = tid; e < ne; e += PT) {
-            int i, j, k;
-            unflatten3(e, ey, ez, inv_ez, inv_ey, i, j, k);
-            const I v = win[(i * D + j) * D + k];
-            if (v != 0) {
-                const int node = ((((ox + i) & Hm) * H) + ((oy + j) & Hm)) * H + ((oz + k) & Hm);
-                gatomic_add(a.phi + node, (T)v * back);
+        {
+            const int nyz = ((oy + wj) & Hm) * H + ((oz + wk) & Hm);
+            for (int i = i0; i < ex; i += nrep) {
+                const I v = win[(i * D + wj) * D + wk];
+                if (v != 0) gatomic_add(a.phi + ((ox + i) & Hm) * H * H + nyz, (T)v * back);
             }
         }
         __syncthreads();  // the window memory is reused below
@@ -395,13 +433,12 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
                 Wz = sh[5] - sh[2] + 2 + 2 * m;
                 T* Gw = reinterpret_cast<T*>(lds);
                 const int H3 = H * H * H;
-                const int ne = Wx * Wy * Wz;
-                const float inv_ey = 1.0f / (float)Wy, inv_ez = 1.0f / (float)Wz;
-                for (int e = tid; e < ne; e += PT) {
-                    int i, j, k;
-                    unflatten3(e, Wy, Wz, inv_ez, inv_ey, i, j, k);
-                    const int node = ((((ox + i) & Hm) * H) + ((oy + j) & Hm)) * H + ((oz + k) & Hm);
-                    const int o = (i * G + j) * G + k;
+                int i0, wj, wk, nrep;
+                plane_map(Wy, Wz, i0, wj, wk, nrep);
+                const int nyz = ((oy + wj) & Hm) * H + ((oz + wk) & Hm);
+                for (int i = i0; i < Wx; i += nrep) {
+                    const int node = ((ox + i) & Hm) * H * H + nyz;
+                    const int o = (i * G + wj) * G + wk;
                     Gw[o] = gp(a.G)[node];
                     Gw[G3 + o] = gp(a.G)[H3 + node];
                     Gw[2 * G3 + o] = gp(a.G)[2 * H3 + node];
@@ -435,21 +472,28 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         }
         const uint32_t n = *a.step + 1u;
         const size_t H3 = (size_t)H * H * H;
-#pragma unroll
+#pragma unroll SIPF_PUSH_UNROLL
         for (int k = 0; k < PPT; ++k) {
             const int j = tid + k * PT;
             if (j >= cnt) continue;
+#if SIPF_RELOAD
+            // re-read from L2 rather than holding eight particles in registers
+            const T x = gp(ix)[j], y = gp(iy)[j], z = gp(iz)[j];
+            const uint32_t idk = gp(iid)[j];
+#else
             const T x = px[k], y = py[k], z = pz[k];
+            const uint32_t idk = pid[k];
+#endif
             T yx, yy, yz, w0, w1, w2;
             if (SCHEME == SIPF_STRANG) {
                 T m0, m1, m2;
-                noise3<T>(pid[k], n, 0u, a.inst, a.k0, a.k1, m0, m1, m2);
-                noise3<T>(pid[k], n, 1u, a.inst, a.k0, a.k1, w0, w1, w2);
+                noise3<T>(idk, n, 0u, a.inst, a.k0, a.k1, m0, m1, m2);
+                noise3<T>(idk, n, 1u, a.inst, a.k0, a.k1, w0, w1, w2);
                 yx = x + a.s * m0;
                 yy = y + a.s * m1;
                 yz = z + a.s * m2;
             } else {
-                noise3<T>(pid[k], n, 0u, a.inst, a.k0, a.k1, w0, w1, w2);
+                noise3<T>(idk, n, 0u, a.inst, a.k0, a.k1, w0, w1, w2);
                 yx = x;
                 yy = y;
                 yz = z;
@@ -487,7 +531,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
 
 // Persistent over the work items listed by the last sort (count in *nitems).
 template <typename T, bool DEP, bool PUSH, int SCHEME>
-__global__ __launch_bounds__(PT) void k_particles(const PartDesc<T>* __restrict__ pds,
+__global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<T>* __restrict__ pds,
                                                   const WorkItem* __restrict__ items, const int* __restrict__ nitems,
                                                   int win_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -603,11 +647,12 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
     uint32_t* cur = cursor + (size_t)inst * MAX_KEYS;
     WorkItem* items = seg + seg_off[inst];
     const int tid = threadIdx.x;
-    const int per = (nk + 1023) / 1024;
-    uint32_t loc[MAX_KEYS / 1024], nit[MAX_KEYS / 1024];
+    constexpr int PER = MAX_KEYS / 1024;  // keys per thread, consecutive in key order
+    uint32_t loc[PER], nit[PER];
     uint32_t sum = 0, isum = 0;
-    for (int j = 0; j < per; ++j) {
-        const int i = tid * per + j;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = tid * PER + j;
         loc[j] = i < nk ? cnt[i] : 0u;
         nit[j] = (loc[j] + chunk - 1) / chunk;
         sum += loc[j];
@@ -616,19 +661,25 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
     uint32_t total, itotal;
     uint32_t run = block_exclusive_scan(sum, part, total);
     uint32_t irun = block_exclusive_scan(isum, part, itotal);
-    for (int j = 0; j < per; ++j) {
-        const int i = tid * per + j;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = tid * PER + j;
         if (i < nk) {
             cur[i] = run;
             cnt[i] = 0u;
-            for (uint32_t k = 0; k < nit[j]; ++k) {
-                const uint32_t b0 = (uint32_t)(((uint64_t)k * loc[j]) / nit[j]);
-                const uint32_t b1 = (uint32_t)(((uint64_t)(k + 1) * loc[j]) / nit[j]);
-                WorkItem w;
-                w.beg = (int64_t)run + b0;
-                w.cnt = (int32_t)(b1 - b0);
-                w.inst = inst;
-                items[irun + k] = w;
+            if (nit[j] > 0) {
+                // nit items: the first rem of base + 1 particles, the rest of base
+                const uint32_t base = loc[j] / nit[j], rem = loc[j] - base * nit[j];
+                uint32_t b = run;
+                for (uint32_t k = 0; k < nit[j]; ++k) {
+                    const uint32_t c = base + (k < rem ? 1u : 0u);
+                    WorkItem w;
+                    w.beg = (int64_t)b;
+                    w.cnt = (int32_t)c;
+                    w.inst = inst;
+                    items[irun + k] = w;
+                    b += c;
+                }
             }
         }
         run += loc[j];
