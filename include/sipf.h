@@ -20,6 +20,15 @@
  * Both branches of step n read the state after step n-1 (Algorithm 4), so the
  * gradient gathered in step n is that of alpha^(n-1).
  *
+ * Noise (the paper fixes no generator): particle id (its index in X0) at
+ * step n draws one Philox4x32-10 block with key (low, high 32 bits of seed)
+ * and counter (id, n, 0, instance).  Its 128 bits give six 21-bit fields
+ * f_i = r_i >> 11 (i < 4), f_4 = (r0 & 0x7FF) << 10 | (r1 & 0x3FF),
+ * f_5 = (r2 & 0x7FF) << 10 | (r3 & 0x3FF), uniforms u = (f + 1/2) 2^-21 and
+ * three Box-Muller pairs z = sqrt(-2 ln u_2j) (cos, sin)(2 pi u_2j+1).
+ * Split step: W^- = sqrt(mu tau) (z0, z1, z2), W^+ = sqrt(mu tau) (z3, z4, z5);
+ * Euler-Maruyama: W = sqrt(2 mu tau) (z0, z1, z2).
+ *
  * Conventions for every function below:
  *   - Return value: SIPF_OK (0) or a negative SIPF_E* code.  The message of the
  *     last failure on the calling thread is returned by sipf_last_error().
@@ -258,10 +267,10 @@ int sipf_batch_destroy(sipf_batch* b);
  * Test entry points: each exposes one piece of the step on caller data.
  * All pointers are device pointers; each call synchronises the given stream.
  *
- * sipf_dbg_philox: for count counters ctr (count x 4 uint32: id, n, slot,
- *   instance) under key seed, writes the raw Philox4x32-10 outputs
- *   (count x 4 uint32) and the normal 3-vector of the stream contract
- *   (count x 3 in the given precision).
+ * sipf_dbg_philox: for count counters ctr (count x 4 uint32: id, n, 0,
+ *   instance in the step's stream; any words are accepted) under key seed,
+ *   writes the raw Philox4x32-10 outputs (count x 4 uint32) and the six
+ *   normals of the stream contract (count x 6 in the given precision).
  * sipf_dbg_cells: the integer cell g = floor(X H / L) (count x 3 int32) that
  *   the particle pass uses for positions X (count x 3, precision of prm).
  * sipf_dbg_deposit: phi = I(sum_p w delta_{X_p}) with w = M0/count on the

@@ -18,12 +18,17 @@ implement the same counter-based generator from its published definition:
 The stream contract (shared with the GPU library):
 
 * key      = (low 32 bits of seed, high 32 bits of seed)
-* counter  = (particle id, step n, slot, instance); slot 0 is W^- (or the
-             single Euler-Maruyama increment), slot 1 is W^+.
-* uniforms u = ((r >> 9) + 1/2) * 2^-23, an exact float32 and float64 value in
-             [2^-24, 1 - 2^-24]: both sides see identical uniforms.
-* normals  (z0, z1) = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
-           z2       = sqrt(-2 ln u2)  cos 2 pi u3;  one call yields one 3-vector.
+* counter  = (particle id, step n, 0, instance): one call per particle and step.
+* fields   the four outputs r0..r3 give six 21-bit fields
+             f_i = r_i >> 11 (i = 0..3),
+             f_4 = ((r0 & 0x7FF) << 10) | (r1 & 0x3FF),
+             f_5 = ((r2 & 0x7FF) << 10) | (r3 & 0x3FF).
+* uniforms u_i = (f_i + 1/2) 2^-21, an exact float32 and float64 value in
+             [2^-22, 1 - 2^-22]: both sides see identical uniforms.
+* normals  (z_2j, z_2j+1) = sqrt(-2 ln u_2j) (cos 2 pi u_2j+1, sin 2 pi u_2j+1),
+             j = 0, 1, 2.
+* increments  split step: W^- from (z0, z1, z2), W^+ from (z3, z4, z5);
+             Euler-Maruyama: W from (z0, z1, z2).
 """
 
 import numpy as np
@@ -34,10 +39,6 @@ W0 = np.uint64(0x9E3779B9)
 W1 = np.uint64(0xBB67AE85)
 _MASK = np.uint64(0xFFFFFFFF)
 _S32 = np.uint64(32)
-
-SLOT_MINUS = 0  # W^- of the split step, or the single Euler-Maruyama increment
-SLOT_PLUS = 1   # W^+ of the split step
-
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):
     """Ten Philox4x32 rounds; all arguments broadcastable integer arrays < 2^32.
@@ -66,25 +67,35 @@ def seed_key(seed):
     return seed & 0xFFFFFFFF, seed >> 32
 
 
-def uniforms(r):
-    """Map 32-bit outputs to uniforms ((r >> 9) + 1/2) 2^-23 (exact in fp32)."""
-    r = np.asarray(r, dtype=np.uint64)
-    return ((r >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+def fields21(r0, r1, r2, r3):
+    """The six 21-bit fields of one Philox output (uint64 arrays)."""
+    r = [np.asarray(v, dtype=np.uint64) for v in (r0, r1, r2, r3)]
+    s11, m11, m10 = np.uint64(11), np.uint64(0x7FF), np.uint64(0x3FF)
+    f = [v >> s11 for v in r]
+    f.append(((r[0] & m11) << np.uint64(10)) | (r[1] & m10))
+    f.append(((r[2] & m11) << np.uint64(10)) | (r[3] & m10))
+    return f
 
 
-def normals3(ids, n, slot, seed, instance=0):
-    """Standard-normal 3-vectors for particle ids at step n, shape (len(ids), 3).
+def uniforms21(f):
+    """(f + 1/2) 2^-21 for 21-bit fields f (exact in float32)."""
+    return (np.asarray(f, dtype=np.uint64).astype(np.float64) + 0.5) * 2.0 ** -21
 
-    One Philox call per particle: counter (id, n, slot, instance).
-    """
-    ids = np.asarray(ids, dtype=np.uint64)
+
+def normals6_counter(c0, c1, c2, c3, seed):
+    """Six standard normals per counter (c0, c1, c2, c3), shape (..., 6)."""
     k0, k1 = seed_key(seed)
-    r0, r1, r2, r3 = philox4x32_10(ids, n, slot, instance, k0, k1)
-    u0, u1, u2, u3 = uniforms(r0), uniforms(r1), uniforms(r2), uniforms(r3)
-    rad0 = np.sqrt(-2.0 * np.log(u0))
-    rad2 = np.sqrt(-2.0 * np.log(u2))
-    z = np.empty(ids.shape + (3,), dtype=np.float64)
-    z[..., 0] = rad0 * np.cos(2.0 * np.pi * u1)
-    z[..., 1] = rad0 * np.sin(2.0 * np.pi * u1)
-    z[..., 2] = rad2 * np.cos(2.0 * np.pi * u3)
+    u = [uniforms21(f) for f in fields21(*philox4x32_10(c0, c1, c2, c3, k0, k1))]
+    z = np.empty(np.broadcast(*u).shape + (6,), dtype=np.float64)
+    for j in range(3):
+        rad = np.sqrt(-2.0 * np.log(u[2 * j]))
+        z[..., 2 * j] = rad * np.cos(2.0 * np.pi * u[2 * j + 1])
+        z[..., 2 * j + 1] = rad * np.sin(2.0 * np.pi * u[2 * j + 1])
     return z
+
+
+def normals6(ids, n, seed, instance=0):
+    """The six normals of particle ids at step n, shape (len(ids), 6): counter
+    (id, n, 0, instance)."""
+    ids = np.asarray(ids, dtype=np.uint64)
+    return normals6_counter(ids, n, 0, instance, seed)

@@ -213,14 +213,14 @@ def push(X, G, n, prm, ids):
     H, L, tau = prm.H, prm.L, prm.dt
     if prm.scheme == "strang":
         s = math.sqrt(prm.mu * tau)
-        Zm = philox.normals3(ids, n, philox.SLOT_MINUS, prm.seed, prm.instance)
-        Zp = philox.normals3(ids, n, philox.SLOT_PLUS, prm.seed, prm.instance)
+        Z6 = philox.normals6(ids, n, prm.seed, prm.instance)
+        Zm, Zp = Z6[:, 0:3], Z6[:, 3:6]
         Y = X + s * Zm
         v = interp(G, Y, H, L, prm.g2p_order)
         return wrap(Y + prm.chi * tau * v + s * Zp, L), Y, v, Zm, Zp
     if prm.scheme == "em":
         s = math.sqrt(2.0 * prm.mu * tau)
-        Z = philox.normals3(ids, n, philox.SLOT_MINUS, prm.seed, prm.instance)
+        Z = philox.normals6(ids, n, prm.seed, prm.instance)[:, 0:3]
         v = interp(G, X, H, L, prm.g2p_order)
         return wrap(X + prm.chi * tau * v + s * Z, L), X, v, Z, None
     raise ValueError("scheme must be 'strang' or 'em'")
@@ -313,8 +313,8 @@ def sipf_direct_step(X, alpha, n, prm, ids=None, use_filter=True):
     alpha_new = mode_update(alpha, beta, prm)
     tau, L = prm.dt, prm.L
     s = math.sqrt(prm.mu * tau)
-    Zm = philox.normals3(ids, n, philox.SLOT_MINUS, prm.seed, prm.instance)
-    Zp = philox.normals3(ids, n, philox.SLOT_PLUS, prm.seed, prm.instance)
+    Z6 = philox.normals6(ids, n, prm.seed, prm.instance)
+    Zm, Zp = Z6[:, 0:3], Z6[:, 3:6]
     Y = X + s * Zm
     v = direct_gradient(alpha, Y, prm, use_filter)
     return wrap(Y + prm.chi * tau * v + s * Zp, L), alpha_new

@@ -270,14 +270,18 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
         if (j >= cnt) continue;
         const T X[3] = {px[k], py[k], pz[k]};
         const T xb[3] = {qx[k], qy[k], qz[k]};
-        T zm[3], zp[3], Y[3];
+        T zm[3], zp[3], Y[3], zn[6];
         if (SCHEME == SIPF_STRANG) {
-            noise3<T>(pid[k], a.n, 0u, a.inst, a.k0, a.k1, zm[0], zm[1], zm[2]);
-            noise3<T>(pid[k], a.n, 1u, a.inst, a.k0, a.k1, zp[0], zp[1], zp[2]);
-            for (int d = 0; d < 3; ++d) Y[d] = X[d] + a.s * zm[d];
-        } else {
-            noise3<T>(pid[k], a.n, 0u, a.inst, a.k0, a.k1, zp[0], zp[1], zp[2]);
+            noise6<3, T>(pid[k], a.n, a.inst, a.k0, a.k1, zn);
             for (int d = 0; d < 3; ++d) {
+                zm[d] = zn[d];
+                zp[d] = zn[3 + d];
+                Y[d] = X[d] + a.s * zm[d];
+            }
+        } else {
+            noise6<2, T>(pid[k], a.n, a.inst, a.k0, a.k1, zn);
+            for (int d = 0; d < 3; ++d) {
+                zp[d] = zn[d];
                 zm[d] = 0;
                 Y[d] = X[d];
             }

@@ -202,8 +202,8 @@ template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
     d.k0 = (uint32_t)p.seed;
     d.k1 = (uint32_t)(p.seed >> 32);
     d.inst = p.instance;
-    // |W^-| <= s max|z| with max|z| = sqrt(-2 ln 2^-24) (uniforms are >= 2^-24)
-    d.gmargin = p.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.7677 * (double)d.hl) : 0;
+    // |W^-| <= s max|z| with max|z| = sqrt(-2 ln 2^-22) = 5.5176 (uniforms are >= 2^-22)
+    d.gmargin = p.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.52 * (double)d.hl) : 0;
     d.tshift = ilog2(I.tile);
     const int nt = I.H / I.tile;
     d.nkeys = nt * nt * nt;

@@ -41,9 +41,10 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.v0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.v2;
         u32x4 n;
-        n.v0 = (uint32_t)(p1 >> 32) ^ c.v1 ^ k0;
+        // three-input XOR in one gfx950 v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
+        n.v0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.v1, k0, 0x96);
         n.v1 = (uint32_t)p1;
-        n.v2 = (uint32_t)(p0 >> 32) ^ c.v3 ^ k1;
+        n.v2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.v3, k1, 0x96);
         n.v3 = (uint32_t)p0;
         c = n;
         k0 += 0x9E3779B9u;
@@ -52,44 +53,58 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-// Uniform in [2^-24, 1 - 2^-24]: ((r >> 9) + 1/2) 2^-23, exact in float and double.
-template <typename T> __device__ __forceinline__ T u01(uint32_t r) {
-    return ((T)(r >> 9) + (T)0.5) * (T)1.1920928955078125e-07;  // 2^-23
+// One Philox call gives six 21-bit fields (126 of its 128 bits):
+//   f_i = r_i >> 11 (i < 4), f_4 = (r0 & 0x7FF) << 10 | (r1 & 0x3FF),
+//   f_5 = (r2 & 0x7FF) << 10 | (r3 & 0x3FF),
+// uniforms u = (f + 1/2) 2^-21 in [2^-22, 1 - 2^-22] (exact in float), and
+// three Box-Muller pairs (z_2j, z_2j+1) = sqrt(-2 ln u_2j) (cos, sin)(2 pi u_2j+1).
+// NPAIR = 3 gives all six normals, NPAIR = 2 the first four.
+template <typename T> __device__ __forceinline__ T u01_21(uint32_t f) {
+    return ((T)f + (T)0.5) * (T)4.76837158203125e-07;  // 2^-21
 }
-
-// Box-Muller: (z0, z1) = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1),
-//             z2       = sqrt(-2 ln u2) cos 2 pi u3.
+__device__ __forceinline__ void fields21(u32x4 r, uint32_t f[6]) {
+    f[0] = r.v0 >> 11;
+    f[1] = r.v1 >> 11;
+    f[2] = r.v2 >> 11;
+    f[3] = r.v3 >> 11;
+    f[4] = ((r.v0 & 0x7FFu) << 10) | (r.v1 & 0x3FFu);
+    f[5] = ((r.v2 & 0x7FFu) << 10) | (r.v3 & 0x3FFu);
+}
 // float: the hardware transcendentals (v_log_f32 is log2; v_sin/v_cos take
-// revolutions, so cos 2 pi u is one instruction); u in [2^-24, 1) keeps every
+// revolutions, so cos 2 pi u is one instruction); u in [2^-22, 1) keeps every
 // argument in range.
-__device__ __forceinline__ void normals3(u32x4 r, float& z0, float& z1, float& z2) {
-    const float u0 = u01<float>(r.v0), u1 = u01<float>(r.v1);
-    const float u2 = u01<float>(r.v2), u3 = u01<float>(r.v3);
+template <int NPAIR> __device__ __forceinline__ void normals6(u32x4 r, float z[6]) {
+    uint32_t f[6];
+    fields21(r, f);
     constexpr float m2ln2 = -1.3862943611198906f;  // -2 ln 2
-    const float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
-    const float b = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
-    z0 = a * __builtin_amdgcn_cosf(u1);
-    z1 = a * __builtin_amdgcn_sinf(u1);
-    z2 = b * __builtin_amdgcn_cosf(u3);
+#pragma unroll
+    for (int j = 0; j < NPAIR; ++j) {
+        const float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01_21<float>(f[2 * j])));
+        const float b = u01_21<float>(f[2 * j + 1]);
+        z[2 * j] = a * __builtin_amdgcn_cosf(b);
+        z[2 * j + 1] = a * __builtin_amdgcn_sinf(b);
+    }
 }
-__device__ __forceinline__ void normals3(u32x4 r, double& z0, double& z1, double& z2) {
-    const double u0 = u01<double>(r.v0), u1 = u01<double>(r.v1);
-    const double u2 = u01<double>(r.v2), u3 = u01<double>(r.v3);
-    const double a = sqrt(-2.0 * log(u0));
-    const double b = sqrt(-2.0 * log(u2));
-    double s1, c1;
-    sincospi(2.0 * u1, &s1, &c1);
-    z0 = a * c1;
-    z1 = a * s1;
-    z2 = b * cospi(2.0 * u3);
+template <int NPAIR> __device__ __forceinline__ void normals6(u32x4 r, double z[6]) {
+    uint32_t f[6];
+    fields21(r, f);
+#pragma unroll
+    for (int j = 0; j < NPAIR; ++j) {
+        const double a = sqrt(-2.0 * log(u01_21<double>(f[2 * j])));
+        double s, c;
+        sincospi(2.0 * u01_21<double>(f[2 * j + 1]), &s, &c);
+        z[2 * j] = a * c;
+        z[2 * j + 1] = a * s;
+    }
 }
 
-// Normal 3-vector of particle id at step n, slot, instance (key = seed).
-template <typename T>
-__device__ __forceinline__ void noise3(uint32_t id, uint32_t n, uint32_t slot, uint32_t inst,
-                                       uint32_t k0, uint32_t k1, T& z0, T& z1, T& z2) {
-    u32x4 c{id, n, slot, inst};
-    normals3(philox4x32_10(c, k0, k1), z0, z1, z2);
+// The normals of particle id at step n (counter (id, n, 0, instance), key =
+// seed): split step W^- from z[0..2] and W^+ from z[3..5]; Euler-Maruyama W
+// from z[0..2] (NPAIR = 2).
+template <int NPAIR, typename T>
+__device__ __forceinline__ void noise6(uint32_t id, uint32_t n, uint32_t inst, uint32_t k0, uint32_t k1, T z[6]) {
+    u32x4 c{id, n, 0u, inst};
+    normals6<NPAIR>(philox4x32_10(c, k0, k1), z);
 }
 
 // ---------------------------------------------------------------------------

@@ -485,15 +485,20 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             const uint32_t idk = pid[k];
 #endif
             T yx, yy, yz, w0, w1, w2;
+            T zn[6];
             if (SCHEME == SIPF_STRANG) {
-                T m0, m1, m2;
-                noise3<T>(idk, n, 0u, a.inst, a.k0, a.k1, m0, m1, m2);
-                noise3<T>(idk, n, 1u, a.inst, a.k0, a.k1, w0, w1, w2);
-                yx = x + a.s * m0;
-                yy = y + a.s * m1;
-                yz = z + a.s * m2;
+                noise6<3, T>(idk, n, a.inst, a.k0, a.k1, zn);
+                yx = x + a.s * zn[0];
+                yy = y + a.s * zn[1];
+                yz = z + a.s * zn[2];
+                w0 = zn[3];
+                w1 = zn[4];
+                w2 = zn[5];
             } else {
-                noise3<T>(idk, n, 0u, a.inst, a.k0, a.k1, w0, w1, w2);
+                noise6<2, T>(idk, n, a.inst, a.k0, a.k1, zn);
+                w0 = zn[0];
+                w1 = zn[1];
+                w2 = zn[2];
                 yx = x;
                 yy = y;
                 yz = z;
@@ -848,11 +853,9 @@ __global__ void k_philox_dbg(uint32_t k0, uint32_t k1, int64_t n, const uint32_t
         raw[4 * i + 3] = r.v3;
     }
     if (normals) {
-        T z0, z1, z2;
-        normals3(r, z0, z1, z2);
-        normals[3 * i] = z0;
-        normals[3 * i + 1] = z1;
-        normals[3 * i + 2] = z2;
+        T z[6];
+        normals6<3>(r, z);
+        for (int j = 0; j < 6; ++j) normals[6 * i + j] = z[j];
     }
 }
 template <typename T>

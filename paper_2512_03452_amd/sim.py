@@ -276,12 +276,12 @@ def autotune(X0, nsteps=8, stream=None, **params):
 
 
 def dbg_philox(ctr, seed, precision="fp32"):
-    """Raw Philox outputs and the normal 3-vectors for counters ctr (n, 4) uint32."""
+    """Raw Philox outputs and the six normals for counters ctr (n, 4) uint32."""
     ctr = torch.as_tensor(np.asarray(ctr, dtype=np.uint32).view(np.int32)).cuda().contiguous()
     n = ctr.shape[0]
     raw = torch.empty((n, 4), dtype=torch.int32, device=ctr.device)
     dt = torch.float32 if precision == "fp32" else torch.float64
-    z = torch.empty((n, 3), dtype=dt, device=ctr.device)
+    z = torch.empty((n, 6), dtype=dt, device=ctr.device)
     prec = _lib.SIPF_FP32 if precision == "fp32" else _lib.SIPF_FP64
     check(_lib.load().sipf_dbg_philox(int(seed), n, ctypes.c_void_p(ctr.data_ptr()), ctypes.c_void_p(raw.data_ptr()),
                                       ctypes.c_void_p(z.data_ptr()), prec, _stream_handle()))

@@ -88,7 +88,7 @@ def test_philox_bit_exact(precision):
     ref = np.stack(ophilox.philox4x32_10(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], k0, k1), axis=1)
     assert np.array_equal(raw.astype(np.uint64), ref)
     # normals: the oracle's Box-Muller on the same counters (float64)
-    zr = ophilox.normals3(ctr[:, 0], ctr[:, 1], ctr[:, 2], seed, ctr[:, 3])
+    zr = ophilox.normals6_counter(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], seed)
     tol = 2e-6 if precision == "fp32" else 1e-13
     assert np.abs(to_np(z) - zr).max() < tol * 6
 

@@ -49,31 +49,46 @@ def test_philox_matches_rocrand_engine(rocrand_ref):
     assert np.array_equal(got, ref)
 
 
-def test_uniforms_exact_in_float32_and_open_interval():
-    r = np.array([0, 1, 511, 512, 2 ** 31, 2 ** 32 - 1], dtype=np.uint64)
-    u = philox.uniforms(r)
-    assert np.array_equal(u.astype(np.float32).astype(np.float64), u)
-    assert u.min() == 2.0 ** -24 and u.max() == 1.0 - 2.0 ** -24
+def test_uniform_fields_exact_in_float32_and_open_interval():
+    r = np.array([0, 1, 0x7FF, 0x800, 2 ** 31, 2 ** 32 - 1], dtype=np.uint64)
+    f = philox.fields21(r, r, r, r)
+    for fi in f:
+        assert fi.max() < 2 ** 21
+        u = philox.uniforms21(fi)
+        assert np.array_equal(u.astype(np.float32).astype(np.float64), u)
+        assert u.min() >= 2.0 ** -22 and u.max() <= 1.0 - 2.0 ** -22
+    # every field takes its extreme values, and the fields use disjoint bits
+    allones = philox.fields21(*([np.uint64(2 ** 32 - 1)] * 4))
+    assert all(int(v) == 2 ** 21 - 1 for v in allones)
+    one_bit = [philox.fields21(*[np.uint64(1 << b) if i == w else np.uint64(0) for i in range(4)])
+               for w in range(4) for b in range(32)]
+    hits = [sum(int(v) != 0 for v in fs) for fs in one_bit]
+    assert max(hits) == 1 and sum(hits) == 126   # 126 of the 128 bits are used, each once
 
 
 def test_normals_statistics():
     ids = np.arange(400_000, dtype=np.uint64)
-    z = philox.normals3(ids, 7, 0, seed=123)
+    z = philox.normals6(ids, 7, seed=123)
     n = z.size
     assert abs(z.mean()) < 5 / math.sqrt(n)
     assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / n)
     # fourth moment of N(0,1) is 3
     assert abs((z ** 4).mean() - 3.0) < 0.05
-    # components and neighbouring ids are uncorrelated
+    # the six components and neighbouring ids are uncorrelated
     c = np.corrcoef(z.T)
-    assert np.abs(c - np.eye(3)).max() < 5 / math.sqrt(ids.size)
-    lag = np.corrcoef(z[:-1, 0], z[1:, 0])[0, 1]
-    assert abs(lag) < 5 / math.sqrt(ids.size)
-    # different slots / steps give independent streams
-    z2 = philox.normals3(ids, 7, 1, seed=123)
-    z3 = philox.normals3(ids, 8, 0, seed=123)
-    assert abs(np.corrcoef(z[:, 0], z2[:, 0])[0, 1]) < 5 / math.sqrt(ids.size)
+    assert np.abs(c - np.eye(6)).max() < 5 / math.sqrt(ids.size)
+    for j in range(6):
+        lag = np.corrcoef(z[:-1, j], z[1:, j])[0, 1]
+        assert abs(lag) < 5 / math.sqrt(ids.size)
+    # different steps and instances give independent streams
+    z3 = philox.normals6(ids, 8, seed=123)
+    z4 = philox.normals6(ids, 7, seed=123, instance=1)
     assert abs(np.corrcoef(z[:, 0], z3[:, 0])[0, 1]) < 5 / math.sqrt(ids.size)
+    assert abs(np.corrcoef(z[:, 0], z4[:, 0])[0, 1]) < 5 / math.sqrt(ids.size)
+    # each component is N(0, 1) in distribution (Kolmogorov-Smirnov)
+    from scipy import stats
+    for j in range(6):
+        assert stats.kstest(z[:, j], "norm").pvalue > 1e-4
 
 
 # ---------------------------------------------------------------------------
@@ -393,10 +408,12 @@ def test_first_step_has_no_drift():
     X0 = np.random.default_rng(2).normal(0, 0.1, (500, 3))
     X1, _ = sipf.run(X0, prm, 1)
     ids = np.arange(500, dtype=np.uint64)
-    Z = philox.normals3(ids, 1, 0, 0) + philox.normals3(ids, 1, 1, 0)
+    Z6 = philox.normals6(ids, 1, 0)
+    Z = Z6[:, 0:3] + Z6[:, 3:6]
     assert np.abs(sipf.min_image(X1 - X0 - math.sqrt(prm.mu * prm.dt) * Z, 2.0)).max() < 1e-15
     X2, _ = sipf.run(X0, prm, 2)
-    ids2 = philox.normals3(ids, 2, 0, 0) + philox.normals3(ids, 2, 1, 0)
+    Z62 = philox.normals6(ids, 2, 0)
+    ids2 = Z62[:, 0:3] + Z62[:, 3:6]
     pure = sipf.min_image(X2 - X1 - math.sqrt(prm.mu * prm.dt) * ids2, 2.0)
     assert np.abs(pure).max() > 1e-8   # the second step does feel the field
 
