@@ -123,15 +123,21 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Reverse particle pass over the work items of a tile sort (one item = up to
 // ACH particles of one tile, consecutive in the segment's order).  Per item,
 // the cells of X bound a window of the grid that covers the trilinear stencil
-// at Y = X + W^- (margin gmargin) and the deposit stencil at X:
+// at Y = X + W^- (margin gmargin):
 //   G window     the gradient grids, staged once from HBM (gather of v, J);
 //   Gbar window  fixed-point accumulators of the transpose of the gather,
 //                added to the grid once per item instead of once per particle;
-//   phibar window the deposit cotangent (derivative of the deposit).
+//   phibar window the deposit cotangent.
 // A particle whose Y cell leaves the window, or an item whose window does not
-// fit, goes straight to HBM (gathers, float atomics).
+// fit, goes straight to HBM (gathers, float atomics).  The transpose of the
+// deposit at X gathers the deposit cotangent from a third window (order-4
+// stencil around the cells of X).
 // ---------------------------------------------------------------------------
 constexpr int APT = 512;  // threads per workgroup
+#ifndef ADJ_UNROLL
+#define ADJ_UNROLL 1
+#endif
+
 constexpr int APPT = 8;   // particles per thread
 constexpr int ACH = APT * APPT;
 
@@ -162,8 +168,9 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
     const int H = a.H, Hm = H - 1, Hh = H / 2;
     const T hl = a.hl;
     const size_t H3 = (size_t)H * H * H;
+    // the load phase keeps the particles only long enough for the bounding box
+    // and the cotangent bound; the main loop re-reads each one from L2
     T px[APPT], py[APPT], pz[APPT], qx[APPT], qy[APPT], qz[APPT];
-    uint32_t pid[APPT];
     if (tid < 3) sh[tid] = INT_MAX;
     else if (tid < 6) sh[tid] = INT_MIN;
     else if (tid == 6) sh[6] = 0;
@@ -178,7 +185,6 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
         px[k] = gp(a.x + beg)[jj];
         py[k] = gp(a.y + beg)[jj];
         pz[k] = gp(a.z + beg)[jj];
-        pid[k] = gp(a.id + beg)[jj];
         qx[k] = gp(a.xbx + beg)[jj];
         qy[k] = gp(a.xby + beg)[jj];
         qz[k] = gp(a.xbz + beg)[jj];
@@ -222,6 +228,9 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
         }
     }
     const int gn = gwin ? gWx * gWy * gWz : 0;
+    I* Gb = reinterpret_cast<I*>(lds);
+    T* Gw = reinterpret_cast<T*>(lds + (size_t)3 * gn * sizeof(I));
+    // deposit-cotangent window: the order-4 stencil (-1 .. +2) around the cells of X
     const size_t used = (size_t)3 * gn * (sizeof(I) + sizeof(T));
     int dox = 0, doy = 0, doz = 0, dWx = H, dWy = H, dWz = H;
     bool dwin = false;
@@ -231,9 +240,17 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
         axis_window(rz, sh[2] - 1, sh[5] + 2, H, doz, dWz);
         dwin = used + (size_t)dWx * dWy * dWz * sizeof(T) <= (size_t)lds_bytes;
     }
-    I* Gb = reinterpret_cast<I*>(lds);
-    T* Gw = reinterpret_cast<T*>(lds + (size_t)3 * gn * sizeof(I));
     T* Pw = reinterpret_cast<T*>(lds + used);
+    if (dwin) {
+        const int dn = dWx * dWy * dWz;
+        const float inv_y = 1.0f / (float)dWy, inv_z = 1.0f / (float)dWz;
+        for (int e = tid; e < dn; e += APT) {
+            int i, j, k;
+            unflatten3(e, dWy, dWz, inv_z, inv_y, i, j, k);
+            Pw[e] = gp(a.phibar)[((size_t)((dox + i) & Hm) * H + ((doy + j) & Hm)) * H + ((doz + k) & Hm)];
+        }
+    }
+    const T cdep = a.wmass * hl;
     if (gwin) {
         const float inv_y = 1.0f / (float)gWy, inv_z = 1.0f / (float)gWz;
         for (int e = tid; e < gn; e += APT) {
@@ -248,38 +265,29 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
             Gb[2 * gn + e] = 0;
         }
     }
-    if (dwin) {
-        const int dn = dWx * dWy * dWz;
-        const float inv_y = 1.0f / (float)dWy, inv_z = 1.0f / (float)dWz;
-        for (int e = tid; e < dn; e += APT) {
-            int i, j, k;
-            unflatten3(e, dWy, dWz, inv_z, inv_y, i, j, k);
-            Pw[e] = gp(a.phibar)[((size_t)((dox + i) & Hm) * H + ((doy + j) & Hm)) * H + ((doz + k) & Hm)];
-        }
-    }
     int e2 = 0;
     if (bound > 0 && gwin) (void)frexp(bound, &e2);  // bound < 2^e2
     const T scale = (T)ldexp(1.0, AdjFixed<T>::E - e2);
     const T back = (T)ldexp(1.0, e2 - AdjFixed<T>::E);
     __syncthreads();
 
-    const T c = a.wmass * hl;
-#pragma unroll
+#pragma unroll ADJ_UNROLL
     for (int k = 0; k < APPT; ++k) {
         const int j = tid + k * APT;
         if (j >= cnt) continue;
-        const T X[3] = {px[k], py[k], pz[k]};
-        const T xb[3] = {qx[k], qy[k], qz[k]};
+        const T X[3] = {gp(a.x + beg)[j], gp(a.y + beg)[j], gp(a.z + beg)[j]};
+        const T xb[3] = {gp(a.xbx + beg)[j], gp(a.xby + beg)[j], gp(a.xbz + beg)[j]};
+        const uint32_t pidk = gp(a.id + beg)[j];
         T zm[3], zp[3], Y[3], zn[6];
         if (SCHEME == SIPF_STRANG) {
-            noise6<3, T>(pid[k], a.n, a.inst, a.k0, a.k1, zn);
+            noise6<3, T>(pidk, a.n, a.inst, a.k0, a.k1, zn);
             for (int d = 0; d < 3; ++d) {
                 zm[d] = zn[d];
                 zp[d] = zn[3 + d];
                 Y[d] = X[d] + a.s * zm[d];
             }
         } else {
-            noise6<2, T>(pid[k], a.n, a.inst, a.k0, a.k1, zn);
+            noise6<2, T>(pidk, a.n, a.inst, a.k0, a.k1, zn);
             for (int d = 0; d < 3; ++d) {
                 zp[d] = zn[d];
                 zm[d] = 0;
@@ -312,25 +320,40 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
                             off[q] = (((gc[0] + ia) & Hm) * H + ((gc[1] + ib) & Hm)) * H + ((gc[2] + ic) & Hm);
                     }
         }
-        const T* Gs = inside ? Gw : a.G;
-        const size_t pitch = inside ? (size_t)gn : H3;
+        // gradient values at the 8 nodes: from the LDS window or from HBM (two
+        // explicit paths, so that LDS reads stay ds_read instructions)
+        T gv[3][8];
+        if (inside) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) gv[d][q] = Gw[d * gn + off[q]];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) gv[d][q] = gp(a.G)[d * H3 + off[q]];
+        }
         T v[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, wt[8];
         {
             int q = 0;
+#pragma unroll
             for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
                 for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
                     for (int ic = 0; ic < 2; ++ic, ++q) {
                         const T wyz = w[1][ib] * w[2][ic], wxz = w[0][ia] * w[2][ic], wxy = w[0][ia] * w[1][ib];
                         wt[q] = w[0][ia] * wyz;
                         const T dx = (ia ? hl : -hl) * wyz;
                         const T dy = (ib ? hl : -hl) * wxz;
                         const T dz = (ic ? hl : -hl) * wxy;
+#pragma unroll
                         for (int d = 0; d < 3; ++d) {
-                            const T gv = Gs[d * pitch + off[q]];
-                            v[d] += wt[q] * gv;
-                            J[d][0] += dx * gv;
-                            J[d][1] += dy * gv;
-                            J[d][2] += dz * gv;
+                            v[d] += wt[q] * gv[d][q];
+                            J[d][0] += dx * gv[d][q];
+                            J[d][1] += dy * gv[d][q];
+                            J[d][2] += dz * gv[d][q];
                         }
                     }
         }
@@ -358,9 +381,9 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
             T gx, gy, gz;
             if (dwin) deposit_grad(Pw, X[0], X[1], X[2], hl, H, gx, gy, gz, dox, doy, doz, dWy, dWz);
             else deposit_grad(a.phibar, X[0], X[1], X[2], hl, H, gx, gy, gz);
-            yb[0] += c * gx;
-            yb[1] += c * gy;
-            yb[2] += c * gz;
+            yb[0] += cdep * gx;
+            yb[1] += cdep * gy;
+            yb[2] += cdep * gz;
         }
         gp(a.xbx + beg)[j] = yb[0];
         gp(a.xby + beg)[j] = yb[1];
@@ -394,8 +417,18 @@ __device__ __forceinline__ double block_sum_n(double v, double* sh, int nthreads
     return t;
 }
 
+// Register budget of the reverse pass: waves per SIMD to leave room for (0: the
+// compiler's choice).
+#ifndef ADJ_WAVES
+#define ADJ_WAVES 0
+#endif
+#if ADJ_WAVES > 0
+#define ADJ_ATTR __attribute__((amdgpu_waves_per_eu(ADJ_WAVES)))
+#else
+#define ADJ_ATTR
+#endif
 template <typename T, int SCHEME>
-__global__ __launch_bounds__(APT) void k_adj_items(AdjDesc<T> a, const WorkItem* __restrict__ items,
+__global__ __launch_bounds__(APT) ADJ_ATTR void k_adj_items(AdjDesc<T> a, const WorkItem* __restrict__ items,
                                                    const int* __restrict__ nitems, int lds_bytes) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int sh[8];

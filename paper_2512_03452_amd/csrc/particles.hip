@@ -289,7 +289,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
     const int H = a.H, Hm = H - 1, Hh = H / 2;
     const T hl = a.hl;
     T px[PPT], py[PPT], pz[PPT];
+#if !SIPF_RELOAD
     uint32_t pid[PPT];
+#endif
     // uniform per-item bases and 32-bit offsets; lanes past the end load the
     // item's last particle (cnt >= 1), so all loads issue without branches
     const T* ix = a.x + beg;
