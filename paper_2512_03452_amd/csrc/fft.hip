@@ -28,6 +28,7 @@
 namespace sipf {
 
 template <int N> struct Split;
+template <> struct Split<4>   { static constexpr int N1 = 4,  N2 = 1; };
 template <> struct Split<8>   { static constexpr int N1 = 8,  N2 = 1; };
 template <> struct Split<16>  { static constexpr int N1 = 16, N2 = 1; };
 template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
@@ -191,27 +192,36 @@ constexpr int KB = 16;  // kz columns per x-pencil workgroup
 
 // ---------------------------------------------------------------------------
 // Pass 1: x-plane -> half spectrum along z, transformed along y.
+//
+// Real rows along z by the half-length method: row x (length H = 2M) is read
+// as z[m] = x[2m] + i x[2m+1], transformed with an M-point FFT, and
+//   E_k = (Z_k + conj Z_{M-k}) / 2,  O_k = (Z_k - conj Z_{M-k}) / (2i),
+//   X_k = E_k + exp(-2 pi i k / H) O_k,   k = 0 .. M,
+// so one plane buffer of H x (M+1) values holds both stages.  The pairs
+// (k, M-k) are read into registers before they are written back, since the
+// FFT leaves Z in permuted order.
 // ---------------------------------------------------------------------------
 template <typename T, int H>
 __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>* __restrict__ fds, int consume) {
     using V = cplx_t<T>;
-    constexpr int HH = H / 2 + 1;
-    constexpr int RP = H + 1;          // row pitch (complex) of the packed-row buffer
-    constexpr int OP = HH;             // row pitch of the half plane
-    __shared__ V rows[(H / 2) * RP];
-    __shared__ V half[H * OP];
+    constexpr int M = H / 2;
+    constexpr int HH = M + 1;
+    constexpr int OP = HH;  // row pitch (complex)
+    constexpr int NP = M / 2 + 1;  // pairs (k, M - k) per row, k = 0 .. M/2
+    constexpr int PPT = (H * NP + PLANE_THREADS - 1) / PLANE_THREADS;
+    __shared__ V buf[H * OP];
     __shared__ V tw[H];
+    __shared__ V twm[M];
     const FieldDesc<T>& fd = fds[blockIdx.y];
     const int ix = blockIdx.x % H;
     const int comp = blockIdx.x / H;  // component of a multi-grid input (phi + comp H^3)
     const int tid = threadIdx.x, nt = blockDim.x;
     make_twiddles<T, H>(tw);
+    make_twiddles<T, M>(twm);
     T* plane = fd.phi + ((size_t)comp * H + ix) * H * H;
-    for (int u = tid; u < (H / 2) * H; u += nt) {
-        const int m = u / H, iz = u % H;
-        const T a = plane[(2 * m) * H + iz];
-        const T b = plane[(2 * m + 1) * H + iz];
-        rows[m * RP + iz] = cmake<V, T>(a, b);
+    for (int u = tid; u < H * M; u += nt) {
+        const int row = u / M, m = u % M;
+        buf[row * OP + m] = cmake<V, T>(plane[row * H + 2 * m], plane[row * H + 2 * m + 1]);
     }
     __syncthreads();
     if (consume) {
@@ -219,22 +229,37 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>
         for (int u = tid; u < H * H; u += nt) plane[u] = (T)0;
         if (ix == 0 && comp == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
     }
-    lds_fft<T, H, -1>(rows, H / 2, RP, 1, tw);
+    lds_fft<T, M, -1>(buf, H, OP, 1, twm);
     __syncthreads();
-    // split Z = FFT(a + i b): A_k = (Z_k + conj Z_{-k}) / 2, B_k = (Z_k - conj Z_{-k}) / (2i)
-    for (int u = tid; u < (H / 2) * HH; u += nt) {
-        const int m = u / HH, k = u % HH;
-        const V zk = rows[m * RP + perm_pos<H>(k)];
-        const V zc = cconj(rows[m * RP + perm_pos<H>((H - k) & (H - 1))]);
-        const V s = cadd(zk, zc), d = csub(zk, zc);
-        half[(2 * m) * OP + k] = cmake<V, T>(s.x * (T)0.5, s.y * (T)0.5);
-        half[(2 * m + 1) * OP + k] = cmake<V, T>(d.y * (T)0.5, -d.x * (T)0.5);
+    V za[PPT], zb[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * PLANE_THREADS;
+        if (u < H * NP) {
+            const int row = u / NP, k = u % NP;
+            za[q] = buf[row * OP + perm_pos<M>(k % M)];
+            zb[q] = buf[row * OP + perm_pos<M>((M - k) % M)];
+        }
     }
     __syncthreads();
-    lds_fft<T, H, -1>(half, HH, 1, OP, tw);
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * PLANE_THREADS;
+        if (u < H * NP) {
+            const int row = u / NP, k = u % NP;
+            const V zc = cconj(zb[q]);
+            const V e = cscale(cadd(za[q], zc), (T)0.5);
+            const V dd = csub(za[q], zc);
+            const V o = cmake<V, T>(dd.y * (T)0.5, -dd.x * (T)0.5);  // (Z_k - conj Z_{M-k}) / (2i)
+            buf[row * OP + k] = cadd(e, cmul(tw[k], o));
+            if (k != M - k) buf[row * OP + (M - k)] = cadd(cconj(e), cmul(tw[M - k], cconj(o)));
+        }
+    }
+    __syncthreads();
+    lds_fft<T, H, -1>(buf, HH, 1, OP, tw);
     __syncthreads();
     V* out = fd.B1 + ((size_t)comp * H + ix) * H * HH;
-    for (int u = tid; u < H * HH; u += nt) out[u] = half[(u / HH) * OP + (u % HH)];
+    for (int u = tid; u < H * HH; u += nt) out[u] = buf[u];
 }
 
 // ---------------------------------------------------------------------------
@@ -421,16 +446,23 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
 
 // ---------------------------------------------------------------------------
 // Pass 3: inverse along y, complex-to-real inverse along z, per component.
+//
+// Along z the half spectrum X_0 .. X_M of each row gives the M-point input
+//   Z_k = (X_k + conj X_{M-k}) + i exp(+2 pi i k / H) (X_k - conj X_{M-k}),
+// whose inverse transform is z[m] = x[2m] + i x[2m+1] (unnormalised, as the
+// gradient synthesis needs).
 // ---------------------------------------------------------------------------
 template <typename T, int H>
 __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>* __restrict__ fds, int ncomp) {
     using V = cplx_t<T>;
-    constexpr int HH = H / 2 + 1;
-    constexpr int RP = H + 1;
+    constexpr int M = H / 2;
+    constexpr int HH = M + 1;
     constexpr int OP = HH;
-    __shared__ V rows[(H / 2) * RP];
-    __shared__ V half[H * OP];
+    constexpr int NP = M / 2 + 1;
+    constexpr int PPT = (H * NP + PLANE_THREADS - 1) / PLANE_THREADS;
+    __shared__ V buf[H * OP];
     __shared__ V tw[H];
+    __shared__ V twm[M];
     const FieldDesc<T>& fd = fds[blockIdx.y];
     // blocks 8c + r (c = (ix / 8) ncomp + d) keep the components of a plane on one XCD
     const int b = blockIdx.x;
@@ -439,33 +471,48 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
     const int ix = (grp / ncomp) * 8 + r;
     const int tid = threadIdx.x, nt = blockDim.x;
     make_twiddles<T, H>(tw);
+    make_twiddles<T, M>(twm);
     const V* in = fd.gspec + ((size_t)d * H + ix) * H * HH;
-    for (int u = tid; u < H * HH; u += nt) half[(u / HH) * OP + (u % HH)] = in[u];
+    for (int u = tid; u < H * HH; u += nt) buf[u] = in[u];
     __syncthreads();
-    lds_fft<T, H, +1>(half, HH, 1, OP, tw);
+    lds_fft<T, H, +1>(buf, HH, 1, OP, tw);
     __syncthreads();
-    // rebuild full rows Z_k = A_k + i B_k (A, B Hermitian) in permuted order
-    for (int u = tid; u < (H / 2) * H; u += nt) {
-        const int m = u / H, k = u % H;
-        V a, bb;
-        if (k <= H / 2) {
-            a = half[(2 * m) * OP + k];
-            bb = half[(2 * m + 1) * OP + k];
-        } else {
-            a = cconj(half[(2 * m) * OP + (H - k)]);
-            bb = cconj(half[(2 * m + 1) * OP + (H - k)]);
+    V xa[PPT], xb[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * PLANE_THREADS;
+        if (u < H * NP) {
+            const int row = u / NP, k = u % NP;
+            xa[q] = buf[row * OP + k];
+            xb[q] = buf[row * OP + (M - k)];
         }
-        rows[m * RP + perm_pos<H>(k)] = cmake<V, T>(a.x - bb.y, a.y + bb.x);
     }
     __syncthreads();
-    lds_fft<T, H, +1>(rows, H / 2, RP, 1, tw);
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * PLANE_THREADS;
+        if (u < H * NP) {
+            const int row = u / NP, k = u % NP;
+            // Z_k from (X_k, X_{M-k}); Z_{M-k} from (X_{M-k}, X_k) for 0 < k < M - k
+            const V s1 = cadd(xa[q], cconj(xb[q])), d1 = csub(xa[q], cconj(xb[q]));
+            const V t1 = cmul(cconj(tw[k]), d1);
+            buf[row * OP + perm_pos<M>(k % M)] = cmake<V, T>(s1.x - t1.y, s1.y + t1.x);
+            if (k != 0 && k != M - k) {
+                const V s2 = cadd(xb[q], cconj(xa[q])), d2 = csub(xb[q], cconj(xa[q]));
+                const V t2 = cmul(cconj(tw[M - k]), d2);
+                buf[row * OP + perm_pos<M>(M - k)] = cmake<V, T>(s2.x - t2.y, s2.y + t2.x);
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<T, M, +1>(buf, H, OP, 1, twm);
     __syncthreads();
     T* outp = fd.G + ((size_t)d * H + ix) * H * H;
-    for (int u = tid; u < (H / 2) * H; u += nt) {
-        const int m = u / H, iz = u % H;
-        const V v = rows[m * RP + iz];
-        outp[(2 * m) * H + iz] = v.x;
-        outp[(2 * m + 1) * H + iz] = v.y;
+    for (int u = tid; u < H * M; u += nt) {
+        const int row = u / M, m = u % M;
+        const V v = buf[row * OP + m];
+        outp[row * H + 2 * m] = v.x;
+        outp[row * H + 2 * m + 1] = v.y;
     }
 }
 
