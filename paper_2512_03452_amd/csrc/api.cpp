@@ -851,11 +851,17 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
             fr[t].gspec = (V*)scr.p;
             fr[t].G = gseg + (size_t)(t % K) * 3 * H3;
             fr[t].step = nullptr;
+            // reads segment slot t mod K, writes slot t mod K + 1 (used while that is < K)
             const int sl = (int)(t % K) + 1 < K ? (int)(t % K) + 1 : 0;
-            T *x, *y, *z;
-            uint32_t* id;
-            slot(seg.p, sl, x, y, z, id);
+            T *x, *y, *z, *x1, *y1, *z1;
+            uint32_t *id, *id1;
+            slot(seg.p, (int)(t % K), x, y, z, id);
+            slot(seg.p, sl, x1, y1, z1, id1);
             pr[t] = pdesc_on<T>(c, x, y, z, id);
+            pr[t].ox = x1;
+            pr[t].oy = y1;
+            pr[t].oz = z1;
+            pr[t].oid = id1;
             pr[t].G = gseg + (size_t)(t % K) * 3 * H3;
             pr[t].step = (const uint32_t*)consts.p + t;
         }
@@ -947,12 +953,8 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
                               c->seg_off, c->seg_n, c->items, c->nitems, c->chunk, c->stream));
         if ((rc = grad_of_tape(base))) return rc;
         for (int m = 1; m < len; ++m) {
-            // X^(base+m) = push of X^(base+m-1) with G^(base+m-1) (step base+m), then G^(base+m)
-            T *x, *y, *z, *px, *py, *pz;
-            uint32_t *id, *pid;
-            slot(seg.p, m, x, y, z, id);
-            slot(seg.p, m - 1, px, py, pz, pid);
-            HIPCHK(launch_copy_positions<T>(x, y, z, id, px, py, pz, pid, P, c->stream));
+            // X^(base+m) = push of X^(base+m-1) (slot m-1 -> slot m) with G^(base+m-1)
+            // (step base+m), then G^(base+m)
             HIPCHK(launch_particles<T>((const PartDesc<T>*)pdR.p + (base + m - 1), c->items, c->nitems, c->pgrid,
                                        false, true, c->scheme, c->win_bytes, c->stream));
             if ((rc = grad_of_tape(base + m))) return rc;

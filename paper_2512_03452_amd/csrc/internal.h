@@ -78,6 +78,10 @@ template <typename T> struct PartDesc {
     int gmargin;            // cells the W^- displacement can reach (gradient window margin)
     int tshift;             // log2 of the sort tile side
     int nkeys;              // (H / tile)^3 sort keys
+    T* ox;                  // push-only passes: positions out (null: in place), ids copied to oid
+    T* oy;
+    T* oz;
+    uint32_t* oid;
 };
 
 // A run of sort-chunk particles of one instance (sort kernels).

@@ -528,9 +528,17 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
             const T ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
             const T nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
-            gp(a.x + beg)[j] = nx;
-            gp(a.y + beg)[j] = ny;
-            gp(a.z + beg)[j] = nz;
+            if (!DEP && a.ox != nullptr) {
+                // out of place (push-only passes): positions and ids to the output set
+                gp(a.ox + beg)[j] = nx;
+                gp(a.oy + beg)[j] = ny;
+                gp(a.oz + beg)[j] = nz;
+                gp(a.oid + beg)[j] = gp(iid)[j];
+            } else {
+                gp(a.x + beg)[j] = nx;
+                gp(a.y + beg)[j] = ny;
+                gp(a.z + beg)[j] = nz;
+            }
             if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(a.err, 1);
         }
     }
