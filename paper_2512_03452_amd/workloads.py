@@ -3,7 +3,8 @@
 This module only draws inputs: it holds none of the method's arithmetic and is
 shared by the tests, the bench and the smoke check.  Positions are returned as
 float64 numpy arrays of shape (P, 3) inside the box [-L/2, L/2)^3 (L = 2 for
-every workload below); callers cast them to the working precision.
+every workload below except the convergence-study ball, which lives in the box
+of side 8); callers cast them to the working precision.
 
 The paper runs on synthetic initial densities only (no datasets); the shapes
 below follow its experiment types at the sizes of the workloads this library
@@ -12,6 +13,8 @@ is measured on:
   * mix         -- half uniform on the box, half N(0, sd^2 I)
   * torus       -- ring of major radius R in the xy-plane with Gaussian tube
                    cross-section sd (shape of the collapsing-ring run)
+  * ball        -- uniform in the unit ball (initial data of the convergence
+                   study, Sec. 5.1)
 """
 
 import math
@@ -47,6 +50,20 @@ def torus(P, R=0.5, sd=0.05, seed=0):
     X = np.stack([(R + a) * np.cos(th), (R + a) * np.sin(th), b], axis=1)
     return _wrap(X)
 
+
+def ball(P, radius=1.0, seed=0):
+    """i.i.d. uniform in the ball |x| <= radius (the initial density of the
+    convergence study, Sec. 5.1)."""
+    rng = np.random.default_rng([seed, 5])
+    v = rng.normal(size=(P, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    return v * (radius * np.cbrt(rng.random(P)))[:, None]
+
+
+# Convergence study of Sec. 5.1: uniform ball of radius 1, M0 = 80,
+# mu = chi = 1, eps = 1e-4, k = 0.1, tau = 1e-5, 2000 steps, L = 8.
+E1_PARAMS = dict(L=8.0, chi=1.0, mu=1.0, eps=1e-4, k=0.1, M0=80.0, dt=1e-5)
+E1_STEPS = 2000
 
 # name -> (parameters, P, steps, position generator)
 CONFIGS = {
