@@ -27,10 +27,16 @@ for 3D parabolic-parabolic chemotaxis systems", arXiv:2512.03452):
                   O(PH^3) SIPF step (Algorithm 1) used as a brute-force check.
 * ``adjoint``  -- hand-written reverse mode of the SIPF-PIC step with the noise
                   held fixed (pathwise gradient of a final-density loss).
+* ``radial``   -- radially symmetric finite-volume reference solution and the
+                  truncated quantile discrepancy of the convergence study
+                  (Sec. 5.1).
+* ``diagnostics`` -- the run-time indicators of Sec. 5 (maximum of the
+                  regularised density, high-frequency energy share, R_num,
+                  second moment, mass and integral of c_hat).
 
 Every floating-point quantity is float64.  Where the paper is silent or
 ambiguous the reading taken is stated at the function that implements it.
 """
 
-from . import philox, stencil, sipf, adjoint  # noqa: F401
+from . import philox, stencil, sipf, adjoint, radial, diagnostics  # noqa: F401
 from .sipf import Params  # noqa: F401
