@@ -167,6 +167,39 @@ int sipf_get_positions(sipf_ctx* ctx, void* out, int on_device);
 int sipf_get_field(sipf_ctx* ctx, int which, void* out, int on_device);
 
 /*
+ * Run-time diagnostics of the current state (Sec. 5.2 and 5.5), computed on
+ * the device:
+ *   step        completed steps n;
+ *   mass        sum_j rho_num(x_j) h^3 over the grid nodes, h = L/H (equals
+ *               M0 up to rounding);
+ *   rho_max     max_j rho_num(x_j), the blow-up indicator of Sec. 5.2;
+ *   hf_share    share of the energy of c_hat in the modes |q| >= 4:
+ *               sum_{|q|>=4} |alpha_q|^2 / sum_q |alpha_q|^2 over the full
+ *               spectrum of alpha^(n) (0 when alpha^(n) = 0);
+ *   c_integral  integral of c_hat over the box, L^3 Re alpha_0^(n);
+ *   r_num       (1/P) sum_p sqrt(X_p1^2 + X_p2^2) (Sec. 5.5);
+ *   m2          (1/P) sum_p |X_p|^2, coordinates in [-L/2, L/2).
+ * rho_num = rho_hat_P * G0 with G0 the isotropic Gaussian of standard
+ * deviation L/H0 per axis, reconstructed on the grid as the step does it: the
+ * order-4 deposit of X^(n), F_H, the factor exp(-2 pi^2 |q|^2 / H0^2) and the
+ * inverse transform (no filter when H0 < 0).  The sums are FP64 and
+ * deterministic for a given particle order.  The state is left unchanged.
+ * The first call allocates a small scratch buffer (about 8 KB per instance)
+ * that the context keeps.  Synchronises.  Errors: SIPF_EINVAL for NULL
+ * arguments, SIPF_EDEVICE, SIPF_ENUMERIC as for sipf_sync.
+ */
+typedef struct sipf_diag {
+    int64_t step;
+    double mass;
+    double rho_max;
+    double hf_share;
+    double c_integral;
+    double r_num;
+    double m2;
+} sipf_diag;
+int sipf_diagnostics(sipf_ctx* ctx, sipf_diag* out);
+
+/*
  * Pathwise adjoint (reverse mode along the fixed Philox noise path).
  * Runs nsteps forward steps from the current state (which must be the
  * initial state, n = 0, with alpha0 = 0; otherwise SIPF_ESTATE), storing the
@@ -259,6 +292,8 @@ int sipf_batch_sync(sipf_batch* b);
 int sipf_batch_get_step(sipf_batch* b, int32_t i, int64_t* n);
 int sipf_batch_get_positions(sipf_batch* b, int32_t i, void* out, int on_device);
 int sipf_batch_get_field(sipf_batch* b, int32_t i, int which, void* out, int on_device);
+/* Diagnostics of every instance (out: n entries, see sipf_diagnostics). */
+int sipf_batch_diagnostics(sipf_batch* b, sipf_diag* out);
 int sipf_batch_profile(sipf_batch* b, int enable);
 int sipf_batch_profile_read(sipf_batch* b, double* ms, int64_t* launches);
 int sipf_batch_destroy(sipf_batch* b);

@@ -43,6 +43,18 @@ class SipfParams(ctypes.Structure):
     ]
 
 
+class SipfDiag(ctypes.Structure):
+    """Mirror of ``sipf_diag``."""
+    _fields_ = [
+        ("step", ctypes.c_int64), ("mass", ctypes.c_double), ("rho_max", ctypes.c_double),
+        ("hf_share", ctypes.c_double), ("c_integral", ctypes.c_double), ("r_num", ctypes.c_double),
+        ("m2", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class SipfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{CODE_NAMES.get(code, code)}: {msg}")
@@ -66,6 +78,8 @@ SIGNATURES = {
     "sipf_get_step": [_vp, ctypes.POINTER(_i64)],
     "sipf_get_positions": [_vp, _vp, ctypes.c_int],
     "sipf_get_field": [_vp, ctypes.c_int, _vp, ctypes.c_int],
+    "sipf_diagnostics": [_vp, ctypes.POINTER(SipfDiag)],
+    "sipf_batch_diagnostics": [_vp, ctypes.POINTER(SipfDiag)],
     "sipf_adjoint": [_vp, _i64, _i32, _vp, _dp, _dp, _dp, _vp],
     "sipf_profile": [_vp, ctypes.c_int],
     "sipf_profile_read": [_vp, _dp, ctypes.POINTER(_i64)],

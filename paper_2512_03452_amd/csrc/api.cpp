@@ -143,6 +143,7 @@ struct Group {
     int* nitems = nullptr;
     int items_cap = 0;
     std::vector<void*> allocs;
+    void* diag = nullptr;  // diagnostics scratch, allocated on first use
     // captured graphs of two sort periods, by starting buffer set
     bool graphs = true;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -688,6 +689,79 @@ template <typename T> int get_positions_typed(Group* g, int i, void* out, int on
     return check_err(g);
 }
 
+// Diagnostics of every instance: deposit of the current positions, forward
+// plane pass (consuming the deposit, step counters untouched), x pencils with
+// the Gaussian factor, inverse plane pass of one component into the deposit
+// grid (rho_num), then the reductions; the deposit grids are cleared again.
+template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
+    const int n = (int)g->in.size();
+    const size_t part_b = (size_t)n * DIAG_BLOCKS * DIAG_NVAL * sizeof(double);
+    const size_t res_b = (size_t)n * DIAG_NVAL * sizeof(double);
+    const size_t dd_b = ((size_t)n * sizeof(DiagDesc<T>) + 255) / 256 * 256;
+    const size_t fd_b = (size_t)n * sizeof(FieldDesc<T>);
+    int rc;
+    if (!g->diag && (rc = dalloc(g, &g->diag, part_b + res_b + dd_b + fd_b))) return rc;
+    char* base = (char*)g->diag;
+    double* part = (double*)base;
+    double* res = (double*)(base + part_b);
+    DiagDesc<T>* ddev = (DiagDesc<T>*)(base + part_b + res_b);
+    FieldDesc<T>* fdev = (FieldDesc<T>*)(base + part_b + res_b + dd_b);
+    std::vector<DiagDesc<T>> dd(n);
+    std::vector<FieldDesc<T>> fd(n);
+    for (int i = 0; i < n; ++i) {
+        const Inst& I = g->in[i];
+        FieldDesc<T> f = make_fdesc<T>(g, i);
+        f.G = (T*)I.phi;
+        f.step = nullptr;
+        fd[g->fslot[i]] = f;
+        DiagDesc<T> d{};
+        d.rho = (const T*)I.phi;
+        d.alpha = (const cplx_t<T>*)I.alpha;
+        d.x = (const T*)I.xs[g->cur];
+        d.y = (const T*)I.ys[g->cur];
+        d.z = (const T*)I.zs[g->cur];
+        d.P = I.P;
+        d.H = I.H;
+        d.n2 = fft_perm(I.H, 1);
+        d.n1 = I.H / d.n2;
+        dd[i] = d;
+    }
+    HIPCHK(hipMemcpyAsync(ddev, dd.data(), n * sizeof(DiagDesc<T>), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(fdev, fd.data(), fd_b, hipMemcpyHostToDevice, g->stream));
+    HIPCHK(launch_particles<T>(pdesc_dev<T>(g, g->cur), g->items, g->nitems, g->pgrid, true, false, g->scheme,
+                               g->win_bytes, g->stream));
+    for (const HClass& h : g->classes) {
+        HIPCHK(launch_fwd_planes<T>(h.H, fdev + h.first, h.count, 1, true, g->stream));
+        HIPCHK(launch_xpencils<T>(h.H, fdev + h.first, h.count, XP_RHO, g->stream));
+        HIPCHK(launch_inv_planes<T>(h.H, fdev + h.first, h.count, 1, g->stream));
+    }
+    HIPCHK(launch_diag<T>(ddev, n, part, res, g->stream));
+    std::vector<double> host((size_t)n * DIAG_NVAL);
+    std::vector<uint32_t> steps(n);
+    HIPCHK(hipMemcpyAsync(host.data(), res, res_b, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipMemcpyAsync(steps.data(), g->steps, n * sizeof(uint32_t), hipMemcpyDeviceToHost, g->stream));
+    for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)J.H * J.H * J.H, (T)0, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    for (int i = 0; i < n; ++i) {
+        const Inst& I = g->in[i];
+        const double* v = host.data() + (size_t)i * DIAG_NVAL;
+        const double L = I.prm.L, h = L / I.H;
+        sipf_diag& o = out[i];
+        o.step = steps[i];
+        o.mass = v[0] * h * h * h;
+        o.rho_max = v[1];
+        o.hf_share = v[2] > 0 ? v[3] / v[2] : 0.0;
+        o.c_integral = L * L * L * v[4];
+        o.r_num = v[5] / (double)I.P;
+        o.m2 = v[6] / (double)I.P;
+    }
+    return check_err(g);
+}
+
+int diagnostics_any(Group* g, sipf_diag* out) {
+    return g->prec == SIPF_FP32 ? diagnostics_typed<float>(g, out) : diagnostics_typed<double>(g, out);
+}
+
 int get_field_any(Group* g, int i, int which, void* out, int on_device) {
     return g->prec == SIPF_FP32 ? get_field_typed<float>(g, i, which, out, on_device)
                                 : get_field_typed<double>(g, i, which, out, on_device);
@@ -1204,6 +1278,11 @@ int sipf_get_step(sipf_ctx* c, int64_t* n) {
     return get_step_any(c, 0, n);
 }
 
+int sipf_diagnostics(sipf_ctx* c, sipf_diag* out) {
+    if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
+    return diagnostics_any(c, out);
+}
+
 int sipf_get_positions(sipf_ctx* c, void* out, int on_device) {
     if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
     return get_positions_any(c, 0, out, on_device);
@@ -1326,6 +1405,11 @@ int sipf_batch_get_step(sipf_batch* b, int32_t i, int64_t* n) {
     if (!b || !n) return fail(SIPF_EINVAL, "NULL argument");
     if (i < 0 || i >= (int)b->in.size()) return fail(SIPF_EINVAL, "instance index out of range");
     return get_step_any(b, i, n);
+}
+
+int sipf_batch_diagnostics(sipf_batch* b, sipf_diag* out) {
+    if (!b || !out) return fail(SIPF_EINVAL, "NULL argument");
+    return diagnostics_any(b, out);
 }
 
 int sipf_batch_get_positions(sipf_batch* b, int32_t i, void* out, int on_device) {

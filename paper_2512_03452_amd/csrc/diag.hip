@@ -1,0 +1,97 @@
+// Run-time diagnostics of the numerical experiments (Sec. 5.2, 5.5): maximum
+// and mass of the regularised density rho_hat * G0 on the grid, the share of
+// the energy of c_hat in the modes |q| >= 4, the integral of c_hat, and the
+// particle moments R_num = mean sqrt(x1^2 + x2^2) and m2 = mean |X|^2.
+//
+// Two deterministic passes: DIAG_BLOCKS workgroups per instance reduce strided
+// slices of the grid, the half spectrum and the particles into per-block
+// partials (FP64), and one workgroup per instance combines the partials in a
+// fixed order.  The half spectrum stands for the full one: the planes kz = 0
+// and kz = H/2 hold every one of their modes once, the other planes hold one
+// of each conjugate pair, which counts twice.
+
+#include "internal.h"
+
+namespace sipf {
+
+constexpr int DIAG_THREADS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_partials(const DiagDesc<T>* __restrict__ dd,
+                                                                double* __restrict__ part) {
+    const DiagDesc<T> d = dd[blockIdx.y];
+    const int tid = threadIdx.x;
+    const int64_t stride = (int64_t)DIAG_BLOCKS * DIAG_THREADS;
+    const int64_t first = (int64_t)blockIdx.x * DIAG_THREADS + tid;
+    const int H = d.H, HH = H / 2 + 1;
+    double v[DIAG_NVAL];
+    for (int k = 0; k < DIAG_NVAL; ++k) v[k] = 0.0;
+    v[1] = -INFINITY;
+    const int64_t H3 = (int64_t)H * H * H;
+    for (int64_t i = first; i < H3; i += stride) {
+        const double r = (double)d.rho[i];
+        v[0] += r;
+        v[1] = fmax(v[1], r);
+    }
+    const int64_t ns = (int64_t)H * H * HH;
+    for (int64_t i = first; i < ns; i += stride) {
+        const int kz = (int)(i % HH);
+        const int64_t row = i / HH;
+        const int kyp = (int)(row % H), kxp = (int)(row / H);
+        const int kx = kxp / d.n2 + d.n1 * (kxp % d.n2);
+        const int ky = kyp / d.n2 + d.n1 * (kyp % d.n2);
+        const int qx = kx < H / 2 ? kx : kx - H;
+        const int qy = ky < H / 2 ? ky : ky - H;
+        const int q2 = qx * qx + qy * qy + kz * kz;
+        const cplx_t<T> a = d.alpha[i];
+        const double w = (kz == 0 || kz == H / 2) ? 1.0 : 2.0;
+        const double e = w * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
+        v[2] += e;
+        if (q2 >= 16) v[3] += e;
+        if (i == 0) v[4] = (double)a.x;
+    }
+    for (int64_t i = first; i < d.P; i += stride) {
+        const double x = (double)d.x[i], y = (double)d.y[i], z = (double)d.z[i];
+        const double rxy2 = x * x + y * y;
+        v[5] += sqrt(rxy2);
+        v[6] += rxy2 + z * z;
+    }
+    __shared__ double red[DIAG_NVAL][DIAG_THREADS];
+    for (int k = 0; k < DIAG_NVAL; ++k) red[k][tid] = v[k];
+    __syncthreads();
+    for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            for (int k = 0; k < DIAG_NVAL; ++k) {
+                if (k == 1) red[k][tid] = fmax(red[k][tid], red[k][tid + s]);
+                else red[k][tid] += red[k][tid + s];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < DIAG_NVAL) part[((size_t)blockIdx.y * DIAG_BLOCKS + blockIdx.x) * DIAG_NVAL + tid] = red[tid][0];
+}
+
+// one workgroup per instance; lane k combines value k over the blocks in order
+__global__ __launch_bounds__(64) void k_diag_finish(const double* __restrict__ part, double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= DIAG_NVAL) return;
+    const double* p = part + (size_t)blockIdx.x * DIAG_BLOCKS * DIAG_NVAL;
+    double acc = k == 1 ? -INFINITY : 0.0;
+    for (int b = 0; b < DIAG_BLOCKS; ++b) {
+        const double x = p[(size_t)b * DIAG_NVAL + k];
+        acc = k == 1 ? fmax(acc, x) : acc + x;
+    }
+    out[(size_t)blockIdx.x * DIAG_NVAL + k] = acc;
+}
+
+template <typename T> hipError_t launch_diag(const DiagDesc<T>* d, int n, double* part, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_diag_partials<T>), dim3(DIAG_BLOCKS, n), dim3(DIAG_THREADS), 0, s, d, part);
+    hipLaunchKernelGGL(k_diag_finish, dim3(n), dim3(64), 0, s, part, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_diag<float>(const DiagDesc<float>*, int, double*, double*, hipStream_t);
+template hipError_t launch_diag<double>(const DiagDesc<double>*, int, double*, double*, hipStream_t);
+
+}  // namespace sipf

@@ -276,7 +276,10 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
 //            into gspec component 0.
 // MODE_ADJ_ACC: adjoint of the gradient and of the propagation: forward x of the
 //            three transformed grids in B1, abar <- A abar + sum_d (-i xi_d Phi) B1_d.
-enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3 };
+// MODE_RHO:  forward x of B1 (a deposit), Gaussian factor Phi and L^-3, inverse x
+//            into gspec component 0: the regularised density rho_hat * G0 after
+//            the inverse plane pass.
+enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3, MODE_RHO = 4 };
 
 template <typename T, int H, int MODE>
 __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>* __restrict__ fds) {
@@ -298,6 +301,33 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
     const T qy = (T)(ky < H / 2 ? ky : ky - H);
     if constexpr (MODE == MODE_ADJ_SRC || MODE == MODE_ADJ_ACC) {
         adjoint_pencils<T, H, MODE>(fd, kyp, kz0, ncol, qy, ky, buf, abuf, tw);
+        return;
+    }
+    if constexpr (MODE == MODE_RHO) {
+        for (int u = tid; u < H * KB; u += nt) {
+            const int ix = u / KB, j = u % KB;
+            buf[ix * BP + j] = j < ncol ? fd.B1[((size_t)ix * H + kyp) * HH + kz0 + j] : cmake<V, T>(0, 0);
+        }
+        __syncthreads();
+        lds_fft<T, H, -1>(buf, KB, 1, BP, tw);
+        __syncthreads();
+        for (int u = tid; u < H * KB; u += nt) {
+            const int p = u / KB, j = u % KB;
+            const int kx = perm_freq<H>(p);
+            const T qx = (T)(kx < H / 2 ? kx : kx - H);
+            const T qz = (T)(kz0 + j);
+            const T q2 = qx * qx + qy * qy + qz * qz;
+            const T f = (fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1) * fd.inv_L3;
+            const V b = buf[p * BP + j];
+            buf[p * BP + j] = j < ncol ? cmake<V, T>(b.x * f, b.y * f) : cmake<V, T>(0, 0);
+        }
+        __syncthreads();
+        lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
+        __syncthreads();
+        for (int u = tid; u < H * KB; u += nt) {
+            const int ix = u / KB, j = u % KB;
+            if (j < ncol) fd.gspec[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
+        }
         return;
     }
     if (UPDATE) {
@@ -533,6 +563,7 @@ static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStr
         case MODE_GRAD: launch_kernel((k_xpencils<T, H, MODE_GRAD>), g, b, 0, s, fd); break;
         case MODE_ADJ_SRC: launch_kernel((k_xpencils<T, H, MODE_ADJ_SRC>), g, b, 0, s, fd); break;
         case MODE_ADJ_ACC: launch_kernel((k_xpencils<T, H, MODE_ADJ_ACC>), g, b, 0, s, fd); break;
+        case MODE_RHO: launch_kernel((k_xpencils<T, H, MODE_RHO>), g, b, 0, s, fd); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

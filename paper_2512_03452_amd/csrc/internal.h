@@ -129,9 +129,9 @@ struct WorkItem {
 // descriptors are consecutive in the device array `fd`.
 // fwd_planes: R2C of ncomp grids (phi + c H^3 -> B1 + c spectrum); consume = clear
 //             the input and advance the step counter (the step's deposit).
-// xpencils:   mode MODE_STEP / MODE_GRAD / MODE_ADJ_SRC / MODE_ADJ_ACC (fft.hip).
+// xpencils:   mode MODE_STEP / MODE_GRAD / MODE_ADJ_SRC / MODE_ADJ_ACC / MODE_RHO (fft.hip).
 // inv_planes: C2R of ncomp spectra (gspec + c spectrum -> G + c H^3).
-enum { XP_STEP = 0, XP_GRAD = 1, XP_ADJ_SRC = 2, XP_ADJ_ACC = 3 };
+enum { XP_STEP = 0, XP_GRAD = 1, XP_ADJ_SRC = 2, XP_ADJ_ACC = 3, XP_RHO = 4 };
 template <typename T>
 hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s);
 template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, int mode, hipStream_t s);
@@ -170,6 +170,26 @@ hipError_t launch_xbar_order(T* xbar, T* bx, T* by, T* bz, const uint32_t* id, i
                              hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 int adj_window_bytes(bool fp64);
+// --- diagnostics (diag.hip) ---------------------------------------------------
+// One instance: the regularised density on the grid, the permuted half
+// spectrum alpha and the current particle positions.
+template <typename T> struct DiagDesc {
+    const T* rho;             // H^3
+    const cplx_t<T>* alpha;   // H x H x (H/2+1), (kx, ky) in FFT storage order
+    const T* x;
+    const T* y;
+    const T* z;
+    int64_t P;
+    int H;
+    int n1, n2;               // digit split of the FFT storage order: freq = pos / n2 + n1 (pos % n2)
+};
+// Sums per instance, in this order: sum rho, max rho, sum_q w|alpha_q|^2,
+// the same over |q| >= 4, Re alpha_0, sum sqrt(x^2 + y^2), sum |X|^2, 0.
+constexpr int DIAG_NVAL = 8;
+constexpr int DIAG_BLOCKS = 120;
+// part: n x DIAG_BLOCKS x DIAG_NVAL doubles of scratch; out: n x DIAG_NVAL doubles
+template <typename T> hipError_t launch_diag(const DiagDesc<T>* d, int n, double* part, double* out, hipStream_t s);
+
 template <typename T> hipError_t launch_dot(const T* u, const T* v, int64_t n, double* out, hipStream_t s);
 template <typename T> hipError_t launch_axpby(T* y, const T* x, T a, T b, int64_t n, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);

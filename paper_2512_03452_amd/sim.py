@@ -92,6 +92,13 @@ class Sim:
             return torch.view_as_complex(out)
         raise ValueError("which must be 'rho', 'alpha' or 'grad'")
 
+    def diagnostics(self):
+        """Diagnostics of the current state (sipf_diagnostics) as a dict:
+        step, mass, rho_max, hf_share, c_integral, r_num, m2."""
+        d = _lib.SipfDiag()
+        check(_lib.load().sipf_diagnostics(self._h, ctypes.byref(d)))
+        return d.as_dict()
+
     def profile(self, enable=True):
         """Start (clearing the accumulators) or stop per-phase event timing."""
         check(_lib.load().sipf_profile(self._h, 1 if enable else 0))
@@ -237,6 +244,12 @@ class Batch:
         out = torch.empty(shape, dtype=self.dtype, device=self.device)
         check(_lib.load().sipf_batch_get_field(self._h, int(i), code, ctypes.c_void_p(out.data_ptr()), 1))
         return torch.view_as_complex(out) if which == "alpha" else out
+
+    def diagnostics(self):
+        """Diagnostics of every instance (sipf_batch_diagnostics): list of dicts."""
+        d = (_lib.SipfDiag * self.n)()
+        check(_lib.load().sipf_batch_diagnostics(self._h, d))
+        return [x.as_dict() for x in d]
 
     def profile(self, enable=True):
         check(_lib.load().sipf_batch_profile(self._h, 1 if enable else 0))

@@ -207,6 +207,10 @@ def test_batch_and_tuning_null_handles():
     assert lib.sipf_batch_destroy(None) == L.SIPF_OK
     assert lib.sipf_use_graphs(None, 0) == L.SIPF_EINVAL
     assert lib.sipf_get_params(None, None, None) == L.SIPF_EINVAL
+    d = L.SipfDiag()
+    assert lib.sipf_diagnostics(None, ctypes.byref(d)) == L.SIPF_EINVAL
+    assert lib.sipf_batch_diagnostics(None, ctypes.byref(d)) == L.SIPF_EINVAL
+    assert ctypes.sizeof(L.SipfDiag) == 7 * 8
     p = L.default_params(H=12)
     best = L.SipfParams()
     ms = ctypes.c_double()
