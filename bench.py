@@ -177,6 +177,28 @@ def calibrate_copy(torch, nbytes=1 << 30, reps=5):
           flush=True)
 
 
+def e1_study(size):
+    """Convergence study of Sec. 5.1 against the stored radial reference:
+    mean truncated quantile discrepancy per (P, H) and the log2 slopes."""
+    from paper_2512_03452_amd import convergence
+    q_ref = convergence.load_reference(os.path.join(ROOT, "tests", "golden", "radial_e1_quantiles.txt"))
+    if size == "full":
+        Ps, Hs, hmax, nsim = [2 ** e for e in range(11, 21)], [8, 16, 32, 64, 128], 128, 30
+    else:
+        Ps, Hs, hmax, nsim = [2 ** 11, 2 ** 13, 2 ** 15], [8, 16, 32], 64, 8
+    pH = Ps[-1] if size == "full" else 2 ** 17
+    configs = [(P, hmax) for P in Ps] + [(pH, H) for H in Hs if (pH, H) != (Ps[-1], hmax)]
+    res, secs = convergence.run_study(configs, nsim, q_ref)
+    eP = [res[(P, hmax)]["mean"] for P in Ps]
+    eH = [res[(pH, H)]["mean"] for H in Hs]
+    runs = nsim * len(configs)
+    return {"nsim": nsim, "runs": runs, "steps": 2000, "gpu_seconds": secs,
+            "particle_steps_per_s": nsim * sum(P for P, _ in configs) * 2000 / secs,
+            "slope_P": convergence.slope(Ps, eP), "slope_H": convergence.slope(Hs, eH),
+            "P": Ps, "E_vs_P": eP, "H_at_P": pH, "H": Hs, "E_vs_H": eH,
+            "paper_slopes": {"P": -0.512, "H": -1.327}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +211,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--e1", default="reduced", choices=["none", "reduced", "full"],
+                    help="convergence study of Sec. 5.1: 8 runs of 6 configurations, or the full 30 x 14")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -269,7 +293,17 @@ def main():
                           / 1e9 / HBM_PEAK_GBS},
         "phases": phases,
     }
+    # run-time diagnostics of the state (one call = deposit, three FFT passes, reductions)
+    sim.diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        diag = sim.diagnostics()
+    out["diagnostics"] = dict(diag, ms_per_call=1e3 * (time.perf_counter() - t0) / 5)
     sim.close()
+    if args.e1 != "none":
+        print(f"# convergence study of Sec. 5.1 ({args.e1})", file=sys.stderr, flush=True)
+        out["e1"] = e1_study(args.e1)
     if not args.no_adjoint:
         print("# fwd+adjoint vs fwd on the adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(pkg, workloads, np, torch)

@@ -184,8 +184,8 @@ int sipf_get_field(sipf_ctx* ctx, int which, void* out, int on_device);
  * order-4 deposit of X^(n), F_H, the factor exp(-2 pi^2 |q|^2 / H0^2) and the
  * inverse transform (no filter when H0 < 0).  The sums are FP64 and
  * deterministic for a given particle order.  The state is left unchanged.
- * The first call allocates a small scratch buffer (about 8 KB per instance)
- * that the context keeps.  Synchronises.  Errors: SIPF_EINVAL for NULL
+ * The first call allocates a scratch buffer (about 64 KB per instance) that
+ * the context keeps.  Synchronises.  Errors: SIPF_EINVAL for NULL
  * arguments, SIPF_EDEVICE, SIPF_ENUMERIC as for sipf_sync.
  */
 typedef struct sipf_diag {

@@ -695,7 +695,7 @@ template <typename T> int get_positions_typed(Group* g, int i, void* out, int on
 // grid (rho_num), then the reductions; the deposit grids are cleared again.
 template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
     const int n = (int)g->in.size();
-    const size_t part_b = (size_t)n * DIAG_BLOCKS * DIAG_NVAL * sizeof(double);
+    const size_t part_b = (size_t)n * DIAG_MAX_BLOCKS * DIAG_NVAL * sizeof(double);
     const size_t res_b = (size_t)n * DIAG_NVAL * sizeof(double);
     const size_t dd_b = ((size_t)n * sizeof(DiagDesc<T>) + 255) / 256 * 256;
     const size_t fd_b = (size_t)n * sizeof(FieldDesc<T>);
@@ -708,6 +708,7 @@ template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
     FieldDesc<T>* fdev = (FieldDesc<T>*)(base + part_b + res_b + dd_b);
     std::vector<DiagDesc<T>> dd(n);
     std::vector<FieldDesc<T>> fd(n);
+    int nbmax = 1;
     for (int i = 0; i < n; ++i) {
         const Inst& I = g->in[i];
         FieldDesc<T> f = make_fdesc<T>(g, i);
@@ -724,6 +725,8 @@ template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
         d.H = I.H;
         d.n2 = fft_perm(I.H, 1);
         d.n1 = I.H / d.n2;
+        d.nb = diag_blocks(I.P, I.H);
+        nbmax = std::max(nbmax, d.nb);
         dd[i] = d;
     }
     HIPCHK(hipMemcpyAsync(ddev, dd.data(), n * sizeof(DiagDesc<T>), hipMemcpyHostToDevice, g->stream));
@@ -735,7 +738,7 @@ template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
         HIPCHK(launch_xpencils<T>(h.H, fdev + h.first, h.count, XP_RHO, g->stream));
         HIPCHK(launch_inv_planes<T>(h.H, fdev + h.first, h.count, 1, g->stream));
     }
-    HIPCHK(launch_diag<T>(ddev, n, part, res, g->stream));
+    HIPCHK(launch_diag<T>(ddev, n, nbmax, part, res, g->stream));
     std::vector<double> host((size_t)n * DIAG_NVAL);
     std::vector<uint32_t> steps(n);
     HIPCHK(hipMemcpyAsync(host.data(), res, res_b, hipMemcpyDeviceToHost, g->stream));

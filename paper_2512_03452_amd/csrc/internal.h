@@ -182,13 +182,18 @@ template <typename T> struct DiagDesc {
     int64_t P;
     int H;
     int n1, n2;               // digit split of the FFT storage order: freq = pos / n2 + n1 (pos % n2)
+    int nb;                   // workgroups reducing this instance, 1 .. DIAG_MAX_BLOCKS
 };
 // Sums per instance, in this order: sum rho, max rho, sum_q w|alpha_q|^2,
 // the same over |q| >= 4, Re alpha_0, sum sqrt(x^2 + y^2), sum |X|^2, 0.
 constexpr int DIAG_NVAL = 8;
-constexpr int DIAG_BLOCKS = 120;
-// part: n x DIAG_BLOCKS x DIAG_NVAL doubles of scratch; out: n x DIAG_NVAL doubles
-template <typename T> hipError_t launch_diag(const DiagDesc<T>* d, int n, double* part, double* out, hipStream_t s);
+constexpr int DIAG_MAX_BLOCKS = 1024;
+// workgroups for an instance with P particles on an H^3 grid
+int diag_blocks(int64_t P, int H);
+// part: n x DIAG_MAX_BLOCKS x DIAG_NVAL doubles of scratch; out: n x DIAG_NVAL
+// doubles; nbmax = max over instances of DiagDesc::nb
+template <typename T>
+hipError_t launch_diag(const DiagDesc<T>* d, int n, int nbmax, double* part, double* out, hipStream_t s);
 
 template <typename T> hipError_t launch_dot(const T* u, const T* v, int64_t n, double* out, hipStream_t s);
 template <typename T> hipError_t launch_axpby(T* y, const T* x, T a, T b, int64_t n, hipStream_t s);
