@@ -25,6 +25,8 @@ for 3D parabolic-parabolic chemotaxis systems", arXiv:2512.03452):
                   gradient (Algorithm 4), the split push (Algorithm 4) and the
                   Euler-Maruyama push (eq. ``rho_hat_update``); the direct
                   O(PH^3) SIPF step (Algorithm 1) used as a brute-force check.
+* ``sipf2d``   -- the step in two dimensions and the elliptic (eps = 0)
+                  field update used by the 2-D experiments of Sec. 5.2.
 * ``adjoint``  -- hand-written reverse mode of the SIPF-PIC step with the noise
                   held fixed (pathwise gradient of a final-density loss).
 * ``radial``   -- radially symmetric finite-volume reference solution and the
@@ -38,5 +40,5 @@ Every floating-point quantity is float64.  Where the paper is silent or
 ambiguous the reading taken is stated at the function that implements it.
 """
 
-from . import philox, stencil, sipf, adjoint, radial, diagnostics  # noqa: F401
+from . import philox, stencil, sipf, sipf2d, adjoint, radial, diagnostics  # noqa: F401
 from .sipf import Params  # noqa: F401

@@ -153,10 +153,16 @@ def inverse_transform(alpha):
 def mode_factors(prm):
     """A_q = 1/(1 + tau/eps (|xi|^2 + k^2)), B_q = 1/(|xi|^2 + k^2 + eps/tau).
 
-    Eq. ``alpha_hat_update`` / the mode update of Algorithm 4.
+    Eq. ``alpha_hat_update`` / the mode update of Algorithm 4.  With eps = 0 the
+    c-equation of eq. ``system`` is elliptic, -Lap c + k^2 c = rho: A_q = 0,
+    B_q = 1/(|xi|^2 + k^2), and alpha_0 := 0 when k = 0 (the periodic Poisson
+    problem fixes c only up to a constant and sees rho minus its mean).
     """
     xi = wavevectors(prm.H, prm.L)
     xi2 = (xi ** 2).sum(axis=0)
+    if prm.eps == 0:
+        s = xi2 + prm.k ** 2
+        return np.zeros_like(s), np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
     A = 1.0 / (1.0 + prm.dt / prm.eps * (xi2 + prm.k ** 2))
     B = 1.0 / (xi2 + prm.k ** 2 + prm.eps / prm.dt)
     return A, B

@@ -19,6 +19,13 @@ and weights F_gamma(lambda); node g + gamma is stored at (g + gamma) mod H.
       F_{..-1..} = -(2 - l_a) l_a (1 - l_a) / 6 * prod_{s != a} w_{j_s}(l_s)
   with w_0(l) = 1 - l, w_1(l) = l; the inner weights are
       F_j = prod_s w_{j_s}(l_s) * (1 + sum_k l_k (1 - l_k) / 2).
+
+Two dimensions (the 2-D experiments of Sec. 5.2 use "fourth-order
+particle-to-grid" without printing the weights).  Reading taken: the same
+construction with d = 2, Gamma_4 = {0,1}^2 plus the 8 nodes with one
+coordinate in {-1, 2} and the other in {0,1}; the inner correction sums over
+the two axes.  The weights still sum to one and reproduce polynomials of
+degree 3 (pinned).
 """
 
 import itertools
@@ -131,3 +138,43 @@ def dweights(lam, order):
             d.append(f)
         out.append(np.stack(d, axis=-1))
     return np.stack(out, axis=-2)
+
+
+# ---------------------------------------------------------------------------
+# two dimensions
+# ---------------------------------------------------------------------------
+_INNER2 = [tuple(j) for j in itertools.product((0, 1), repeat=2)]
+_OUTER2 = []
+for _a in range(2):
+    for _e in (-1, 2):
+        for _j in (0, 1):
+            _o = [_j]
+            _o.insert(_a, _e)
+            _OUTER2.append((tuple(_o), _a))
+
+OFFSETS2_2D = np.array(_INNER2, dtype=np.int64)                           # (4, 2)
+OFFSETS4_2D = np.array(_INNER2 + [o for o, _ in _OUTER2], dtype=np.int64)  # (12, 2)
+
+
+def offsets2d(order):
+    return OFFSETS2_2D if order == 2 else OFFSETS4_2D
+
+
+def weights2d(lam, order):
+    """F_gamma(lambda) in two dimensions; lam (..., 2) -> (..., n_nodes)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    ls = (lam[..., 0], lam[..., 1])
+    cols = []
+    if order == 2:
+        for j in _INNER2:
+            cols.append(_w(j[0], ls[0]) * _w(j[1], ls[1]))
+        return np.stack(cols, axis=-1)
+    if order != 4:
+        raise ValueError("order must be 2 or 4")
+    S = 1.0 + (ls[0] * (1.0 - ls[0]) + ls[1] * (1.0 - ls[1])) / 2.0
+    for j in _INNER2:
+        cols.append(_w(j[0], ls[0]) * _w(j[1], ls[1]) * S)
+    for o, a in _OUTER2:
+        b = 1 - a
+        cols.append(_outer1d(o[a], ls[a]) * _w(o[b], ls[b]))
+    return np.stack(cols, axis=-1)
