@@ -51,6 +51,23 @@
  *   - H must be a power of two with 8 <= H <= 128 (FP32) or 8 <= H <= 64
  *     (FP64): one yz-plane of the half spectrum must fit in the 160 KB of LDS
  *     of a gfx950 compute unit.  Other sizes return SIPF_EINVAL.
+ *
+ * Variants (Sec. 5.2):
+ *   - eps = 0 makes the c-equation elliptic, -lap c + k^2 c = rho: the mode
+ *     update becomes alpha_q = B_q beta_q with B_q = 1/(|xi_q|^2 + k^2), and
+ *     alpha_0 = 0 when k = 0 (the periodic problem only sees rho minus its
+ *     mean and fixes c up to a constant).  tau still sets the push.
+ *   - sipf_params.dim = 2 runs the same algorithm in two dimensions on
+ *     [-L/2, L/2)^2: the 12-node fourth-order deposit (the construction of
+ *     eq. 4ord with d = 2), bilinear gather, beta_q = L^-2 sum_j phi_j
+ *     exp(-2 pi i q.j/H).  Positions are P x 2; grids H x H (index ix*H + iy);
+ *     spectra H x (H/2+1) (index kx*(H/2+1) + ky, ky = 0..H/2); gradients
+ *     2 x H^2.  Split-step noise W^- = sqrt(mu tau) (z0, z1),
+ *     W^+ = sqrt(mu tau) (z2, z3); Euler-Maruyama W = sqrt(2 mu tau) (z0, z1).
+ *     H is a power of two with 8 <= H <= 4096 in both precisions (one row of
+ *     the spectrum and its twiddles fit in LDS).  sipf_adjoint and the test
+ *     entry points are 3-D only (SIPF_EINVAL); every other call works in 2-D
+ *     with the sizes above.
  */
 #ifndef SIPF_H
 #define SIPF_H
@@ -92,7 +109,7 @@ typedef struct sipf_params {
     double   L;            /* box side; Omega = [-L/2, L/2)^3, periodic            */
     double   chi;          /* chemotactic sensitivity (>= 0)                      */
     double   mu;           /* particle diffusivity (>= 0)                         */
-    double   eps;          /* relaxation constant of c (> 0)                      */
+    double   eps;          /* relaxation constant of c (>= 0; 0: elliptic)        */
     double   k;            /* degradation constant of c (>= 0)                    */
     double   M0;           /* total mass of the particles (>= 0)                  */
     double   dt;           /* time step tau (> 0)                                 */
@@ -102,12 +119,13 @@ typedef struct sipf_params {
     int32_t  g2p_order;    /* must be 2 (same remark)                             */
     int32_t  scheme;       /* SIPF_STRANG (default) or SIPF_EM                    */
     int32_t  precision;    /* SIPF_FP32 (default) or SIPF_FP64                    */
-    int32_t  tile;         /* binning tile side in cells; 0 = tuned default        */
+    int32_t  tile;         /* binning tile side in cells; 0 = tuned default; at most
+                              16 (3-D) or 64 (2-D) tiles per axis                 */
     int32_t  resort_every; /* re-sort period in steps; 0 = tuned default           */
     int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = tuned */
     uint64_t seed;         /* Philox key                                          */
     uint32_t instance;     /* fourth Philox counter word                          */
-    uint32_t reserved;     /* must be 0                                           */
+    uint32_t dim;          /* space dimension: 3 (0 means 3) or 2                 */
 } sipf_params;
 
 typedef struct sipf_ctx sipf_ctx;

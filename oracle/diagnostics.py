@@ -21,15 +21,17 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 import numpy as np
 
-from . import sipf
+from . import sipf, sipf2d
 
 
 def rho_num(X, prm):
-    """rho_num at the grid nodes (H, H, H): Re F_H^{-1}(Phi F_H I(rho_hat_P))."""
+    """rho_num at the grid nodes, (H, H, H) or (H, H) for 2-D positions:
+    Re F_H^{-1}(Phi F_H I(rho_hat_P))."""
     X = np.asarray(X, dtype=np.float64)
-    phi = sipf.deposit(X, prm.M0 / X.shape[0], prm.H, prm.L, prm.p2g_order)
-    beta = sipf.forward_transform(phi, prm.L)
-    return sipf.inverse_transform(sipf.filter_factors(prm) * beta).real
+    m = sipf2d if X.shape[1] == 2 else sipf
+    phi = m.deposit(X, prm.M0 / X.shape[0], prm.H, prm.L, prm.p2g_order)
+    beta = m.forward_transform(phi, prm.L)
+    return m.inverse_transform(m.filter_factors(prm) * beta).real
 
 
 def rho_num_direct(X, prm, nodes, images=1):
@@ -51,9 +53,9 @@ def rho_num_direct(X, prm, nodes, images=1):
 
 
 def grid_mass(rho, L):
-    """sum_j rho(x_j) h^3 with h = L / H."""
+    """sum_j rho(x_j) h^d with h = L / H (d = rho.ndim)."""
     H = rho.shape[-1]
-    return float(rho.sum() * (L / H) ** 3)
+    return float(rho.sum() * (L / H) ** rho.ndim)
 
 
 def hf_share(alpha, qmin=4.0):
@@ -61,7 +63,10 @@ def hf_share(alpha, qmin=4.0):
     alpha = np.asarray(alpha)
     H = alpha.shape[-1]
     q = sipf.freqs(H).astype(np.float64)
-    q2 = q[:, None, None] ** 2 + q[None, :, None] ** 2 + q[None, None, :] ** 2
+    if alpha.ndim == 2:
+        q2 = q[:, None] ** 2 + q[None, :] ** 2
+    else:
+        q2 = q[:, None, None] ** 2 + q[None, :, None] ** 2 + q[None, None, :] ** 2
     e = np.abs(alpha) ** 2
     tot = e.sum()
     return float(e[q2 >= qmin * qmin].sum() / tot) if tot > 0 else 0.0
@@ -78,8 +83,9 @@ def second_moment(X):
 
 
 def c_integral(alpha, L):
-    """Integral of c_hat over the box: L^3 Re alpha_0."""
-    return float(L ** 3 * np.real(np.asarray(alpha)[0, 0, 0]))
+    """Integral of c_hat over the box: L^d Re alpha_0."""
+    alpha = np.asarray(alpha)
+    return float(L ** alpha.ndim * np.real(alpha.flat[0]))
 
 
 def all_diagnostics(X, alpha, prm):

@@ -39,7 +39,7 @@ class SipfParams(ctypes.Structure):
         ("H", ctypes.c_int32), ("p2g_order", ctypes.c_int32), ("g2p_order", ctypes.c_int32),
         ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("resort_every", ctypes.c_int32), ("chunk", ctypes.c_int32),
-        ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32), ("dim", ctypes.c_uint32),
     ]
 
 

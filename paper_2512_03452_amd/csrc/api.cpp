@@ -50,15 +50,22 @@ int ilog2(int v) {
     return r;
 }
 
+int dim_of(const sipf_params* p) { return p->dim == 2 ? 2 : 3; }
+size_t grid_size(int H, int d) { return d == 2 ? (size_t)H * H : (size_t)H * H * H; }
+size_t spec_size(int H, int d) { return d == 2 ? (size_t)H * (H / 2 + 1) : (size_t)H * H * (H / 2 + 1); }
+
 int validate(const sipf_params* p, int64_t P) {
     if (!p) return fail(SIPF_EINVAL, "params is NULL");
     if (p->precision != SIPF_FP32 && p->precision != SIPF_FP64) return fail(SIPF_EINVAL, "precision must be SIPF_FP32 or SIPF_FP64");
-    if (!fft_size_supported(p->H, p->precision == SIPF_FP64))
+    if (p->dim != 0 && p->dim != 2 && p->dim != 3) return fail(SIPF_EINVAL, "dim must be 0, 2 or 3");
+    if (dim_of(p) == 3 && !fft_size_supported(p->H, p->precision == SIPF_FP64))
         return fail(SIPF_EINVAL, "H must be a power of two in [8, 128] (FP32) or [8, 64] (FP64)");
+    if (dim_of(p) == 2 && !fft2d_size_supported(p->H))
+        return fail(SIPF_EINVAL, "H must be a power of two in [8, 4096] in two dimensions");
     auto fin = [](double v) { return std::isfinite(v); };
     if (!(fin(p->L) && p->L > 0)) return fail(SIPF_EINVAL, "L must be finite and > 0");
     if (!(fin(p->dt) && p->dt > 0)) return fail(SIPF_EINVAL, "dt must be finite and > 0");
-    if (!(fin(p->eps) && p->eps > 0)) return fail(SIPF_EINVAL, "eps must be finite and > 0");
+    if (!(fin(p->eps) && p->eps >= 0)) return fail(SIPF_EINVAL, "eps must be finite and >= 0");
     if (!(fin(p->mu) && p->mu >= 0)) return fail(SIPF_EINVAL, "mu must be finite and >= 0");
     if (!(fin(p->chi) && p->chi >= 0)) return fail(SIPF_EINVAL, "chi must be finite and >= 0");
     if (!(fin(p->k) && p->k >= 0)) return fail(SIPF_EINVAL, "k must be finite and >= 0");
@@ -67,11 +74,12 @@ int validate(const sipf_params* p, int64_t P) {
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
     if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
     if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
-    if (p->tile != 0 && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > 16))
-        return fail(SIPF_EINVAL, "tile must be 0 or a power of two with H/16 <= tile <= H");
+    const int max_tiles = dim_of(p) == 2 ? 64 : 16;
+    if (p->tile != 0 && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > max_tiles))
+        return fail(SIPF_EINVAL, dim_of(p) == 2 ? "tile must be 0 or a power of two with H/64 <= tile <= H"
+                                                : "tile must be 0 or a power of two with H/16 <= tile <= H");
     if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
     if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 4096)) return fail(SIPF_EINVAL, "chunk must be 0 or in [256, 4096]");
-    if (p->reserved != 0) return fail(SIPF_EINVAL, "reserved must be 0");
     if (P < 1 || P >= (int64_t(1) << 32)) return fail(SIPF_EINVAL, "P must be in [1, 2^32)");
     return SIPF_OK;
 }
@@ -82,8 +90,14 @@ double filter_h0(const sipf_params* p) {
 }
 
 // Defaults where the parameters leave the tuning open (0): an 8-cell tile at
-// H = 128 and H/8 below, a re-sort every 4 steps, items of up to 4096.
+// H = 128 and H/8 below (3-D), 16-cell tiles up to H = 1024 and H/64 above
+// (2-D), a re-sort every 4 steps, items of up to 4096.
 int default_tile(const sipf_params* p) {
+    if (dim_of(p) == 2) {
+        int t = p->tile ? p->tile : std::min(p->H, std::max(16, p->H / 64));
+        if (p->H / t > 64) t = p->H / 64;
+        return t;
+    }
     int t = p->tile ? p->tile : (p->H >= 128 ? 8 : (p->H >= 16 ? p->H / 8 : p->H));
     if (p->H / t > 16) t = p->H / 16;
     return t;
@@ -98,6 +112,7 @@ struct Inst {
     sipf_params prm{};
     int64_t P = 0;
     int H = 0;
+    int dim = 3;
     int tile = 8;
     void* xs[2] = {nullptr, nullptr};
     void* ys[2] = {nullptr, nullptr};
@@ -117,6 +132,7 @@ struct HClass {
 
 struct Group {
     int prec = SIPF_FP32;
+    int dim = 3;  // shared by every instance
     size_t tsize = 4;
     int scheme = SIPF_STRANG;
     hipStream_t stream = nullptr;
@@ -192,6 +208,7 @@ template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
     d.step = g->steps + i;
     d.err = g->errs + i;
     d.H = I.H;
+    d.dim = I.dim;
     d.scheme = p.scheme;
     d.hl = (T)(I.H / p.L);
     d.L = (T)p.L;
@@ -207,7 +224,7 @@ template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
     d.gmargin = p.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.52 * (double)d.hl) : 0;
     d.tshift = ilog2(I.tile);
     const int nt = I.H / I.tile;
-    d.nkeys = nt * nt * nt;
+    d.nkeys = I.dim == 2 ? nt * nt : nt * nt * nt;
     return d;
 }
 
@@ -221,10 +238,11 @@ template <typename T> FieldDesc<T> make_fdesc(const Group* g, int i) {
     f.gspec = (cplx_t<T>*)I.gspec;
     f.G = (T*)I.G;
     f.step = g->steps + i;
-    f.dt_over_eps = (T)(p.dt / p.eps);
+    f.elliptic = p.eps == 0.0 ? 1 : 0;
+    f.dt_over_eps = f.elliptic ? (T)0 : (T)(p.dt / p.eps);
     f.eps_over_dt = (T)(p.eps / p.dt);
     f.k2 = (T)(p.k * p.k);
-    f.inv_L3 = (T)(1.0 / (p.L * p.L * p.L));
+    f.inv_Ld = (T)(I.dim == 2 ? 1.0 / (p.L * p.L) : 1.0 / (p.L * p.L * p.L));
     f.two_pi_over_L = (T)(2.0 * M_PI / p.L);
     const double h0 = filter_h0(&p);
     f.filt = p.H0 < 0 ? (T)0 : (T)(2.0 * M_PI * M_PI / (h0 * h0));
@@ -308,13 +326,34 @@ template <typename T> int do_sort(Group* g) {
     const int dst = 1 - g->cur;
     {
         Timed t(g, SIPF_PHASE_SORT);
-        HIPCHK(launch_sort<T>(pdesc_dev<T>(g, g->cur), pdesc_dev<T>(g, dst), g->chunks, g->nchunks, (int)g->in.size(),
+        HIPCHK(launch_sort<T>(g->dim, pdesc_dev<T>(g, g->cur), pdesc_dev<T>(g, dst), g->chunks, g->nchunks, (int)g->in.size(),
                               g->counts, g->cursor, g->seg, g->seg_off, g->seg_n, g->items, g->nitems, g->chunk,
                               g->stream));
     }
     g->cur = dst;
     g->since_sort = 0;
     return SIPF_OK;
+}
+
+// The passes of a step in the group's dimension.
+template <typename T>
+hipError_t particles_any(const Group* g, const PartDesc<T>* pd, bool deposit, bool push) {
+    return g->dim == 2 ? launch_particles2<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
+                                              g->win_bytes, g->stream)
+                       : launch_particles<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
+                                             g->win_bytes, g->stream);
+}
+template <typename T> hipError_t field_fwd(const Group* g, int H, const FieldDesc<T>* fd, int count, bool consume) {
+    return g->dim == 2 ? launch_fwd_rows2<T>(H, fd, count, consume, g->stream)
+                       : launch_fwd_planes<T>(H, fd, count, 1, consume, g->stream);
+}
+template <typename T> hipError_t field_x(const Group* g, int H, const FieldDesc<T>* fd, int count, int mode) {
+    return g->dim == 2 ? launch_xrows2<T>(H, fd, count, mode, g->stream)
+                       : launch_xpencils<T>(H, fd, count, mode, g->stream);
+}
+template <typename T> hipError_t field_inv(const Group* g, int H, const FieldDesc<T>* fd, int count, int ncomp) {
+    return g->dim == 2 ? launch_inv_rows2<T>(H, fd, count, ncomp, g->stream)
+                       : launch_inv_planes<T>(H, fd, count, ncomp, g->stream);
 }
 
 // One step n-1 -> n of every instance: particle pass (deposit X^(n-1), gather
@@ -327,23 +366,20 @@ template <typename T> int enqueue_step(Group* g) {
     }
     {
         Timed t(g, SIPF_PHASE_PARTICLES);
-        HIPCHK(launch_particles<T>(pdesc_dev<T>(g, g->cur), g->items, g->nitems, g->pgrid, true, true, g->scheme,
-                                   g->win_bytes, g->stream));
+        HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, true));
     }
     {
         Timed t(g, SIPF_PHASE_FWD);
-        for (const HClass& h : g->classes)
-            HIPCHK(launch_fwd_planes<T>(h.H, fdesc_dev<T>(g, h.first), h.count, 1, true, g->stream));
+        for (const HClass& h : g->classes) HIPCHK(field_fwd<T>(g, h.H, fdesc_dev<T>(g, h.first), h.count, true));
     }
     {
         Timed t(g, SIPF_PHASE_XPENCIL);
-        for (const HClass& h : g->classes)
-            HIPCHK(launch_xpencils<T>(h.H, fdesc_dev<T>(g, h.first), h.count, XP_STEP, g->stream));
+        for (const HClass& h : g->classes) HIPCHK(field_x<T>(g, h.H, fdesc_dev<T>(g, h.first), h.count, XP_STEP));
     }
     {
         Timed t(g, SIPF_PHASE_INV);
         for (const HClass& h : g->classes)
-            HIPCHK(launch_inv_planes<T>(h.H, fdesc_dev<T>(g, h.first), h.count, 3, g->stream));
+            HIPCHK(field_inv<T>(g, h.H, fdesc_dev<T>(g, h.first), h.count, g->dim));
     }
     g->since_sort++;
     g->n_host++;
@@ -443,6 +479,22 @@ int check_err(Group* g) {
     return SIPF_OK;
 }
 
+// 2-D: natural (kx, ky) half spectrum H x (H/2+1) <-> the device layout
+// (H/2+1) x H, ky-major with kx in the FFT storage order
+void permute_spectrum2(const void* src, void* dst, int H, size_t tsize, bool to_perm) {
+    const int HH = H / 2 + 1;
+    const size_t e = 2 * tsize;
+    for (int kx = 0; kx < H; ++kx) {
+        const int p = fft_perm(H, kx);
+        for (int ky = 0; ky < HH; ++ky) {
+            const size_t nat = (size_t)kx * HH + ky;
+            const size_t per = (size_t)ky * H + p;
+            if (to_perm) std::memcpy((char*)dst + per * e, (const char*)src + nat * e, e);
+            else std::memcpy((char*)dst + nat * e, (const char*)src + per * e, e);
+        }
+    }
+}
+
 // natural <-> permuted (kx, ky) layout of a half spectrum (host arrays of 2*T per entry)
 void permute_spectrum(const void* src, void* dst, int H, size_t tsize, bool to_perm) {
     const int HH = H / 2 + 1;
@@ -485,23 +537,24 @@ template <typename T> int alloc_group(Group* g) {
     for (int i = 0; i < n; ++i) {
         Inst& I = g->in[i];
         const int64_t P = I.P;
-        const size_t H3 = (size_t)I.H * I.H * I.H;
-        const size_t nspec = (size_t)I.H * I.H * (I.H / 2 + 1);
+        const int d = I.dim;
+        const size_t ng = grid_size(I.H, d);
+        const size_t nspec = spec_size(I.H, d);
         for (int s = 0; s < 2; ++s) {
             if ((rc = dalloc(g, &I.xs[s], P * sizeof(T)))) return rc;
             if ((rc = dalloc(g, &I.ys[s], P * sizeof(T)))) return rc;
-            if ((rc = dalloc(g, &I.zs[s], P * sizeof(T)))) return rc;
+            if (d == 3 && (rc = dalloc(g, &I.zs[s], P * sizeof(T)))) return rc;
             if ((rc = dalloc(g, (void**)&I.ids[s], P * sizeof(uint32_t)))) return rc;
         }
-        if ((rc = dalloc(g, &I.phi, H3 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.phi, ng * sizeof(T)))) return rc;
         if ((rc = dalloc(g, &I.B1, nspec * 2 * sizeof(T)))) return rc;
         if ((rc = dalloc(g, &I.alpha, nspec * 2 * sizeof(T)))) return rc;
-        if ((rc = dalloc(g, &I.gspec, 3 * nspec * 2 * sizeof(T)))) return rc;
-        if ((rc = dalloc(g, &I.G, 3 * H3 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.gspec, d * nspec * 2 * sizeof(T)))) return rc;
+        if ((rc = dalloc(g, &I.G, d * ng * sizeof(T)))) return rc;
         for (int64_t b = 0; b < P; b += sc) chunks.push_back(SortChunk{b, i, 0});
         const int nt = I.H / I.tile;
         seg_off[i] = (int)cap;
-        cap += (P + g->chunk - 1) / g->chunk + (int64_t)nt * nt * nt;
+        cap += (P + g->chunk - 1) / g->chunk + (d == 2 ? (int64_t)nt * nt : (int64_t)nt * nt * nt);
     }
     if (cap >= (int64_t(1) << 31) || chunks.size() >= (size_t(1) << 31))
         return fail(SIPF_EINVAL, "too many particles in one group");
@@ -525,7 +578,8 @@ template <typename T> int alloc_group(Group* g) {
     HIPCHK(hipMemset(g->counts, 0, (size_t)n * mk * sizeof(uint32_t)));
     HIPCHK(hipMemset(g->steps, 0, n * sizeof(uint32_t)));
     HIPCHK(hipMemset(g->errs, 0, n * sizeof(int)));
-    g->pgrid = std::max(1, std::min(g->items_cap, particle_resident_blocks<T>(g->scheme, g->win_bytes)));
+    g->pgrid = std::max(1, std::min(g->items_cap, g->dim == 2 ? particle_resident_blocks2<T>(g->scheme, g->win_bytes)
+                                                                : particle_resident_blocks<T>(g->scheme, g->win_bytes)));
     return upload_descs<T>(g);
 }
 
@@ -540,11 +594,12 @@ template <typename T> int load_positions(Group* g, int i, const void* X0, int on
     }
     // host positions go through a temporary device buffer freed before return
     void* tmp = nullptr;
-    if (hipMalloc(&tmp, 3 * P * sizeof(T)) != hipSuccess) {
+    const int64_t nv = (int64_t)g->in[i].dim * P;
+    if (hipMalloc(&tmp, nv * sizeof(T)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(SIPF_ENOMEM, "hipMalloc failed for the staging buffer");
     }
-    hipError_t e = hipMemcpyAsync(tmp, X0, 3 * P * sizeof(T), hipMemcpyHostToDevice, g->stream);
+    hipError_t e = hipMemcpyAsync(tmp, X0, nv * sizeof(T), hipMemcpyHostToDevice, g->stream);
     if (e == hipSuccess) e = launch_load_positions<T>((const T*)tmp, P, L, d0, g->errs + i, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     (void)hipFree(tmp);
@@ -555,10 +610,10 @@ template <typename T> int load_positions(Group* g, int i, const void* X0, int on
 template <typename T> int init_fields(Group* g, int i, const void* alpha0, int alpha0_on_device) {
     const Inst& I = g->in[i];
     const int H = I.H;
-    const size_t nspec = (size_t)H * H * (H / 2 + 1);
-    const size_t H3 = (size_t)H * H * H;
-    HIPCHK(launch_fill<T>((T*)I.phi, H3, (T)0, g->stream));
-    HIPCHK(launch_fill<T>((T*)I.G, 3 * H3, (T)0, g->stream));
+    const size_t nspec = spec_size(H, I.dim);
+    const size_t ng = grid_size(H, I.dim);
+    HIPCHK(launch_fill<T>((T*)I.phi, ng, (T)0, g->stream));
+    HIPCHK(launch_fill<T>((T*)I.G, I.dim * ng, (T)0, g->stream));
     if (alpha0 == nullptr) {
         HIPCHK(launch_fill<T>((T*)I.alpha, 2 * nspec, (T)0, g->stream));
         return SIPF_OK;
@@ -568,10 +623,11 @@ template <typename T> int init_fields(Group* g, int i, const void* alpha0, int a
     else std::memcpy(nat.data(), alpha0, nat.size() * sizeof(T));
     for (T v : nat)
         if (!std::isfinite((double)v)) return fail(SIPF_ENUMERIC, "non-finite alpha0");
-    permute_spectrum(nat.data(), per.data(), H, sizeof(T), true);
+    if (I.dim == 2) permute_spectrum2(nat.data(), per.data(), H, sizeof(T), true);
+    else permute_spectrum(nat.data(), per.data(), H, sizeof(T), true);
     HIPCHK(hipMemcpyAsync(I.alpha, per.data(), per.size() * sizeof(T), hipMemcpyHostToDevice, g->stream));
-    HIPCHK(launch_xpencils<T>(H, fdesc_dev<T>(g, g->fslot[i]), 1, XP_GRAD, g->stream));
-    HIPCHK(launch_inv_planes<T>(H, fdesc_dev<T>(g, g->fslot[i]), 1, 3, g->stream));
+    HIPCHK(field_x<T>(g, H, fdesc_dev<T>(g, g->fslot[i]), 1, XP_GRAD));
+    HIPCHK(field_inv<T>(g, H, fdesc_dev<T>(g, g->fslot[i]), 1, I.dim));
     HIPCHK(hipStreamSynchronize(g->stream));
     return SIPF_OK;
 }
@@ -611,17 +667,19 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
         if (!X0[i]) return fail(SIPF_EINVAL, "X0 is NULL");
         if (prm[i].precision != prm[0].precision) return fail(SIPF_EINVAL, "all instances must share the precision");
         if (prm[i].scheme != prm[0].scheme) return fail(SIPF_EINVAL, "all instances must share the scheme");
+        if (dim_of(&prm[i]) != dim_of(&prm[0])) return fail(SIPF_EINVAL, "all instances must share the dimension");
     }
     const size_t ts = prm[0].precision == SIPF_FP32 ? 4 : 8;
     if (!x0_on_device) {
         // reject non-finite host input before touching the device
         for (int i = 0; i < n; ++i)
-            for (int64_t j = 0; j < 3 * P[i]; ++j) {
+            for (int64_t j = 0; j < dim_of(&prm[i]) * P[i]; ++j) {
                 const double v = ts == 4 ? (double)((const float*)X0[i])[j] : ((const double*)X0[i])[j];
                 if (!std::isfinite(v)) return fail(SIPF_ENUMERIC, "non-finite value in X0");
             }
     }
     g->prec = prm[0].precision;
+    g->dim = dim_of(&prm[0]);
     g->tsize = ts;
     g->scheme = prm[0].scheme;
     g->stream = (hipStream_t)hip_stream;
@@ -634,6 +692,7 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
         I.prm = prm[i];
         I.P = P[i];
         I.H = prm[i].H;
+        I.dim = dim_of(&prm[i]);
         I.tile = default_tile(&prm[i]);
     }
     return SIPF_OK;
@@ -647,22 +706,22 @@ int init_any(Group* g, const void* const* X0, int x0_on_device, const void* alph
 template <typename T> int get_field_typed(Group* g, int i, int which, void* out, int on_device) {
     const Inst& I = g->in[i];
     const int H = I.H;
-    const size_t H3 = (size_t)H * H * H;
-    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+    const size_t ng = grid_size(H, I.dim);
+    const size_t nspec = spec_size(H, I.dim);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (which == SIPF_FIELD_RHO) {
         // deposit-only pass over every instance, then clear every deposit again
-        HIPCHK(launch_particles<T>(pdesc_dev<T>(g, g->cur), g->items, g->nitems, g->pgrid, true, false, g->scheme,
-                                   g->win_bytes, g->stream));
-        HIPCHK(hipMemcpyAsync(out, I.phi, H3 * sizeof(T), kind, g->stream));
-        for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)J.H * J.H * J.H, (T)0, g->stream));
+        HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, false));
+        HIPCHK(hipMemcpyAsync(out, I.phi, ng * sizeof(T), kind, g->stream));
+        for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)grid_size(J.H, J.dim), (T)0, g->stream));
     } else if (which == SIPF_FIELD_GRAD) {
-        HIPCHK(hipMemcpyAsync(out, I.G, 3 * H3 * sizeof(T), kind, g->stream));
+        HIPCHK(hipMemcpyAsync(out, I.G, I.dim * ng * sizeof(T), kind, g->stream));
     } else if (which == SIPF_FIELD_ALPHA) {
         std::vector<T> per(2 * nspec), nat(2 * nspec);
         HIPCHK(hipMemcpyAsync(per.data(), I.alpha, per.size() * sizeof(T), hipMemcpyDeviceToHost, g->stream));
         HIPCHK(hipStreamSynchronize(g->stream));
-        permute_spectrum(per.data(), nat.data(), H, sizeof(T), false);
+        if (I.dim == 2) permute_spectrum2(per.data(), nat.data(), H, sizeof(T), false);
+        else permute_spectrum(per.data(), nat.data(), H, sizeof(T), false);
         if (on_device) HIPCHK(hipMemcpy(out, nat.data(), nat.size() * sizeof(T), hipMemcpyHostToDevice));
         else std::memcpy(out, nat.data(), nat.size() * sizeof(T));
     } else {
@@ -678,9 +737,10 @@ template <typename T> int get_positions_typed(Group* g, int i, void* out, int on
         HIPCHK(launch_unsort<T>(&d, (T*)out, g->stream));
     } else {
         void* tmp = nullptr;
-        HIPCHK(hipMalloc(&tmp, 3 * d.P * sizeof(T)));
+        const size_t bytes = (size_t)d.dim * d.P * sizeof(T);
+        HIPCHK(hipMalloc(&tmp, bytes));
         hipError_t e = launch_unsort<T>(&d, (T*)tmp, g->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, 3 * d.P * sizeof(T), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, g->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         (void)hipFree(tmp);
         if (e != hipSuccess) return fail(SIPF_EDEVICE, std::string("get_positions: ") + hipGetErrorString(e));
@@ -723,38 +783,41 @@ template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
         d.z = (const T*)I.zs[g->cur];
         d.P = I.P;
         d.H = I.H;
-        d.n2 = fft_perm(I.H, 1);
-        d.n1 = I.H / d.n2;
-        d.nb = diag_blocks(I.P, I.H);
+        d.dim = I.dim;
+        d.pm = I.H > 256 ? I.H / 16 : I.H;
+        d.pt = I.H > 256 ? 16 : 1;
+        d.n2 = fft_perm(d.pm, 1);
+        d.n1 = d.pm / d.n2;
+        d.nb = diag_blocks(I.P, (int64_t)grid_size(I.H, I.dim));
         nbmax = std::max(nbmax, d.nb);
         dd[i] = d;
     }
     HIPCHK(hipMemcpyAsync(ddev, dd.data(), n * sizeof(DiagDesc<T>), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(fdev, fd.data(), fd_b, hipMemcpyHostToDevice, g->stream));
-    HIPCHK(launch_particles<T>(pdesc_dev<T>(g, g->cur), g->items, g->nitems, g->pgrid, true, false, g->scheme,
-                               g->win_bytes, g->stream));
+    HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, false));
     for (const HClass& h : g->classes) {
-        HIPCHK(launch_fwd_planes<T>(h.H, fdev + h.first, h.count, 1, true, g->stream));
-        HIPCHK(launch_xpencils<T>(h.H, fdev + h.first, h.count, XP_RHO, g->stream));
-        HIPCHK(launch_inv_planes<T>(h.H, fdev + h.first, h.count, 1, g->stream));
+        HIPCHK(field_fwd<T>(g, h.H, fdev + h.first, h.count, true));
+        HIPCHK(field_x<T>(g, h.H, fdev + h.first, h.count, XP_RHO));
+        HIPCHK(field_inv<T>(g, h.H, fdev + h.first, h.count, 1));
     }
     HIPCHK(launch_diag<T>(ddev, n, nbmax, part, res, g->stream));
     std::vector<double> host((size_t)n * DIAG_NVAL);
     std::vector<uint32_t> steps(n);
     HIPCHK(hipMemcpyAsync(host.data(), res, res_b, hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipMemcpyAsync(steps.data(), g->steps, n * sizeof(uint32_t), hipMemcpyDeviceToHost, g->stream));
-    for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)J.H * J.H * J.H, (T)0, g->stream));
+    for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)grid_size(J.H, J.dim), (T)0, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
     for (int i = 0; i < n; ++i) {
         const Inst& I = g->in[i];
         const double* v = host.data() + (size_t)i * DIAG_NVAL;
         const double L = I.prm.L, h = L / I.H;
+        const double hd = I.dim == 2 ? h * h : h * h * h, Ld = I.dim == 2 ? L * L : L * L * L;
         sipf_diag& o = out[i];
         o.step = steps[i];
-        o.mass = v[0] * h * h * h;
+        o.mass = v[0] * hd;
         o.rho_max = v[1];
         o.hf_share = v[2] > 0 ? v[3] / v[2] : 0.0;
-        o.c_integral = L * L * L * v[4];
+        o.c_integral = Ld * v[4];
         o.r_num = v[5] / (double)I.P;
         o.m2 = v[6] / (double)I.P;
     }
@@ -1026,7 +1089,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
         const int64_t base = sgi * K;
         const int len = (int)std::min<int64_t>(K, N - base);
-        HIPCHK(launch_sort<T>(ps_dev + sgi, ps_dev + nseg, c->chunks, c->nchunks, 1, c->counts, c->cursor, c->seg,
+        HIPCHK(launch_sort<T>(3, ps_dev + sgi, ps_dev + nseg, c->chunks, c->nchunks, 1, c->counts, c->cursor, c->seg,
                               c->seg_off, c->seg_n, c->items, c->nitems, c->chunk, c->stream));
         if ((rc = grad_of_tape(base))) return rc;
         for (int m = 1; m < len; ++m) {
@@ -1108,8 +1171,7 @@ struct SnapHeader {
 
 int save_ctx(sipf_ctx* c, const char* path) {
     const Inst& I = c->in[0];
-    const int H = I.H;
-    const size_t nspec = (size_t)H * H * (H / 2 + 1);
+    const size_t nspec = spec_size(I.H, I.dim);
     SnapHeader h{};
     std::memcpy(h.magic, kMagic, 8);
     h.version = kVersion;
@@ -1118,7 +1180,7 @@ int save_ctx(sipf_ctx* c, const char* path) {
     h.P = I.P;
     int rc;
     if ((rc = get_step_any(c, 0, &h.n))) return rc;
-    std::vector<char> X((size_t)I.P * 3 * c->tsize), A(2 * nspec * c->tsize);
+    std::vector<char> X((size_t)I.P * I.dim * c->tsize), A(2 * nspec * c->tsize);
     if ((rc = get_positions_any(c, 0, X.data(), 0))) return rc;
     if ((rc = get_field_any(c, 0, SIPF_FIELD_ALPHA, A.data(), 0))) return rc;
     FILE* f = std::fopen(path, "wb");
@@ -1139,10 +1201,12 @@ int load_ctx(const char* path, void* hip_stream, sipf_ctx** out) {
               h.version == kVersion && (h.tsize == 4 || h.tsize == 8) &&
               h.tsize == (h.prm.precision == SIPF_FP32 ? 4u : 8u) && h.P >= 1 && h.P < (int64_t(1) << 32) &&
               h.n >= 0 && h.n < (int64_t(1) << 32);
-    if (ok) ok = fft_size_supported(h.prm.H, h.prm.precision == SIPF_FP64);
+    if (ok) ok = h.prm.dim == 0 || h.prm.dim == 2 || h.prm.dim == 3;
+    if (ok) ok = dim_of(&h.prm) == 2 ? fft2d_size_supported(h.prm.H) : fft_size_supported(h.prm.H, h.prm.precision == SIPF_FP64);
     if (ok) {
-        const size_t nspec = (size_t)h.prm.H * h.prm.H * (h.prm.H / 2 + 1);
-        X.resize((size_t)h.P * 3 * h.tsize);
+        const int d = dim_of(&h.prm);
+        const size_t nspec = spec_size(h.prm.H, d);
+        X.resize((size_t)h.P * d * h.tsize);
         A.resize(2 * nspec * h.tsize);
         ok = std::fread(X.data(), 1, X.size(), f) == X.size() && std::fread(A.data(), 1, A.size(), f) == A.size();
         char extra;
@@ -1221,6 +1285,7 @@ int sipf_params_default(sipf_params* p) {
     p->g2p_order = 2;
     p->scheme = SIPF_STRANG;
     p->precision = SIPF_FP32;
+    p->dim = 3;
     return SIPF_OK;
 }
 
@@ -1311,6 +1376,7 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
     if (!c || !loss || !dchi || !dmu || !dX0) return fail(SIPF_EINVAL, "NULL argument");
     if (nsteps < 1 || nsteps > (int64_t)1 << 30) return fail(SIPF_EINVAL, "nsteps must be >= 1");
     if (ckpt_every < 1) return fail(SIPF_EINVAL, "ckpt_every must be >= 1");
+    if (c->dim != 3) return fail(SIPF_EINVAL, "sipf_adjoint is available in three dimensions only");
     return c->prec == SIPF_FP32
                ? adjoint_typed<float>(c, nsteps, ckpt_every, (const float*)phi_bar, loss, dchi, dmu, (float*)dX0)
                : adjoint_typed<double>(c, nsteps, ckpt_every, (const double*)phi_bar, loss, dchi, dmu, (double*)dX0);
@@ -1364,8 +1430,13 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
         return SIPF_OK;
     };
     std::vector<int> tiles;
-    for (int t = 4; t <= 32; t *= 2)
-        if (t <= prm->H && prm->H / t <= 16) tiles.push_back(t);
+    if (dim_of(prm) == 2) {
+        for (int t = 8; t <= 128; t *= 2)
+            if (t <= prm->H && prm->H / t <= 64) tiles.push_back(t);
+    } else {
+        for (int t = 4; t <= 32; t *= 2)
+            if (t <= prm->H && prm->H / t <= 16) tiles.push_back(t);
+    }
     if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
     if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 4096}))) return rc;
     if ((rc = try_axis(&sipf_params::resort_every, {2, 4, 8, 16}))) return rc;
@@ -1464,6 +1535,7 @@ int sipf_dbg_philox(uint64_t seed, int64_t count, const uint32_t* ctr, uint32_t*
 int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t* cells, void* hip_stream) {
     int rc = validate(prm, count > 0 ? count : 1);
     if (rc) return rc;
+    if (dim_of(prm) != 3) return fail(SIPF_EINVAL, "test entry points are three-dimensional");
     if (count < 0 || (count > 0 && (!X || !cells))) return fail(SIPF_EINVAL, "bad arguments");
     hipStream_t s = (hipStream_t)hip_stream;
     if (prm->precision == SIPF_FP32)
@@ -1476,6 +1548,7 @@ int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t
 
 int sipf_dbg_deposit(const sipf_params* prm, int64_t count, const void* X, void* phi, void* hip_stream) {
     if (!phi) return fail(SIPF_EINVAL, "phi is NULL");
+    if (prm && dim_of(prm) != 3) return fail(SIPF_EINVAL, "test entry points are three-dimensional");
     sipf_ctx* c = nullptr;
     int rc = sipf_init(prm, count, X, 1, nullptr, 0, hip_stream, &c);
     if (rc) return rc;

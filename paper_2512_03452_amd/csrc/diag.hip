@@ -17,8 +17,8 @@ namespace sipf {
 
 constexpr int DIAG_THREADS = 256;
 
-int diag_blocks(int64_t P, int H) {
-    const int64_t work = std::max<int64_t>(P, (int64_t)H * H * H);
+int diag_blocks(int64_t P, int64_t ng) {
+    const int64_t work = std::max<int64_t>(P, ng);
     const int64_t nb = (work + DIAG_THREADS * 16 - 1) / (DIAG_THREADS * 16);
     return (int)std::min<int64_t>(std::max<int64_t>(nb, 1), DIAG_MAX_BLOCKS);
 }
@@ -50,31 +50,45 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_partials(const DiagDesc<T
     double v[DIAG_NVAL];
     for (int k = 0; k < DIAG_NVAL; ++k) v[k] = 0.0;
     v[1] = -INFINITY;
-    const int64_t H3 = (int64_t)H * H * H;
-    for (int64_t i = first; i < H3; i += stride) {
+    const bool two = d.dim == 2;
+    const int64_t ng = two ? (int64_t)H * H : (int64_t)H * H * H;
+    for (int64_t i = first; i < ng; i += stride) {
         const double r = (double)d.rho[i];
         v[0] += r;
         v[1] = fmax(v[1], r);
     }
-    const int64_t ns = (int64_t)H * H * HH;
+    // frequency of a storage position along a permuted axis
+    auto freq = [&](int pos) {
+        const int r = pos % d.pm;
+        return pos / d.pm + d.pt * (r / d.n2 + d.n1 * (r % d.n2));
+    };
+    const int64_t ns = two ? (int64_t)HH * H : (int64_t)H * H * HH;
     for (int64_t i = first; i < ns; i += stride) {
-        const int kz = (int)(i % HH);
-        const int64_t row = i / HH;
-        const int kyp = (int)(row % H), kxp = (int)(row / H);
-        const int kx = kxp / d.n2 + d.n1 * (kxp % d.n2);
-        const int ky = kyp / d.n2 + d.n1 * (kyp % d.n2);
-        const int qx = kx < H / 2 ? kx : kx - H;
-        const int qy = ky < H / 2 ? ky : ky - H;
-        const int q2 = qx * qx + qy * qy + kz * kz;
+        int qx, qy, qz, kh;
+        if (two) {
+            kh = (int)(i / H);  // ky, the halved axis
+            const int kx = freq((int)(i % H));
+            qx = kx < H / 2 ? kx : kx - H;
+            qy = kh;
+            qz = 0;
+        } else {
+            kh = (int)(i % HH);  // kz, the halved axis
+            const int64_t row = i / HH;
+            const int kx = freq((int)(row / H)), ky = freq((int)(row % H));
+            qx = kx < H / 2 ? kx : kx - H;
+            qy = ky < H / 2 ? ky : ky - H;
+            qz = kh;
+        }
+        const int q2 = qx * qx + qy * qy + qz * qz;
         const cplx_t<T> a = d.alpha[i];
-        const double w = (kz == 0 || kz == H / 2) ? 1.0 : 2.0;
+        const double w = (kh == 0 || kh == H / 2) ? 1.0 : 2.0;
         const double e = w * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
         v[2] += e;
         if (q2 >= 16) v[3] += e;
         if (i == 0) v[4] = (double)a.x;
     }
     for (int64_t i = first; i < d.P; i += stride) {
-        const double x = (double)d.x[i], y = (double)d.y[i], z = (double)d.z[i];
+        const double x = (double)d.x[i], y = (double)d.y[i], z = two ? 0.0 : (double)d.z[i];
         const double rxy2 = x * x + y * y;
         v[5] += sqrt(rxy2);
         v[6] += rxy2 + z * z;

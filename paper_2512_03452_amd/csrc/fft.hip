@@ -7,42 +7,39 @@
 // grad c(x_j) = sum_q i xi_q Phi_q alpha_q e^{+2 pi i q.j/H}.
 //
 // Three passes over HBM per step, each staged through LDS:
-//   fwd_planes  one workgroup per x-plane: real rows of the plane are packed
-//               two at a time into one complex row (z = a + i b), transformed
-//               along z, split into the half spectra of a and b (kz = 0..H/2),
-//               then transformed along y.  Also zeroes the deposit grid for
-//               the next step and advances the step counter.
+//   fwd_planes  one workgroup per x-plane: each real row along z is read as
+//               H/2 complex values, transformed, and split into its half
+//               spectrum (kz = 0..H/2); then the plane is transformed along y.
+//               Also zeroes the deposit grid for the next step and advances
+//               the step counter.
 //   xpencils    one workgroup per (ky, 16 kz) block of x-pencils: transform
 //               along x, alpha <- A alpha + B beta, form i xi_d Phi alpha for
 //               d = 0,1,2 and inverse-transform each along x.
 //   inv_planes  one workgroup per (component, x-plane): inverse along y, then
-//               the complex-to-real inverse along z two rows at a time.
+//               the half-length complex-to-real inverse along z.
 //
-// In-place LDS FFT of length N = N1 * N2 (N1, N2 <= 16): a stage of N1-point
-// register DFTs with twiddles, then a stage of N2-point register DFTs.  The
-// forward transform takes natural order and leaves frequency k at position
-// (k mod N1) * N2 + k div N1; the inverse takes that order and returns natural
-// order.  The x and y frequency axes of the stored spectra use this order.
+// The LDS FFT (lds_fft.h) leaves the forward transform in a digit-permuted
+// order and takes that order back in the inverse; the x and y frequency axes
+// of the stored spectra use it.
 #include "internal.h"
+#include "lds_fft.h"
 
 namespace sipf {
-
-template <int N> struct Split;
-template <> struct Split<4>   { static constexpr int N1 = 4,  N2 = 1; };
-template <> struct Split<8>   { static constexpr int N1 = 8,  N2 = 1; };
-template <> struct Split<16>  { static constexpr int N1 = 16, N2 = 1; };
-template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
-template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8; };
-template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
 
 int fft_perm(int N, int k) {
     int N1 = 8, N2 = 1;
     switch (N) {
+        case 4: N1 = 4; N2 = 1; break;
         case 8: N1 = 8; N2 = 1; break;
         case 16: N1 = 16; N2 = 1; break;
         case 32: N1 = 8; N2 = 4; break;
         case 64: N1 = 8; N2 = 8; break;
         case 128: N1 = 16; N2 = 8; break;
+        case 256: N1 = 16; N2 = 16; break;
+        case 512: case 1024: case 2048: case 4096: {
+            const int M = N / 16;
+            return (k % 16) * M + fft_perm(M, k / 16);
+        }
         default: return -1;
     }
     return (k % N1) * N2 + k / N1;
@@ -51,139 +48,6 @@ int fft_perm(int N, int k) {
 bool fft_size_supported(int H, bool fp64) {
     if (!(H == 8 || H == 16 || H == 32 || H == 64 || H == 128)) return false;
     return !(fp64 && H > 64);
-}
-
-// cos and sin of 2 pi j / 16, j = 0..7
-struct Tw16 {
-    static constexpr double c[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-                                    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
-    static constexpr double s[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
-                                    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
-};
-
-// v * exp(DIR 2 pi i k / R)
-template <typename T, int R, int DIR, int K>
-__device__ __forceinline__ cplx_t<T> twiddle(cplx_t<T> v) {
-    using V = cplx_t<T>;
-    if constexpr (K == 0) {
-        return v;
-    } else if constexpr (4 * K == R) {
-        return DIR > 0 ? cmake<V, T>(-v.y, v.x) : cmake<V, T>(v.y, -v.x);
-    } else {
-        constexpr int j = K * (16 / R);
-        const T c = (T)Tw16::c[j];
-        const T s = (T)(DIR * Tw16::s[j]);
-        return cmake<V, T>(v.x * c - v.y * s, v.x * s + v.y * c);
-    }
-}
-
-// In-register DFT of length R (power of two <= 16), natural order in and out.
-template <typename T, int R, int DIR> struct Dft {
-    using V = cplx_t<T>;
-    template <int K>
-    __device__ __forceinline__ static void combine(V* x, const V* e, const V* o) {
-        if constexpr (K < R / 2) {
-            const V t = twiddle<T, R, DIR, K>(o[K]);
-            x[K] = cadd(e[K], t);
-            x[K + R / 2] = csub(e[K], t);
-            combine<K + 1>(x, e, o);
-        }
-    }
-    __device__ __forceinline__ static void run(V* x) {
-        V e[R / 2], o[R / 2];
-#pragma unroll
-        for (int i = 0; i < R / 2; ++i) {
-            e[i] = x[2 * i];
-            o[i] = x[2 * i + 1];
-        }
-        Dft<T, R / 2, DIR>::run(e);
-        Dft<T, R / 2, DIR>::run(o);
-        combine<0>(x, e, o);
-    }
-};
-template <typename T, int DIR> struct Dft<T, 1, DIR> {
-    __device__ __forceinline__ static void run(cplx_t<T>*) {}
-};
-
-// count independent length-N transforms; element e of transform b at
-// buf[b * bs + e * es].  tw[m] = exp(-2 pi i m / N).  Caller synchronises
-// before and after.
-template <typename T, int N, int DIR>
-__device__ __forceinline__ void lds_fft(cplx_t<T>* buf, int count, int bs, int es, const cplx_t<T>* tw) {
-    using V = cplx_t<T>;
-    constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if constexpr (DIR < 0) {
-        for (int u = tid; u < count * N2; u += nt) {
-            const int b = u % count, n2 = u / count;
-            V* p = buf + b * bs + n2 * es;
-            V r[N1];
-#pragma unroll
-            for (int i = 0; i < N1; ++i) r[i] = p[i * N2 * es];
-            Dft<T, N1, -1>::run(r);
-            if constexpr (N2 > 1) {
-#pragma unroll
-                for (int k1 = 1; k1 < N1; ++k1) r[k1] = cmul(r[k1], tw[n2 * k1]);
-            }
-#pragma unroll
-            for (int i = 0; i < N1; ++i) p[i * N2 * es] = r[i];
-        }
-        if constexpr (N2 > 1) {
-            __syncthreads();
-            for (int u = tid; u < count * N1; u += nt) {
-                const int b = u % count, k1 = u / count;
-                V* p = buf + b * bs + k1 * N2 * es;
-                V r[N2];
-#pragma unroll
-                for (int i = 0; i < N2; ++i) r[i] = p[i * es];
-                Dft<T, N2, -1>::run(r);
-#pragma unroll
-                for (int i = 0; i < N2; ++i) p[i * es] = r[i];
-            }
-        }
-    } else {
-        if constexpr (N2 > 1) {
-            for (int u = tid; u < count * N1; u += nt) {
-                const int b = u % count, k1 = u / count;
-                V* p = buf + b * bs + k1 * N2 * es;
-                V r[N2];
-#pragma unroll
-                for (int i = 0; i < N2; ++i) r[i] = p[i * es];
-                Dft<T, N2, +1>::run(r);
-#pragma unroll
-                for (int n2 = 1; n2 < N2; ++n2) r[n2] = cmul(r[n2], cconj(tw[n2 * k1]));
-#pragma unroll
-                for (int i = 0; i < N2; ++i) p[i * es] = r[i];
-            }
-            __syncthreads();
-        }
-        for (int u = tid; u < count * N2; u += nt) {
-            const int b = u % count, n2 = u / count;
-            V* p = buf + b * bs + n2 * es;
-            V r[N1];
-#pragma unroll
-            for (int i = 0; i < N1; ++i) r[i] = p[i * N2 * es];
-            Dft<T, N1, +1>::run(r);
-#pragma unroll
-            for (int i = 0; i < N1; ++i) p[i * N2 * es] = r[i];
-        }
-    }
-}
-
-template <int N> __device__ __forceinline__ int perm_pos(int k) {
-    return (k % Split<N>::N1) * Split<N>::N2 + k / Split<N>::N1;
-}
-template <int N> __device__ __forceinline__ int perm_freq(int pos) {
-    return pos / Split<N>::N2 + Split<N>::N1 * (pos % Split<N>::N2);
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void make_twiddles(cplx_t<T>* tw) {
-    for (int m = threadIdx.x; m < N; m += blockDim.x) {
-        double s, c;
-        sincospi(2.0 * (double)m / (double)N, &s, &c);
-        tw[m] = cmake<cplx_t<T>, T>((T)c, (T)(-s));
-    }
 }
 
 constexpr int PLANE_THREADS = 512;
@@ -317,7 +181,7 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
             const T qx = (T)(kx < H / 2 ? kx : kx - H);
             const T qz = (T)(kz0 + j);
             const T q2 = qx * qx + qy * qy + qz * qz;
-            const T f = (fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1) * fd.inv_L3;
+            const T f = (fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1) * fd.inv_Ld;
             const V b = buf[p * BP + j];
             buf[p * BP + j] = j < ncol ? cmake<V, T>(b.x * f, b.y * f) : cmake<V, T>(0, 0);
         }
@@ -355,10 +219,10 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
         const size_t ai = ((size_t)p * H + kyp) * HH + kz;
         V a = fd.alpha[ai];
         if (UPDATE) {
-            const T A = (T)1 / ((T)1 + fd.dt_over_eps * (xi2 + fd.k2));
-            const T B = (T)1 / (xi2 + fd.k2 + fd.eps_over_dt);
+            T A, B;
+            mode_ab(fd, xi2 + fd.k2, A, B);
             const V beta = buf[p * BP + j];
-            const T bs = B * fd.inv_L3;
+            const T bs = B * fd.inv_Ld;
             a = cmake<V, T>(A * a.x + bs * beta.x, A * a.y + bs * beta.y);
             fd.alpha[ai] = a;
         }
@@ -404,8 +268,7 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
         const T qz = (T)kz;
         const T q2 = qx * qx + qy * qy + qz * qz;
         const T xi2 = q2 * fd.two_pi_over_L * fd.two_pi_over_L;
-        A = (T)1 / ((T)1 + fd.dt_over_eps * (xi2 + fd.k2));
-        B = (T)1 / (xi2 + fd.k2 + fd.eps_over_dt);
+        mode_ab(fd, xi2 + fd.k2, A, B);
         phi = fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1;
         const int kd[3] = {kx, ky, kz};
         for (int d = 0; d < 3; ++d) {
@@ -421,7 +284,7 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
                 T A, B, phi, xi[3];
                 factors(p, j, A, B, phi, xi);
                 const V a = fd.alpha[((size_t)p * H + kyp) * HH + kz0 + j];
-                const T s = B * fd.inv_L3;
+                const T s = B * fd.inv_Ld;
                 v = cmake<V, T>(a.x * s, a.y * s);
             }
             buf[p * BP + j] = v;

@@ -33,24 +33,39 @@ inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStre
 }
 
 // Everything the field passes (FFT, mode update, gradient) need for one
-// instance.  Spectral arrays are Hermitian half spectra H x H x (H/2+1) whose
-// kx and ky indices are stored in the digit-permuted order of the LDS FFT
-// (see fft.hip); grids are H^3 row-major; G holds the three gradient
-// components one after another (d-major).
+// instance.  3-D: spectral arrays are Hermitian half spectra H x H x (H/2+1)
+// whose kx and ky indices are stored in the digit-permuted order of the LDS
+// FFT (see fft.hip); grids are H^3 row-major; G holds the three gradient
+// components one after another (d-major).  2-D (field2d.hip): spectra are
+// (H/2+1) x H, ky-major (ky = 0..H/2), kx in the digit-permuted order; grids
+// H^2 row-major; G holds two components.
 template <typename T> struct FieldDesc {
     T* phi;                 // deposit accumulator (mass units); zeroed by the forward pass
     cplx_t<T>* B1;          // yz-plane pass output (x not yet transformed)
     cplx_t<T>* alpha;       // alpha^(n), permuted (kx, ky)
-    cplx_t<T>* gspec;       // 3 gradient spectra after the x inverse pass
-    T* G;                   // 3 x H^3 gradient grids
+    cplx_t<T>* gspec;       // gradient spectra after the x inverse pass
+    T* G;                   // gradient grids, one per axis
     uint32_t* step;         // completed-step counter, incremented by the forward pass
-    T dt_over_eps;          // tau / eps
+    T dt_over_eps;          // tau / eps (0 when elliptic)
     T eps_over_dt;          // eps / tau
     T k2;                   // k^2
-    T inv_L3;               // L^-3 (F_H normalisation, Sec. 3.1)
+    T inv_Ld;               // L^-d (F_H normalisation, Sec. 3.1)
     T two_pi_over_L;        // xi = 2 pi q / L
     T filt;                 // 2 pi^2 / H0^2, or 0 (no filter)
+    int elliptic;           // eps = 0: A = 0, B = 1/(|xi|^2 + k^2), B = 0 where that vanishes
 };
+
+// Mode factors of the implicit update (eq. alpha_hat_update) for
+// s = |xi|^2 + k^2; the elliptic limit when eps = 0.
+template <typename T> __device__ __forceinline__ void mode_ab(const FieldDesc<T>& fd, T s, T& A, T& B) {
+    if (fd.elliptic) {
+        A = (T)0;
+        B = s > (T)0 ? (T)1 / s : (T)0;
+    } else {
+        A = (T)1 / ((T)1 + fd.dt_over_eps * s);
+        B = (T)1 / (s + fd.eps_over_dt);
+    }
+}
 
 // One instance of the particle pass.  Particles are stored SoA and kept
 // approximately sorted by tile; id is the original particle index.
@@ -65,6 +80,7 @@ template <typename T> struct PartDesc {
     const uint32_t* step;   // completed steps; this step is *step + 1
     int* err;               // device error flags (bit 0: non-finite position)
     int H;
+    int dim;                // 2 or 3 (z unused in 2-D)
     int scheme;             // SIPF_STRANG or SIPF_EM
     T hl;                   // H / L
     T L;
@@ -77,7 +93,7 @@ template <typename T> struct PartDesc {
     uint32_t inst;          // fourth counter word
     int gmargin;            // cells the W^- displacement can reach (gradient window margin)
     int tshift;             // log2 of the sort tile side
-    int nkeys;              // (H / tile)^3 sort keys
+    int nkeys;              // (H / tile)^dim sort keys
     T* ox;                  // push-only passes: positions out (null: in place), ids copied to oid
     T* oy;
     T* oz;
@@ -137,6 +153,13 @@ hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, int ncomp
 template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, int mode, hipStream_t s);
 template <typename T> hipError_t launch_inv_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s);
 bool fft_size_supported(int H, bool fp64);
+// 2-D field passes (field2d.hip): same roles for instances of grid H x H
+// (H = 8 .. 4096); xrows takes XP_STEP, XP_GRAD or XP_RHO.
+template <typename T>
+hipError_t launch_fwd_rows2(int H, const FieldDesc<T>* fd, int count, bool consume, hipStream_t s);
+template <typename T> hipError_t launch_xrows2(int H, const FieldDesc<T>* fd, int count, int mode, hipStream_t s);
+template <typename T> hipError_t launch_inv_rows2(int H, const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s);
+bool fft2d_size_supported(int H);
 // digit permutation of the LDS FFT of length N: storage position of frequency k
 int fft_perm(int N, int k);
 
@@ -144,8 +167,13 @@ int fft_perm(int N, int k);
 template <typename T>
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
                             bool push, int scheme, int win_bytes, hipStream_t s);
+// 2-D particle pass (particles2d.hip)
 template <typename T>
-hipError_t launch_sort(const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks, int ninst,
+hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+                             bool push, int scheme, int win_bytes, hipStream_t s);
+template <typename T> int particle_resident_blocks2(int scheme, int win_bytes);
+template <typename T>
+hipError_t launch_sort(int dim, const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks, int ninst,
                        uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
                        WorkItem* items, int* nitems, int chunk, hipStream_t s);
 int sort_chunk();
@@ -181,15 +209,17 @@ template <typename T> struct DiagDesc {
     const T* z;
     int64_t P;
     int H;
-    int n1, n2;               // digit split of the FFT storage order: freq = pos / n2 + n1 (pos % n2)
+    int dim;                  // 3: H x H x (H/2+1) spectrum, (kx, ky) permuted; 2: (H/2+1) x H, kx permuted
+    int pm, pt, n1, n2;       // FFT storage order: freq(pos) = pos / pm + pt inner(pos % pm),
+                              // inner(r) = r / n2 + n1 (r % n2)
     int nb;                   // workgroups reducing this instance, 1 .. DIAG_MAX_BLOCKS
 };
 // Sums per instance, in this order: sum rho, max rho, sum_q w|alpha_q|^2,
 // the same over |q| >= 4, Re alpha_0, sum sqrt(x^2 + y^2), sum |X|^2, 0.
 constexpr int DIAG_NVAL = 8;
 constexpr int DIAG_MAX_BLOCKS = 1024;
-// workgroups for an instance with P particles on an H^3 grid
-int diag_blocks(int64_t P, int H);
+// workgroups for an instance with P particles on a grid of ng nodes
+int diag_blocks(int64_t P, int64_t ng);
 // part: n x DIAG_MAX_BLOCKS x DIAG_NVAL doubles of scratch; out: n x DIAG_NVAL
 // doubles; nbmax = max over instances of DiagDesc::nb
 template <typename T>

@@ -8,10 +8,11 @@
 // order) by a periodic counting sort.  A workgroup takes a contiguous chunk of
 // the sorted array, measures the bounding box of the chunk's cells, and, when
 // the box plus the stencil reach (-1..+2) fits, accumulates the deposit in an
-// LDS window with LDS float atomics, then adds the window into the global grid
-// once.  A chunk whose box does not fit (sparse regions, long drift since the
-// last sort) deposits straight into the global grid with atomics; the result
-// is the same sum in a different order.
+// LDS window in fixed point with integer LDS atomics, then adds the window into
+// the global grid once.  A chunk whose box does not fit (sparse regions, long
+// drift since the last sort) deposits straight into the global grid with
+// atomics; the result is the same sum in a different order.  The sort also
+// serves the two-dimensional pass (particles2d.hip): tiles of T^2 cells.
 #include <climits>
 
 #include "internal.h"
@@ -26,7 +27,7 @@ constexpr int CH = PT * PPT;       // particles per work item at most
 constexpr int SORT_THREADS = 512;  // threads per sort workgroup
 constexpr int SORT_PER_THREAD = 8;
 constexpr int SORT_CHUNK = SORT_THREADS * SORT_PER_THREAD;
-constexpr int MAX_KEYS = 4096;     // (H / tile)^3 <= 16^3
+constexpr int MAX_KEYS = 4096;     // (H / tile)^3 <= 16^3, (H / tile)^2 <= 64^2
 constexpr int MIN_WINDOW_ITEM = 64;  // smaller items deposit and gather straight from global memory
 
 // Push phase: re-read each particle (1) or keep the item's particles in
@@ -60,6 +61,13 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
     return r;
 }
 
+__device__ __forceinline__ uint32_t spread2(uint32_t v) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) r |= ((v >> b) & 1u) << (2 * b);
+    return r;
+}
+
 // Morton key of the tile of the cell containing (x, y, z).
 template <typename T>
 __device__ __forceinline__ uint32_t tile_key(T x, T y, T z, T hl, int Hm, int tshift) {
@@ -67,6 +75,18 @@ __device__ __forceinline__ uint32_t tile_key(T x, T y, T z, T hl, int Hm, int ts
     const uint32_t ty = (uint32_t)(ifloor(y * hl) & Hm) >> tshift;
     const uint32_t tz = (uint32_t)(ifloor(z * hl) & Hm) >> tshift;
     return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tz);
+}
+// the same in two dimensions (up to 64 tiles per axis)
+template <typename T>
+__device__ __forceinline__ uint32_t tile_key2(T x, T y, T hl, int Hm, int tshift) {
+    const uint32_t tx = (uint32_t)(ifloor(x * hl) & Hm) >> tshift;
+    const uint32_t ty = (uint32_t)(ifloor(y * hl) & Hm) >> tshift;
+    return (spread2(tx) << 1) | spread2(ty);
+}
+template <typename T, int DIM>
+__device__ __forceinline__ uint32_t key_of(const PartDesc<T>& a, T x, T y, T z) {
+    if constexpr (DIM == 3) return tile_key(x, y, z, a.hl, a.H - 1, a.tshift);
+    else return tile_key2(x, y, a.hl, a.H - 1, a.tshift);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,7 +630,7 @@ hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const 
 // own segment; the combine pass concatenates the segments into one list that
 // the (persistent) particle pass walks.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int DIM>
 __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* __restrict__ pds,
                                                             const SortChunk* __restrict__ chunks,
                                                             uint32_t* counts) {
@@ -623,7 +643,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* _
     __syncthreads();
     const int64_t end = min(ch.beg + (int64_t)SORT_CHUNK, a.P);
     for (int64_t i = ch.beg + tid; i < end; i += SORT_THREADS)
-        atomicAdd(&h[tile_key(a.x[i], a.y[i], a.z[i], a.hl, a.H - 1, a.tshift)], 1u);
+        atomicAdd(&h[key_of<T, DIM>(a, a.x[i], a.y[i], DIM == 3 ? a.z[i] : (T)0)], 1u);
     __syncthreads();
     uint32_t* cnt = counts + (size_t)ch.inst * MAX_KEYS;
     for (int i = tid; i < nk; i += SORT_THREADS)
@@ -722,7 +742,7 @@ __global__ __launch_bounds__(1024) void k_items_combine(const WorkItem* __restri
     if (tid == 0) *nitems = (int)total;
 }
 
-template <typename T>
+template <typename T, int DIM>
 __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>* __restrict__ src,
                                                                const PartDesc<T>* __restrict__ dst,
                                                                const SortChunk* __restrict__ chunks,
@@ -745,9 +765,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>
         if (i < a.P && i < ch.beg + SORT_CHUNK) {
             px[k] = a.x[i];
             py[k] = a.y[i];
-            pz[k] = a.z[i];
+            pz[k] = DIM == 3 ? a.z[i] : (T)0;
             pid[k] = a.id[i];
-            key[k] = tile_key(px[k], py[k], pz[k], a.hl, a.H - 1, a.tshift);
+            key[k] = key_of<T, DIM>(a, px[k], py[k], pz[k]);
             rank[k] = atomicAdd(&lc[key[k]], 1u);
         }
     }
@@ -762,7 +782,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>
             const uint32_t d = lb[key[k]] + rank[k];
             b.x[d] = px[k];
             b.y[d] = py[k];
-            b.z[d] = pz[k];
+            if constexpr (DIM == 3) b.z[d] = pz[k];
             b.id[d] = pid[k];
         }
     }
@@ -771,57 +791,71 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>
 int sort_chunk() { return SORT_CHUNK; }
 
 template <typename T>
-hipError_t launch_sort(const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks, int ninst,
-                       uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
+hipError_t launch_sort(int dim, const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks,
+                       int ninst, uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
                        WorkItem* items, int* nitems, int chunk, hipStream_t s) {
     if (chunk <= 0 || chunk > CH) chunk = CH;
-    if (ninst < 1 || ninst > 1024) return hipErrorInvalidValue;
-    launch_kernel((k_tile_hist<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+    if (ninst < 1 || ninst > 1024 || (dim != 2 && dim != 3)) return hipErrorInvalidValue;
+    if (dim == 3) launch_kernel((k_tile_hist<T, 3>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+    else launch_kernel((k_tile_hist<T, 2>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
     launch_kernel((k_tile_scan<T>), dim3(ninst), dim3(1024), 0, s, src, counts, cursor, seg, seg_off, seg_n,
                        chunk);
     launch_kernel(k_items_combine, dim3(1), dim3(1024), 0, s, seg, seg_off, seg_n, ninst, items, nitems);
-    launch_kernel((k_tile_scatter<T>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
+    if (dim == 3)
+        launch_kernel((k_tile_scatter<T, 3>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
+    else
+        launch_kernel((k_tile_scatter<T, 2>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // small kernels: layout conversion, test entry points
 // ---------------------------------------------------------------------------
-template <typename T>
+// P x DIM positions (row-major) -> SoA, wrapped into the box, ids 0..P-1
+template <typename T, int DIM>
 __global__ void k_load_positions(const T* __restrict__ xyz, int64_t P, T L, T halfL, T invL, T* x, T* y, T* z,
                                  uint32_t* id, int* err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
-    const T a = xyz[3 * i], b = xyz[3 * i + 1], c = xyz[3 * i + 2];
+    const T a = xyz[DIM * i], b = xyz[DIM * i + 1];
+    const T c = DIM == 3 ? xyz[DIM * i + 2] : (T)0;
     if (!(isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(err, 2);
     x[i] = wrap_box(a, L, halfL, invL);
     y[i] = wrap_box(b, L, halfL, invL);
-    z[i] = wrap_box(c, L, halfL, invL);
+    if constexpr (DIM == 3) z[i] = wrap_box(c, L, halfL, invL);
     id[i] = (uint32_t)i;
 }
 
 template <typename T>
 hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd, int* err, hipStream_t s) {
     const int nb = (int)((P + 255) / 256);
-    hipLaunchKernelGGL((k_load_positions<T>), dim3(nb), dim3(256), 0, s, xyz, P, L, L / 2, (T)1 / L, pd.x, pd.y, pd.z,
-                       pd.id, err);
+    if (pd.dim == 2)
+        hipLaunchKernelGGL((k_load_positions<T, 2>), dim3(nb), dim3(256), 0, s, xyz, P, L, L / 2, (T)1 / L, pd.x,
+                           pd.y, pd.z, pd.id, err);
+    else
+        hipLaunchKernelGGL((k_load_positions<T, 3>), dim3(nb), dim3(256), 0, s, xyz, P, L, L / 2, (T)1 / L, pd.x,
+                           pd.y, pd.z, pd.id, err);
     return hipGetLastError();
 }
 
-template <typename T>
+// SoA in sorted order -> P x DIM row-major in original particle order
+template <typename T, int DIM>
 __global__ void k_unsort(const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z,
                          const uint32_t* __restrict__ id, int64_t P, T* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const int64_t j = id[i];
-    out[3 * j] = x[i];
-    out[3 * j + 1] = y[i];
-    out[3 * j + 2] = z[i];
+    out[DIM * j] = x[i];
+    out[DIM * j + 1] = y[i];
+    if constexpr (DIM == 3) out[DIM * j + 2] = z[i];
 }
 
 template <typename T> hipError_t launch_unsort(const PartDesc<T>* pd, T* out, hipStream_t s) {
     const int nb = (int)((pd->P + 255) / 256);
-    hipLaunchKernelGGL((k_unsort<T>), dim3(nb), dim3(256), 0, s, pd->x, pd->y, pd->z, pd->id, pd->P, out);
+    if (pd->dim == 2)
+        hipLaunchKernelGGL((k_unsort<T, 2>), dim3(nb), dim3(256), 0, s, pd->x, pd->y, pd->z, pd->id, pd->P, out);
+    else
+        hipLaunchKernelGGL((k_unsort<T, 3>), dim3(nb), dim3(256), 0, s, pd->x, pd->y, pd->z, pd->id, pd->P, out);
     return hipGetLastError();
 }
 
@@ -880,7 +914,7 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
     template int particle_resident_blocks<T>(int, int);                                                           \
     template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, const int*, int, bool, bool, int, \
                                             int, hipStream_t);                                                    \
-    template hipError_t launch_sort<T>(const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,        \
+    template hipError_t launch_sort<T>(int, const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,   \
                                        uint32_t*, uint32_t*, WorkItem*, const int*, int*, WorkItem*, int*, int,    \
                                        hipStream_t);                                                               \
     template hipError_t launch_load_positions<T>(const T*, int64_t, T, PartDesc<T>, int*, hipStream_t);          \

@@ -19,12 +19,25 @@ def _dtype(prm):
     return torch.float32 if prm.precision == _lib.SIPF_FP32 else torch.float64
 
 
+def _dim(prm):
+    return 2 if prm.dim == 2 else 3
+
+
+def _shapes(H, d):
+    """Shapes of the fields of the ABI in dimension d: rho, grad, alpha (re/im last)."""
+    if d == 2:
+        return {"rho": (H, H), "grad": (2, H, H), "alpha": (H, H // 2 + 1, 2)}
+    return {"rho": (H, H, H), "grad": (3, H, H, H), "alpha": (H, H, H // 2 + 1, 2)}
+
+
 class Sim:
     """One SIPF-PIC simulation (Algorithm 4) held by the library.
 
-    X0: (P, 3) positions (numpy array or torch tensor); alpha0: optional
-    complex (H, H, H/2+1) half spectrum of c(x, 0).  Keyword arguments are
-    ``sipf_params`` fields (scheme/precision may be given as strings).
+    X0: (P, d) positions (numpy array or torch tensor); alpha0: optional
+    complex half spectrum of c(x, 0), (H, H, H/2+1) in 3-D or (H, H/2+1) in
+    2-D.  Keyword arguments are ``sipf_params`` fields (scheme/precision may
+    be given as strings; dim=2 selects the two-dimensional variant, eps=0 the
+    elliptic c-equation).
     """
 
     def __init__(self, X0, alpha0=None, stream=None, **params):
@@ -34,8 +47,9 @@ class Sim:
         self.device = torch.device("cuda", torch.cuda.current_device())
         X = torch.as_tensor(np.asarray(X0) if not torch.is_tensor(X0) else X0)
         X = X.to(device=self.device, dtype=self.dtype).contiguous()
-        if X.ndim != 2 or X.shape[1] != 3:
-            raise ValueError("X0 must have shape (P, 3)")
+        self.dim = _dim(self.params)
+        if X.ndim != 2 or X.shape[1] != self.dim:
+            raise ValueError(f"X0 must have shape (P, {self.dim})")
         self.P = int(X.shape[0])
         self.H = int(self.params.H)
         a_ptr = None
@@ -43,8 +57,9 @@ class Sim:
             a = torch.as_tensor(alpha0)
             cdt = torch.complex64 if self.dtype == torch.float32 else torch.complex128
             a = a.to(device=self.device, dtype=cdt).contiguous()
-            if tuple(a.shape) != (self.H, self.H, self.H // 2 + 1):
-                raise ValueError("alpha0 must have shape (H, H, H/2+1)")
+            want = _shapes(self.H, self.dim)["alpha"][:-1]
+            if tuple(a.shape) != want:
+                raise ValueError(f"alpha0 must have shape {want}")
             a_ptr = ctypes.c_void_p(a.data_ptr())
         self._stream = stream
         h = ctypes.c_void_p()
@@ -71,23 +86,24 @@ class Sim:
 
     # -- state ----------------------------------------------------------------
     def positions(self):
-        out = torch.empty((self.P, 3), dtype=self.dtype, device=self.device)
+        out = torch.empty((self.P, self.dim), dtype=self.dtype, device=self.device)
         check(_lib.load().sipf_get_positions(self._h, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
     def field(self, which):
         H = self.H
         lib = _lib.load()
+        shp = _shapes(H, self.dim)
         if which in ("rho", _lib.SIPF_FIELD_RHO):
-            out = torch.empty((H, H, H), dtype=self.dtype, device=self.device)
+            out = torch.empty(shp["rho"], dtype=self.dtype, device=self.device)
             check(lib.sipf_get_field(self._h, _lib.SIPF_FIELD_RHO, ctypes.c_void_p(out.data_ptr()), 1))
             return out
         if which in ("grad", _lib.SIPF_FIELD_GRAD):
-            out = torch.empty((3, H, H, H), dtype=self.dtype, device=self.device)
+            out = torch.empty(shp["grad"], dtype=self.dtype, device=self.device)
             check(lib.sipf_get_field(self._h, _lib.SIPF_FIELD_GRAD, ctypes.c_void_p(out.data_ptr()), 1))
             return out
         if which in ("alpha", _lib.SIPF_FIELD_ALPHA):
-            out = torch.empty((H, H, H // 2 + 1, 2), dtype=self.dtype, device=self.device)
+            out = torch.empty(shp["alpha"], dtype=self.dtype, device=self.device)
             check(lib.sipf_get_field(self._h, _lib.SIPF_FIELD_ALPHA, ctypes.c_void_p(out.data_ptr()), 1))
             return torch.view_as_complex(out)
         raise ValueError("which must be 'rho', 'alpha' or 'grad'")
@@ -149,6 +165,7 @@ class Sim:
         self.params = p
         self.P = P.value
         self.H = int(p.H)
+        self.dim = _dim(p)
         self.dtype = _dtype(p)
         self.device = torch.device("cuda", torch.cuda.current_device())
         return self
@@ -193,6 +210,7 @@ class Batch:
         Ps = (ctypes.c_int64 * n)()
         ptrs = (ctypes.c_void_p * n)()
         self.params, self.P, self.H = [], [], []
+        self.dim = None
         keep = []
         for i, inst in enumerate(instances):
             p = _lib.default_params(**inst["params"])
@@ -202,7 +220,9 @@ class Batch:
             X = inst["X0"]
             X = torch.as_tensor(np.asarray(X) if not torch.is_tensor(X) else X)
             X = X.to(device="cuda", dtype=dt).contiguous()
-            if X.ndim != 2 or X.shape[1] != 3:
+            if self.dim is None:
+                self.dim = _dim(p)
+            if X.ndim != 2 or X.shape[1] != _dim(p):
                 raise ValueError(f"instance {i}: X0 must have shape (P, 3)")
             keep.append(X)
             Ps[i] = int(X.shape[0])
@@ -232,14 +252,15 @@ class Batch:
         return v.value
 
     def positions(self, i):
-        out = torch.empty((self.P[i], 3), dtype=self.dtype, device=self.device)
+        out = torch.empty((self.P[i], self.dim), dtype=self.dtype, device=self.device)
         check(_lib.load().sipf_batch_get_positions(self._h, int(i), ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
     def field(self, i, which):
         H = self.H[i]
-        codes = {"rho": (_lib.SIPF_FIELD_RHO, (H, H, H)), "grad": (_lib.SIPF_FIELD_GRAD, (3, H, H, H)),
-                 "alpha": (_lib.SIPF_FIELD_ALPHA, (H, H, H // 2 + 1, 2))}
+        shp = _shapes(H, self.dim)
+        codes = {"rho": (_lib.SIPF_FIELD_RHO, shp["rho"]), "grad": (_lib.SIPF_FIELD_GRAD, shp["grad"]),
+                 "alpha": (_lib.SIPF_FIELD_ALPHA, shp["alpha"])}
         code, shape = codes[which]
         out = torch.empty(shape, dtype=self.dtype, device=self.device)
         check(_lib.load().sipf_batch_get_field(self._h, int(i), code, ctypes.c_void_p(out.data_ptr()), 1))

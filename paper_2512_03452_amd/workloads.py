@@ -15,6 +15,8 @@ is measured on:
                    cross-section sd (shape of the collapsing-ring run)
   * ball        -- uniform in the unit ball (initial data of the convergence
                    study, Sec. 5.1)
+  * disk        -- uniform in a disk, positions (P, 2) (the 2-D experiments of
+                   Sec. 5.2)
 """
 
 import math
@@ -58,6 +60,15 @@ def ball(P, radius=1.0, seed=0):
     v = rng.normal(size=(P, 3))
     v /= np.linalg.norm(v, axis=1)[:, None]
     return v * (radius * np.cbrt(rng.random(P)))[:, None]
+
+
+def disk(P, radius=1.0, seed=0):
+    """i.i.d. uniform in the disk |x| <= radius, shape (P, 2) (the initial
+    density of the 2-D experiments of Sec. 5.2)."""
+    rng = np.random.default_rng([seed, 6])
+    th = rng.uniform(0.0, 2.0 * math.pi, P)
+    r = radius * np.sqrt(rng.random(P))
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
 
 
 # Convergence study of Sec. 5.1: uniform ball of radius 1, M0 = 80,

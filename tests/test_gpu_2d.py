@@ -1,0 +1,180 @@
+"""Two-dimensional step and the elliptic (eps = 0) variant on the GPU against
+the FP64 oracle (oracle/sipf2d.py, oracle/sipf.py).
+
+Tolerances: FP64 trajectories 1e-9 in positions and 1e-11 (relative L2) in
+alpha; FP32 single steps 2e-5 relative in alpha and the gradient grids (an
+H^2 deposit and three FFT passes of up to 4096 points in single precision),
+positions to 1e-6 plus the FP32 rounding of the drift.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import diagnostics as odiag  # noqa: E402
+from oracle import sipf as osipf  # noqa: E402
+from oracle import sipf2d as o2  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2512_03452_amd as pkg  # noqa: E402
+from paper_2512_03452_amd import workloads  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oparams(**kw):
+    kw = dict(kw)
+    for k in ("precision", "tile", "resort_every", "chunk", "dim"):
+        kw.pop(k, None)
+    return osipf.Params(**kw)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    nb = np.linalg.norm(b.ravel())
+    return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = [
+    # H, P, scheme, eps, k
+    (8, 1, "strang", 1.0, 1.0),
+    (16, 333, "strang", 0.0, 0.0),
+    (64, 4099, "em", 0.0, 0.0),
+    (256, 20001, "strang", 1.0, 0.5),
+    (1024, 5000, "strang", 0.0, 0.0),
+]
+
+
+@pytest.mark.parametrize("H,P,scheme,eps,k", CASES)
+def test_2d_fp64_trajectory_matches_oracle(H, P, scheme, eps, k):
+    say("2d fp64", H, P, scheme, eps, k)
+    kw = dict(L=2.0, chi=1.5, mu=1.0, eps=eps, k=k, M0=20.0, dt=1e-3, H=H, precision="fp64", seed=3, dim=2,
+              scheme=scheme)
+    X0 = workloads.disk(P, 0.5, seed=H)
+    sim = pkg.Sim(X0, **kw)
+    nsteps = 12  # eager steps, then a captured graph of two re-sort periods, then eager again
+    sim.run(nsteps)
+    Xo, ao = o2.run(X0, oparams(**kw), nsteps)
+    X = to_np(sim.positions())
+    A = to_np(sim.field("alpha"))
+    assert sim.n == nsteps
+    assert np.abs(osipf.min_image(X - Xo, 2.0)).max() < 1e-9
+    assert rel_l2(A, o2.half_spectrum(ao)) < 1e-11
+    if eps == 0 and k == 0:
+        assert A[0, 0] == 0
+    G = to_np(sim.field("grad"))
+    Go = o2.gradient_grid(ao, oparams(**kw))
+    assert rel_l2(G, Go) < 1e-11
+    sim.close()
+
+
+@pytest.mark.parametrize("H,precision", [(4096, "fp32"), (2048, "fp64"), (512, "fp32")])
+def test_2d_large_grid_step_from_gpu_state(H, precision):
+    """Two GPU steps, then one oracle step from the GPU state against the GPU's
+    third step."""
+    say("2d large", H, precision)
+    P = 100_000
+    kw = dict(L=8.0, chi=1.0, mu=1.0, eps=0.0, k=0.0, M0=25.0, dt=5e-4, H=H, precision=precision, seed=5, dim=2)
+    X0 = workloads.disk(P, 1.0, seed=7).astype(np.float32 if precision == "fp32" else np.float64)
+    sim = pkg.Sim(X0, **kw)
+    sim.run(2)
+    X2 = to_np(sim.positions()).astype(np.float64)
+    A2 = to_np(sim.field("alpha")).astype(np.complex128)
+    sim.run(1)
+    rec = {}
+    prm = oparams(**kw)
+    Xo, ao = o2.step(X2, o2.full_spectrum(A2), 3, prm, record=rec)
+    tol = 2e-5 if precision == "fp32" else 1e-11
+    assert rel_l2(to_np(sim.field("alpha")), o2.half_spectrum(ao)) < tol
+    assert rel_l2(to_np(sim.field("grad")), o2.gradient_grid(ao, prm)) < tol
+    drift = prm.chi * prm.dt * np.abs(rec["v"]).max()
+    ptol = (1e-6 + 1e-5 * drift) if precision == "fp32" else 1e-11
+    assert np.abs(osipf.min_image(to_np(sim.positions()).astype(np.float64) - Xo, 8.0)).max() < ptol
+    sim.close()
+
+
+@pytest.mark.parametrize("k", [0.0, 0.5])
+def test_3d_elliptic_fp64_matches_oracle(k):
+    say("3d elliptic", k)
+    kw = dict(L=2.0, chi=1.5, mu=1.0, eps=0.0, k=k, M0=30.0, dt=1e-3, H=16, precision="fp64", seed=2)
+    X0 = workloads.blob(3000, 0.15, seed=4)
+    sim = pkg.Sim(X0, **kw)
+    sim.run(10)
+    Xo, ao = osipf.run(X0, oparams(**kw), 10)
+    assert np.abs(osipf.min_image(to_np(sim.positions()) - Xo, 2.0)).max() < 1e-9
+    assert rel_l2(to_np(sim.field("alpha")), osipf.half_spectrum(ao)) < 1e-11
+    sim.close()
+
+
+def test_2d_batch_and_diagnostics_match_oracle():
+    specs = [(16, 2000, 10.0), (64, 9000, 25.0), (256, 30001, 40.0)]
+    inst = []
+    for i, (H, P, M0) in enumerate(specs):
+        prm = dict(L=4.0, chi=1.0, mu=1.0, eps=0.0, k=0.0, M0=M0, dt=1e-3, H=H, precision="fp64", seed=1,
+                   instance=i, dim=2)
+        inst.append(dict(params=prm, X0=workloads.disk(P, 1.0, seed=20 + i)))
+    b = pkg.Batch(inst)
+    b.run(9)
+    ds = b.diagnostics()
+    for i, it in enumerate(inst):
+        prm = oparams(**it["params"])
+        Xo, ao = o2.run(it["X0"], prm, 9)
+        X = to_np(b.positions(i))
+        A = to_np(b.field(i, "alpha"))
+        assert np.abs(osipf.min_image(X - Xo, 4.0)).max() < 1e-9, i
+        assert rel_l2(A, o2.half_spectrum(ao)) < 1e-11, i
+        want = odiag.all_diagnostics(X, o2.full_spectrum(A), prm)
+        say(" instance", i, ds[i])
+        for key in ("mass", "rho_max", "c_integral", "r_num", "m2"):
+            assert abs(ds[i][key] - want[key]) <= 1e-10 * max(abs(want[key]), 1e-30), (i, key)
+        assert abs(ds[i]["hf_share"] - want["hf_share"]) < 1e-12
+        assert abs(ds[i]["mass"] - prm.M0) < 1e-10 * prm.M0
+        assert ds[i]["c_integral"] == 0.0  # elliptic, k = 0: alpha_0 := 0
+    b.close()
+
+
+def test_2d_snapshot_and_graph_replay(tmp_path):
+    kw = dict(L=2.0, chi=2.0, mu=1.0, eps=0.0, k=0.0, M0=15.0, dt=1e-3, H=64, precision="fp64", seed=9, dim=2,
+              resort_every=2)
+    X0 = workloads.disk(3000, 0.5, seed=1)
+    a = pkg.Sim(X0, **kw)
+    e = pkg.Sim(X0, **kw)
+    e.use_graphs(False)
+    for chunk in (3, 9, 1):
+        a.run(chunk)
+        e.run(chunk)
+    assert np.abs(osipf.min_image(to_np(a.positions()) - to_np(e.positions()), 2.0)).max() < 1e-11
+    path = tmp_path / "s2d.sipf"
+    a.save(path)
+    c = pkg.Sim.load(path)
+    assert c.dim == 2 and c.n == 13 and c.P == 3000
+    assert np.array_equal(to_np(a.positions()), to_np(c.positions()))
+    a.run(5)
+    c.run(5)
+    assert np.abs(osipf.min_image(to_np(a.positions()) - to_np(c.positions()), 2.0)).max() < 1e-11
+    Xo, _ = o2.run(X0, oparams(**kw), 18)
+    assert np.abs(osipf.min_image(to_np(c.positions()) - Xo, 2.0)).max() < 1e-9
+    for s in (a, c, e):
+        s.close()
+
+
+def test_2d_adjoint_is_rejected():
+    sim = pkg.Sim(workloads.disk(100, 0.5, seed=2), L=2.0, H=16, dim=2, precision="fp64")
+    with pytest.raises(pkg.SipfError):
+        sim.adjoint(3)
+    sim.close()

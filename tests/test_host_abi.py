@@ -61,9 +61,9 @@ def test_defaults():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("H", 48), ("H", 4), ("H", 256), ("dt", 0.0), ("dt", float("nan")), ("eps", 0.0), ("mu", -1.0),
+    ("H", 48), ("H", 4), ("H", 256), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
     ("chi", float("inf")), ("M0", -2.0), ("L", 0.0), ("p2g_order", 2), ("g2p_order", 4),
-    ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("reserved", 1),
+    ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4),
 ])
 def test_invalid_parameters_rejected_before_device(field, value):
     L = _lib()
@@ -75,6 +75,18 @@ def test_invalid_parameters_rejected_before_device(field, value):
     assert rc == L.SIPF_EINVAL
     assert h.value is None
     assert lib.sipf_last_error()
+
+
+@pytest.mark.parametrize("H,tile", [(4, 0), (8192, 0), (48, 0), (1024, 8), (64, 3)])
+def test_invalid_2d_parameters_rejected(H, tile):
+    L = _lib()
+    lib = L.load()
+    p = L.default_params(dim=2, H=H, tile=tile)
+    X = np.zeros((4, 2), np.float32)
+    h = ctypes.c_void_p()
+    rc = lib.sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
+    assert rc == L.SIPF_EINVAL
+    assert h.value is None
 
 
 def test_fp64_h128_rejected():

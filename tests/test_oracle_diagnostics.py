@@ -88,3 +88,38 @@ def test_c_integral_follows_the_mean_mode_recursion():
     A0 = 1.0 / (1.0 + prm.dt * prm.k ** 2 / prm.eps)
     want = prm.M0 / prm.k ** 2 * (1.0 - A0 ** 9)
     assert abs(D.c_integral(alpha, prm.L) - want) < 1e-12 * want
+
+
+def test_rho_num_2d_converges_to_the_gaussian_convolution():
+    """Two dimensions: deposit-filter-inverse against the plain sum of 2-D
+    Gaussians of standard deviation L/H0 (periodic images)."""
+    rng = np.random.default_rng(11)
+    X = rng.normal(0.0, 0.2, (400, 2))
+    errs = []
+    for H in (16, 32, 64):
+        prm = sipf.Params(L=2.0, H=H, H0=6.0, M0=3.0)
+        rho = D.rho_num(X, prm)
+        assert abs(D.grid_mass(rho, 2.0) - 3.0) < 1e-12
+        idx = rng.integers(0, H, (150, 2))
+        g = np.arange(H)
+        g = np.where(g < H // 2, g, g - H) * (2.0 / H)
+        nodes = g[idx]
+        s = 2.0 / 6.0
+        direct = np.zeros(len(nodes))
+        for mx in (-1, 0, 1):
+            for my in (-1, 0, 1):
+                d = nodes[:, None, :] - X[None, :, :] - 2.0 * np.array([mx, my])
+                direct += (3.0 / 400) / (2 * np.pi * s * s) * np.exp(-np.sum(d * d, axis=2) / (2 * s * s)).sum(axis=1)
+        errs.append(np.abs(rho[idx[:, 0], idx[:, 1]] - direct).max() / np.abs(direct).max())
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10, errs
+
+
+def test_hf_share_2d_and_c_integral_2d():
+    H, L = 16, 2.0
+    x = np.arange(H) * (L / H)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    a = np.fft.fft2(1.0 + np.cos(2 * np.pi * (3 * X + 3 * Y) / L)) / H ** 2
+    assert abs(D.hf_share(a) - 1.0 / 3.0) < 1e-13          # |q| = sqrt(18) >= 4
+    a = np.fft.fft2(2.0 + np.cos(2 * np.pi * (2 * X + 3 * Y) / L)) / H ** 2
+    assert D.hf_share(a) < 1e-25                             # |q| = sqrt(13) < 4
+    assert abs(D.c_integral(a, L) - 2.0 * L ** 2) < 1e-12
