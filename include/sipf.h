@@ -91,6 +91,10 @@ extern "C" {
 #define SIPF_STRANG 0       /* X' = wrap(Y + chi tau I*grad c(Y) + W+), Y = X + W-, W+- ~ N(0, mu tau) */
 #define SIPF_EM     1       /* X' = wrap(X + chi tau I*grad c(X) + W),  W ~ N(0, 2 mu tau) */
 
+/* propagator of the c-equation over one step (eps > 0) */
+#define SIPF_PROP_IMPLICIT 0  /* eq. alpha_hat_update: alpha' = A (alpha + (tau/eps) beta), A = 1/(1 + tau s/eps) */
+#define SIPF_PROP_EXP      1  /* Sec. 3.4: the same with kappa = exp(-tau s/eps) in place of A; s = |xi|^2 + k^2 */
+
 /* arithmetic precision of particles, grids and spectra */
 #define SIPF_FP32 0
 #define SIPF_FP64 1
@@ -126,6 +130,8 @@ typedef struct sipf_params {
     uint64_t seed;         /* Philox key                                          */
     uint32_t instance;     /* fourth Philox counter word                          */
     uint32_t dim;          /* space dimension: 3 (0 means 3) or 2                 */
+    int32_t  propagator;   /* SIPF_PROP_IMPLICIT (default) or SIPF_PROP_EXP (needs eps > 0) */
+    int32_t  reserved;     /* must be 0                                           */
 } sipf_params;
 
 typedef struct sipf_ctx sipf_ctx;

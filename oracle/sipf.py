@@ -59,6 +59,7 @@ class Params:
     scheme: str = "strang"  # "strang" (Algorithm 4) or "em" (eq. rho_hat_update)
     seed: int = 0           # Philox key
     instance: int = 0       # fourth Philox counter word
+    propagator: str = "implicit"  # "implicit" (eq. alpha_hat_update) or "exp" (Sec. 3.4)
 
     def h0(self):
         """Filter scale H0 (Sec. 5.1 rule when H0 == 0)."""
@@ -159,12 +160,32 @@ def mode_factors(prm):
     problem fixes c only up to a constant and sees rho minus its mean).
     """
     xi = wavevectors(prm.H, prm.L)
-    xi2 = (xi ** 2).sum(axis=0)
+    return mode_factors_s((xi ** 2).sum(axis=0) + prm.k ** 2, prm)
+
+
+def mode_factors_s(s, prm):
+    """A, B as functions of s = |xi|^2 + k^2 (any dimension).
+
+    implicit (eq. alpha_hat_update): A = 1/(1 + tau s/eps), B = 1/(s + eps/tau),
+    i.e. alpha' = A (alpha + (tau/eps) beta);
+    exponential (Sec. 3.4): the attenuation kappa = exp(-tau s/eps) in place of
+    A, alpha' = kappa (alpha + (tau/eps) beta).  Sec. 3.4 prints the source
+    weight as tau; it equals tau/eps for eps = 1, and tau/eps is the weight of
+    the implicit form, so that is the reading taken;
+    elliptic (eps = 0): A = 0, B = 1/s, B = 0 where s = 0.
+    """
     if prm.eps == 0:
-        s = xi2 + prm.k ** 2
+        if prm.propagator != "implicit":
+            raise ValueError("the exponential propagator needs eps > 0")
         return np.zeros_like(s), np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
-    A = 1.0 / (1.0 + prm.dt / prm.eps * (xi2 + prm.k ** 2))
-    B = 1.0 / (xi2 + prm.k ** 2 + prm.eps / prm.dt)
+    r = prm.dt / prm.eps
+    if prm.propagator == "exp":
+        A = np.exp(-r * s)
+        return A, A * r
+    if prm.propagator != "implicit":
+        raise ValueError("propagator must be 'implicit' or 'exp'")
+    A = 1.0 / (1.0 + r * s)
+    B = 1.0 / (s + prm.eps / prm.dt)
     return A, B
 
 

@@ -29,7 +29,7 @@ import math
 import numpy as np
 
 from . import philox, stencil
-from .sipf import Params, cell_and_frac, freqs, wrap  # noqa: F401  (Params re-exported)
+from .sipf import Params, cell_and_frac, freqs, mode_factors_s, wrap  # noqa: F401  (Params re-exported)
 
 
 def deposit(X, w, H, L, order=4):
@@ -78,16 +78,10 @@ def inverse_transform(alpha):
 
 
 def mode_factors(prm):
-    """A_q, B_q of eq. ``alpha_hat_update``; the elliptic limit for eps = 0."""
+    """A_q, B_q of eq. ``alpha_hat_update`` (or the exponential propagator of
+    Sec. 3.4); the elliptic limit for eps = 0 (see ``sipf.mode_factors_s``)."""
     xi = wavevectors(prm.H, prm.L)
-    s = (xi ** 2).sum(axis=0) + prm.k ** 2
-    if prm.eps == 0:
-        A = np.zeros_like(s)
-        B = np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
-        return A, B
-    A = 1.0 / (1.0 + prm.dt / prm.eps * s)
-    B = 1.0 / (s + prm.eps / prm.dt)
-    return A, B
+    return mode_factors_s((xi ** 2).sum(axis=0) + prm.k ** 2, prm)
 
 
 def filter_factors(prm):

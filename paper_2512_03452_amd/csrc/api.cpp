@@ -71,6 +71,11 @@ int validate(const sipf_params* p, int64_t P) {
     if (!(fin(p->k) && p->k >= 0)) return fail(SIPF_EINVAL, "k must be finite and >= 0");
     if (!(fin(p->M0) && p->M0 >= 0)) return fail(SIPF_EINVAL, "M0 must be finite and >= 0");
     if (!fin(p->H0)) return fail(SIPF_EINVAL, "H0 must be finite");
+    if (p->propagator != SIPF_PROP_IMPLICIT && p->propagator != SIPF_PROP_EXP)
+        return fail(SIPF_EINVAL, "propagator must be SIPF_PROP_IMPLICIT or SIPF_PROP_EXP");
+    if (p->propagator == SIPF_PROP_EXP && p->eps == 0)
+        return fail(SIPF_EINVAL, "the exponential propagator needs eps > 0");
+    if (p->reserved != 0) return fail(SIPF_EINVAL, "reserved must be 0");
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
     if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
     if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
@@ -239,6 +244,7 @@ template <typename T> FieldDesc<T> make_fdesc(const Group* g, int i) {
     f.G = (T*)I.G;
     f.step = g->steps + i;
     f.elliptic = p.eps == 0.0 ? 1 : 0;
+    f.expo = p.propagator == SIPF_PROP_EXP ? 1 : 0;
     f.dt_over_eps = f.elliptic ? (T)0 : (T)(p.dt / p.eps);
     f.eps_over_dt = (T)(p.eps / p.dt);
     f.k2 = (T)(p.k * p.k);
@@ -1158,7 +1164,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
 // snapshots: header, positions in original order, alpha in natural order
 // ---------------------------------------------------------------------------
 const char kMagic[8] = {'S', 'I', 'P', 'F', 'S', 'N', 'A', 'P'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct SnapHeader {
     char magic[8];

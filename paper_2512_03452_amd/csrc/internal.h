@@ -53,14 +53,19 @@ template <typename T> struct FieldDesc {
     T two_pi_over_L;        // xi = 2 pi q / L
     T filt;                 // 2 pi^2 / H0^2, or 0 (no filter)
     int elliptic;           // eps = 0: A = 0, B = 1/(|xi|^2 + k^2), B = 0 where that vanishes
+    int expo;               // exponential propagator (Sec. 3.4): A = exp(-tau s / eps), B = A tau / eps
 };
 
 // Mode factors of the implicit update (eq. alpha_hat_update) for
-// s = |xi|^2 + k^2; the elliptic limit when eps = 0.
+// s = |xi|^2 + k^2, of the exponential propagator of Sec. 3.4 (source weight
+// tau/eps, as in the implicit form), or the elliptic limit when eps = 0.
 template <typename T> __device__ __forceinline__ void mode_ab(const FieldDesc<T>& fd, T s, T& A, T& B) {
     if (fd.elliptic) {
         A = (T)0;
         B = s > (T)0 ? (T)1 / s : (T)0;
+    } else if (fd.expo) {
+        A = exp(-fd.dt_over_eps * s);
+        B = A * fd.dt_over_eps;
     } else {
         A = (T)1 / ((T)1 + fd.dt_over_eps * s);
         B = (T)1 / (s + fd.eps_over_dt);

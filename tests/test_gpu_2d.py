@@ -178,3 +178,24 @@ def test_2d_adjoint_is_rejected():
     with pytest.raises(pkg.SipfError):
         sim.adjoint(3)
     sim.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exponential_propagator_matches_oracle(dim):
+    say("exponential propagator", dim)
+    kw = dict(L=2.0, chi=1.5, mu=1.0, eps=0.3, k=0.5, M0=30.0, dt=2e-3, H=16 if dim == 3 else 64,
+              precision="fp64", seed=6, propagator="exp")
+    if dim == 2:
+        kw["dim"] = 2
+        X0 = workloads.disk(4000, 0.5, seed=9)
+        run, half = o2.run, o2.half_spectrum
+    else:
+        X0 = workloads.blob(4000, 0.15, seed=9)
+        run, half = osipf.run, osipf.half_spectrum
+    sim = pkg.Sim(X0, **kw)
+    sim.run(10)
+    prm = oparams(**kw)
+    Xo, ao = run(X0, prm, 10)
+    assert np.abs(osipf.min_image(to_np(sim.positions()) - Xo, 2.0)).max() < 1e-9
+    assert rel_l2(to_np(sim.field("alpha")), half(ao)) < 1e-11
+    sim.close()

@@ -63,7 +63,7 @@ def test_defaults():
 @pytest.mark.parametrize("field,value", [
     ("H", 48), ("H", 4), ("H", 256), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
     ("chi", float("inf")), ("M0", -2.0), ("L", 0.0), ("p2g_order", 2), ("g2p_order", 4),
-    ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4),
+    ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4), ("propagator", 2), ("reserved", 1),
 ])
 def test_invalid_parameters_rejected_before_device(field, value):
     L = _lib()
@@ -87,6 +87,16 @@ def test_invalid_2d_parameters_rejected(H, tile):
     rc = lib.sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
     assert rc == L.SIPF_EINVAL
     assert h.value is None
+
+
+def test_exponential_propagator_needs_positive_eps():
+    L = _lib()
+    lib = L.load()
+    p = L.default_params(eps=0.0, propagator="exp")
+    X = np.zeros((4, 3), np.float32)
+    h = ctypes.c_void_p()
+    rc = lib.sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
+    assert rc == L.SIPF_EINVAL and h.value is None
 
 
 def test_fp64_h128_rejected():
@@ -146,12 +156,12 @@ def test_load_of_corrupt_snapshot_is_eio(tmp_path, damage):
     Hdr = _snap_header_type()
     p = L.default_params(H=8)
     P = 10
-    h = Hdr(b"SIPFSNAP", 1, 4, p, P, 3)
+    h = Hdr(b"SIPFSNAP", 2, 4, p, P, 3)
     payload = bytes(P * 3 * 4 + 8 * 8 * 5 * 2 * 4)
     if damage == "magic":
         h.magic = b"SIPFSNAQ"
     elif damage == "version":
-        h.version = 2
+        h.version = 1  # the layout before the propagator field
     elif damage == "tsize":
         h.tsize = 8
     elif damage == "truncated":

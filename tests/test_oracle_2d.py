@@ -148,3 +148,32 @@ def test_half_spectrum_round_trip_2d():
     rng = np.random.default_rng(7)
     a = np.fft.fft2(rng.normal(size=(8, 8)))
     assert np.abs(sipf2d.full_spectrum(sipf2d.half_spectrum(a)) - a).max() < 1e-12
+
+
+def test_exponential_propagator_is_exact_for_free_modes():
+    """Sec. 3.4: kappa = exp(-tau s / eps) makes the homogeneous update exact:
+    after n steps a free mode has decayed by exp(-n tau s / eps), and with
+    k = 0 the mean of c grows exactly as M0 t / eps (eps C' = M0)."""
+    for mod, H in ((sipf, 8), (sipf2d, 16)):
+        prm = Params(L=2.0, H=H, eps=0.4, k=0.3, dt=0.01, propagator="exp")
+        A, B = mod.mode_factors(prm)
+        xi = mod.wavevectors(H, 2.0)
+        s = (xi ** 2).sum(axis=0) + 0.09
+        assert np.abs(A ** 25 - np.exp(-25 * 0.01 * s / 0.4)).max() < 1e-14
+        assert np.abs(B - A * 0.01 / 0.4).max() < 1e-16
+    prm = Params(L=2.0, H=8, eps=0.5, k=0.0, dt=0.02, propagator="exp", M0=3.0)
+    X = np.random.default_rng(1).normal(0, 0.2, (50, 3))
+    _, alpha = sipf.run(X, prm, 7)
+    assert abs(alpha[0, 0, 0].real * 8.0 - 3.0 * 7 * 0.02 / 0.5) < 1e-12
+
+
+def test_exponential_and_implicit_propagators_agree_to_first_order():
+    """The two updates differ at O((tau s / eps)^2) per step (Sec. 3.4 remark)."""
+    prm_i = Params(L=2.0, H=8, eps=1.0, k=1.0, dt=1e-4)
+    prm_e = Params(L=2.0, H=8, eps=1.0, k=1.0, dt=1e-4, propagator="exp")
+    Ai, Bi = sipf.mode_factors(prm_i)
+    Ae, Be = sipf.mode_factors(prm_e)
+    s = (sipf.wavevectors(8, 2.0) ** 2).sum(axis=0) + 1.0
+    r = 1e-4 * s
+    assert np.abs(Ai - Ae).max() <= (r ** 2).max()
+    assert np.abs(Bi - Be).max() <= 1e-4 * (r ** 2).max()
