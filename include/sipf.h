@@ -95,6 +95,20 @@ extern "C" {
 #define SIPF_PROP_IMPLICIT 0  /* eq. alpha_hat_update: alpha' = A (alpha + (tau/eps) beta), A = 1/(1 + tau s/eps) */
 #define SIPF_PROP_EXP      1  /* Sec. 3.4: the same with kappa = exp(-tau s/eps) in place of A; s = |xi|^2 + k^2 */
 
+/* method of a context: SIPF-PIC (Algorithm 4), or the direct SIPF method of
+ * Algorithm 1 (every particle meets every mode of U, O(P H^3) per step, no
+ * grid), the baseline the particle-in-cell step is measured against.  A
+ * direct context is three-dimensional and single-instance; it supports
+ * sipf_step/run/sync/get_step/get_positions/get_params/destroy and
+ * sipf_get_field(SIPF_FIELD_ALPHA) (the kz = 0..H/2 half of its full
+ * spectrum); the other calls return SIPF_EINVAL.  Its push follows
+ * sipf_params.scheme (Algorithm 1 prints Euler-Maruyama) and its gradient
+ * sum is Re sum_{q in U} i xi_q Phi_q alpha_q exp(i xi_q . X) (eq. gradc; set
+ * H0 < 0 for Algorithm 1's unfiltered sum).  An alpha0 given to sipf_init is
+ * extended to U by Hermitian symmetry. */
+#define SIPF_METHOD_PIC    0
+#define SIPF_METHOD_DIRECT 1
+
 /* arithmetic precision of particles, grids and spectra */
 #define SIPF_FP32 0
 #define SIPF_FP64 1
@@ -131,7 +145,7 @@ typedef struct sipf_params {
     uint32_t instance;     /* fourth Philox counter word                          */
     uint32_t dim;          /* space dimension: 3 (0 means 3) or 2                 */
     int32_t  propagator;   /* SIPF_PROP_IMPLICIT (default) or SIPF_PROP_EXP (needs eps > 0) */
-    int32_t  reserved;     /* must be 0                                           */
+    int32_t  method;       /* SIPF_METHOD_PIC (default, Algorithm 4) or SIPF_METHOD_DIRECT */
 } sipf_params;
 
 typedef struct sipf_ctx sipf_ctx;

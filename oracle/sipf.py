@@ -327,10 +327,13 @@ def direct_gradient(alpha, X, prm, use_filter=True):
 
 
 def sipf_direct_step(X, alpha, n, prm, ids=None, use_filter=True):
-    """One step of Algorithm 1's structure with the split push of Algorithm 4.
-
-    beta from the direct sum; drift from the direct gradient sum at the
-    particles (no grid).  Used to check that SIPF-PIC approaches SIPF as H grows.
+    """One step of the direct SIPF method (Algorithm 1): beta from the direct
+    sum over the particles (eq. beta_hat_comp), alpha by eq. alpha_hat_update,
+    drift from the direct gradient sum at the particles (eq. gradc, real part;
+    no grid).  Euler-Maruyama push as Algorithm 1 prints it (scheme "em"), or
+    the split push of Algorithm 4 (scheme "strang") for a like-for-like
+    comparison with SIPF-PIC.  ``use_filter`` applies Phi_q to the gradient
+    sum (Algorithm 1 has none; prm.H0 < 0 also switches it off).
     """
     X = np.asarray(X, dtype=np.float64)
     P = X.shape[0]
@@ -339,12 +342,25 @@ def sipf_direct_step(X, alpha, n, prm, ids=None, use_filter=True):
     beta = direct_beta(X, prm.M0, prm.H, prm.L)
     alpha_new = mode_update(alpha, beta, prm)
     tau, L = prm.dt, prm.L
-    s = math.sqrt(prm.mu * tau)
     Z6 = philox.normals6(ids, n, prm.seed, prm.instance)
+    if prm.scheme == "em":
+        v = direct_gradient(alpha, X, prm, use_filter)
+        return wrap(X + prm.chi * tau * v + math.sqrt(2.0 * prm.mu * tau) * Z6[:, 0:3], L), alpha_new
+    s = math.sqrt(prm.mu * tau)
     Zm, Zp = Z6[:, 0:3], Z6[:, 3:6]
     Y = X + s * Zm
     v = direct_gradient(alpha, Y, prm, use_filter)
     return wrap(Y + prm.chi * tau * v + s * Zp, L), alpha_new
+
+
+def sipf_direct_run(X0, prm, nsteps, use_filter=True):
+    """nsteps of ``sipf_direct_step`` from alpha^(0) = 0."""
+    X = np.asarray(X0, dtype=np.float64).copy()
+    H = prm.H
+    alpha = np.zeros((H, H, H), dtype=np.complex128)
+    for n in range(1, nsteps + 1):
+        X, alpha = sipf_direct_step(X, alpha, n, prm, use_filter=use_filter)
+    return X, alpha
 
 
 # ---------------------------------------------------------------------------

@@ -26,6 +26,8 @@ SIPF_FP32 = 0
 SIPF_FP64 = 1
 SIPF_PROP_IMPLICIT = 0
 SIPF_PROP_EXP = 1
+SIPF_METHOD_PIC = 0
+SIPF_METHOD_DIRECT = 1
 SIPF_FIELD_RHO = 0
 SIPF_FIELD_ALPHA = 1
 SIPF_FIELD_GRAD = 2
@@ -42,7 +44,7 @@ class SipfParams(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("resort_every", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32), ("dim", ctypes.c_uint32),
-        ("propagator", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("propagator", ctypes.c_int32), ("method", ctypes.c_int32),
     ]
 
 
@@ -147,6 +149,8 @@ def default_params(**overrides):
             v = {"fp32": SIPF_FP32, "fp64": SIPF_FP64}[v]
         if k == "propagator" and isinstance(v, str):
             v = {"implicit": SIPF_PROP_IMPLICIT, "exp": SIPF_PROP_EXP}[v]
+        if k == "method" and isinstance(v, str):
+            v = {"pic": SIPF_METHOD_PIC, "direct": SIPF_METHOD_DIRECT}[v]
         if not hasattr(p, k):
             raise KeyError(f"unknown parameter {k}")
         setattr(p, k, v)

@@ -75,7 +75,10 @@ int validate(const sipf_params* p, int64_t P) {
         return fail(SIPF_EINVAL, "propagator must be SIPF_PROP_IMPLICIT or SIPF_PROP_EXP");
     if (p->propagator == SIPF_PROP_EXP && p->eps == 0)
         return fail(SIPF_EINVAL, "the exponential propagator needs eps > 0");
-    if (p->reserved != 0) return fail(SIPF_EINVAL, "reserved must be 0");
+    if (p->method != SIPF_METHOD_PIC && p->method != SIPF_METHOD_DIRECT)
+        return fail(SIPF_EINVAL, "method must be SIPF_METHOD_PIC or SIPF_METHOD_DIRECT");
+    if (p->method == SIPF_METHOD_DIRECT && dim_of(p) != 3)
+        return fail(SIPF_EINVAL, "the direct SIPF method is three-dimensional");
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
     if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
     if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
@@ -128,6 +131,10 @@ struct Inst {
     void* alpha = nullptr;  // alpha^(n), permuted (kx, ky)
     void* gspec = nullptr;  // 3 gradient spectra
     void* G = nullptr;      // 3 x H^3 gradient grids
+    // direct SIPF (Algorithm 1): alpha is the full H^3 spectrum in natural order
+    void* gc = nullptr;     // 3 x H^3 gradient coefficients
+    void* part = nullptr;   // nslices x H^3 partial sums of beta
+    int nslices = 0;
 };
 
 // Instances of one grid size: FieldDesc slots [first, first + count).
@@ -138,6 +145,7 @@ struct HClass {
 struct Group {
     int prec = SIPF_FP32;
     int dim = 3;  // shared by every instance
+    int method = SIPF_METHOD_PIC;
     size_t tsize = 4;
     int scheme = SIPF_STRANG;
     hipStream_t stream = nullptr;
@@ -365,7 +373,41 @@ template <typename T> hipError_t field_inv(const Group* g, int H, const FieldDes
 // One step n-1 -> n of every instance: particle pass (deposit X^(n-1), gather
 // grad c^(n-1), push), then the field passes that turn the deposit into
 // alpha^(n) and grad c^(n).
+template <typename T> DirDesc<T> make_ddesc(const Group* g) {
+    const Inst& I = g->in[0];
+    const sipf_params& p = I.prm;
+    DirDesc<T> d{};
+    d.x = (T*)I.xs[0];
+    d.y = (T*)I.ys[0];
+    d.z = (T*)I.zs[0];
+    d.P = I.P;
+    d.H = I.H;
+    d.scheme = p.scheme;
+    d.L = (T)p.L;
+    d.halfL = (T)(p.L / 2);
+    d.invL = (T)(1.0 / p.L);
+    d.bscale = (T)(p.M0 / ((double)I.P * p.L * p.L * p.L));
+    d.chitau = (T)(p.chi * p.dt);
+    d.s = (T)(p.scheme == SIPF_STRANG ? std::sqrt(p.mu * p.dt) : std::sqrt(2.0 * p.mu * p.dt));
+    d.alpha = (cplx_t<T>*)I.alpha;
+    d.gc = (cplx_t<T>*)I.gc;
+    d.step = g->steps;
+    d.err = g->errs;
+    d.k0 = (uint32_t)p.seed;
+    d.k1 = (uint32_t)(p.seed >> 32);
+    d.inst = p.instance;
+    d.fd = make_fdesc<T>(g, 0);
+    return d;
+}
+
 template <typename T> int enqueue_step(Group* g) {
+    if (g->method == SIPF_METHOD_DIRECT) {
+        Timed t(g, SIPF_PHASE_PARTICLES);
+        const Inst& I = g->in[0];
+        HIPCHK(launch_direct_step<T>(make_ddesc<T>(g), (cplx_t<T>*)I.part, I.nslices, g->stream));
+        g->n_host++;
+        return SIPF_OK;
+    }
     if (g->since_sort >= g->resort) {
         int rc = do_sort<T>(g);
         if (rc) return rc;
@@ -516,7 +558,30 @@ void permute_spectrum(const void* src, void* dst, int H, size_t tsize, bool to_p
 
 // Set up the group's instances (parameters already in g->in): tuning, H
 // classes, device buffers and descriptors.
+template <typename T> int alloc_direct(Group* g) {
+    Inst& I = g->in[0];
+    int rc;
+    const size_t H3 = (size_t)I.H * I.H * I.H;
+    const size_t V = 2 * sizeof(T);
+    I.nslices = dir_slices(I.H, I.P);
+    if ((rc = dalloc(g, &I.xs[0], I.P * sizeof(T)))) return rc;
+    if ((rc = dalloc(g, &I.ys[0], I.P * sizeof(T)))) return rc;
+    if ((rc = dalloc(g, &I.zs[0], I.P * sizeof(T)))) return rc;
+    if ((rc = dalloc(g, (void**)&I.ids[0], I.P * sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(g, &I.alpha, H3 * V))) return rc;
+    if ((rc = dalloc(g, &I.gc, 3 * H3 * V))) return rc;
+    if ((rc = dalloc(g, &I.part, (size_t)I.nslices * H3 * V))) return rc;
+    if ((rc = dalloc(g, (void**)&g->steps, sizeof(uint32_t)))) return rc;
+    if ((rc = dalloc(g, (void**)&g->errs, sizeof(int)))) return rc;
+    HIPCHK(hipMemset(g->steps, 0, sizeof(uint32_t)));
+    HIPCHK(hipMemset(g->errs, 0, sizeof(int)));
+    g->classes.push_back(HClass{I.H, 0, 1});
+    g->fslot.assign(1, 0);
+    return SIPF_OK;
+}
+
 template <typename T> int alloc_group(Group* g) {
+    if (g->method == SIPF_METHOD_DIRECT) return alloc_direct<T>(g);
     const int n = (int)g->in.size();
     const int mk = sort_max_keys();
     int rc;
@@ -613,7 +678,37 @@ template <typename T> int load_positions(Group* g, int i, const void* X0, int on
     return SIPF_OK;
 }
 
+// alpha0 (natural half spectrum) -> the full spectrum of a direct context,
+// extended by Hermitian symmetry alpha_{-q} = conj(alpha_q)
+template <typename T> int init_direct_fields(Group* g, const void* alpha0, int alpha0_on_device) {
+    const Inst& I = g->in[0];
+    const int H = I.H, HH = H / 2 + 1;
+    const size_t H3 = (size_t)H * H * H;
+    if (alpha0 == nullptr) {
+        HIPCHK(launch_fill<T>((T*)I.alpha, 2 * H3, (T)0, g->stream));
+        return SIPF_OK;
+    }
+    std::vector<T> half(2 * (size_t)H * H * HH), full(2 * H3);
+    if (alpha0_on_device) HIPCHK(hipMemcpy(half.data(), alpha0, half.size() * sizeof(T), hipMemcpyDeviceToHost));
+    else std::memcpy(half.data(), alpha0, half.size() * sizeof(T));
+    for (T v : half)
+        if (!std::isfinite((double)v)) return fail(SIPF_ENUMERIC, "non-finite alpha0");
+    for (int kx = 0; kx < H; ++kx)
+        for (int ky = 0; ky < H; ++ky)
+            for (int kz = 0; kz < H; ++kz) {
+                const bool direct = kz <= H / 2;
+                const int sx = direct ? kx : (H - kx) % H, sy = direct ? ky : (H - ky) % H;
+                const int sz = direct ? kz : H - kz;
+                const size_t src = ((size_t)sx * H + sy) * HH + sz, dst = ((size_t)kx * H + ky) * H + kz;
+                full[2 * dst] = half[2 * src];
+                full[2 * dst + 1] = direct ? half[2 * src + 1] : -half[2 * src + 1];
+            }
+    HIPCHK(hipMemcpy(I.alpha, full.data(), full.size() * sizeof(T), hipMemcpyHostToDevice));
+    return SIPF_OK;
+}
+
 template <typename T> int init_fields(Group* g, int i, const void* alpha0, int alpha0_on_device) {
+    if (g->method == SIPF_METHOD_DIRECT) return init_direct_fields<T>(g, alpha0, alpha0_on_device);
     const Inst& I = g->in[i];
     const int H = I.H;
     const size_t nspec = spec_size(H, I.dim);
@@ -648,7 +743,7 @@ int init_group(Group* g, const void* const* X0, int x0_on_device, const void* al
         if ((rc = init_fields<T>(g, i, i == 0 ? alpha0 : nullptr, alpha0_on_device))) return rc;
     }
     g->cur = 0;
-    if ((rc = do_sort<T>(g))) return rc;
+    if (g->method != SIPF_METHOD_DIRECT && (rc = do_sort<T>(g))) return rc;
     HIPCHK(hipStreamSynchronize(g->stream));
     return check_err(g);
 }
@@ -675,6 +770,8 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
         if (prm[i].scheme != prm[0].scheme) return fail(SIPF_EINVAL, "all instances must share the scheme");
         if (dim_of(&prm[i]) != dim_of(&prm[0])) return fail(SIPF_EINVAL, "all instances must share the dimension");
     }
+    if (prm[0].method == SIPF_METHOD_DIRECT && n != 1)
+        return fail(SIPF_EINVAL, "the direct SIPF method runs single contexts, not batches");
     const size_t ts = prm[0].precision == SIPF_FP32 ? 4 : 8;
     if (!x0_on_device) {
         // reject non-finite host input before touching the device
@@ -686,6 +783,8 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
     }
     g->prec = prm[0].precision;
     g->dim = dim_of(&prm[0]);
+    g->method = prm[0].method;
+    if (g->method == SIPF_METHOD_DIRECT) g->graphs = false;
     g->tsize = ts;
     g->scheme = prm[0].scheme;
     g->stream = (hipStream_t)hip_stream;
@@ -711,6 +810,18 @@ int init_any(Group* g, const void* const* X0, int x0_on_device, const void* alph
 
 template <typename T> int get_field_typed(Group* g, int i, int which, void* out, int on_device) {
     const Inst& I = g->in[i];
+    if (g->method == SIPF_METHOD_DIRECT) {
+        if (which != SIPF_FIELD_ALPHA) return fail(SIPF_EINVAL, "a direct SIPF context has no grids");
+        const int H = I.H, HH = H / 2 + 1;
+        std::vector<T> full(2 * (size_t)H * H * H), half(2 * (size_t)H * H * HH);
+        HIPCHK(hipMemcpyAsync(full.data(), I.alpha, full.size() * sizeof(T), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        for (size_t r = 0; r < (size_t)H * H; ++r)
+            std::memcpy(half.data() + 2 * r * HH, full.data() + 2 * r * H, 2 * HH * sizeof(T));
+        if (on_device) HIPCHK(hipMemcpy(out, half.data(), half.size() * sizeof(T), hipMemcpyHostToDevice));
+        else std::memcpy(out, half.data(), half.size() * sizeof(T));
+        return check_err(g);
+    }
     const int H = I.H;
     const size_t ng = grid_size(H, I.dim);
     const size_t nspec = spec_size(H, I.dim);
@@ -1331,7 +1442,7 @@ int sipf_run(sipf_ctx* c, int64_t nsteps) {
 
 int sipf_use_graphs(sipf_ctx* c, int enable) {
     if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
-    c->graphs = enable != 0;
+    c->graphs = enable != 0 && c->method != SIPF_METHOD_DIRECT;
     return SIPF_OK;
 }
 
@@ -1354,6 +1465,7 @@ int sipf_get_step(sipf_ctx* c, int64_t* n) {
 
 int sipf_diagnostics(sipf_ctx* c, sipf_diag* out) {
     if (!c || !out) return fail(SIPF_EINVAL, "NULL argument");
+    if (c->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "a direct SIPF context has no grids");
     return diagnostics_any(c, out);
 }
 
@@ -1383,6 +1495,7 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
     if (nsteps < 1 || nsteps > (int64_t)1 << 30) return fail(SIPF_EINVAL, "nsteps must be >= 1");
     if (ckpt_every < 1) return fail(SIPF_EINVAL, "ckpt_every must be >= 1");
     if (c->dim != 3) return fail(SIPF_EINVAL, "sipf_adjoint is available in three dimensions only");
+    if (c->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "sipf_adjoint runs SIPF-PIC contexts only");
     return c->prec == SIPF_FP32
                ? adjoint_typed<float>(c, nsteps, ckpt_every, (const float*)phi_bar, loss, dchi, dmu, (float*)dX0)
                : adjoint_typed<double>(c, nsteps, ckpt_every, (const double*)phi_bar, loss, dchi, dmu, (double*)dX0);
@@ -1390,6 +1503,8 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
 
 int sipf_save(sipf_ctx* c, const char* path) {
     if (!c || !path) return fail(SIPF_EINVAL, "NULL argument");
+    if (c->method == SIPF_METHOD_DIRECT)
+        return fail(SIPF_EINVAL, "snapshots hold half spectra; a direct SIPF context keeps the full one");
     return save_ctx(c, path);
 }
 
@@ -1413,6 +1528,7 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
     if (rc) return rc;
     if (!X0) return fail(SIPF_EINVAL, "X0 is NULL");
     if (nsteps < 1) return fail(SIPF_EINVAL, "nsteps must be >= 1");
+    if (prm->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "the direct SIPF method has nothing to tune");
     sipf_params cur = *prm;
     cur.tile = default_tile(prm);
     cur.chunk = default_chunk(prm);

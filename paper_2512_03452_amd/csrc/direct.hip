@@ -1,0 +1,228 @@
+// The direct SIPF method (Algorithm 1): every particle meets every Fourier
+// mode, O(P H^3) work per step, no grid.  It is the in-house baseline the
+// particle-in-cell step is measured against.
+//
+//   beta_q  = M0 / (P L^3) sum_p exp(-i xi_q . X_p)          (eq. beta_hat_comp)
+//   alpha_q <- A_q alpha_q + B_q beta_q                       (eq. alpha_hat_update)
+//   grad c(X_p) = Re sum_q i xi_q Phi_q alpha_q exp(i xi_q . X_p)   (eq. gradc)
+// over the full index set U = {-H/2 .. H/2-1}^3, spectra in natural order
+// (array index k stands for q = k for k < H/2 and q = k - H otherwise).
+//
+// The exponentials are separable: for a fixed (qx, qy) the phases along qz
+// form a geometric sequence, so a thread evaluates one sincos and then
+// advances by a complex multiplication per qz (exp(-/+ i 2 pi z / L) per
+// particle, computed once).  Three kernels per step:
+//   dir_beta    thread = (kx, ky, run of QZ consecutive q_z); the particles of
+//               one slice of the particle range pass through LDS; per-slice
+//               partial sums.  Also advances the step counter.
+//   dir_modes   thread = mode: sums the slice partials in a fixed order, forms
+//               the gradient coefficients i xi Phi alpha^(n-1), then updates
+//               alpha.
+//   dir_push    thread = particle: the gradient sum at the particle (the
+//               coefficients of a run of (kx, ky) pairs pass through LDS),
+//               then the push of Algorithm 1 (Euler-Maruyama) or Algorithm 4.
+#include "internal.h"
+#include "pass_common.h"
+#include "sipf.h"
+
+namespace sipf {
+
+constexpr int DIR_THREADS = 256;
+constexpr int DIR_PCHUNK = 256;  // particles staged per LDS pass of dir_beta
+constexpr int DIR_PAIRS = 8;     // (kx, ky) pairs staged per LDS pass of dir_push
+
+__device__ __forceinline__ int signed_q(int k, int H) { return k < H / 2 ? k : k - H; }
+
+// exp(-2 pi i t) with t reduced to [-1/2, 1/2] first
+template <typename T> __device__ __forceinline__ cplx_t<T> cis_neg(T t) {
+    t -= rint(t);
+    T s, c;
+    if constexpr (sizeof(T) == 4) sincospif(-2.0f * t, &s, &c);
+    else sincospi(-2.0 * t, &s, &c);
+    return cmake<cplx_t<T>, T>(c, s);
+}
+
+template <typename T, int H, int QZ>
+__global__ __launch_bounds__(DIR_THREADS) void k_dir_beta(DirDesc<T> d, cplx_t<T>* __restrict__ part) {
+    using V = cplx_t<T>;
+    constexpr int NZC = H / QZ;
+    __shared__ T sx[DIR_PCHUNK], sy[DIR_PCHUNK], sz[DIR_PCHUNK];
+    __shared__ V sstep[DIR_PCHUNK];
+    const int tid = threadIdx.x;
+    const int c = blockIdx.x * DIR_THREADS + tid;  // column: (kx, ky, run of q_z)
+    const bool active = c < H * H * NZC;
+    const int zc = c % NZC, rest = c / NZC;
+    const int qx = signed_q(rest / H, H), qy = signed_q(rest % H, H);
+    const int qz0 = signed_q(zc * QZ, H);  // runs of QZ indices hold consecutive q_z (QZ divides H/2)
+    const int64_t per = (d.P + gridDim.y - 1) / gridDim.y;
+    const int64_t p0 = (int64_t)blockIdx.y * per;
+    const int64_t p1 = min(d.P, p0 + per);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && d.step != nullptr) *d.step += 1u;
+    V acc[QZ];
+#pragma unroll
+    for (int j = 0; j < QZ; ++j) acc[j] = cmake<V, T>(0, 0);
+    for (int64_t b = p0; b < p1; b += DIR_PCHUNK) {
+        const int n = (int)min((int64_t)DIR_PCHUNK, p1 - b);
+        __syncthreads();
+        if (tid < n) {
+            const T x = d.x[b + tid] * d.invL, y = d.y[b + tid] * d.invL, z = d.z[b + tid] * d.invL;
+            sx[tid] = x;
+            sy[tid] = y;
+            sz[tid] = z;
+            sstep[tid] = cis_neg<T>(z);
+        }
+        __syncthreads();
+        if (active) {
+            for (int i = 0; i < n; ++i) {
+                V e = cis_neg<T>((T)qx * sx[i] + (T)qy * sy[i] + (T)qz0 * sz[i]);
+                const V st = sstep[i];
+#pragma unroll
+                for (int j = 0; j < QZ; ++j) {
+                    acc[j] = cadd(acc[j], e);
+                    e = cmul(e, st);
+                }
+            }
+        }
+    }
+    if (active) {
+        V* out = part + (size_t)blockIdx.y * H * H * H + (size_t)c * QZ;
+#pragma unroll
+        for (int j = 0; j < QZ; ++j) out[j] = acc[j];
+    }
+}
+
+template <typename T, int H>
+__global__ __launch_bounds__(DIR_THREADS) void k_dir_modes(DirDesc<T> d, const cplx_t<T>* __restrict__ part,
+                                                           int nslices) {
+    using V = cplx_t<T>;
+    const int m = blockIdx.x * DIR_THREADS + threadIdx.x;
+    if (m >= H * H * H) return;
+    const int kz = m % H, ky = (m / H) % H, kx = m / (H * H);
+    const T qx = (T)signed_q(kx, H), qy = (T)signed_q(ky, H), qz = (T)signed_q(kz, H);
+    V beta = cmake<V, T>(0, 0);
+    for (int s = 0; s < nslices; ++s) beta = cadd(beta, part[(size_t)s * H * H * H + m]);
+    beta = cscale(beta, d.bscale);
+    const V a = d.alpha[m];
+    const T q2 = qx * qx + qy * qy + qz * qz;
+    const T phi = d.fd.filt > (T)0 ? exp(-d.fd.filt * q2) : (T)1;
+    const T w = d.fd.two_pi_over_L;
+    const T xs[3] = {qx * w, qy * w, qz * w};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)  // i xi_c Phi alpha
+        d.gc[(size_t)c * H * H * H + m] = cmake<V, T>(-xs[c] * phi * a.y, xs[c] * phi * a.x);
+    T A, B;
+    mode_ab(d.fd, q2 * w * w + d.fd.k2, A, B);
+    d.alpha[m] = cmake<V, T>(A * a.x + B * beta.x, A * a.y + B * beta.y);
+}
+
+template <typename T, int H, int SCHEME>
+__global__ __launch_bounds__(DIR_THREADS) void k_dir_push(DirDesc<T> d) {
+    using V = cplx_t<T>;
+    __shared__ V sg[3][DIR_PAIRS][H];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * DIR_THREADS + tid;
+    const bool active = p < d.P;
+    T x = 0, y = 0, z = 0, w0 = 0, w1 = 0, w2 = 0;
+    if (active) {
+        x = d.x[p];
+        y = d.y[p];
+        z = d.z[p];
+        T zn[6];
+        const uint32_t n = *d.step;  // advanced by this step's dir_beta
+        if (SCHEME == SIPF_STRANG) {
+            noise6<3, T>((uint32_t)p, n, d.inst, d.k0, d.k1, zn);
+            x += d.s * zn[0];
+            y += d.s * zn[1];
+            z += d.s * zn[2];
+            w0 = zn[3];
+            w1 = zn[4];
+            w2 = zn[5];
+        } else {
+            noise6<2, T>((uint32_t)p, n, d.inst, d.k0, d.k1, zn);
+            w0 = zn[0];
+            w1 = zn[1];
+            w2 = zn[2];
+        }
+    }
+    const T xl = x * d.invL, yl = y * d.invL, zl = z * d.invL;
+    // exp(+i xi . X): conjugate of cis_neg
+    V st = cis_neg<T>(zl);
+    st.y = -st.y;
+    T g0 = 0, g1 = 0, g2 = 0;
+    for (int pr0 = 0; pr0 < H * H; pr0 += DIR_PAIRS) {
+        __syncthreads();
+        for (int u = tid; u < 3 * DIR_PAIRS * H; u += DIR_THREADS) {
+            const int c = u / (DIR_PAIRS * H), r = u % (DIR_PAIRS * H);
+            const int pr = r / H, j = r % H;
+            // q_z ascends from -H/2: storage index (j + H/2) mod H
+            sg[c][pr][j] = d.gc[(size_t)c * H * H * H + (size_t)(pr0 + pr) * H + ((j + H / 2) & (H - 1))];
+        }
+        __syncthreads();
+        if (active) {
+            for (int pr = 0; pr < DIR_PAIRS; ++pr) {
+                const int kx = (pr0 + pr) / H, ky = (pr0 + pr) % H;
+                V e = cis_neg<T>(-((T)signed_q(kx, H) * xl + (T)signed_q(ky, H) * yl - (T)(H / 2) * zl));
+#pragma unroll 8
+                for (int j = 0; j < H; ++j) {
+                    const V a = sg[0][pr][j], b = sg[1][pr][j], c = sg[2][pr][j];
+                    g0 += a.x * e.x - a.y * e.y;
+                    g1 += b.x * e.x - b.y * e.y;
+                    g2 += c.x * e.x - c.y * e.y;
+                    e = cmul(e, st);
+                }
+            }
+        }
+    }
+    if (active) {
+        const T nx = wrap_box(x + d.chitau * g0 + d.s * w0, d.L, d.halfL, d.invL);
+        const T ny = wrap_box(y + d.chitau * g1 + d.s * w1, d.L, d.halfL, d.invL);
+        const T nz = wrap_box(z + d.chitau * g2 + d.s * w2, d.L, d.halfL, d.invL);
+        d.x[p] = nx;
+        d.y[p] = ny;
+        d.z[p] = nz;
+        if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(d.err, 1);
+    }
+}
+
+int dir_qz(int H) { return H / 2 < 32 ? H / 2 : 32; }
+
+int dir_slices(int H, int64_t P) {
+    const int64_t cols = (int64_t)H * H * (H / dir_qz(H));
+    const int64_t bx = (cols + DIR_THREADS - 1) / DIR_THREADS;
+    int64_t s = (2048 + bx - 1) / bx;
+    s = std::min<int64_t>(s, (P + 63) / 64);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(s, 1024));
+}
+
+template <typename T, int H>
+static hipError_t dir_step_h(const DirDesc<T>& d, cplx_t<T>* part, int nslices, hipStream_t s) {
+    constexpr int QZ = H / 2 < 32 ? H / 2 : 32;
+    const int cols = H * H * (H / QZ);
+    launch_kernel((k_dir_beta<T, H, QZ>), dim3((cols + DIR_THREADS - 1) / DIR_THREADS, nslices), dim3(DIR_THREADS), 0,
+                  s, d, part);
+    launch_kernel((k_dir_modes<T, H>), dim3((H * H * H + DIR_THREADS - 1) / DIR_THREADS), dim3(DIR_THREADS), 0, s, d,
+                  (const cplx_t<T>*)part, nslices);
+    const dim3 g((unsigned)((d.P + DIR_THREADS - 1) / DIR_THREADS));
+    if (d.scheme == SIPF_STRANG) launch_kernel((k_dir_push<T, H, SIPF_STRANG>), g, dim3(DIR_THREADS), 0, s, d);
+    else launch_kernel((k_dir_push<T, H, SIPF_EM>), g, dim3(DIR_THREADS), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, hipStream_t s) {
+    switch (d.H) {
+        case 8: return dir_step_h<T, 8>(d, part, nslices, s);
+        case 16: return dir_step_h<T, 16>(d, part, nslices, s);
+        case 32: return dir_step_h<T, 32>(d, part, nslices, s);
+        case 64: return dir_step_h<T, 64>(d, part, nslices, s);
+        case 128:
+            if constexpr (sizeof(T) == 4) return dir_step_h<T, 128>(d, part, nslices, s);
+            else return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_direct_step<float>(const DirDesc<float>&, cplx_t<float>*, int, hipStream_t);
+template hipError_t launch_direct_step<double>(const DirDesc<double>&, cplx_t<double>*, int, hipStream_t);
+
+}  // namespace sipf

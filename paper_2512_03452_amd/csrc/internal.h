@@ -203,6 +203,32 @@ hipError_t launch_xbar_order(T* xbar, T* bx, T* by, T* bz, const uint32_t* id, i
                              hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 int adj_window_bytes(bool fp64);
+// --- direct SIPF (direct.hip) -------------------------------------------------
+// One instance of Algorithm 1: particles in original order (SoA), full
+// spectra H^3 in natural order.
+template <typename T> struct DirDesc {
+    T* x;
+    T* y;
+    T* z;
+    int64_t P;
+    int H;
+    int scheme;
+    T L, halfL, invL;
+    T bscale;               // M0 / (P L^3)
+    T chitau;               // chi tau
+    T s;                    // noise scale (as in PartDesc)
+    cplx_t<T>* alpha;       // H^3, updated in place
+    cplx_t<T>* gc;          // 3 x H^3: i xi_d Phi alpha^(n-1)
+    uint32_t* step;         // completed steps, advanced by the step's first kernel
+    int* err;
+    uint32_t k0, k1, inst;
+    FieldDesc<T> fd;        // mode factors, filter, 2 pi / L (the grid pointers are unused)
+};
+int dir_slices(int H, int64_t P);
+// part: dir_slices(H, P) x H^3 complex scratch
+template <typename T>
+hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, hipStream_t s);
+
 // --- diagnostics (diag.hip) ---------------------------------------------------
 // One instance: the regularised density on the grid, the permuted half
 // spectrum alpha and the current particle positions.

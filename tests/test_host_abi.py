@@ -63,7 +63,7 @@ def test_defaults():
 @pytest.mark.parametrize("field,value", [
     ("H", 48), ("H", 4), ("H", 256), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
     ("chi", float("inf")), ("M0", -2.0), ("L", 0.0), ("p2g_order", 2), ("g2p_order", 4),
-    ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4), ("propagator", 2), ("reserved", 1),
+    ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4), ("propagator", 2), ("method", 2),
 ])
 def test_invalid_parameters_rejected_before_device(field, value):
     L = _lib()

@@ -504,3 +504,31 @@ def test_adjoint_linear_functional_cotangent():
     p0 = sipf.Params(**{**prm.__dict__, "chi": prm.chi - e})
     fd = (adjoint.loss_only(X0, p1, 2, phi_bar=pb) - adjoint.loss_only(X0, p0, 2, phi_bar=pb)) / (2 * e)
     assert abs(gchi - fd) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_direct_gradient_of_a_single_mode_off_grid():
+    """eq. gradc for alpha = a at q0 and conj(a) at -q0 (a real field
+    c = 2 Re(a e^{i xi.x})): grad c = -2 xi |a| sin(xi.x + arg a) at any point."""
+    H, L = 8, 2.0
+    q0 = np.array([2, -1, 3])
+    a = 0.3 - 0.4j
+    alpha = np.zeros((H, H, H), dtype=np.complex128)
+    alpha[tuple(q0 % H)] = a
+    alpha[tuple((-q0) % H)] = np.conj(a)
+    prm = sipf.Params(L=L, H=H, H0=-1.0)
+    X = np.random.default_rng(0).uniform(-1, 1, (40, 3))
+    xi = 2 * np.pi * q0 / L
+    want = -2 * abs(a) * np.sin(X @ xi + np.angle(a))[:, None] * xi[None, :]
+    got = sipf.direct_gradient(alpha, X, prm, use_filter=False)
+    assert np.abs(got - want).max() < 1e-12
+
+
+def test_direct_em_step_without_chemotaxis_is_pure_noise():
+    """Algorithm 1 with chi = 0: X' = wrap(X + sqrt(2 mu tau) (z0, z1, z2))."""
+    from oracle import philox
+    prm = sipf.Params(L=2.0, H=8, chi=0.0, mu=0.7, dt=1e-3, scheme="em", seed=5, M0=10.0)
+    X = np.random.default_rng(1).uniform(-1, 1, (30, 3))
+    X1, a1 = sipf.sipf_direct_step(X, np.zeros((8, 8, 8), complex), 4, prm)
+    Z = philox.normals6(np.arange(30, dtype=np.uint64), 4, 5, 0)
+    assert np.abs(X1 - sipf.wrap(X + np.sqrt(2 * 0.7 * 1e-3) * Z[:, 0:3], 2.0)).max() < 1e-15
+    assert abs(a1[0, 0, 0] - sipf.mode_factors(prm)[1][0, 0, 0] * 10.0 / 8.0) < 1e-15
