@@ -165,6 +165,67 @@ def ensemble_throughput(pkg, workloads, np, torch, steps=40):
             "phases_us_per_step": {k: 1e3 * v[0] / 8 for k, v in prof.items() if v[1]}}
 
 
+def algorithmic_bytes_2d(phase, P, H, tsize):
+    """Bytes each 2-D pass must move (every array read or written once)."""
+    spec = 2 * tsize * H * (H // 2 + 1)
+    grid = tsize * H * H
+    if phase == "particles":
+        # X read + write (2 coordinates), id read, deposit out, 2 gradient grids in
+        return 4 * tsize * P + 4 * P + grid + 2 * grid
+    if phase == "fwd_planes":
+        return grid + spec
+    if phase == "xpencils":
+        return spec + 2 * spec + 2 * spec
+    if phase == "inv_planes":
+        return 2 * spec + 2 * grid
+    return 0
+
+
+def two_d_section(pkg, workloads, np, torch, level, steps=100, warmup=20):
+    """The 2-D parabolic-elliptic runs of Sec. 5.2: step throughput at the
+    critical-mass configuration (P = 2^22, H = 2048, L = 8), then the
+    critical-mass and second-moment studies (full: the paper's sizes)."""
+    from paper_2512_03452_amd import critical2d
+    P, H, L = 1 << 22, 2048, 8.0
+    prm = dict(critical2d.PARAMS_2D, L=L, H=H, M0=25.0, dt=5e-4, precision="fp32", seed=0)
+    sim = pkg.Sim(workloads.disk(P, 1.0, seed=0).astype(np.float32), **prm)
+    sim.run(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    sim.sync()
+    el = time.perf_counter() - t0
+    sim.profile(True)
+    sim.run(steps)
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.close()
+    phases = {k: {"us_avg": 1e3 * v[0] / v[1]} for k, v in prof.items() if v[1]}
+    avg = prof["particles"][0] / prof["particles"][1] / 1e3
+    ab = algorithmic_bytes_2d("particles", P, H, 4)
+    out = {"workload": "disk_2d_elliptic_h2048", "P": P, "H": H, "L": L, "M0": 25.0, "dt": 5e-4, "steps": steps,
+           "ms_per_step": 1e3 * el / steps, "particle_steps_per_s": P * steps / el, "phases": phases,
+           "roofline": {"bound": "hbm", "kernel": "particles", "achieved": ab / avg / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": ab / avg / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": ab,
+                        "avg_launch_us": avg * 1e6}}
+    if level == "full":
+        cm, secs = critical2d.critical_mass_study()
+        out["critical_mass"] = {"gpu_seconds": secs, "L": 8.0, "H": 2048, "P": 1 << 22, "T": 2.0,
+                                "final": {str(M0): {"t": s[-1][0], "rho_max": s[-1][1], "hf_share": s[-1][2],
+                                                    "m2": s[-1][3], "rho_max_t0": s[0][1]} for M0, s in cm.items()}}
+        rows, secs = critical2d.second_moment_study()
+        out["second_moment"] = {"gpu_seconds": secs, "T": 2.0, "P": 1 << 20, "rows": rows}
+    else:
+        cm, secs = critical2d.critical_mass_study(M0s=(22.0, 27.0), H=1024, P=1 << 20, T=0.5, every=250)
+        out["critical_mass"] = {"gpu_seconds": secs, "L": 8.0, "H": 1024, "P": 1 << 20, "T": 0.5,
+                                "final": {str(M0): {"t": s[-1][0], "rho_max": s[-1][1], "hf_share": s[-1][2],
+                                                    "m2": s[-1][3], "rho_max_t0": s[0][1]} for M0, s in cm.items()}}
+        rows, secs = critical2d.second_moment_study(Ls=(10.0, 20.0), M0s=(25.0,), P=1 << 18, T=0.5)
+        out["second_moment"] = {"gpu_seconds": secs, "T": 0.5, "P": 1 << 18, "rows": rows}
+    return out
+
+
 def calibrate_copy(torch, nbytes=1 << 30, reps=5):
     """A plain device copy of nbytes, reps times: the reference whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) scale those of the step's kernels."""
@@ -199,6 +260,18 @@ def e1_study(size):
             "paper_slopes": {"P": -0.512, "H": -1.327}}
 
 
+def e2_study(size):
+    """SIPF (direct, Algorithm 1) against SIPF-PIC with P = H^3 in the setup of
+    the convergence study: mean error and time of one run per grid size."""
+    from paper_2512_03452_amd import convergence
+    q_ref = convergence.load_reference(os.path.join(ROOT, "tests", "golden", "radial_e1_quantiles.txt"))
+    if size == "full":
+        rows = convergence.cost_error_study((8, 16, 32, 64, 128), 8, q_ref, max_direct_H=64, timing_steps=20)
+    else:
+        rows = convergence.cost_error_study((8, 16, 32, 64), 4, q_ref, max_direct_H=32, timing_steps=10)
+    return {"steps": 2000, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +286,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--e1", default="reduced", choices=["none", "reduced", "full"],
                     help="convergence study of Sec. 5.1: 8 runs of 6 configurations, or the full 30 x 14")
+    ap.add_argument("--e2", default="quick", choices=["none", "quick", "full"],
+                    help="SIPF (direct) against SIPF-PIC with P = H^3: error and time per run")
+    ap.add_argument("--two-d", default="quick", choices=["none", "quick", "full"],
+                    help="2-D parabolic-elliptic runs of Sec. 5.2 (throughput, critical mass, second moment)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -304,6 +381,12 @@ def main():
     if args.e1 != "none":
         print(f"# convergence study of Sec. 5.1 ({args.e1})", file=sys.stderr, flush=True)
         out["e1"] = e1_study(args.e1)
+    if args.e2 != "none":
+        print(f"# SIPF against SIPF-PIC ({args.e2})", file=sys.stderr, flush=True)
+        out["e2"] = e2_study(args.e2)
+    if args.two_d != "none":
+        print(f"# 2-D parabolic-elliptic runs ({args.two_d})", file=sys.stderr, flush=True)
+        out["two_d"] = two_d_section(pkg, workloads, np, torch, args.two_d)
     if not args.no_adjoint:
         print("# fwd+adjoint vs fwd on the adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(pkg, workloads, np, torch)

@@ -139,7 +139,8 @@ typedef struct sipf_params {
     int32_t  precision;    /* SIPF_FP32 (default) or SIPF_FP64                    */
     int32_t  tile;         /* binning tile side in cells; 0 = tuned default; at most
                               16 (3-D) or 64 (2-D) tiles per axis                 */
-    int32_t  resort_every; /* re-sort period in steps; 0 = tuned default           */
+    int32_t  resort_every; /* re-sort period in steps; 0 = default: 4, or fewer when
+                              sqrt(2 mu tau n) exceeds a quarter of a tile      */
     int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = tuned */
     uint64_t seed;         /* Philox key                                          */
     uint32_t instance;     /* fourth Philox counter word                          */
@@ -307,7 +308,8 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
  * Batched ensembles: n (1..1024) independent instances advanced together.
  * Each has its own parameters (H, chi, mu, M0, dt, seed, instance word, tile
  * ...); all must share the precision and the scheme (SIPF_EINVAL otherwise).
- * The group's chunk and re-sort period are those of prm[0].  Per step the
+ * The group's chunk is that of prm[0] and its re-sort period the smallest
+ * of the instances' periods.  Per step the
  * batch issues one persistent particle launch over the work items of every
  * instance and one launch per FFT phase and distinct grid size H; every
  * re-sort period one sort of every instance (four launches).

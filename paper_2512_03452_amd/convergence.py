@@ -125,6 +125,57 @@ def run_study(configs, nsim, q_ref, steps=workloads.E1_STEPS, seed=0, precision=
     return out, elapsed
 
 
+def _run_single(method, H, P, seed, instance, steps, precision):
+    """One run of the study's setup with P particles on grid H: final
+    positions and the GPU time of the steps (seconds)."""
+    from .sim import Sim
+    dt = np.float32 if precision == "fp32" else np.float64
+    prm = dict(workloads.E1_PARAMS, H=H, precision=precision, seed=seed, instance=instance)
+    if method == "direct":
+        # Algorithm 1 as printed: Euler-Maruyama push, unfiltered gradient sum
+        prm.update(method="direct", scheme="em", H0=-1.0)
+    sim = Sim(workloads.ball(P, 1.0, seed=seed * 1_000_003 + instance).astype(dt), **prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    sim.sync()
+    secs = time.perf_counter() - t0
+    X = sim.positions()
+    sim.close()
+    return X, secs
+
+
+def cost_error_study(Hs, nsim, q_ref, methods=("pic", "direct"), steps=workloads.E1_STEPS, seed=0,
+                     precision="fp32", max_direct_H=64, timing_steps=None, log=None):
+    """Sec. 5.1 comparison of SIPF and SIPF-PIC: P = H^3 particles, the
+    setup of the convergence study, nsim runs per (method, H): mean truncated
+    quantile discrepancy and mean time of one run.  Runs of the direct method
+    above max_direct_H are only timed over timing_steps steps and scaled to the
+    full run (no error reported)."""
+    probs = probabilities()
+    out = []
+    for method in methods:
+        for H in Hs:
+            P = H ** 3
+            if method == "direct" and H > max_direct_H:
+                if not timing_steps:
+                    continue
+                _, secs = _run_single(method, H, P, seed, 0, timing_steps, precision)
+                out.append(dict(method=method, H=H, P=P, runs=0, E=None, seconds_per_run=secs * steps / timing_steps,
+                                timed_steps=timing_steps))
+                continue
+            E, T = [], []
+            for l in range(nsim):
+                X, secs = _run_single(method, H, P, seed, 1000 * H + l, steps, precision)
+                E.append(discrepancy(q_ref, empirical_quantiles(X, probs).cpu().numpy()))
+                T.append(secs)
+            out.append(dict(method=method, H=H, P=P, runs=nsim, E=float(np.mean(E)), E_std=float(np.std(E)),
+                            seconds_per_run=float(np.mean(T)), timed_steps=steps))
+            if log:
+                log(f"{method} H={H} E={np.mean(E):.4g} s/run={np.mean(T):.3g}")
+    return out
+
+
 def load_reference(path):
     """Read a reference quantile table ("p q_p" lines, '#' comments)."""
     data = np.loadtxt(path)

@@ -110,7 +110,17 @@ int default_tile(const sipf_params* p) {
     if (p->H / t > 16) t = p->H / 16;
     return t;
 }
-int default_resort(const sipf_params* p) { return p->resort_every ? p->resort_every : 4; }
+// Re-sort period: every 4 steps, or more often when the Brownian spread over
+// the period, sqrt(2 mu tau n), would exceed a quarter of a tile (item boxes
+// then outgrow their LDS windows and the pass falls back to global atomics).
+int default_resort(const sipf_params* p) {
+    if (p->resort_every) return p->resort_every;
+    const double q = default_tile(p) * p->L / p->H / 4.0;
+    const double spread = 2.0 * p->mu * p->dt;
+    if (spread <= 0) return 4;
+    const double n = std::floor(q * q / spread);
+    return (int)std::max(1.0, std::min(4.0, n));
+}
 int default_chunk(const sipf_params* p) { return p->chunk ? p->chunk : 4096; }
 
 }  // namespace
@@ -789,6 +799,7 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
     g->scheme = prm[0].scheme;
     g->stream = (hipStream_t)hip_stream;
     g->resort = default_resort(&prm[0]);
+    for (int i = 1; i < n; ++i) g->resort = std::min(g->resort, default_resort(&prm[i]));
     g->chunk = default_chunk(&prm[0]);
     g->win_bytes = particle_window_bytes(g->prec == SIPF_FP64);
     g->in.resize(n);
