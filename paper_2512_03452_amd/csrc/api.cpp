@@ -144,7 +144,8 @@ struct Inst {
     // direct SIPF (Algorithm 1): alpha is the full H^3 spectrum in natural order
     void* gc = nullptr;     // 3 x H^3 gradient coefficients
     void* part = nullptr;   // nslices x H^3 partial sums of beta
-    int nslices = 0;
+    void* gpart = nullptr;  // mslices x 3 x P partial gradient sums
+    int nslices = 0, mslices = 0;
 };
 
 // Instances of one grid size: FieldDesc slots [first, first + count).
@@ -414,7 +415,8 @@ template <typename T> int enqueue_step(Group* g) {
     if (g->method == SIPF_METHOD_DIRECT) {
         Timed t(g, SIPF_PHASE_PARTICLES);
         const Inst& I = g->in[0];
-        HIPCHK(launch_direct_step<T>(make_ddesc<T>(g), (cplx_t<T>*)I.part, I.nslices, g->stream));
+        HIPCHK(launch_direct_step<T>(make_ddesc<T>(g), (cplx_t<T>*)I.part, I.nslices, (T*)I.gpart, I.mslices,
+                                     g->stream));
         g->n_host++;
         return SIPF_OK;
     }
@@ -574,6 +576,7 @@ template <typename T> int alloc_direct(Group* g) {
     const size_t H3 = (size_t)I.H * I.H * I.H;
     const size_t V = 2 * sizeof(T);
     I.nslices = dir_slices(I.H, I.P);
+    I.mslices = dir_mode_slices(I.H, I.P);
     if ((rc = dalloc(g, &I.xs[0], I.P * sizeof(T)))) return rc;
     if ((rc = dalloc(g, &I.ys[0], I.P * sizeof(T)))) return rc;
     if ((rc = dalloc(g, &I.zs[0], I.P * sizeof(T)))) return rc;
@@ -581,6 +584,7 @@ template <typename T> int alloc_direct(Group* g) {
     if ((rc = dalloc(g, &I.alpha, H3 * V))) return rc;
     if ((rc = dalloc(g, &I.gc, 3 * H3 * V))) return rc;
     if ((rc = dalloc(g, &I.part, (size_t)I.nslices * H3 * V))) return rc;
+    if ((rc = dalloc(g, &I.gpart, (size_t)I.mslices * 3 * I.P * sizeof(T)))) return rc;
     if ((rc = dalloc(g, (void**)&g->steps, sizeof(uint32_t)))) return rc;
     if ((rc = dalloc(g, (void**)&g->errs, sizeof(int)))) return rc;
     HIPCHK(hipMemset(g->steps, 0, sizeof(uint32_t)));

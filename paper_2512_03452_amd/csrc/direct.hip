@@ -18,9 +18,11 @@
 //   dir_modes   thread = mode: sums the slice partials in a fixed order, forms
 //               the gradient coefficients i xi Phi alpha^(n-1), then updates
 //               alpha.
-//   dir_push    thread = particle: the gradient sum at the particle (the
-//               coefficients of a run of (kx, ky) pairs pass through LDS),
-//               then the push of Algorithm 1 (Euler-Maruyama) or Algorithm 4.
+//   dir_grad    thread = particle, workgroup row = slice of the (kx, ky)
+//               pairs: the gradient sum at the particle over the slice (the
+//               coefficients of DIR_PAIRS pairs at a time pass through LDS).
+//   dir_push    sums the slices in a fixed order and pushes: Algorithm 1
+//               (Euler-Maruyama) or the split step of Algorithm 4.
 #include "internal.h"
 #include "pass_common.h"
 #include "sipf.h"
@@ -115,41 +117,49 @@ __global__ __launch_bounds__(DIR_THREADS) void k_dir_modes(DirDesc<T> d, const c
     d.alpha[m] = cmake<V, T>(A * a.x + B * beta.x, A * a.y + B * beta.y);
 }
 
+// the particle's position at which the drift is taken (Y = X + W^- for the
+// split step, X for Euler-Maruyama) and its remaining noise
+template <typename T, int SCHEME>
+__device__ __forceinline__ void dir_noise(const DirDesc<T>& d, int64_t p, T& x, T& y, T& z, T& w0, T& w1, T& w2) {
+    x = d.x[p];
+    y = d.y[p];
+    z = d.z[p];
+    T zn[6];
+    const uint32_t n = *d.step;  // advanced by this step's dir_beta
+    if (SCHEME == SIPF_STRANG) {
+        noise6<3, T>((uint32_t)p, n, d.inst, d.k0, d.k1, zn);
+        x += d.s * zn[0];
+        y += d.s * zn[1];
+        z += d.s * zn[2];
+        w0 = zn[3];
+        w1 = zn[4];
+        w2 = zn[5];
+    } else {
+        noise6<2, T>((uint32_t)p, n, d.inst, d.k0, d.k1, zn);
+        w0 = zn[0];
+        w1 = zn[1];
+        w2 = zn[2];
+    }
+}
+
+// partial gradient sums over the (kx, ky) pairs of slice blockIdx.y
 template <typename T, int H, int SCHEME>
-__global__ __launch_bounds__(DIR_THREADS) void k_dir_push(DirDesc<T> d) {
+__global__ __launch_bounds__(DIR_THREADS) void k_dir_grad(DirDesc<T> d, T* __restrict__ gpart) {
     using V = cplx_t<T>;
     __shared__ V sg[3][DIR_PAIRS][H];
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * DIR_THREADS + tid;
     const bool active = p < d.P;
-    T x = 0, y = 0, z = 0, w0 = 0, w1 = 0, w2 = 0;
-    if (active) {
-        x = d.x[p];
-        y = d.y[p];
-        z = d.z[p];
-        T zn[6];
-        const uint32_t n = *d.step;  // advanced by this step's dir_beta
-        if (SCHEME == SIPF_STRANG) {
-            noise6<3, T>((uint32_t)p, n, d.inst, d.k0, d.k1, zn);
-            x += d.s * zn[0];
-            y += d.s * zn[1];
-            z += d.s * zn[2];
-            w0 = zn[3];
-            w1 = zn[4];
-            w2 = zn[5];
-        } else {
-            noise6<2, T>((uint32_t)p, n, d.inst, d.k0, d.k1, zn);
-            w0 = zn[0];
-            w1 = zn[1];
-            w2 = zn[2];
-        }
-    }
+    T x = 0, y = 0, z = 0, w0, w1, w2;
+    if (active) dir_noise<T, SCHEME>(d, p, x, y, z, w0, w1, w2);
     const T xl = x * d.invL, yl = y * d.invL, zl = z * d.invL;
     // exp(+i xi . X): conjugate of cis_neg
     V st = cis_neg<T>(zl);
     st.y = -st.y;
     T g0 = 0, g1 = 0, g2 = 0;
-    for (int pr0 = 0; pr0 < H * H; pr0 += DIR_PAIRS) {
+    const int npairs = H * H / gridDim.y;  // pairs per slice (a multiple of DIR_PAIRS)
+    const int first = blockIdx.y * npairs;
+    for (int pr0 = first; pr0 < first + npairs; pr0 += DIR_PAIRS) {
         __syncthreads();
         for (int u = tid; u < 3 * DIR_PAIRS * H; u += DIR_THREADS) {
             const int c = u / (DIR_PAIRS * H), r = u % (DIR_PAIRS * H);
@@ -174,17 +184,46 @@ __global__ __launch_bounds__(DIR_THREADS) void k_dir_push(DirDesc<T> d) {
         }
     }
     if (active) {
-        const T nx = wrap_box(x + d.chitau * g0 + d.s * w0, d.L, d.halfL, d.invL);
-        const T ny = wrap_box(y + d.chitau * g1 + d.s * w1, d.L, d.halfL, d.invL);
-        const T nz = wrap_box(z + d.chitau * g2 + d.s * w2, d.L, d.halfL, d.invL);
-        d.x[p] = nx;
-        d.y[p] = ny;
-        d.z[p] = nz;
-        if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(d.err, 1);
+        T* out = gpart + (size_t)blockIdx.y * 3 * d.P;
+        out[p] = g0;
+        out[d.P + p] = g1;
+        out[2 * d.P + p] = g2;
     }
 }
 
+// sum of the slices in a fixed order, then the push
+template <typename T, int SCHEME>
+__global__ __launch_bounds__(DIR_THREADS) void k_dir_push(DirDesc<T> d, const T* __restrict__ gpart, int ms) {
+    const int64_t p = (int64_t)blockIdx.x * DIR_THREADS + threadIdx.x;
+    if (p >= d.P) return;
+    T x, y, z, w0, w1, w2;
+    dir_noise<T, SCHEME>(d, p, x, y, z, w0, w1, w2);
+    T g0 = 0, g1 = 0, g2 = 0;
+    for (int k = 0; k < ms; ++k) {
+        const T* g = gpart + (size_t)k * 3 * d.P;
+        g0 += g[p];
+        g1 += g[d.P + p];
+        g2 += g[2 * d.P + p];
+    }
+    const T nx = wrap_box(x + d.chitau * g0 + d.s * w0, d.L, d.halfL, d.invL);
+    const T ny = wrap_box(y + d.chitau * g1 + d.s * w1, d.L, d.halfL, d.invL);
+    const T nz = wrap_box(z + d.chitau * g2 + d.s * w2, d.L, d.halfL, d.invL);
+    d.x[p] = nx;
+    d.y[p] = ny;
+    d.z[p] = nz;
+    if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(d.err, 1);
+}
+
 int dir_qz(int H) { return H / 2 < 32 ? H / 2 : 32; }
+
+// slices of the (kx, ky) pairs in the gradient sum: enough workgroups to fill
+// the device when the particles alone do not
+int dir_mode_slices(int H, int64_t P) {
+    const int64_t pb = (P + DIR_THREADS - 1) / DIR_THREADS;
+    int ms = 1;
+    while (ms * pb < 2048 && ms * 2 * DIR_PAIRS <= H * H && ms < 64) ms *= 2;
+    return ms;
+}
 
 int dir_slices(int H, int64_t P) {
     const int64_t cols = (int64_t)H * H * (H / dir_qz(H));
@@ -195,34 +234,41 @@ int dir_slices(int H, int64_t P) {
 }
 
 template <typename T, int H>
-static hipError_t dir_step_h(const DirDesc<T>& d, cplx_t<T>* part, int nslices, hipStream_t s) {
+static hipError_t dir_step_h(const DirDesc<T>& d, cplx_t<T>* part, int nslices, T* gpart, int ms, hipStream_t s) {
     constexpr int QZ = H / 2 < 32 ? H / 2 : 32;
     const int cols = H * H * (H / QZ);
     launch_kernel((k_dir_beta<T, H, QZ>), dim3((cols + DIR_THREADS - 1) / DIR_THREADS, nslices), dim3(DIR_THREADS), 0,
                   s, d, part);
     launch_kernel((k_dir_modes<T, H>), dim3((H * H * H + DIR_THREADS - 1) / DIR_THREADS), dim3(DIR_THREADS), 0, s, d,
                   (const cplx_t<T>*)part, nslices);
-    const dim3 g((unsigned)((d.P + DIR_THREADS - 1) / DIR_THREADS));
-    if (d.scheme == SIPF_STRANG) launch_kernel((k_dir_push<T, H, SIPF_STRANG>), g, dim3(DIR_THREADS), 0, s, d);
-    else launch_kernel((k_dir_push<T, H, SIPF_EM>), g, dim3(DIR_THREADS), 0, s, d);
+    const unsigned pb = (unsigned)((d.P + DIR_THREADS - 1) / DIR_THREADS);
+    if (d.scheme == SIPF_STRANG) {
+        launch_kernel((k_dir_grad<T, H, SIPF_STRANG>), dim3(pb, ms), dim3(DIR_THREADS), 0, s, d, gpart);
+        launch_kernel((k_dir_push<T, SIPF_STRANG>), dim3(pb), dim3(DIR_THREADS), 0, s, d, (const T*)gpart, ms);
+    } else {
+        launch_kernel((k_dir_grad<T, H, SIPF_EM>), dim3(pb, ms), dim3(DIR_THREADS), 0, s, d, gpart);
+        launch_kernel((k_dir_push<T, SIPF_EM>), dim3(pb), dim3(DIR_THREADS), 0, s, d, (const T*)gpart, ms);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, hipStream_t s) {
+hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, T* gpart, int ms, hipStream_t s) {
+    if (ms < 1 || (d.H * d.H) % (ms * DIR_PAIRS) != 0) return hipErrorInvalidValue;
     switch (d.H) {
-        case 8: return dir_step_h<T, 8>(d, part, nslices, s);
-        case 16: return dir_step_h<T, 16>(d, part, nslices, s);
-        case 32: return dir_step_h<T, 32>(d, part, nslices, s);
-        case 64: return dir_step_h<T, 64>(d, part, nslices, s);
+        case 8: return dir_step_h<T, 8>(d, part, nslices, gpart, ms, s);
+        case 16: return dir_step_h<T, 16>(d, part, nslices, gpart, ms, s);
+        case 32: return dir_step_h<T, 32>(d, part, nslices, gpart, ms, s);
+        case 64: return dir_step_h<T, 64>(d, part, nslices, gpart, ms, s);
         case 128:
-            if constexpr (sizeof(T) == 4) return dir_step_h<T, 128>(d, part, nslices, s);
+            if constexpr (sizeof(T) == 4) return dir_step_h<T, 128>(d, part, nslices, gpart, ms, s);
             else return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_direct_step<float>(const DirDesc<float>&, cplx_t<float>*, int, hipStream_t);
-template hipError_t launch_direct_step<double>(const DirDesc<double>&, cplx_t<double>*, int, hipStream_t);
+template hipError_t launch_direct_step<float>(const DirDesc<float>&, cplx_t<float>*, int, float*, int, hipStream_t);
+template hipError_t launch_direct_step<double>(const DirDesc<double>&, cplx_t<double>*, int, double*, int,
+                                               hipStream_t);
 
 }  // namespace sipf

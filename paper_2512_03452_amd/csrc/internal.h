@@ -225,9 +225,11 @@ template <typename T> struct DirDesc {
     FieldDesc<T> fd;        // mode factors, filter, 2 pi / L (the grid pointers are unused)
 };
 int dir_slices(int H, int64_t P);
-// part: dir_slices(H, P) x H^3 complex scratch
+int dir_mode_slices(int H, int64_t P);
+// part: dir_slices(H, P) x H^3 complex scratch; gpart: ms x 3 x P partial
+// gradients, ms = dir_mode_slices(H, P)
 template <typename T>
-hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, hipStream_t s);
+hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, T* gpart, int ms, hipStream_t s);
 
 // --- diagnostics (diag.hip) ---------------------------------------------------
 // One instance: the regularised density on the grid, the permuted half
