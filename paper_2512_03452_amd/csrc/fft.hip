@@ -50,7 +50,17 @@ bool fft_size_supported(int H, bool fp64) {
     return !(fp64 && H > 64);
 }
 
-constexpr int PLANE_THREADS = 512;
+// threads of the plane passes: the forward pass has only H workgroups and the
+// inverse 3H, so a plane gets 1024 threads (measured at H = 128: 16.9 -> 13.3
+// us forward, 19.6 -> 17.6 us inverse, against 512)
+#ifndef SIPF_FWD_THREADS
+#define SIPF_FWD_THREADS 1024
+#endif
+#ifndef SIPF_INV_THREADS
+#define SIPF_INV_THREADS 1024
+#endif
+constexpr int FWD_THREADS = SIPF_FWD_THREADS;
+constexpr int PLANE_THREADS = SIPF_INV_THREADS;
 constexpr int PENCIL_THREADS = 256;
 constexpr int KB = 16;  // kz columns per x-pencil workgroup
 
@@ -66,13 +76,13 @@ constexpr int KB = 16;  // kz columns per x-pencil workgroup
 // FFT leaves Z in permuted order.
 // ---------------------------------------------------------------------------
 template <typename T, int H>
-__global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>* __restrict__ fds, int consume) {
+__global__ __launch_bounds__(FWD_THREADS) void k_fwd_planes(const FieldDesc<T>* __restrict__ fds, int consume) {
     using V = cplx_t<T>;
     constexpr int M = H / 2;
     constexpr int HH = M + 1;
     constexpr int OP = HH;  // row pitch (complex)
     constexpr int NP = M / 2 + 1;  // pairs (k, M - k) per row, k = 0 .. M/2
-    constexpr int PPT = (H * NP + PLANE_THREADS - 1) / PLANE_THREADS;
+    constexpr int PPT = (H * NP + FWD_THREADS - 1) / FWD_THREADS;
     __shared__ V buf[H * OP];
     __shared__ V tw[H];
     __shared__ V twm[M];
@@ -98,7 +108,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>
     V za[PPT], zb[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const int u = tid + q * PLANE_THREADS;
+        const int u = tid + q * FWD_THREADS;
         if (u < H * NP) {
             const int row = u / NP, k = u % NP;
             za[q] = buf[row * OP + perm_pos<M>(k % M)];
@@ -108,7 +118,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_fwd_planes(const FieldDesc<T>
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const int u = tid + q * PLANE_THREADS;
+        const int u = tid + q * FWD_THREADS;
         if (u < H * NP) {
             const int row = u / NP, k = u % NP;
             const V zc = cconj(zb[q]);
@@ -414,7 +424,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
 // ---------------------------------------------------------------------------
 template <typename T, int H>
 static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s) {
-    launch_kernel((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(PLANE_THREADS), 0, s, fd, consume ? 1 : 0);
+    launch_kernel((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(FWD_THREADS), 0, s, fd, consume ? 1 : 0);
     return hipGetLastError();
 }
 template <typename T, int H>

@@ -22,14 +22,23 @@
 
 namespace sipf {
 
+#ifndef SIPF_XROW_THREADS
+#define SIPF_XROW_THREADS 256
+#endif
+#ifndef SIPF_ROWS2_MUL
+#define SIPF_ROWS2_MUL 1
+#endif
 constexpr int ROW_THREADS = 512;
-constexpr int XROW_THREADS = 256;
+constexpr int XROW_THREADS = SIPF_XROW_THREADS;
 
 // rows per workgroup of the row passes: R (H/2 + 1) values plus an H-entry
 // twiddle table stay within LDS; R rows give R-value runs in the transposed
 // spectrum
-template <int H> struct Rows2 {
-    static constexpr int R = H <= 16 ? H : (H <= 512 ? 16 : (H == 1024 ? 8 : (H == 2048 ? 4 : 2)));
+template <typename T, int H> struct Rows2 {
+    static constexpr int R0 = H <= 16 ? H : (H <= 512 ? 16 : (H == 1024 ? 8 : (H == 2048 ? 4 : 2)));
+    static constexpr int R1 = R0 * SIPF_ROWS2_MUL;
+    static constexpr bool fits = (size_t)(R1 * (H / 2 + 1) + H) * 2 * sizeof(T) <= 150 * 1024;
+    static constexpr int R = (H >= 1024 && R1 <= 16 && fits) ? R1 : R0;
 };
 
 enum { XR_STEP = 0, XR_GRAD = 1, XR_RHO = 4 };
@@ -37,7 +46,7 @@ enum { XR_STEP = 0, XR_GRAD = 1, XR_RHO = 4 };
 template <typename T, int H>
 __global__ __launch_bounds__(ROW_THREADS) void k2_fwd_rows(const FieldDesc<T>* __restrict__ fds, int consume) {
     using V = cplx_t<T>;
-    constexpr int M = H / 2, HH = M + 1, OP = HH, R = Rows2<H>::R;
+    constexpr int M = H / 2, HH = M + 1, OP = HH, R = Rows2<T, H>::R;
     constexpr int NP = M / 2 + 1;  // pairs (k, M - k) per row
     constexpr int PPT = (R * NP + ROW_THREADS - 1) / ROW_THREADS;
     __shared__ V buf[R * OP];
@@ -167,7 +176,7 @@ __global__ __launch_bounds__(XROW_THREADS) void k2_xrows(const FieldDesc<T>* __r
 template <typename T, int H>
 __global__ __launch_bounds__(ROW_THREADS) void k2_inv_rows(const FieldDesc<T>* __restrict__ fds, int ncomp) {
     using V = cplx_t<T>;
-    constexpr int M = H / 2, HH = M + 1, OP = HH, R = Rows2<H>::R;
+    constexpr int M = H / 2, HH = M + 1, OP = HH, R = Rows2<T, H>::R;
     constexpr int NP = M / 2 + 1;
     constexpr int PPT = (R * NP + ROW_THREADS - 1) / ROW_THREADS;
     __shared__ V buf[R * OP];
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(ROW_THREADS) void k2_inv_rows(const FieldDesc<T>* _
 // ---------------------------------------------------------------------------
 template <typename T, int H>
 static hipError_t fwd_rows_h(const FieldDesc<T>* fd, int count, bool consume, hipStream_t s) {
-    launch_kernel((k2_fwd_rows<T, H>), dim3(H / Rows2<H>::R, count), dim3(ROW_THREADS), 0, s, fd, consume ? 1 : 0);
+    launch_kernel((k2_fwd_rows<T, H>), dim3(H / Rows2<T, H>::R, count), dim3(ROW_THREADS), 0, s, fd, consume ? 1 : 0);
     return hipGetLastError();
 }
 template <typename T, int H>
@@ -243,7 +252,7 @@ static hipError_t xrows_h(const FieldDesc<T>* fd, int count, int mode, hipStream
 }
 template <typename T, int H>
 static hipError_t inv_rows_h(const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s) {
-    launch_kernel((k2_inv_rows<T, H>), dim3((H / Rows2<H>::R) * ncomp, count), dim3(ROW_THREADS), 0, s, fd, ncomp);
+    launch_kernel((k2_inv_rows<T, H>), dim3((H / Rows2<T, H>::R) * ncomp, count), dim3(ROW_THREADS), 0, s, fd, ncomp);
     return hipGetLastError();
 }
 
