@@ -50,7 +50,11 @@
  *     destroyed.
  *   - H must be a power of two with 8 <= H <= 128 (FP32) or 8 <= H <= 64
  *     (FP64): one yz-plane of the half spectrum must fit in the 160 KB of LDS
- *     of a gfx950 compute unit.  Other sizes return SIPF_EINVAL.
+ *     of a gfx950 compute unit.  The mixed-radix grids H = 12, 22, 46 (both
+ *     precisions) and 90 (FP32) of the SIPF against SIPF-PIC comparison
+ *     (Sec. 5.1) are also accepted; on them the tile side must divide H, and
+ *     sipf_adjoint and the direct method (SIPF_METHOD_DIRECT) return
+ *     SIPF_EINVAL.  Other sizes return SIPF_EINVAL.
  *
  * Variants (Sec. 5.2):
  *   - eps = 0 makes the c-equation elliptic, -lap c + k^2 c = rho: the mode
@@ -132,13 +136,14 @@ typedef struct sipf_params {
     double   M0;           /* total mass of the particles (>= 0)                  */
     double   dt;           /* time step tau (> 0)                                 */
     double   H0;           /* filter scale; 0: ceil(8 H^(8/13) L^(5/13)); <0: off */
-    int32_t  H;            /* grid points per axis (power of two, see above)      */
+    int32_t  H;            /* grid points per axis (see above)                    */
     int32_t  p2g_order;    /* must be 4 (Remark after Definition grid2particle)  */
     int32_t  g2p_order;    /* must be 2 (same remark)                             */
     int32_t  scheme;       /* SIPF_STRANG (default) or SIPF_EM                    */
     int32_t  precision;    /* SIPF_FP32 (default) or SIPF_FP64                    */
     int32_t  tile;         /* binning tile side in cells; 0 = tuned default; at most
-                              16 (3-D) or 64 (2-D) tiles per axis                 */
+                              16 (3-D) or 64 (2-D) tiles per axis; a power of two,
+                              or a divisor of H when H is not one                */
     int32_t  resort_every; /* re-sort period in steps; 0 = default: 4, or fewer when
                               sqrt(2 mu tau n) exceeds a quarter of a tile      */
     int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = tuned */
@@ -252,7 +257,8 @@ int sipf_diagnostics(sipf_ctx* ctx, sipf_diag* out);
  *   dX0      out: dL/dX^(0), device buffer P x 3 in original particle order.
  * floor() is treated as locally constant and the periodic wrap as the
  * identity (both hold almost everywhere).  After return the context holds
- * X^(N), alpha^(N) (n = nsteps).  Synchronises.
+ * X^(N), alpha^(N) (n = nsteps).  Synchronises.  SIPF_EINVAL in two
+ * dimensions, for the direct method and for H that is not a power of two.
  */
 int sipf_adjoint(sipf_ctx* ctx, int64_t nsteps, int32_t ckpt_every, const void* phi_bar,
                  double* loss, double* dchi, double* dmu, void* dX0);
@@ -294,7 +300,8 @@ const char* sipf_last_error(void);
  * Tile / chunk / re-sort autotuner.  Times nsteps steps (after a warm-up that
  * includes graph capture) of fresh contexts built from prm, P and X0 (same
  * meaning as in sipf_init), searching one axis at a time: the binning tile
- * (powers of two from 4 to 32 within the limits of sipf_params.tile), the
+ * (powers of two from 4 to 32, or the divisors of H when H is not a power of
+ * two, within the limits of sipf_params.tile), the
  * work-item size (1024, 2048, 4096) and the re-sort period (2, 4, 8, 16),
  * starting from the defaults.  *best receives prm with tile, chunk and
  * resort_every set to the fastest combination found, *ms_per_step its time.

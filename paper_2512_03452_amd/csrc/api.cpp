@@ -59,7 +59,7 @@ int validate(const sipf_params* p, int64_t P) {
     if (p->precision != SIPF_FP32 && p->precision != SIPF_FP64) return fail(SIPF_EINVAL, "precision must be SIPF_FP32 or SIPF_FP64");
     if (p->dim != 0 && p->dim != 2 && p->dim != 3) return fail(SIPF_EINVAL, "dim must be 0, 2 or 3");
     if (dim_of(p) == 3 && !fft_size_supported(p->H, p->precision == SIPF_FP64))
-        return fail(SIPF_EINVAL, "H must be a power of two in [8, 128] (FP32) or [8, 64] (FP64)");
+        return fail(SIPF_EINVAL, "H must be 8, 12, 16, 22, 32, 46, 64, 90 or 128 (FP32), or one of those up to 64 (FP64)");
     if (dim_of(p) == 2 && !fft2d_size_supported(p->H))
         return fail(SIPF_EINVAL, "H must be a power of two in [8, 4096] in two dimensions");
     auto fin = [](double v) { return std::isfinite(v); };
@@ -79,13 +79,17 @@ int validate(const sipf_params* p, int64_t P) {
         return fail(SIPF_EINVAL, "method must be SIPF_METHOD_PIC or SIPF_METHOD_DIRECT");
     if (p->method == SIPF_METHOD_DIRECT && dim_of(p) != 3)
         return fail(SIPF_EINVAL, "the direct SIPF method is three-dimensional");
+    if (p->method == SIPF_METHOD_DIRECT && !is_pow2(p->H))
+        return fail(SIPF_EINVAL, "the direct SIPF method needs H a power of two");
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
     if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
     if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
     const int max_tiles = dim_of(p) == 2 ? 64 : 16;
-    if (p->tile != 0 && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > max_tiles))
+    if (p->tile != 0 && is_pow2(p->H) && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > max_tiles))
         return fail(SIPF_EINVAL, dim_of(p) == 2 ? "tile must be 0 or a power of two with H/64 <= tile <= H"
                                                 : "tile must be 0 or a power of two with H/16 <= tile <= H");
+    if (p->tile != 0 && !is_pow2(p->H) && (p->tile < 1 || p->tile > p->H || p->H % p->tile != 0 || p->H / p->tile > max_tiles))
+        return fail(SIPF_EINVAL, "tile must be 0 or a divisor of H with H/16 <= tile <= H");
     if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
     if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 4096)) return fail(SIPF_EINVAL, "chunk must be 0 or in [256, 4096]");
     if (P < 1 || P >= (int64_t(1) << 32)) return fail(SIPF_EINVAL, "P must be in [1, 2^32)");
@@ -99,8 +103,17 @@ double filter_h0(const sipf_params* p) {
 
 // Defaults where the parameters leave the tuning open (0): an 8-cell tile at
 // H = 128 and H/8 below (3-D), 16-cell tiles up to H = 1024 and H/64 above
-// (2-D), a re-sort every 4 steps, items of up to 4096.
+// (2-D), a re-sort every 4 steps, items of up to 4096.  A 3-D grid that is not
+// a power of two takes the smallest divisor of H with at most 8 tiles per axis
+// (the whole axis below H = 16).
 int default_tile(const sipf_params* p) {
+    if (dim_of(p) == 3 && !is_pow2(p->H)) {
+        if (p->tile) return p->tile;
+        if (p->H < 16) return p->H;
+        int t = 1;
+        while (p->H % t != 0 || p->H / t > 8) ++t;
+        return t;
+    }
     if (dim_of(p) == 2) {
         int t = p->tile ? p->tile : std::min(p->H, std::max(16, p->H / 64));
         if (p->H / t > 64) t = p->H / 64;
@@ -157,6 +170,7 @@ struct Group {
     int prec = SIPF_FP32;
     int dim = 3;  // shared by every instance
     int method = SIPF_METHOD_PIC;
+    bool pow2 = true;  // every instance's H is a power of two
     size_t tsize = 4;
     int scheme = SIPF_STRANG;
     hipStream_t stream = nullptr;
@@ -246,8 +260,10 @@ template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
     d.inst = p.instance;
     // |W^-| <= s max|z| with max|z| = sqrt(-2 ln 2^-22) = 5.5176 (uniforms are >= 2^-22)
     d.gmargin = p.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.52 * (double)d.hl) : 0;
-    d.tshift = ilog2(I.tile);
-    const int nt = I.H / I.tile;
+    // the Morton key space is a power of two per axis; tiles past H / tile stay empty
+    d.tshift = is_pow2(I.H) && is_pow2(I.tile) ? ilog2(I.tile) : -1;
+    d.tile = I.tile;
+    const int nt = 1 << ilog2(I.H / I.tile);
     d.nkeys = I.dim == 2 ? nt * nt : nt * nt * nt;
     return d;
 }
@@ -366,7 +382,7 @@ hipError_t particles_any(const Group* g, const PartDesc<T>* pd, bool deposit, bo
     return g->dim == 2 ? launch_particles2<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
                                               g->win_bytes, g->stream)
                        : launch_particles<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
-                                             g->win_bytes, g->stream);
+                                             g->win_bytes, g->pow2, g->stream);
 }
 template <typename T> hipError_t field_fwd(const Group* g, int H, const FieldDesc<T>* fd, int count, bool consume) {
     return g->dim == 2 ? launch_fwd_rows2<T>(H, fd, count, consume, g->stream)
@@ -814,6 +830,7 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
         I.H = prm[i].H;
         I.dim = dim_of(&prm[i]);
         I.tile = default_tile(&prm[i]);
+        if (!is_pow2(I.H)) g->pow2 = false;
     }
     return SIPF_OK;
 }
@@ -1175,7 +1192,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     // ---- loss and its cotangent phibar^(N)
     HIPCHK(launch_zero_f64((double*)acc.p, 4, c->stream));
     HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false, c->scheme,
-                               c->win_bytes, c->stream));
+                               c->win_bytes, c->pow2, c->stream));
     if (phibar_in) {
         HIPCHK(launch_dot<T>(phibar_in, (const T*)I.phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
         HIPCHK(hipMemcpyAsync(phibar.p, phibar_in, H3 * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
@@ -1228,7 +1245,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
             // X^(base+m) = push of X^(base+m-1) (slot m-1 -> slot m) with G^(base+m-1)
             // (step base+m), then G^(base+m)
             HIPCHK(launch_particles<T>((const PartDesc<T>*)pdR.p + (base + m - 1), c->items, c->nitems, c->pgrid,
-                                       false, true, c->scheme, c->win_bytes, c->stream));
+                                       false, true, c->scheme, c->win_bytes, c->pow2, c->stream));
             if ((rc = grad_of_tape(base + m))) return rc;
         }
         {
@@ -1511,6 +1528,7 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
     if (ckpt_every < 1) return fail(SIPF_EINVAL, "ckpt_every must be >= 1");
     if (c->dim != 3) return fail(SIPF_EINVAL, "sipf_adjoint is available in three dimensions only");
     if (c->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "sipf_adjoint runs SIPF-PIC contexts only");
+    if (!c->pow2) return fail(SIPF_EINVAL, "sipf_adjoint needs H a power of two");
     return c->prec == SIPF_FP32
                ? adjoint_typed<float>(c, nsteps, ckpt_every, (const float*)phi_bar, loss, dchi, dmu, (float*)dX0)
                : adjoint_typed<double>(c, nsteps, ckpt_every, (const double*)phi_bar, loss, dchi, dmu, (double*)dX0);
@@ -1570,9 +1588,12 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
     if (dim_of(prm) == 2) {
         for (int t = 8; t <= 128; t *= 2)
             if (t <= prm->H && prm->H / t <= 64) tiles.push_back(t);
-    } else {
+    } else if (is_pow2(prm->H)) {
         for (int t = 4; t <= 32; t *= 2)
             if (t <= prm->H && prm->H / t <= 16) tiles.push_back(t);
+    } else {
+        for (int t = 2; t <= prm->H; ++t)
+            if (prm->H % t == 0 && prm->H / t <= 16) tiles.push_back(t);
     }
     if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
     if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 4096}))) return rc;

@@ -27,15 +27,14 @@
 namespace sipf {
 
 int fft_perm(int N, int k) {
-    int N1 = 8, N2 = 1;
+    int N1 = 0, N2 = 1;
     switch (N) {
-        case 4: N1 = 4; N2 = 1; break;
-        case 8: N1 = 8; N2 = 1; break;
-        case 16: N1 = 16; N2 = 1; break;
-        case 32: N1 = 8; N2 = 4; break;
-        case 64: N1 = 8; N2 = 8; break;
-        case 128: N1 = 16; N2 = 8; break;
-        case 256: N1 = 16; N2 = 16; break;
+#define SIPF_SPLIT_CASE(n) case n: N1 = Split<n>::N1; N2 = Split<n>::N2; break;
+        SIPF_SPLIT_CASE(3) SIPF_SPLIT_CASE(4) SIPF_SPLIT_CASE(5) SIPF_SPLIT_CASE(6) SIPF_SPLIT_CASE(8)
+        SIPF_SPLIT_CASE(11) SIPF_SPLIT_CASE(12) SIPF_SPLIT_CASE(16) SIPF_SPLIT_CASE(22) SIPF_SPLIT_CASE(23)
+        SIPF_SPLIT_CASE(32) SIPF_SPLIT_CASE(45) SIPF_SPLIT_CASE(46) SIPF_SPLIT_CASE(64) SIPF_SPLIT_CASE(90)
+        SIPF_SPLIT_CASE(128) SIPF_SPLIT_CASE(256)
+#undef SIPF_SPLIT_CASE
         case 512: case 1024: case 2048: case 4096: {
             const int M = N / 16;
             return (k % 16) * M + fft_perm(M, k / 16);
@@ -45,9 +44,14 @@ int fft_perm(int N, int k) {
     return (k % N1) * N2 + k / N1;
 }
 
+// 3-D grids: powers of two 8 .. 128 and the mixed-radix sizes 12, 22, 46, 90;
+// FP64 up to 64 (the plane passes' LDS)
 bool fft_size_supported(int H, bool fp64) {
-    if (!(H == 8 || H == 16 || H == 32 || H == 64 || H == 128)) return false;
-    return !(fp64 && H > 64);
+    switch (H) {
+        case 8: case 12: case 16: case 22: case 32: case 46: case 64: return true;
+        case 90: case 128: return !fp64;
+        default: return false;
+    }
 }
 
 // threads of the plane passes: the forward pass has only H workgroups and the
@@ -367,11 +371,18 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
     __shared__ V tw[H];
     __shared__ V twm[M];
     const FieldDesc<T>& fd = fds[blockIdx.y];
-    // blocks 8c + r (c = (ix / 8) ncomp + d) keep the components of a plane on one XCD
+    // blocks 8c + r (c = (ix / 8) ncomp + d) keep the components of a plane on
+    // one XCD; grids that are not a multiple of 8 take block ix ncomp + d
     const int b = blockIdx.x;
-    const int grp = b / 8, r = b % 8;
-    const int d = grp % ncomp;
-    const int ix = (grp / ncomp) * 8 + r;
+    int d, ix;
+    if constexpr (H % 8 == 0) {
+        const int grp = b / 8, r = b % 8;
+        d = grp % ncomp;
+        ix = (grp / ncomp) * 8 + r;
+    } else {
+        d = b % ncomp;
+        ix = b / ncomp;
+    }
     const int tid = threadIdx.x, nt = blockDim.x;
     make_twiddles<T, H>(tw);
     make_twiddles<T, M>(twm);
@@ -443,7 +454,6 @@ static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStr
 }
 template <typename T, int H>
 static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s) {
-    static_assert(H % 8 == 0, "plane blocks are grouped by 8");
     launch_kernel((k_inv_planes<T, H>), dim3(ncomp * H, count), dim3(PLANE_THREADS), 0, s, fd, ncomp);
     return hipGetLastError();
 }
@@ -451,9 +461,13 @@ static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, int ncomp, hip
 #define SIPF_H_SWITCH(H, FN, ...)                         \
     switch (H) {                                          \
         case 8: return FN<T, 8>(__VA_ARGS__);             \
+        case 12: return FN<T, 12>(__VA_ARGS__);           \
         case 16: return FN<T, 16>(__VA_ARGS__);           \
+        case 22: return FN<T, 22>(__VA_ARGS__);           \
         case 32: return FN<T, 32>(__VA_ARGS__);           \
+        case 46: return FN<T, 46>(__VA_ARGS__);           \
         case 64: return FN<T, 64>(__VA_ARGS__);           \
+        case 90: if constexpr (sizeof(T) == 4) return FN<T, 90>(__VA_ARGS__); else return hipErrorInvalidValue; \
         case 128: if constexpr (sizeof(T) == 4) return FN<T, 128>(__VA_ARGS__); else return hipErrorInvalidValue; \
         default: return hipErrorInvalidValue;             \
     }

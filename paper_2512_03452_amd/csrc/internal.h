@@ -97,8 +97,9 @@ template <typename T> struct PartDesc {
     uint32_t k0, k1;        // Philox key
     uint32_t inst;          // fourth counter word
     int gmargin;            // cells the W^- displacement can reach (gradient window margin)
-    int tshift;             // log2 of the sort tile side
-    int nkeys;              // (H / tile)^dim sort keys
+    int tshift;             // log2 of the sort tile side, or -1 when the side is not a power of two
+    int tile;               // sort tile side (cells; divides H)
+    int nkeys;              // Morton keys: (H / tile)^dim, or that with H / tile rounded up to a power of two
     T* ox;                  // push-only passes: positions out (null: in place), ids copied to oid
     T* oy;
     T* oz;
@@ -170,8 +171,9 @@ int fft_perm(int N, int k);
 
 // --- particle pass (particles.hip) -------------------------------------------
 template <typename T>
+// pow2: every instance's H is a power of two (index wraps by mask; else by remainder)
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
-                            bool push, int scheme, int win_bytes, hipStream_t s);
+                            bool push, int scheme, int win_bytes, bool pow2, hipStream_t s);
 // 2-D particle pass (particles2d.hip)
 template <typename T>
 hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,

@@ -1,10 +1,14 @@
 // In-place LDS FFT building blocks shared by the 3-D and 2-D field passes.
 //
-// Length N = N1 * N2 (N1, N2 <= 16): a stage of N1-point register DFTs with
+// Length N = N1 * N2 (N1, N2 <= 23): a stage of N1-point register DFTs with
 // twiddles, then a stage of N2-point register DFTs.  The forward transform
 // takes natural order and leaves frequency k at position
 // (k mod N1) * N2 + k div N1; the inverse takes that order and returns
-// natural order.
+// natural order.  A register DFT of even length splits into two halves
+// (radix 2); one of odd length is summed directly, pairing the terms j and
+// R - j, with cosines and sines fixed at compile time.  Lengths with odd
+// factors (12, 22, 46, 90 and their halves) serve grids that are not powers
+// of two.
 //
 // Lengths 512 .. 4096 (N = 16 M, M <= 256) add a first stage: 16-point DFTs
 // across the 16 blocks of M elements with twiddles w_N^(m k1), then the
@@ -24,6 +28,55 @@ template <> struct Split<32>  { static constexpr int N1 = 8,  N2 = 4; };
 template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8; };
 template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
+// lengths with odd factors
+template <> struct Split<3>   { static constexpr int N1 = 3,  N2 = 1; };
+template <> struct Split<5>   { static constexpr int N1 = 5,  N2 = 1; };
+template <> struct Split<6>   { static constexpr int N1 = 6,  N2 = 1; };
+template <> struct Split<11>  { static constexpr int N1 = 11, N2 = 1; };
+template <> struct Split<12>  { static constexpr int N1 = 12, N2 = 1; };
+template <> struct Split<22>  { static constexpr int N1 = 11, N2 = 2; };
+template <> struct Split<23>  { static constexpr int N1 = 23, N2 = 1; };
+template <> struct Split<45>  { static constexpr int N1 = 9,  N2 = 5; };
+template <> struct Split<46>  { static constexpr int N1 = 23, N2 = 2; };
+template <> struct Split<90>  { static constexpr int N1 = 10, N2 = 9; };
+
+// cos and sin of 2 pi m / R at compile time: the angle is reduced exactly to
+// the nearest quarter turn q, leaving x = 2 pi (4m - qR) / (4R) with
+// |x| <= pi / 4, where the Taylor series of cos and sin is summed far below
+// double rounding (the 14th term is under 1e-30); then rotated by q quarters.
+struct TrigC {
+    static constexpr double PI = 3.14159265358979323846264338327950288;
+    static constexpr double cos_s(double x) {
+        double t = 1.0, r = 1.0;
+        for (int n = 1; n < 14; ++n) {
+            t *= -x * x / (double)((2 * n - 1) * (2 * n));
+            r += t;
+        }
+        return r;
+    }
+    static constexpr double sin_s(double x) {
+        double t = x, r = x;
+        for (int n = 1; n < 14; ++n) {
+            t *= -x * x / (double)((2 * n) * (2 * n + 1));
+            r += t;
+        }
+        return r;
+    }
+    // want_sin ? sin : cos of 2 pi m / R
+    static constexpr double cs(int m, int R, bool want_sin) {
+        m %= R;
+        if (m < 0) m += R;
+        const int q = (8 * m + R) / (2 * R);  // nearest quarter, round(4m / R)
+        const double x = 2.0 * PI * (double)(4 * m - q * R) / (4.0 * (double)R);
+        const double c = cos_s(x), s = sin_s(x);
+        switch (q & 3) {
+            case 0: return want_sin ? s : c;
+            case 1: return want_sin ? c : -s;
+            case 2: return want_sin ? -s : -c;
+            default: return want_sin ? -c : s;
+        }
+    }
+};
 
 
 // cos and sin of 2 pi j / 16, j = 0..7
@@ -42,16 +95,76 @@ __device__ __forceinline__ cplx_t<T> twiddle(cplx_t<T> v) {
         return v;
     } else if constexpr (4 * K == R) {
         return DIR > 0 ? cmake<V, T>(-v.y, v.x) : cmake<V, T>(v.y, -v.x);
-    } else {
+    } else if constexpr (16 % R == 0) {
         constexpr int j = K * (16 / R);
         const T c = (T)Tw16::c[j];
         const T s = (T)(DIR * Tw16::s[j]);
         return cmake<V, T>(v.x * c - v.y * s, v.x * s + v.y * c);
+    } else {
+        constexpr double cd = TrigC::cs(K, R, false), sd = TrigC::cs(K, R, true);
+        const T c = (T)cd;
+        const T s = (T)(DIR * sd);
+        return cmake<V, T>(v.x * c - v.y * s, v.x * s + v.y * c);
     }
 }
 
-// In-register DFT of length R (power of two <= 16), natural order in and out.
-template <typename T, int R, int DIR> struct Dft {
+// compile-time table of cos and sin of 2 pi m / R, m = 0 .. R - 1
+template <int R> struct TrigTab {
+    double c[R], s[R];
+    constexpr TrigTab() : c(), s() {
+        for (int m = 0; m < R; ++m) {
+            c[m] = TrigC::cs(m, R, false);
+            s[m] = TrigC::cs(m, R, true);
+        }
+    }
+};
+
+// In-register DFT of length R, natural order in and out: X_k = sum_j x_j
+// exp(DIR 2 pi i j k / R).
+template <typename T, int R, int DIR, bool EVEN = (R % 2 == 0)> struct Dft;
+
+// odd R: X_0 = sum_j x_j; for 0 < k <= (R - 1) / 2, with a_j = x_j + x_{R-j}
+// and b_j = x_j - x_{R-j},
+//   X_k, X_{R-k} = x_0 + sum_j a_j cos(2 pi j k / R) +- DIR i sum_j b_j sin(2 pi j k / R)
+template <typename T, int R, int DIR> struct Dft<T, R, DIR, false> {
+    using V = cplx_t<T>;
+    __device__ __forceinline__ static void run(V* x) {
+        if constexpr (R > 1) {
+            constexpr int Q = (R - 1) / 2;
+            constexpr TrigTab<R> tab{};
+            V a[Q], b[Q];
+            const V x0 = x[0];
+            V sum = x0;
+#pragma unroll
+            for (int j = 1; j <= Q; ++j) {
+                a[j - 1] = cadd(x[j], x[R - j]);
+                b[j - 1] = csub(x[j], x[R - j]);
+                sum = cadd(sum, a[j - 1]);
+            }
+            x[0] = sum;
+#pragma unroll
+            for (int k = 1; k <= Q; ++k) {
+                T sr = x0.x, si = x0.y, dr = 0, di = 0;
+#pragma unroll
+                for (int j = 1; j <= Q; ++j) {
+                    const int m = (j * k) % R;
+                    const T c = (T)tab.c[m], sn = (T)tab.s[m];
+                    sr += a[j - 1].x * c;
+                    si += a[j - 1].y * c;
+                    dr += b[j - 1].x * sn;
+                    di += b[j - 1].y * sn;
+                }
+                // DIR i (dr + i di) = DIR (-di + i dr)
+                const T ir = (T)(-DIR) * di, ii = (T)DIR * dr;
+                x[k] = cmake<V, T>(sr + ir, si + ii);
+                x[R - k] = cmake<V, T>(sr - ir, si - ii);
+            }
+        }
+    }
+};
+
+// even R: radix 2 over the even and odd samples
+template <typename T, int R, int DIR> struct Dft<T, R, DIR, true> {
     using V = cplx_t<T>;
     template <int K>
     __device__ __forceinline__ static void combine(V* x, const V* e, const V* o) {
@@ -73,9 +186,6 @@ template <typename T, int R, int DIR> struct Dft {
         Dft<T, R / 2, DIR>::run(o);
         combine<0>(x, e, o);
     }
-};
-template <typename T, int DIR> struct Dft<T, 1, DIR> {
-    __device__ __forceinline__ static void run(cplx_t<T>*) {}
 };
 
 // count independent length-N transforms; element e of transform b at

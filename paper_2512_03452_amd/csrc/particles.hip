@@ -68,34 +68,33 @@ __device__ __forceinline__ uint32_t spread2(uint32_t v) {
     return r;
 }
 
-// Morton key of the tile of the cell containing (x, y, z).
+// Tile coordinate of position v along one axis: a shift when the tile side is a
+// power of two (tshift >= 0), else a division by the tile side, which then
+// divides H.
 template <typename T>
-__device__ __forceinline__ uint32_t tile_key(T x, T y, T z, T hl, int Hm, int tshift) {
-    const uint32_t tx = (uint32_t)(ifloor(x * hl) & Hm) >> tshift;
-    const uint32_t ty = (uint32_t)(ifloor(y * hl) & Hm) >> tshift;
-    const uint32_t tz = (uint32_t)(ifloor(z * hl) & Hm) >> tshift;
-    return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tz);
+__device__ __forceinline__ uint32_t tile_coord(const PartDesc<T>& a, T v) {
+    const int g = ifloor(v * a.hl);
+    if (a.tshift >= 0) return (uint32_t)(g & (a.H - 1)) >> a.tshift;
+    int c = g % a.H;
+    if (c < 0) c += a.H;
+    return (uint32_t)(c / a.tile);
 }
-// the same in two dimensions (up to 64 tiles per axis)
-template <typename T>
-__device__ __forceinline__ uint32_t tile_key2(T x, T y, T hl, int Hm, int tshift) {
-    const uint32_t tx = (uint32_t)(ifloor(x * hl) & Hm) >> tshift;
-    const uint32_t ty = (uint32_t)(ifloor(y * hl) & Hm) >> tshift;
-    return (spread2(tx) << 1) | spread2(ty);
-}
+// Morton key of the tile of the cell containing (x, y, z) (up to 32 tiles per
+// axis in 3-D, 64 in 2-D)
 template <typename T, int DIM>
 __device__ __forceinline__ uint32_t key_of(const PartDesc<T>& a, T x, T y, T z) {
-    if constexpr (DIM == 3) return tile_key(x, y, z, a.hl, a.H - 1, a.tshift);
-    else return tile_key2(x, y, a.hl, a.H - 1, a.tshift);
+    const uint32_t tx = tile_coord(a, x), ty = tile_coord(a, y);
+    if constexpr (DIM == 3) return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tile_coord(a, z));
+    else return (spread2(tx) << 1) | spread2(ty);
 }
 
 // ---------------------------------------------------------------------------
 // deposit of one particle: 32 nodes of Gamma_4 with the weights of eq. 4ord.
 // sink(index, F) receives the window index and the weight F (without mass).
 // ---------------------------------------------------------------------------
-template <typename T, typename Sink>
-__device__ __forceinline__ void deposit_one(Sink& sink, T x, T y, T z, T hl, int Hm, int ox, int oy, int oz, int Wy,
-                                            int Wz) {
+template <typename T, typename Sink, bool P2>
+__device__ __forceinline__ void deposit_one(Sink& sink, T x, T y, T z, T hl, const Wrap<P2>& wr, int ox, int oy, int oz,
+                                            int Wy, int Wz) {
     const T sx = x * hl, sy = y * hl, sz = z * hl;
     const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
     const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
@@ -105,9 +104,9 @@ __device__ __forceinline__ void deposit_one(Sink& sink, T x, T y, T z, T hl, int
     int cx[4], cy[4], cz[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        cx[j] = ((gx - 1 + j - ox) & Hm) * WyWz;
-        cy[j] = ((gy - 1 + j - oy) & Hm) * Wz;
-        cz[j] = (gz - 1 + j - oz) & Hm;
+        cx[j] = wr(gx - 1 + j - ox) * WyWz;
+        cy[j] = wr(gy - 1 + j - oy) * Wz;
+        cz[j] = wr(gz - 1 + j - oz);
     }
     const T wx[2] = {ax.w0, ax.w1}, wy[2] = {ay.w0, ay.w1}, wz[2] = {az.w0, az.w1};
 #pragma unroll
@@ -221,9 +220,9 @@ __device__ __forceinline__ void plane_map(int ey, int ez, int& i0, int& j, int& 
 // Deposit of one particle into a fixed-stride fixed-point window whose node
 // (i, j, k) is at (i D + j) D + k, origin (ox, oy, oz).  The scale 2^S is
 // folded into the x factors (every Gamma_4 weight has exactly one).
-template <typename T>
-__device__ __forceinline__ void deposit_fast(typename Fixed<T>::I* win, T x, T y, T z, T hl, int Hm, int ox, int oy,
-                                             int oz, T scale) {
+template <typename T, bool P2>
+__device__ __forceinline__ void deposit_fast(typename Fixed<T>::I* win, T x, T y, T z, T hl, const Wrap<P2>& wr, int ox,
+                                             int oy, int oz, T scale) {
     constexpr int D = Win<T>::D;
     using U = typename Fixed<T>::U;
     const T sx = x * hl, sy = y * hl, sz = z * hl;
@@ -231,7 +230,7 @@ __device__ __forceinline__ void deposit_fast(typename Fixed<T>::I* win, T x, T y
     const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
     const Axis4<T> ax = axis4(sx - fx), ay = axis4(sy - fy), az = axis4(sz - fz);
     const T S = (T)1 + (ax.w0 * ax.w1 + ay.w0 * ay.w1 + az.w0 * az.w1) * (T)0.5;
-    const int base = (((gx - 1 - ox) & Hm) * D + ((gy - 1 - oy) & Hm)) * D + ((gz - 1 - oz) & Hm);
+    const int base = (wr(gx - 1 - ox) * D + wr(gy - 1 - oy)) * D + wr(gz - 1 - oz);
     U* w = reinterpret_cast<U*>(win) + base;
     const T X[4] = {ax.wm * scale, ax.w0 * scale, ax.w1 * scale, ax.wp * scale};
     const T Y[4] = {ay.wm, ay.w0, ay.w1, ay.wp};
@@ -270,12 +269,12 @@ __device__ __forceinline__ void deposit_fast(typename Fixed<T>::I* win, T x, T y
 // Trilinear gather from a fixed-stride window (node (i, j, k) at (i G + j) G + k,
 // three planes of G^3); false if the cell is not covered by the loaded part
 // (ex, ey, ez) of the window.
-template <typename T>
-__device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz, T lx, T ly, T lz, int Hm, int ox,
-                                            int oy, int oz, int ex, int ey, int ez, T& vx, T& vy, T& vz) {
+template <typename T, bool P2>
+__device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz, T lx, T ly, T lz, const Wrap<P2>& wr,
+                                            int ox, int oy, int oz, int ex, int ey, int ez, T& vx, T& vy, T& vz) {
     constexpr int G = Win<T>::G;
     constexpr int G3 = G * G * G;
-    const int ix = (gx - ox) & Hm, iy = (gy - oy) & Hm, iz = (gz - oz) & Hm;
+    const int ix = wr(gx - ox), iy = wr(gy - oy), iz = wr(gz - oz);
     if (ix > ex - 2 || iy > ey - 2 || iz > ez - 2) return false;
     const T* p = Gw + (ix * G + iy) * G + iz;
     const T wx[2] = {(T)1 - lx, lx}, wy[2] = {(T)1 - ly, ly}, wz[2] = {(T)1 - lz, lz};
@@ -301,12 +300,13 @@ __device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz,
 }
 
 // One work item: particles [beg, beg + cnt) of one instance, held in registers.
-template <typename T, bool DEP, bool PUSH, int SCHEME>
+template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
 __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int cnt, unsigned char* lds,
                                           int win_bytes, int* sh) {
     using I = typename Fixed<T>::I;
     const int tid = threadIdx.x;
-    const int H = a.H, Hm = H - 1, Hh = H / 2;
+    const int H = a.H, Hh = H / 2;
+    const Wrap<P2> wr{H, H - 1};
     const T hl = a.hl;
     T px[PPT], py[PPT], pz[PPT];
 #if !SIPF_RELOAD
@@ -336,16 +336,16 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         if (tid < 3) sh[tid] = INT_MAX;
         else if (tid < 6) sh[tid] = INT_MIN;
         __syncthreads();
-        rx = ifloor(gp(a.x)[beg] * hl) & Hm;
-        ry = ifloor(gp(a.y)[beg] * hl) & Hm;
-        rz = ifloor(gp(a.z)[beg] * hl) & Hm;
+        rx = wr(ifloor(gp(a.x)[beg] * hl));
+        ry = wr(ifloor(gp(a.y)[beg] * hl));
+        rz = wr(ifloor(gp(a.z)[beg] * hl));
         int mnx = INT_MAX, mny = INT_MAX, mnz = INT_MAX, mxx = INT_MIN, mxy = INT_MIN, mxz = INT_MIN;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (tid + k * PT < cnt) {
-                const int cx = (((ifloor(px[k] * hl) & Hm) - rx + Hh) & Hm) - Hh;
-                const int cy = (((ifloor(py[k] * hl) & Hm) - ry + Hh) & Hm) - Hh;
-                const int cz = (((ifloor(pz[k] * hl) & Hm) - rz + Hh) & Hm) - Hh;
+                const int cx = wr(wr(ifloor(px[k] * hl)) - rx + Hh) - Hh;
+                const int cy = wr(wr(ifloor(py[k] * hl)) - ry + Hh) - Hh;
+                const int cz = wr(wr(ifloor(pz[k] * hl)) - rz + Hh) - Hh;
                 mnx = min(mnx, cx); mxx = max(mxx, cx);
                 mny = min(mny, cy); mxy = max(mxy, cy);
                 mnz = min(mnz, cz); mxz = max(mxz, cz);
@@ -365,7 +365,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         // fast path: fixed-stride window, nodes -1..+2 around the box
         constexpr int D = Win<T>::D;
         I* win = reinterpret_cast<I*>(lds);
-        const int ox = (rx + sh[0] - 1) & Hm, oy = (ry + sh[1] - 1) & Hm, oz = (rz + sh[2] - 1) & Hm;
+        const int ox = wr(rx + sh[0] - 1), oy = wr(ry + sh[1] - 1), oz = wr(rz + sh[2] - 1);
         const int ex = sh[3] - sh[0] + 4, ey = sh[4] - sh[1] + 4, ez = sh[5] - sh[2] + 4;
         // each thread owns one (j, k) column of the window and walks i
         int i0, wj, wk, nrep;
@@ -377,14 +377,14 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
-            if (tid + k * PT < cnt) deposit_fast<T>(win, px[k], py[k], pz[k], hl, Hm, ox, oy, oz, scale);
+            if (tid + k * PT < cnt) deposit_fast<T>(win, px[k], py[k], pz[k], hl, wr, ox, oy, oz, scale);
         __syncthreads();
         const T back = a.wmass * (T)ldexp(1.0, -S);
         {
-            const int nyz = ((oy + wj) & Hm) * H + ((oz + wk) & Hm);
+            const int nyz = wr(oy + wj) * H + wr(oz + wk);
             for (int i = i0; i < ex; i += nrep) {
                 const I v = win[(i * D + wj) * D + wk];
-                if (v != 0) gatomic_add(a.phi + ((ox + i) & Hm) * H * H + nyz, (T)v * back);
+                if (v != 0) gatomic_add(a.phi + wr(ox + i) * H * H + nyz, (T)v * back);
             }
         }
         __syncthreads();  // the window memory is reused below
@@ -393,9 +393,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         bool use_win = false;
         if (windows) {
             // nodes -1..+2 around every cell of the box
-            axis_window(rx, sh[0] - 1, sh[3] + 2, H, ox, Wx);
-            axis_window(ry, sh[1] - 1, sh[4] + 2, H, oy, Wy);
-            axis_window(rz, sh[2] - 1, sh[5] + 2, H, oz, Wz);
+            axis_window(rx, sh[0] - 1, sh[3] + 2, wr, ox, Wx);
+            axis_window(ry, sh[1] - 1, sh[4] + 2, wr, oy, Wy);
+            axis_window(rz, sh[2] - 1, sh[5] + 2, wr, oz, Wz);
             use_win = (int64_t)Wx * Wy * Wz * (int64_t)sizeof(I) <= win_bytes;
         }
         if (use_win) {
@@ -410,7 +410,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             LdsSink<T> sink{win, scale};
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (tid + k * PT < cnt) deposit_one(sink, px[k], py[k], pz[k], hl, Hm, ox, oy, oz, Wy, Wz);
+                if (tid + k * PT < cnt) deposit_one(sink, px[k], py[k], pz[k], hl, wr, ox, oy, oz, Wy, Wz);
             __syncthreads();
             const T back = a.wmass * (T)ldexp(1.0, -S);
             const int WyWz = Wy * Wz;
@@ -419,7 +419,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
                 if (v != 0) {
                     const int ex = e / WyWz, r = e - ex * WyWz;
                     const int ey = r / Wz, ez = r - ey * Wz;
-                    const size_t node = ((size_t)((ox + ex) & Hm) * H + ((oy + ey) & Hm)) * H + ((oz + ez) & Hm);
+                    const size_t node = ((size_t)wr(ox + ex) * H + wr(oy + ey)) * H + wr(oz + ez);
                     gatomic_add(a.phi + node, (T)v * back);
                 }
             }
@@ -428,7 +428,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             GlobalSink<T> sink{a.phi, a.wmass};
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (tid + k * PT < cnt) deposit_one(sink, px[k], py[k], pz[k], hl, Hm, 0, 0, 0, H, H);
+                if (tid + k * PT < cnt) deposit_one(sink, px[k], py[k], pz[k], hl, wr, 0, 0, 0, H, H);
         }
     }
 
@@ -447,9 +447,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             if (fast) {
                 int m = a.gmargin;
                 while (sh[3] - sh[0] + 2 + 2 * m > G || sh[4] - sh[1] + 2 + 2 * m > G || sh[5] - sh[2] + 2 + 2 * m > G) --m;
-                ox = (rx + sh[0] - m) & Hm;
-                oy = (ry + sh[1] - m) & Hm;
-                oz = (rz + sh[2] - m) & Hm;
+                ox = wr(rx + sh[0] - m);
+                oy = wr(ry + sh[1] - m);
+                oz = wr(rz + sh[2] - m);
                 Wx = sh[3] - sh[0] + 2 + 2 * m;
                 Wy = sh[4] - sh[1] + 2 + 2 * m;
                 Wz = sh[5] - sh[2] + 2 + 2 * m;
@@ -457,9 +457,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
                 const int H3 = H * H * H;
                 int i0, wj, wk, nrep;
                 plane_map(Wy, Wz, i0, wj, wk, nrep);
-                const int nyz = ((oy + wj) & Hm) * H + ((oz + wk) & Hm);
+                const int nyz = wr(oy + wj) * H + wr(oz + wk);
                 for (int i = i0; i < Wx; i += nrep) {
-                    const int node = ((ox + i) & Hm) * H * H + nyz;
+                    const int node = wr(ox + i) * H * H + nyz;
                     const int o = (i * G + wj) * G + wk;
                     Gw[o] = gp(a.G)[node];
                     Gw[G3 + o] = gp(a.G)[H3 + node];
@@ -470,9 +470,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
         }
         if (windows && !fast) {
             for (int m = a.gmargin; m >= 0 && !use_win; --m) {
-                axis_window(rx, sh[0] - m, sh[3] + 1 + m, H, ox, Wx);
-                axis_window(ry, sh[1] - m, sh[4] + 1 + m, H, oy, Wy);
-                axis_window(rz, sh[2] - m, sh[5] + 1 + m, H, oz, Wz);
+                axis_window(rx, sh[0] - m, sh[3] + 1 + m, wr, ox, Wx);
+                axis_window(ry, sh[1] - m, sh[4] + 1 + m, wr, oy, Wy);
+                axis_window(rz, sh[2] - m, sh[5] + 1 + m, wr, oz, Wz);
                 use_win = 3 * (int64_t)Wx * Wy * Wz * (int64_t)sizeof(T) <= win_bytes;
             }
             if (use_win) {
@@ -484,7 +484,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
                 for (int e = tid; e < nw; e += PT) {
                     const int ex = e / WyWz, r = e - ex * WyWz;
                     const int ey = r / Wz, ez = r - ey * Wz;
-                    const size_t node = ((size_t)((ox + ex) & Hm) * H + ((oy + ey) & Hm)) * H + ((oz + ez) & Hm);
+                    const size_t node = ((size_t)wr(ox + ex) * H + wr(oy + ey)) * H + wr(oz + ez);
                     Gw[e] = gp(a.G)[node];
                     Gw[nw + e] = gp(a.G)[H3 + node];
                     Gw[2 * nw + e] = gp(a.G)[2 * H3 + node];
@@ -528,21 +528,21 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             const T sx = yx * hl, sy = yy * hl, sz = yz * hl;
             const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
             const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
-            int ix[2] = {(gx - ox) & Hm, (gx + 1 - ox) & Hm};
-            int iy[2] = {(gy - oy) & Hm, (gy + 1 - oy) & Hm};
-            int iz[2] = {(gz - oz) & Hm, (gz + 1 - oz) & Hm};
+            int ix[2] = {wr(gx - ox), wr(gx + 1 - ox)};
+            int iy[2] = {wr(gy - oy), wr(gy + 1 - oy)};
+            int iz[2] = {wr(gz - oz), wr(gz + 1 - oz)};
             T vx, vy, vz;
             const bool inside = !fast && use_win && (Wx == H || ix[0] <= Wx - 2) && (Wy == H || iy[0] <= Wy - 2) &&
                                 (Wz == H || iz[0] <= Wz - 2);
-            if (fast && gather_fast<T>(Gl, gx, gy, gz, sx - fx, sy - fy, sz - fz, Hm, ox, oy, oz, Wx, Wy, Wz, vx, vy,
+            if (fast && gather_fast<T>(Gl, gx, gy, gz, sx - fx, sy - fy, sz - fz, wr, ox, oy, oz, Wx, Wy, Wz, vx, vy,
                                        vz)) {
                 // gathered from the fixed-stride window
             } else if (inside) {
                 trilinear3<T>(Gl, n3, Wy, Wz, ix, iy, iz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
             } else {
-                ix[0] = gx & Hm; ix[1] = (gx + 1) & Hm;
-                iy[0] = gy & Hm; iy[1] = (gy + 1) & Hm;
-                iz[0] = gz & Hm; iz[1] = (gz + 1) & Hm;
+                ix[0] = wr(gx); ix[1] = wr(gx + 1);
+                iy[0] = wr(gy); iy[1] = wr(gy + 1);
+                iz[0] = wr(gz); iz[1] = wr(gz + 1);
                 trilinear3<T>(gp(a.G), H3, H, H, ix, iy, iz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
             }
             const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
@@ -565,7 +565,7 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
 }
 
 // Persistent over the work items listed by the last sort (count in *nitems).
-template <typename T, bool DEP, bool PUSH, int SCHEME>
+template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
 __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<T>* __restrict__ pds,
                                                   const WorkItem* __restrict__ items, const int* __restrict__ nitems,
                                                   int win_bytes) {
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<
     const int n = *nitems;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const WorkItem w = items[it];
-        item_pass<T, DEP, PUSH, SCHEME>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
+        item_pass<T, DEP, PUSH, SCHEME, P2>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
         __syncthreads();
     }
 }
@@ -587,9 +587,9 @@ template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = scheme == SIPF_STRANG
                        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &per_cu, (const void*)k_particles<T, true, true, SIPF_STRANG>, PT, win_bytes)
+                             &per_cu, (const void*)k_particles<T, true, true, SIPF_STRANG, true>, PT, win_bytes)
                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &per_cu, (const void*)k_particles<T, true, true, SIPF_EM>, PT, win_bytes);
+                             &per_cu, (const void*)k_particles<T, true, true, SIPF_EM, true>, PT, win_bytes);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess || per_cu < 1 || cus < 1) {
@@ -599,25 +599,32 @@ template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
     return per_cu * cus;
 }
 
-template <typename T>
-hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
-                            bool push, int scheme, int win_bytes, hipStream_t s) {
-    if (grid <= 0) return hipSuccess;
+template <typename T, bool P2>
+static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, dim3 g, bool deposit,
+                         bool push, int scheme, int win_bytes, hipStream_t s) {
+    const dim3 b(PT);
     const size_t shm = (size_t)win_bytes;
-    const dim3 g(grid), b(PT);
     if (deposit && push) {
         if (scheme == SIPF_STRANG)
-            launch_kernel((k_particles<T, true, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, true, true, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
         else
-            launch_kernel((k_particles<T, true, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, true, true, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (deposit) {
-        launch_kernel((k_particles<T, true, false, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
+        launch_kernel((k_particles<T, true, false, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (push) {
         if (scheme == SIPF_STRANG)
-            launch_kernel((k_particles<T, false, true, SIPF_STRANG>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, false, true, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
         else
-            launch_kernel((k_particles<T, false, true, SIPF_EM>), g, b, shm, s, pd, items, nitems, win_bytes);
+            launch_kernel((k_particles<T, false, true, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
     }
+}
+
+template <typename T>
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+                            bool push, int scheme, int win_bytes, bool pow2, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (pow2) particles_p2<T, true>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, s);
+    else particles_p2<T, false>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, s);
     return hipGetLastError();
 }
 
@@ -913,7 +920,7 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 #define SIPF_INST(T)                                                                                              \
     template int particle_resident_blocks<T>(int, int);                                                           \
     template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, const int*, int, bool, bool, int, \
-                                            int, hipStream_t);                                                    \
+                                            int, bool, hipStream_t);                                              \
     template hipError_t launch_sort<T>(int, const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,   \
                                        uint32_t*, uint32_t*, WorkItem*, const int*, int*, WorkItem*, int*, int,    \
                                        hipStream_t);                                                               \

@@ -99,5 +99,31 @@ __device__ __forceinline__ void axis_window(int r, int lo, int hi, int H, int& o
     }
 }
 
+// Periodic grid index onto [0, H): a mask when H is a power of two, else the
+// remainder, which holds for any int argument.
+template <bool P2> struct Wrap {
+    int H, m;  // m = H - 1
+    __device__ __forceinline__ int operator()(int v) const {
+        if constexpr (P2) {
+            return v & m;
+        } else {
+            const int r = v % H;
+            return r < 0 ? r + H : r;
+        }
+    }
+};
+
+// axis_window for any grid size
+template <bool P2>
+__device__ __forceinline__ void axis_window(int r, int lo, int hi, const Wrap<P2>& wr, int& o, int& W) {
+    const int w = hi - lo + 1;
+    if (w >= wr.H) {
+        o = 0;
+        W = wr.H;
+    } else {
+        o = wr(r + lo);
+        W = w;
+    }
+}
 
 }  // namespace sipf

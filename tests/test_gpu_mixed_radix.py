@@ -1,0 +1,181 @@
+"""Parity of the 3-D path on grids that are not powers of two (H = 12, 22, 46,
+90: the mixed-radix sizes of the SIPF against SIPF-PIC comparison, Sec. 5.1)
+with the FP64 oracle, through the C ABI.
+
+These grids take the remainder-wrapped particle pass and the mixed-radix LDS
+FFT (radices 2, 3, 5, 9, 11, 23).  Tolerances as for the power-of-two grids:
+FP32 fields within 1e-5 relative L2 per step, FP64 within 1e-12; positions by
+the same per-step budget.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import diagnostics as odiag  # noqa: E402
+from oracle import sipf as osipf  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2512_03452_amd as pkg  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
+    b = np.asarray(b, dtype=a.dtype)
+    nb = np.linalg.norm(b.ravel())
+    return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def oparams(**kw):
+    kw = dict(kw)
+    for k in ("precision", "tile", "resort_every", "chunk"):
+        kw.pop(k, None)
+    return osipf.Params(**kw)
+
+
+def hermitian_alpha(H, seed, scale, dtype):
+    """Half spectrum of a smooth random real field."""
+    rng = np.random.default_rng(seed)
+    full = np.fft.fftn(rng.standard_normal((H, H, H))) * scale / H ** 3
+    q = osipf.freqs(H).astype(float)
+    q2 = q[:, None, None] ** 2 + q[None, :, None] ** 2 + q[None, None, :] ** 2
+    full *= np.exp(-q2 / (H / 4) ** 2)
+    return osipf.half_spectrum(full).astype(np.complex64 if dtype == "fp32" else np.complex128)
+
+
+def _positions(kind, P, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        return rng.uniform(-1, 1, (P, 3))
+    if kind == "blob":
+        return osipf.wrap(rng.normal(0, 0.08, (P, 3)), 2.0)
+    if kind == "corner":
+        return osipf.wrap(rng.normal(-1.0, 0.05, (P, 3)), 2.0)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("precision,H,P,kind,tile", [
+    ("fp32", 12, 1, "uniform", 0), ("fp32", 12, 5000, "blob", 0), ("fp32", 12, 7001, "uniform", 4),
+    ("fp32", 12, 3000, "corner", 3), ("fp32", 22, 30000, "uniform", 0), ("fp32", 22, 20000, "corner", 2),
+    ("fp32", 46, 100003, "blob", 0), ("fp32", 46, 40000, "uniform", 23), ("fp32", 90, 200001, "blob", 0),
+    ("fp32", 90, 60000, "corner", 9), ("fp64", 12, 4000, "uniform", 0), ("fp64", 22, 9999, "blob", 11),
+    ("fp64", 46, 20000, "corner", 0),
+])
+def test_deposit_parity(precision, H, P, kind, tile):
+    say("mixed-radix deposit", precision, H, P, kind, tile)
+    X = _positions(kind, P, seed=H + P).astype(np.float32 if precision == "fp32" else np.float64)
+    M0 = 37.5
+    phi = to_np(pkg.dbg_deposit(X, H=H, precision=precision, M0=M0, tile=tile))
+    ref = osipf.deposit(X.astype(np.float64), M0 / P, H, 2.0, 4)
+    tol = 1e-5 if precision == "fp32" else 1e-12
+    assert rel_l2(phi, ref) < tol
+    assert abs(phi.sum() - M0) < tol * M0
+
+
+@pytest.mark.parametrize("precision,H,P,scheme", [
+    ("fp32", 12, 777, "strang"), ("fp32", 22, 6001, "em"), ("fp32", 46, 50000, "strang"),
+    ("fp32", 90, 120001, "strang"), ("fp64", 12, 1500, "strang"), ("fp64", 22, 4000, "em"),
+    ("fp64", 46, 8000, "strang"),
+])
+def test_one_step_parity(precision, H, P, scheme):
+    say("mixed-radix step", precision, H, P, scheme)
+    kw = dict(L=2.0, chi=3.0, mu=0.5, eps=1.0, k=1.0, M0=50.0, dt=1e-3, H=H, seed=11, scheme=scheme)
+    X0 = osipf.wrap(np.random.default_rng(H).normal(0, 0.3, (P, 3)), 2.0)
+    X0 = X0.astype(np.float32 if precision == "fp32" else np.float64)
+    a0 = hermitian_alpha(H, seed=H, scale=40.0, dtype=precision)
+    sim = pkg.Sim(X0, alpha0=a0, precision=precision, **kw)
+    Xs = to_np(sim.positions()).astype(np.float64)
+    As = to_np(sim.field("alpha")).astype(np.complex128)
+    prm = oparams(**kw)
+    afull = osipf.full_spectrum(As)
+    tol = 1e-5 if precision == "fp32" else 1e-12
+    assert rel_l2(to_np(sim.field("grad")), osipf.gradient_grid(afull, prm)) < tol
+    sim.step()
+    X1 = to_np(sim.positions()).astype(np.float64)
+    A1 = to_np(sim.field("alpha")).astype(np.complex128)
+    rec = {}
+    Xo, ao = osipf.step(Xs, afull, 1, prm, record=rec)
+    assert rel_l2(A1, osipf.half_spectrum(ao)) < tol
+    assert rel_l2(to_np(sim.field("grad")), osipf.gradient_grid(osipf.full_spectrum(A1), prm)) < tol
+    drift = prm.chi * prm.dt * np.abs(rec["v"]).max()
+    ptol = (1e-6 + 1e-5 * drift) if precision == "fp32" else (1e-12 + 1e-11 * drift)
+    assert np.abs(osipf.min_image(X1 - Xo, 2.0)).max() < ptol
+    sim.close()
+
+
+@pytest.mark.parametrize("precision,H,P,steps", [("fp64", 22, 3000, 40), ("fp32", 46, 20000, 40)])
+def test_trajectory(precision, H, P, steps):
+    say("mixed-radix trajectory", precision, H, P, steps)
+    kw = dict(L=2.0, chi=1.0, mu=0.5, eps=1.0, k=0.5, M0=60.0, dt=5e-4, H=H, seed=5)
+    X0 = osipf.wrap(np.random.default_rng(7).normal(0, 0.2, (P, 3)), 2.0)
+    X0 = X0.astype(np.float32 if precision == "fp32" else np.float64)
+    sim = pkg.Sim(X0, precision=precision, **kw)
+    sim.run(steps)
+    X = to_np(sim.positions()).astype(np.float64)
+    A = to_np(sim.field("alpha")).astype(np.complex128)
+    Xo, ao = osipf.run(X0.astype(np.float64), oparams(**kw), steps)
+    xt, at = (1e-9, 1e-12) if precision == "fp64" else (1e-4, 1e-5)
+    assert np.abs(osipf.min_image(X - Xo, 2.0)).max() < xt
+    assert rel_l2(A, osipf.half_spectrum(ao)) < at
+    sim.close()
+
+
+def test_batch_mixes_power_of_two_and_mixed_radix_grids():
+    """One group of H = 8, 12, 22 and 16: every instance, power of two or not,
+    runs in the remainder-wrapped particle pass and matches its own oracle run."""
+    say("mixed-radix batch")
+    Hs = (8, 12, 22, 16)
+    insts, refs = [], []
+    for i, H in enumerate(Hs):
+        kw = dict(L=2.0, chi=2.0, mu=0.3, eps=1.0, k=1.0, M0=30.0 + 10 * i, dt=1e-3, H=H, seed=3, instance=i)
+        P = 2000 + 1000 * i
+        X0 = osipf.wrap(np.random.default_rng(i).normal(0, 0.25, (P, 3)), 2.0)
+        insts.append(dict(params=dict(kw, precision="fp64"), X0=X0))
+        refs.append((X0, oparams(**kw)))
+    b = pkg.Batch(insts)
+    b.run(10)
+    for i, (X0, prm) in enumerate(refs):
+        Xo, ao = osipf.run(X0, prm, 10)
+        X = to_np(b.positions(i)).astype(np.float64)
+        assert np.abs(osipf.min_image(X - Xo, 2.0)).max() < 1e-10, i
+    b.close()
+
+
+def test_diagnostics_on_a_mixed_radix_grid():
+    say("mixed-radix diagnostics")
+    H, P = 22, 5000
+    kw = dict(L=2.0, chi=1.0, mu=0.5, eps=1.0, k=1.0, M0=40.0, dt=1e-3, H=H, seed=2)
+    X0 = osipf.wrap(np.random.default_rng(4).normal(0, 0.3, (P, 3)), 2.0)
+    sim = pkg.Sim(X0, precision="fp64", **kw)
+    sim.run(3)
+    d = sim.diagnostics()
+    X = to_np(sim.positions()).astype(np.float64)
+    A = osipf.full_spectrum(to_np(sim.field("alpha")).astype(np.complex128))
+    ref = odiag.all_diagnostics(X, A, oparams(**kw))
+    for key in ("mass", "rho_max", "hf_share", "c_integral", "r_num", "m2"):
+        assert abs(d[key] - ref[key]) <= 1e-10 * max(1.0, abs(ref[key])), key
+    sim.close()
+
+
+def test_adjoint_rejects_mixed_radix_grids():
+    X0 = osipf.wrap(np.random.default_rng(0).normal(0, 0.3, (100, 3)), 2.0)
+    sim = pkg.Sim(X0, precision="fp64", H=12, L=2.0, M0=10.0, dt=1e-3)
+    with pytest.raises(Exception):
+        sim.adjoint(2, 1)
+    sim.close()

@@ -99,6 +99,21 @@ def test_exponential_propagator_needs_positive_eps():
     assert rc == L.SIPF_EINVAL and h.value is None
 
 
+@pytest.mark.parametrize("kw", [
+    dict(H=24), dict(H=90, precision="fp64"), dict(H=12, tile=5), dict(H=90, tile=4), dict(H=46, tile=2),
+    dict(H=12, method="direct"), dict(H=22, tile=-11),
+])
+def test_mixed_radix_parameters_rejected(kw):
+    """3-D grids take 12, 22, 46 and 90 besides powers of two; a tile must then
+    divide H with at most 16 tiles per axis; direct SIPF keeps powers of two."""
+    L = _lib()
+    p = L.default_params(**kw)
+    h = ctypes.c_void_p()
+    X = np.zeros((4, 3), np.float64 if kw.get("precision") == "fp64" else np.float32)
+    rc = L.load().sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
+    assert rc == L.SIPF_EINVAL and h.value is None
+
+
 def test_fp64_h128_rejected():
     L = _lib()
     p = L.default_params(H=128, precision="fp64")
@@ -233,7 +248,7 @@ def test_batch_and_tuning_null_handles():
     assert lib.sipf_diagnostics(None, ctypes.byref(d)) == L.SIPF_EINVAL
     assert lib.sipf_batch_diagnostics(None, ctypes.byref(d)) == L.SIPF_EINVAL
     assert ctypes.sizeof(L.SipfDiag) == 7 * 8
-    p = L.default_params(H=12)
+    p = L.default_params(H=24)
     best = L.SipfParams()
     ms = ctypes.c_double()
     X = np.zeros((4, 3), np.float32)

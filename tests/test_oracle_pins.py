@@ -183,20 +183,21 @@ def test_deposit_continuous_across_cell_faces(order):
 # Deposit / interpolation (Definitions particle2grid, grid2particle)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("order", [2, 4])
-def test_deposit_conserves_mass(order):
+@pytest.mark.parametrize("order,H", [(2, 16), (4, 16), (4, 12), (4, 22)])
+def test_deposit_conserves_mass(order, H):
     """Sum of phi equals M0 for any particle set (Sec. 3.4 mass conservation)."""
     rng = np.random.default_rng(0)
     X = rng.uniform(-1, 1, (5000, 3))
     X[:10] = -1.0   # on the lower box face
     X[10:20] = 1.0 - 1e-15
-    phi = sipf.deposit(X, 37.0 / X.shape[0], 16, 2.0, order)
+    phi = sipf.deposit(X, 37.0 / X.shape[0], H, 2.0, order)
     assert abs(phi.sum() - 37.0) < 1e-12 * 37
 
 
-def test_deposit_translation_by_one_cell_is_a_roll():
+@pytest.mark.parametrize("H", [16, 12])
+def test_deposit_translation_by_one_cell_is_a_roll(H):
     """Shifting all particles by exactly h shifts phi by one index (node g at g mod H)."""
-    H, L = 16, 2.0
+    L = 2.0
     h = L / H
     X = np.random.default_rng(2).uniform(-1, 1, (3000, 3))
     for axis in range(3):
@@ -252,7 +253,7 @@ def _naive_dft(f, sign):
     return out
 
 
-@pytest.mark.parametrize("H", [4, 8])
+@pytest.mark.parametrize("H", [4, 6, 8])
 def test_transforms_equal_naive_dft(H):
     L = 2.0
     rng = np.random.default_rng(H)
@@ -351,9 +352,10 @@ def _single_mode(prm, qs, amp):
     return a
 
 
-def test_single_mode_decay_and_gradient():
+@pytest.mark.parametrize("H", [16, 12, 22])
+def test_single_mode_decay_and_gradient(H):
     """M0 = 0: alpha_q^(n) = A_q^n alpha_q^(0); grid gradient = Phi_q grad c exactly."""
-    prm = sipf.Params(L=2.0, chi=0.0, mu=0.0, eps=1.0, k=1.0, M0=0.0, dt=1e-4, H=16)
+    prm = sipf.Params(L=2.0, chi=0.0, mu=0.0, eps=1.0, k=1.0, M0=0.0, dt=1e-4, H=H)
     qs = (1, 2, -3)
     amp = 0.3 - 0.2j
     a0 = _single_mode(prm, qs, amp)
@@ -361,7 +363,7 @@ def test_single_mode_decay_and_gradient():
     _, a = sipf.run(X0, prm, 100, alpha0=a0)
     xi = np.array(qs) * 2 * np.pi / prm.L
     A = 1 / (1 + prm.dt / prm.eps * ((xi ** 2).sum() + prm.k ** 2))
-    assert abs(a[tuple(q % 16 for q in qs)] - amp * A ** 100) < 1e-15
+    assert abs(a[tuple(q % H for q in qs)] - amp * A ** 100) < 1e-15
     # continuous analogue exp(-(|xi|^2 + k^2) t), within implicit Euler's n (a tau)^2 / 2
     at = prm.dt * ((xi ** 2).sum() + 1)
     assert abs(A ** 100 - math.exp(-100 * at)) < 100 * at ** 2 / 2
@@ -458,8 +460,8 @@ def test_sipf_pic_approaches_direct_sipf():
     assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
 
 
-def test_half_spectrum_round_trip():
-    H = 8
+@pytest.mark.parametrize("H", [8, 12, 22])
+def test_half_spectrum_round_trip(H):
     phi = np.random.default_rng(0).standard_normal((H, H, H))
     full = np.fft.fftn(phi)
     assert np.abs(sipf.full_spectrum(sipf.half_spectrum(full)) - full).max() < 1e-12
