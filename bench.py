@@ -264,11 +264,17 @@ def e2_study(size):
     """SIPF (direct, Algorithm 1) against SIPF-PIC with P = H^3 in the setup of
     the convergence study: mean error and time of one run per grid size."""
     from paper_2512_03452_amd import convergence
+
+    def log(msg):
+        print("#   " + msg, file=sys.stderr, flush=True)
     q_ref = convergence.load_reference(os.path.join(ROOT, "tests", "golden", "radial_e1_quantiles.txt"))
+    # the grid sizes of the paper's comparison (P = H^3), mixed-radix ones included
     if size == "full":
-        rows = convergence.cost_error_study((8, 16, 32, 64, 128), 8, q_ref, max_direct_H=64, timing_steps=20)
+        rows = convergence.cost_error_study((8, 12, 16, 22, 32, 46, 64, 90, 128), 8, q_ref, max_direct_H=46,
+                                            timing_steps=10, log=log)
     else:
-        rows = convergence.cost_error_study((8, 16, 32, 64), 4, q_ref, max_direct_H=32, timing_steps=10)
+        rows = convergence.cost_error_study((8, 12, 16, 22, 32, 46, 64), 4, q_ref, max_direct_H=32, timing_steps=10,
+                                            log=log)
     return {"steps": 2000, "rows": rows}
 
 

@@ -52,9 +52,9 @@
  *     (FP64): one yz-plane of the half spectrum must fit in the 160 KB of LDS
  *     of a gfx950 compute unit.  The mixed-radix grids H = 12, 22, 46 (both
  *     precisions) and 90 (FP32) of the SIPF against SIPF-PIC comparison
- *     (Sec. 5.1) are also accepted; on them the tile side must divide H, and
- *     sipf_adjoint and the direct method (SIPF_METHOD_DIRECT) return
- *     SIPF_EINVAL.  Other sizes return SIPF_EINVAL.
+ *     (Sec. 5.1) are also accepted; on them the tile side is any integer
+ *     with at most 16 tiles per axis (the last may be partial), and
+ *     sipf_adjoint returns SIPF_EINVAL.  Other sizes return SIPF_EINVAL.
  *
  * Variants (Sec. 5.2):
  *   - eps = 0 makes the c-equation elliptic, -lap c + k^2 c = rho: the mode
@@ -143,7 +143,7 @@ typedef struct sipf_params {
     int32_t  precision;    /* SIPF_FP32 (default) or SIPF_FP64                    */
     int32_t  tile;         /* binning tile side in cells; 0 = tuned default; at most
                               16 (3-D) or 64 (2-D) tiles per axis; a power of two,
-                              or a divisor of H when H is not one                */
+                              or any side when H is not one                      */
     int32_t  resort_every; /* re-sort period in steps; 0 = default: 4, or fewer when
                               sqrt(2 mu tau n) exceeds a quarter of a tile      */
     int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = tuned */
@@ -300,8 +300,8 @@ const char* sipf_last_error(void);
  * Tile / chunk / re-sort autotuner.  Times nsteps steps (after a warm-up that
  * includes graph capture) of fresh contexts built from prm, P and X0 (same
  * meaning as in sipf_init), searching one axis at a time: the binning tile
- * (powers of two from 4 to 32, or the divisors of H when H is not a power of
- * two, within the limits of sipf_params.tile), the
+ * (powers of two from 4 to 32, or 4, 6, 8, 12, 16, 24, 32 when H is not a
+ * power of two, within the limits of sipf_params.tile), the
  * work-item size (1024, 2048, 4096) and the re-sort period (2, 4, 8, 16),
  * starting from the defaults.  *best receives prm with tile, chunk and
  * resort_every set to the fastest combination found, *ms_per_step its time.

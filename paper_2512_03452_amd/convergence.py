@@ -169,6 +169,8 @@ def cost_error_study(Hs, nsim, q_ref, methods=("pic", "direct"), steps=workloads
                 X, secs = _run_single(method, H, P, seed, 1000 * H + l, steps, precision)
                 E.append(discrepancy(q_ref, empirical_quantiles(X, probs).cpu().numpy()))
                 T.append(secs)
+                if log and secs > 2.0:
+                    log(f"{method} H={H} run {l}: {secs:.3g} s")
             out.append(dict(method=method, H=H, P=P, runs=nsim, E=float(np.mean(E)), E_std=float(np.std(E)),
                             seconds_per_run=float(np.mean(T)), timed_steps=steps))
             if log:

@@ -79,8 +79,6 @@ int validate(const sipf_params* p, int64_t P) {
         return fail(SIPF_EINVAL, "method must be SIPF_METHOD_PIC or SIPF_METHOD_DIRECT");
     if (p->method == SIPF_METHOD_DIRECT && dim_of(p) != 3)
         return fail(SIPF_EINVAL, "the direct SIPF method is three-dimensional");
-    if (p->method == SIPF_METHOD_DIRECT && !is_pow2(p->H))
-        return fail(SIPF_EINVAL, "the direct SIPF method needs H a power of two");
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
     if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
     if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
@@ -88,8 +86,8 @@ int validate(const sipf_params* p, int64_t P) {
     if (p->tile != 0 && is_pow2(p->H) && (!is_pow2(p->tile) || p->tile > p->H || (p->H / p->tile) > max_tiles))
         return fail(SIPF_EINVAL, dim_of(p) == 2 ? "tile must be 0 or a power of two with H/64 <= tile <= H"
                                                 : "tile must be 0 or a power of two with H/16 <= tile <= H");
-    if (p->tile != 0 && !is_pow2(p->H) && (p->tile < 1 || p->tile > p->H || p->H % p->tile != 0 || p->H / p->tile > max_tiles))
-        return fail(SIPF_EINVAL, "tile must be 0 or a divisor of H with H/16 <= tile <= H");
+    if (p->tile != 0 && !is_pow2(p->H) && (p->tile < 1 || p->tile > p->H || (p->H + p->tile - 1) / p->tile > max_tiles))
+        return fail(SIPF_EINVAL, "tile must be 0 or in [1, H] with at most 16 tiles per axis");
     if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
     if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 4096)) return fail(SIPF_EINVAL, "chunk must be 0 or in [256, 4096]");
     if (P < 1 || P >= (int64_t(1) << 32)) return fail(SIPF_EINVAL, "P must be in [1, 2^32)");
@@ -104,15 +102,12 @@ double filter_h0(const sipf_params* p) {
 // Defaults where the parameters leave the tuning open (0): an 8-cell tile at
 // H = 128 and H/8 below (3-D), 16-cell tiles up to H = 1024 and H/64 above
 // (2-D), a re-sort every 4 steps, items of up to 4096.  A 3-D grid that is not
-// a power of two takes the smallest divisor of H with at most 8 tiles per axis
-// (the whole axis below H = 16).
+// a power of two takes the same rule with ceil(H / 8) below H = 128 (the last
+// tile of an axis may be partial; the whole axis below H = 16).
 int default_tile(const sipf_params* p) {
     if (dim_of(p) == 3 && !is_pow2(p->H)) {
         if (p->tile) return p->tile;
-        if (p->H < 16) return p->H;
-        int t = 1;
-        while (p->H % t != 0 || p->H / t > 8) ++t;
-        return t;
+        return p->H < 16 ? p->H : (p->H >= 128 ? 8 : (p->H + 7) / 8);
     }
     if (dim_of(p) == 2) {
         int t = p->tile ? p->tile : std::min(p->H, std::max(16, p->H / 64));
@@ -263,7 +258,7 @@ template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
     // the Morton key space is a power of two per axis; tiles past H / tile stay empty
     d.tshift = is_pow2(I.H) && is_pow2(I.tile) ? ilog2(I.tile) : -1;
     d.tile = I.tile;
-    const int nt = 1 << ilog2(I.H / I.tile);
+    const int nt = 1 << ilog2((I.H + I.tile - 1) / I.tile);
     d.nkeys = I.dim == 2 ? nt * nt : nt * nt * nt;
     return d;
 }
@@ -653,7 +648,7 @@ template <typename T> int alloc_group(Group* g) {
         if ((rc = dalloc(g, &I.gspec, d * nspec * 2 * sizeof(T)))) return rc;
         if ((rc = dalloc(g, &I.G, d * ng * sizeof(T)))) return rc;
         for (int64_t b = 0; b < P; b += sc) chunks.push_back(SortChunk{b, i, 0});
-        const int nt = I.H / I.tile;
+        const int nt = (I.H + I.tile - 1) / I.tile;  // tiles per axis, the last may be partial
         seg_off[i] = (int)cap;
         cap += (P + g->chunk - 1) / g->chunk + (d == 2 ? (int64_t)nt * nt : (int64_t)nt * nt * nt);
     }
@@ -1592,8 +1587,8 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
         for (int t = 4; t <= 32; t *= 2)
             if (t <= prm->H && prm->H / t <= 16) tiles.push_back(t);
     } else {
-        for (int t = 2; t <= prm->H; ++t)
-            if (prm->H % t == 0 && prm->H / t <= 16) tiles.push_back(t);
+        for (int t : {4, 6, 8, 12, 16, 24, 32})
+            if (t <= prm->H && (prm->H + t - 1) / t <= 16) tiles.push_back(t);
     }
     if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
     if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 4096}))) return rc;

@@ -157,19 +157,21 @@ __global__ __launch_bounds__(DIR_THREADS) void k_dir_grad(DirDesc<T> d, T* __res
     V st = cis_neg<T>(zl);
     st.y = -st.y;
     T g0 = 0, g1 = 0, g2 = 0;
-    const int npairs = H * H / gridDim.y;  // pairs per slice (a multiple of DIR_PAIRS)
-    const int first = blockIdx.y * npairs;
-    for (int pr0 = first; pr0 < first + npairs; pr0 += DIR_PAIRS) {
+    // pairs [first, last) of this slice; the last group of DIR_PAIRS may be ragged
+    const int first = (int)((int64_t)blockIdx.y * H * H / gridDim.y);
+    const int last = (int)((int64_t)(blockIdx.y + 1) * H * H / gridDim.y);
+    for (int pr0 = first; pr0 < last; pr0 += DIR_PAIRS) {
+        const int npr = min(DIR_PAIRS, last - pr0);
         __syncthreads();
         for (int u = tid; u < 3 * DIR_PAIRS * H; u += DIR_THREADS) {
             const int c = u / (DIR_PAIRS * H), r = u % (DIR_PAIRS * H);
             const int pr = r / H, j = r % H;
             // q_z ascends from -H/2: storage index (j + H/2) mod H
-            sg[c][pr][j] = d.gc[(size_t)c * H * H * H + (size_t)(pr0 + pr) * H + ((j + H / 2) & (H - 1))];
+            if (pr < npr) sg[c][pr][j] = d.gc[(size_t)c * H * H * H + (size_t)(pr0 + pr) * H + (j + H / 2) % H];
         }
         __syncthreads();
         if (active) {
-            for (int pr = 0; pr < DIR_PAIRS; ++pr) {
+            for (int pr = 0; pr < npr; ++pr) {
                 const int kx = (pr0 + pr) / H, ky = (pr0 + pr) % H;
                 V e = cis_neg<T>(-((T)signed_q(kx, H) * xl + (T)signed_q(ky, H) * yl - (T)(H / 2) * zl));
 #pragma unroll 8
@@ -214,14 +216,21 @@ __global__ __launch_bounds__(DIR_THREADS) void k_dir_push(DirDesc<T> d, const T*
     if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(d.err, 1);
 }
 
-int dir_qz(int H) { return H / 2 < 32 ? H / 2 : 32; }
+// q_z run length of dir_beta: the largest divisor of H/2 up to 32 (runs must
+// not straddle q_z = H/2 -> -H/2)
+constexpr int dir_qz_of(int H) {
+    int q = H / 2 < 32 ? H / 2 : 32;
+    while ((H / 2) % q != 0) --q;
+    return q;
+}
+int dir_qz(int H) { return dir_qz_of(H); }
 
 // slices of the (kx, ky) pairs in the gradient sum: enough workgroups to fill
 // the device when the particles alone do not
 int dir_mode_slices(int H, int64_t P) {
     const int64_t pb = (P + DIR_THREADS - 1) / DIR_THREADS;
     int ms = 1;
-    while (ms * pb < 2048 && ms * 2 * DIR_PAIRS <= H * H && ms < 64) ms *= 2;
+    while (ms * pb < 2048 && ms * 2 * DIR_PAIRS <= H * H && ms < 64) ms *= 2;  // >= DIR_PAIRS pairs per slice
     return ms;
 }
 
@@ -235,7 +244,7 @@ int dir_slices(int H, int64_t P) {
 
 template <typename T, int H>
 static hipError_t dir_step_h(const DirDesc<T>& d, cplx_t<T>* part, int nslices, T* gpart, int ms, hipStream_t s) {
-    constexpr int QZ = H / 2 < 32 ? H / 2 : 32;
+    constexpr int QZ = dir_qz_of(H);
     const int cols = H * H * (H / QZ);
     launch_kernel((k_dir_beta<T, H, QZ>), dim3((cols + DIR_THREADS - 1) / DIR_THREADS, nslices), dim3(DIR_THREADS), 0,
                   s, d, part);
@@ -254,12 +263,18 @@ static hipError_t dir_step_h(const DirDesc<T>& d, cplx_t<T>* part, int nslices, 
 
 template <typename T>
 hipError_t launch_direct_step(const DirDesc<T>& d, cplx_t<T>* part, int nslices, T* gpart, int ms, hipStream_t s) {
-    if (ms < 1 || (d.H * d.H) % (ms * DIR_PAIRS) != 0) return hipErrorInvalidValue;
+    if (ms < 1 || ms > d.H * d.H) return hipErrorInvalidValue;
     switch (d.H) {
         case 8: return dir_step_h<T, 8>(d, part, nslices, gpart, ms, s);
+        case 12: return dir_step_h<T, 12>(d, part, nslices, gpart, ms, s);
         case 16: return dir_step_h<T, 16>(d, part, nslices, gpart, ms, s);
+        case 22: return dir_step_h<T, 22>(d, part, nslices, gpart, ms, s);
         case 32: return dir_step_h<T, 32>(d, part, nslices, gpart, ms, s);
+        case 46: return dir_step_h<T, 46>(d, part, nslices, gpart, ms, s);
         case 64: return dir_step_h<T, 64>(d, part, nslices, gpart, ms, s);
+        case 90:
+            if constexpr (sizeof(T) == 4) return dir_step_h<T, 90>(d, part, nslices, gpart, ms, s);
+            else return hipErrorInvalidValue;
         case 128:
             if constexpr (sizeof(T) == 4) return dir_step_h<T, 128>(d, part, nslices, gpart, ms, s);
             else return hipErrorInvalidValue;

@@ -98,8 +98,8 @@ template <typename T> struct PartDesc {
     uint32_t inst;          // fourth counter word
     int gmargin;            // cells the W^- displacement can reach (gradient window margin)
     int tshift;             // log2 of the sort tile side, or -1 when the side is not a power of two
-    int tile;               // sort tile side (cells; divides H)
-    int nkeys;              // Morton keys: (H / tile)^dim, or that with H / tile rounded up to a power of two
+    int tile;               // sort tile side (cells)
+    int nkeys;              // Morton keys: (H / tile)^dim, or with ceil(H / tile) rounded up to a power of two
     T* ox;                  // push-only passes: positions out (null: in place), ids copied to oid
     T* oy;
     T* oz;

@@ -68,9 +68,9 @@ __device__ __forceinline__ uint32_t spread2(uint32_t v) {
     return r;
 }
 
-// Tile coordinate of position v along one axis: a shift when the tile side is a
-// power of two (tshift >= 0), else a division by the tile side, which then
-// divides H.
+// Tile coordinate of position v along one axis: a shift when H and the tile
+// side are powers of two (tshift >= 0), else a division by the tile side (the
+// last tile of the axis may then be partial).
 template <typename T>
 __device__ __forceinline__ uint32_t tile_coord(const PartDesc<T>& a, T v) {
     const int g = ifloor(v * a.hl);

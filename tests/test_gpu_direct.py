@@ -45,6 +45,11 @@ def rel_l2(a, b):
     (8, 1, "em", -1.0, "fp64"),
     (32, 4000, "em", -1.0, "fp32"),
     (64, 2000, "strang", 0.0, "fp32"),
+    # mixed-radix grids (q_z runs of 6, 11, 23, 15; ragged pair groups)
+    (12, 700, "em", -1.0, "fp64"),
+    (22, 999, "strang", 0.0, "fp64"),
+    (46, 300, "em", -1.0, "fp32"),
+    (90, 64, "em", -1.0, "fp32"),
 ])
 def test_direct_sipf_matches_oracle(H, P, scheme, H0, precision):
     say("direct", H, P, scheme, H0, precision)

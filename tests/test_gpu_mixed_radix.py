@@ -3,7 +3,8 @@
 with the FP64 oracle, through the C ABI.
 
 These grids take the remainder-wrapped particle pass and the mixed-radix LDS
-FFT (radices 2, 3, 5, 9, 11, 23).  Tolerances as for the power-of-two grids:
+FFT (radices 2, 3, 5, 9, 11, 23); sort tiles need not divide H (cases 5, 7, 8
+leave a partial last tile).  Tolerances as for the power-of-two grids:
 FP32 fields within 1e-5 relative L2 per step, FP64 within 1e-12; positions by
 the same per-step budget.
 """
@@ -74,7 +75,8 @@ def _positions(kind, P, seed):
     ("fp32", 12, 1, "uniform", 0), ("fp32", 12, 5000, "blob", 0), ("fp32", 12, 7001, "uniform", 4),
     ("fp32", 12, 3000, "corner", 3), ("fp32", 22, 30000, "uniform", 0), ("fp32", 22, 20000, "corner", 2),
     ("fp32", 46, 100003, "blob", 0), ("fp32", 46, 40000, "uniform", 23), ("fp32", 90, 200001, "blob", 0),
-    ("fp32", 90, 60000, "corner", 9), ("fp64", 12, 4000, "uniform", 0), ("fp64", 22, 9999, "blob", 11),
+    ("fp32", 90, 60000, "corner", 9), ("fp32", 46, 50000, "uniform", 8), ("fp32", 90, 80000, "blob", 7),
+    ("fp32", 22, 5000, "corner", 5), ("fp64", 12, 4000, "uniform", 0), ("fp64", 22, 9999, "blob", 11),
     ("fp64", 46, 20000, "corner", 0),
 ])
 def test_deposit_parity(precision, H, P, kind, tile):

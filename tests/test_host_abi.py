@@ -100,12 +100,12 @@ def test_exponential_propagator_needs_positive_eps():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(H=24), dict(H=90, precision="fp64"), dict(H=12, tile=5), dict(H=90, tile=4), dict(H=46, tile=2),
-    dict(H=12, method="direct"), dict(H=22, tile=-11),
+    dict(H=24), dict(H=90, precision="fp64"), dict(H=12, tile=13), dict(H=90, tile=5), dict(H=46, tile=2),
+    dict(H=22, tile=-11),
 ])
 def test_mixed_radix_parameters_rejected(kw):
-    """3-D grids take 12, 22, 46 and 90 besides powers of two; a tile must then
-    divide H with at most 16 tiles per axis; direct SIPF keeps powers of two."""
+    """3-D grids take 12, 22, 46 and 90 besides powers of two; a tile then
+    leaves at most 16 tiles per axis, the last one possibly partial."""
     L = _lib()
     p = L.default_params(**kw)
     h = ctypes.c_void_p()
