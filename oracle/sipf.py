@@ -60,6 +60,7 @@ class Params:
     seed: int = 0           # Philox key
     instance: int = 0       # fourth Philox counter word
     propagator: str = "implicit"  # "implicit" (eq. alpha_hat_update) or "exp" (Sec. 3.4)
+    positivity: bool = False  # positivity-preserving deposit (``deposit_positive``)
 
     def h0(self):
         """Filter scale H0 (Sec. 5.1 rule when H0 == 0)."""
@@ -96,6 +97,47 @@ def deposit(X, w, H, L, order=4):
         idx = (g + gam) % H
         flat = (idx[:, 0] * H + idx[:, 1]) * H + idx[:, 2]
         phi += np.bincount(flat, weights=w * F[:, j], minlength=H ** 3)
+    return phi.reshape(H, H, H)
+
+
+def deposit_positive(X, w, H, L, record=None):
+    """Positivity-preserving order-4 deposit (reading of Remark ``smoothness``
+    and Sec. 3.4): the order-4 weights are negative on the outer nodes, so the
+    deposit can be negative next to the edge of the particle cloud.  Every
+    particle starts with the order-4 weights; in each round, every particle
+    still on order 4 whose 32 stencil nodes include a node where the current
+    deposit is negative switches to the order-2 weights of eq. ``2ord`` (its
+    inner nodes only).  Rounds repeat until one switches nobody.
+
+    Both weight sets sum to one, so the mass is that of ``deposit``.  A node
+    that is still negative has an order-4 contributor with a negative weight
+    (order-2 weights are not negative), which the next round switches; the
+    result is therefore >= 0, and in the bulk of the cloud, where no node is
+    negative, it equals the order-4 deposit.  ``record`` receives the switched
+    mask and the number of rounds that switched someone.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    P = X.shape[0]
+    g, lam = cell_and_frac(X, H, L)
+    w = np.broadcast_to(np.asarray(w, dtype=np.float64), (P,))
+    offs = stencil.offsets(4)
+    F4 = stencil.weights(lam, 4)
+    F2 = np.zeros_like(F4)
+    F2[:, :8] = stencil.weights(lam, 2)     # the first 8 nodes of Gamma_4 are Gamma_2, in the same order
+    idx = (g[:, None, :] + offs[None, :, :]) % H
+    flat = (idx[..., 0] * H + idx[..., 1]) * H + idx[..., 2]    # (P, 32)
+    switched = np.zeros(P, dtype=bool)
+    rounds = 0
+    while True:
+        F = np.where(switched[:, None], F2, F4) * w[:, None]
+        phi = np.bincount(flat.ravel(), weights=F.ravel(), minlength=H ** 3)
+        new = (phi[flat] < 0).any(axis=1) & ~switched
+        if not new.any():
+            break
+        switched |= new
+        rounds += 1
+    if record is not None:
+        record.update(switched=switched, rounds=rounds)
     return phi.reshape(H, H, H)
 
 
@@ -265,7 +307,10 @@ def step(X, alpha, n, prm, ids=None, record=None):
     P = X.shape[0]
     if ids is None:
         ids = np.arange(P, dtype=np.uint64)
-    phi = deposit(X, prm.M0 / P, prm.H, prm.L, prm.p2g_order)
+    if prm.positivity:
+        phi = deposit_positive(X, prm.M0 / P, prm.H, prm.L)
+    else:
+        phi = deposit(X, prm.M0 / P, prm.H, prm.L, prm.p2g_order)
     beta = forward_transform(phi, prm.L)
     alpha_new = mode_update(alpha, beta, prm)
     G = gradient_grid(alpha, prm)
