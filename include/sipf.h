@@ -113,6 +113,21 @@ extern "C" {
 #define SIPF_METHOD_PIC    0
 #define SIPF_METHOD_DIRECT 1
 
+/* sipf_params.positivity = 1: positivity-preserving deposit, the smoothing near
+ * the edge of the particle cloud that Remark `smoothness` (Sec. 3.1) asks for
+ * so that the operator-splitting update of Sec. 3.4 keeps c non-negative (the
+ * paper cites the procedure without giving it; this is the reading built
+ * here).  After the order-4 deposit, rounds repeat until one switches nobody:
+ * every particle still on the order-4 weights whose 32 stencil nodes include a
+ * node where the deposit is below -2^-20 (FP32) or -2^-44 (FP64) of a
+ * particle's mass M0/P switches to the order-2 weights of eq. 2ord; then
+ * negative values left by rounding are set to zero.  The mass is unchanged up
+ * to that rounding; in the bulk of the cloud the deposit stays order 4.  Each
+ * round reads a count on the host, so such a context steps without graphs
+ * (sipf_use_graphs keeps them off).  3-D SIPF-PIC only; all instances of a
+ * batch share it; sipf_adjoint returns SIPF_EINVAL.  It applies to the step's
+ * deposit, sipf_get_field(SIPF_FIELD_RHO) and sipf_diagnostics. */
+
 /* arithmetic precision of particles, grids and spectra */
 #define SIPF_FP32 0
 #define SIPF_FP64 1
@@ -152,6 +167,7 @@ typedef struct sipf_params {
     uint32_t dim;          /* space dimension: 3 (0 means 3) or 2                 */
     int32_t  propagator;   /* SIPF_PROP_IMPLICIT (default) or SIPF_PROP_EXP (needs eps > 0) */
     int32_t  method;       /* SIPF_METHOD_PIC (default, Algorithm 4) or SIPF_METHOD_DIRECT */
+    int32_t  positivity;   /* 1: positivity-preserving deposit (see below), 0: plain order 4 */
 } sipf_params;
 
 typedef struct sipf_ctx sipf_ctx;
@@ -262,6 +278,15 @@ int sipf_diagnostics(sipf_ctx* ctx, sipf_diag* out);
  */
 int sipf_adjoint(sipf_ctx* ctx, int64_t nsteps, int32_t ckpt_every, const void* phi_bar,
                  double* loss, double* dchi, double* dmu, void* dX0);
+
+/*
+ * Counts of the last positivity-preserving deposit of a context (see
+ * sipf_params.positivity): *switched = particles that moved to the order-2
+ * weights, *rounds = rounds that switched at least one.  Both 0 when the
+ * option is off or nothing was negative.  Errors: SIPF_EINVAL for NULL
+ * arguments.
+ */
+int sipf_positivity_stats(sipf_ctx* ctx, int64_t* switched, int32_t* rounds);
 
 /* Per-phase timing with HIP events recorded on the context's stream around
  * every launch of the step's kernels (enable = 1 starts it, 0 stops it; the

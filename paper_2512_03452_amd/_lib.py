@@ -44,7 +44,7 @@ class SipfParams(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("resort_every", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32), ("dim", ctypes.c_uint32),
-        ("propagator", ctypes.c_int32), ("method", ctypes.c_int32),
+        ("propagator", ctypes.c_int32), ("method", ctypes.c_int32), ("positivity", ctypes.c_int32),
     ]
 
 
@@ -86,6 +86,7 @@ SIGNATURES = {
     "sipf_diagnostics": [_vp, ctypes.POINTER(SipfDiag)],
     "sipf_batch_diagnostics": [_vp, ctypes.POINTER(SipfDiag)],
     "sipf_adjoint": [_vp, _i64, _i32, _vp, _dp, _dp, _dp, _vp],
+    "sipf_positivity_stats": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
     "sipf_profile": [_vp, ctypes.c_int],
     "sipf_profile_read": [_vp, _dp, ctypes.POINTER(_i64)],
     "sipf_save": [_vp, ctypes.c_char_p],

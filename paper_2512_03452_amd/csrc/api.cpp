@@ -79,6 +79,9 @@ int validate(const sipf_params* p, int64_t P) {
         return fail(SIPF_EINVAL, "method must be SIPF_METHOD_PIC or SIPF_METHOD_DIRECT");
     if (p->method == SIPF_METHOD_DIRECT && dim_of(p) != 3)
         return fail(SIPF_EINVAL, "the direct SIPF method is three-dimensional");
+    if (p->positivity != 0 && p->positivity != 1) return fail(SIPF_EINVAL, "positivity must be 0 or 1");
+    if (p->positivity && (dim_of(p) != 3 || p->method != SIPF_METHOD_PIC))
+        return fail(SIPF_EINVAL, "the positivity-preserving deposit is for the 3-D SIPF-PIC step");
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
     if (p->g2p_order != 2) return fail(SIPF_EINVAL, "g2p_order must be 2");
     if (p->scheme != SIPF_STRANG && p->scheme != SIPF_EM) return fail(SIPF_EINVAL, "scheme must be SIPF_STRANG or SIPF_EM");
@@ -154,6 +157,9 @@ struct Inst {
     void* part = nullptr;   // nslices x H^3 partial sums of beta
     void* gpart = nullptr;  // mslices x 3 x P partial gradient sums
     int nslices = 0, mslices = 0;
+    // positivity-preserving deposit: per-particle switch tags, node flags
+    uint32_t* pos_sw = nullptr;
+    uint8_t* pos_flag = nullptr;
 };
 
 // Instances of one grid size: FieldDesc slots [first, first + count).
@@ -166,6 +172,11 @@ struct Group {
     int dim = 3;  // shared by every instance
     int method = SIPF_METHOD_PIC;
     bool pow2 = true;  // every instance's H is a power of two
+    bool positivity = false;  // positivity-preserving deposit (shared by every instance)
+    uint32_t pos_tag = 0;     // tag of the last positive deposit
+    int* pos_count = nullptr;  // per-instance particles switched in a round
+    int64_t pos_switched = 0;  // particles switched by the last positive deposit
+    int pos_rounds = 0;        // rounds that switched someone in it
     size_t tsize = 4;
     int scheme = SIPF_STRANG;
     hipStream_t stream = nullptr;
@@ -422,6 +433,44 @@ template <typename T> DirDesc<T> make_ddesc(const Group* g) {
     return d;
 }
 
+// Positivity-preserving deposit (the reading of Remark `smoothness` described
+// in positivity.hip): after a deposit-only pass, rounds of flag + switch until
+// a round switches nobody, then the clamp.  Each round reads its counts on the
+// host, so a group with this option steps without graphs.
+template <typename T> int positivity_rounds(Group* g) {
+    if (!g->positivity) return SIPF_OK;
+    const int n = (int)g->in.size();
+    const uint32_t tag = ++g->pos_tag == 0 ? ++g->pos_tag : g->pos_tag;  // 0 marks "never switched"
+    const PartDesc<T>* pd = pdesc_dev<T>(g, g->cur);
+    // flag threshold: the fixed-point windows round each contribution to
+    // 2^-18 (FP32) or 2^-51 (FP64) of a particle's mass or better; a node only
+    // that far below zero is rounding left by switched particles (it has no
+    // order-4 contributor left), so the threshold sits just under it -- a
+    // larger one would miss real negative nodes
+    const double rel = g->prec == SIPF_FP32 ? std::ldexp(1.0, -20) : std::ldexp(1.0, -44);
+    std::vector<int> cnt(n);
+    g->pos_switched = 0;
+    g->pos_rounds = 0;
+    for (int64_t round = 0; round < (int64_t)1 << 30; ++round) {
+        HIPCHK(launch_fill<int>(g->pos_count, n, 0, g->stream));
+        for (int i = 0; i < n; ++i) {
+            const Inst& I = g->in[i];
+            const T thresh = (T)(rel * I.prm.M0 / (double)I.P);
+            HIPCHK(launch_pos_flag<T>((const T*)I.phi, (int64_t)grid_size(I.H, I.dim), thresh, I.pos_flag, g->stream));
+            HIPCHK(launch_pos_switch<T>(pd + i, I.P, I.pos_flag, I.pos_sw, tag, g->pos_count + i, g->stream));
+        }
+        HIPCHK(hipMemcpyAsync(cnt.data(), g->pos_count, n * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        int64_t total = 0;
+        for (int c : cnt) total += c;
+        if (total == 0) break;
+        g->pos_switched += total;
+        g->pos_rounds++;
+    }
+    for (const Inst& I : g->in) HIPCHK(launch_pos_clamp<T>((T*)I.phi, (int64_t)grid_size(I.H, I.dim), g->stream));
+    return SIPF_OK;
+}
+
 template <typename T> int enqueue_step(Group* g) {
     if (g->method == SIPF_METHOD_DIRECT) {
         Timed t(g, SIPF_PHASE_PARTICLES);
@@ -435,7 +484,14 @@ template <typename T> int enqueue_step(Group* g) {
         int rc = do_sort<T>(g);
         if (rc) return rc;
     }
-    {
+    if (g->positivity) {
+        // deposit, the positivity rounds on it, then the push (Algorithm 4's two branches apart)
+        Timed t(g, SIPF_PHASE_PARTICLES);
+        HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, false));
+        int rc = positivity_rounds<T>(g);
+        if (rc) return rc;
+        HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), false, true));
+    } else {
         Timed t(g, SIPF_PHASE_PARTICLES);
         HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, true));
     }
@@ -674,6 +730,14 @@ template <typename T> int alloc_group(Group* g) {
     HIPCHK(hipMemset(g->counts, 0, (size_t)n * mk * sizeof(uint32_t)));
     HIPCHK(hipMemset(g->steps, 0, n * sizeof(uint32_t)));
     HIPCHK(hipMemset(g->errs, 0, n * sizeof(int)));
+    if (g->positivity) {
+        if ((rc = dalloc(g, (void**)&g->pos_count, n * sizeof(int)))) return rc;
+        for (Inst& I : g->in) {
+            if ((rc = dalloc(g, (void**)&I.pos_sw, I.P * sizeof(uint32_t)))) return rc;
+            if ((rc = dalloc(g, (void**)&I.pos_flag, grid_size(I.H, I.dim)))) return rc;
+            HIPCHK(hipMemset(I.pos_sw, 0, I.P * sizeof(uint32_t)));
+        }
+    }
     g->pgrid = std::max(1, std::min(g->items_cap, g->dim == 2 ? particle_resident_blocks2<T>(g->scheme, g->win_bytes)
                                                                 : particle_resident_blocks<T>(g->scheme, g->win_bytes)));
     return upload_descs<T>(g);
@@ -794,6 +858,8 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
         if (prm[i].precision != prm[0].precision) return fail(SIPF_EINVAL, "all instances must share the precision");
         if (prm[i].scheme != prm[0].scheme) return fail(SIPF_EINVAL, "all instances must share the scheme");
         if (dim_of(&prm[i]) != dim_of(&prm[0])) return fail(SIPF_EINVAL, "all instances must share the dimension");
+        if (prm[i].positivity != prm[0].positivity)
+            return fail(SIPF_EINVAL, "all instances must share the positivity option");
     }
     if (prm[0].method == SIPF_METHOD_DIRECT && n != 1)
         return fail(SIPF_EINVAL, "the direct SIPF method runs single contexts, not batches");
@@ -810,6 +876,8 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
     g->dim = dim_of(&prm[0]);
     g->method = prm[0].method;
     if (g->method == SIPF_METHOD_DIRECT) g->graphs = false;
+    g->positivity = prm[0].positivity != 0;
+    if (g->positivity) g->graphs = false;  // the rounds read their counts on the host
     g->tsize = ts;
     g->scheme = prm[0].scheme;
     g->stream = (hipStream_t)hip_stream;
@@ -856,6 +924,8 @@ template <typename T> int get_field_typed(Group* g, int i, int which, void* out,
     if (which == SIPF_FIELD_RHO) {
         // deposit-only pass over every instance, then clear every deposit again
         HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, false));
+        int rc = positivity_rounds<T>(g);
+        if (rc) return rc;
         HIPCHK(hipMemcpyAsync(out, I.phi, ng * sizeof(T), kind, g->stream));
         for (const Inst& J : g->in) HIPCHK(launch_fill<T>((T*)J.phi, (int64_t)grid_size(J.H, J.dim), (T)0, g->stream));
     } else if (which == SIPF_FIELD_GRAD) {
@@ -939,6 +1009,7 @@ template <typename T> int diagnostics_typed(Group* g, sipf_diag* out) {
     HIPCHK(hipMemcpyAsync(ddev, dd.data(), n * sizeof(DiagDesc<T>), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipMemcpyAsync(fdev, fd.data(), fd_b, hipMemcpyHostToDevice, g->stream));
     HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, false));
+    if (int rc = positivity_rounds<T>(g)) return rc;
     for (const HClass& h : g->classes) {
         HIPCHK(field_fwd<T>(g, h.H, fdev + h.first, h.count, true));
         HIPCHK(field_x<T>(g, h.H, fdev + h.first, h.count, XP_RHO));
@@ -1302,7 +1373,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
 // snapshots: header, positions in original order, alpha in natural order
 // ---------------------------------------------------------------------------
 const char kMagic[8] = {'S', 'I', 'P', 'F', 'S', 'N', 'A', 'P'};
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 
 struct SnapHeader {
     char magic[8];
@@ -1469,7 +1540,7 @@ int sipf_run(sipf_ctx* c, int64_t nsteps) {
 
 int sipf_use_graphs(sipf_ctx* c, int enable) {
     if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
-    c->graphs = enable != 0 && c->method != SIPF_METHOD_DIRECT;
+    c->graphs = enable != 0 && c->method != SIPF_METHOD_DIRECT && !c->positivity;
     return SIPF_OK;
 }
 
@@ -1524,6 +1595,7 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
     if (c->dim != 3) return fail(SIPF_EINVAL, "sipf_adjoint is available in three dimensions only");
     if (c->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "sipf_adjoint runs SIPF-PIC contexts only");
     if (!c->pow2) return fail(SIPF_EINVAL, "sipf_adjoint needs H a power of two");
+    if (c->positivity) return fail(SIPF_EINVAL, "sipf_adjoint does not differentiate the positivity rounds");
     return c->prec == SIPF_FP32
                ? adjoint_typed<float>(c, nsteps, ckpt_every, (const float*)phi_bar, loss, dchi, dmu, (float*)dX0)
                : adjoint_typed<double>(c, nsteps, ckpt_every, (const double*)phi_bar, loss, dchi, dmu, (double*)dX0);
@@ -1661,9 +1733,16 @@ int sipf_batch_profile_read(sipf_batch* b, double* ms, int64_t* launches) {
     return profile_read_any(b, ms, launches);
 }
 
+int sipf_positivity_stats(sipf_ctx* c, int64_t* switched, int32_t* rounds) {
+    if (!c || !switched || !rounds) return fail(SIPF_EINVAL, "NULL argument");
+    *switched = c->pos_switched;
+    *rounds = c->pos_rounds;
+    return SIPF_OK;
+}
+
 int sipf_batch_use_graphs(sipf_batch* b, int enable) {
     if (!b) return fail(SIPF_EINVAL, "batch is NULL");
-    b->graphs = enable != 0;
+    b->graphs = enable != 0 && !b->positivity;
     return SIPF_OK;
 }
 

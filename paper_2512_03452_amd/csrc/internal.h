@@ -174,6 +174,14 @@ template <typename T>
 // pow2: every instance's H is a power of two (index wraps by mask; else by remainder)
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
                             bool push, int scheme, int win_bytes, bool pow2, hipStream_t s);
+// positivity-preserving deposit rounds (positivity.hip): flag nodes below
+// -thresh, switch the order-4 particles touching a flagged node to order 2
+// (count += switched; sw[i] = tag marks them), clamp negatives to zero
+template <typename T> hipError_t launch_pos_flag(const T* phi, int64_t n, T thresh, uint8_t* flag, hipStream_t s);
+template <typename T>
+hipError_t launch_pos_switch(const PartDesc<T>* pd, int64_t P, const uint8_t* flag, uint32_t* sw, uint32_t tag,
+                             int* count, hipStream_t s);
+template <typename T> hipError_t launch_pos_clamp(T* phi, int64_t n, hipStream_t s);
 // 2-D particle pass (particles2d.hip)
 template <typename T>
 hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,

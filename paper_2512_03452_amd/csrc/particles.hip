@@ -932,5 +932,6 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 
 SIPF_INST(float)
 SIPF_INST(double)
+template hipError_t launch_fill<int>(int*, int64_t, int, hipStream_t);
 
 }  // namespace sipf

@@ -174,6 +174,12 @@ class Sim:
         """Replay captured HIP graphs in run() (default) or enqueue every step."""
         check(_lib.load().sipf_use_graphs(self._h, 1 if enable else 0))
 
+    def positivity_stats(self):
+        """(particles switched to order 2, rounds) of the last positive deposit."""
+        sw, r = ctypes.c_int64(), ctypes.c_int32()
+        check(_lib.load().sipf_positivity_stats(self._h, ctypes.byref(sw), ctypes.byref(r)))
+        return int(sw.value), int(r.value)
+
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

@@ -64,6 +64,7 @@ def test_defaults():
     ("H", 48), ("H", 4), ("H", 256), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
     ("chi", float("inf")), ("M0", -2.0), ("L", 0.0), ("p2g_order", 2), ("g2p_order", 4),
     ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4), ("propagator", 2), ("method", 2),
+    ("positivity", 2), ("positivity", -1),
 ])
 def test_invalid_parameters_rejected_before_device(field, value):
     L = _lib()
@@ -112,6 +113,19 @@ def test_mixed_radix_parameters_rejected(kw):
     X = np.zeros((4, 3), np.float64 if kw.get("precision") == "fp64" else np.float32)
     rc = L.load().sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
     assert rc == L.SIPF_EINVAL and h.value is None
+
+
+@pytest.mark.parametrize("kw", [dict(positivity=1, dim=2, H=64), dict(positivity=1, method="direct", H=8)])
+def test_positivity_option_is_for_the_3d_pic_step(kw):
+    L = _lib()
+    p = L.default_params(**kw)
+    h = ctypes.c_void_p()
+    X = np.zeros((4, p.dim if p.dim else 3), np.float32)
+    rc = L.load().sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
+    assert rc == L.SIPF_EINVAL and h.value is None
+    lib = L.load()
+    sw, r = ctypes.c_int64(), ctypes.c_int32()
+    assert lib.sipf_positivity_stats(None, ctypes.byref(sw), ctypes.byref(r)) == L.SIPF_EINVAL
 
 
 def test_fp64_h128_rejected():
@@ -171,12 +185,12 @@ def test_load_of_corrupt_snapshot_is_eio(tmp_path, damage):
     Hdr = _snap_header_type()
     p = L.default_params(H=8)
     P = 10
-    h = Hdr(b"SIPFSNAP", 2, 4, p, P, 3)
+    h = Hdr(b"SIPFSNAP", 3, 4, p, P, 3)
     payload = bytes(P * 3 * 4 + 8 * 8 * 5 * 2 * 4)
     if damage == "magic":
         h.magic = b"SIPFSNAQ"
     elif damage == "version":
-        h.version = 1  # the layout before the propagator field
+        h.version = 2  # the layout before the positivity field
     elif damage == "tsize":
         h.tsize = 8
     elif damage == "truncated":
@@ -204,7 +218,7 @@ def _batch_init(L, prms, Ps, Xs, on_device=0):
 
 
 @pytest.mark.parametrize("case", ["empty", "mixed_precision", "mixed_scheme", "bad_instance", "bad_count",
-                                  "non_finite"])
+                                  "non_finite", "mixed_positivity"])
 def test_batch_init_rejects_before_device(case):
     L = _lib()
     a = L.default_params(H=16)
@@ -223,6 +237,8 @@ def test_batch_init_rejects_before_device(case):
         prms[1] = L.default_params(H=48)
     elif case == "bad_count":
         Ps[0] = 0
+    elif case == "mixed_positivity":
+        prms[1] = L.default_params(H=32, positivity=1)
     elif case == "non_finite":
         Xb[4, 2] = np.inf
         want = L.SIPF_ENUMERIC

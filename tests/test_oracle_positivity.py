@@ -21,7 +21,18 @@ def _ball(P, R, seed):
     return v * R * rng.random(P)[:, None] ** (1.0 / 3.0)
 
 
-@pytest.mark.parametrize("H,kind", [(16, "ball"), (32, "ball"), (12, "ball"), (22, "blob"), (16, "sparse")])
+def _sheet():
+    """A thin sheet of 2681 particles whose positive deposit on H = 16 takes two
+    rounds (switching the first shell leaves new negative nodes next to it)."""
+    rng = np.random.default_rng(28)
+    P = int(rng.integers(50, 4000))
+    X = rng.uniform(-1, 1, (P, 3))
+    X[:, 2] = rng.normal(0, rng.uniform(0.005, 0.1), P)
+    return sipf.wrap(X, 2.0)
+
+
+@pytest.mark.parametrize("H,kind", [(16, "ball"), (32, "ball"), (12, "ball"), (22, "blob"), (16, "sparse"),
+                                    (16, "sheet")])
 def test_nonnegative_with_the_order4_mass(H, kind):
     L = 2.0
     rng = np.random.default_rng(H)
@@ -29,6 +40,8 @@ def test_nonnegative_with_the_order4_mass(H, kind):
         X = _ball(20000, 0.5, H)
     elif kind == "blob":
         X = sipf.wrap(rng.normal(0.2, 0.15, (8000, 3)), L)
+    elif kind == "sheet":
+        X = _sheet()
     else:
         X = rng.uniform(-1, 1, (40, 3))
     w = 3.0 / X.shape[0]
@@ -39,6 +52,8 @@ def test_nonnegative_with_the_order4_mass(H, kind):
     assert phi.min() >= 0.0
     assert abs(phi.sum() - 3.0) < 1e-12 * 3.0
     assert rec["rounds"] >= 1 and rec["switched"].any()
+    if kind == "sheet":
+        assert rec["rounds"] == 2
 
 
 def test_equals_the_order4_deposit_where_nothing_is_negative():
@@ -105,3 +120,22 @@ def test_trilinear_layout_matches_the_inner_nodes():
     """The order-2 nodes are the first eight of Gamma_4, in the same order (the
     fallback puts eq. 2ord's weights there and zero on the outer nodes)."""
     assert np.array_equal(stencil.offsets(4)[:8], stencil.offsets(2))
+
+
+def test_positive_deposit_and_exponential_propagator_keep_c_nonnegative():
+    """Sec. 3.4: with a non-negative deposit and the exponential propagator, c
+    stays non-negative up to rounding once the diffusion length of one step
+    reaches the grid spacing (tau >= h^2 here); the order-4 deposit or the
+    implicit propagator leave clearly negative values in the same run."""
+    X0 = _ball(20000, 0.3, 1)
+
+    def cmin(pos, prop):
+        prm = sipf.Params(L=2.0, chi=0.0, mu=0.0, eps=1.0, k=1.0, M0=10.0, dt=4e-3, H=32, positivity=pos,
+                          propagator=prop)
+        _, a = sipf.run(X0, prm, 3)
+        c = sipf.inverse_transform(a).real
+        return c.min() / c.max()
+
+    assert cmin(True, "exp") > -1e-15
+    assert cmin(False, "exp") < -1e-14
+    assert cmin(True, "implicit") < -1e-7
