@@ -226,6 +226,24 @@ def two_d_section(pkg, workloads, np, torch, level, steps=100, warmup=20):
     return out
 
 
+def positivity_section(pkg, torch, X0, params, plain_ms, steps=20):
+    """Step time with the positivity-preserving deposit (deposit, rounds, push as
+    separate passes, no graphs) against the fused step, and its switch counts."""
+    sim = pkg.Sim(X0, **dict(params, positivity=1))
+    sim.run(3)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    switched, rounds = sim.positivity_stats()
+    sim.close()
+    return {"steps": steps, "ms_per_step": ms, "ratio_to_plain_step": ms / plain_ms,
+            "switched_last_step": switched, "rounds_last_step": rounds, "P": int(X0.shape[0])}
+
+
 def calibrate_copy(torch, nbytes=1 << 30, reps=5):
     """A plain device copy of nbytes, reps times: the reference whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) scale those of the step's kernels."""
@@ -290,6 +308,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-positivity", action="store_true")
     ap.add_argument("--e1", default="reduced", choices=["none", "reduced", "full"],
                     help="convergence study of Sec. 5.1: 8 runs of 6 configurations, or the full 30 x 14")
     ap.add_argument("--e2", default="quick", choices=["none", "quick", "full"],
@@ -384,6 +403,9 @@ def main():
         diag = sim.diagnostics()
     out["diagnostics"] = dict(diag, ms_per_call=1e3 * (time.perf_counter() - t0) / 5)
     sim.close()
+    if not args.no_positivity:
+        print("# positivity-preserving deposit on the same workload", file=sys.stderr, flush=True)
+        out["positivity"] = positivity_section(pkg, torch, X0, params, ms_per_step)
     if args.e1 != "none":
         print(f"# convergence study of Sec. 5.1 ({args.e1})", file=sys.stderr, flush=True)
         out["e1"] = e1_study(args.e1)
