@@ -405,7 +405,9 @@ def main():
     sim.close()
     if not args.no_positivity:
         print("# positivity-preserving deposit on the same workload", file=sys.stderr, flush=True)
+        X0 = cfg["init"](P).astype(np.float32 if fp32 else np.float64)  # the same seeded input as the timed run
         out["positivity"] = positivity_section(pkg, torch, X0, params, ms_per_step)
+        del X0
     if args.e1 != "none":
         print(f"# convergence study of Sec. 5.1 ({args.e1})", file=sys.stderr, flush=True)
         out["e1"] = e1_study(args.e1)
