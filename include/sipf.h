@@ -48,9 +48,11 @@
  *     unless stated otherwise.  A context is not thread-safe; distinct
  *     contexts are independent.  After SIPF_EDEVICE the context must be
  *     destroyed.
- *   - H must be a power of two with 8 <= H <= 128 (FP32) or 8 <= H <= 64
- *     (FP64): one yz-plane of the half spectrum must fit in the 160 KB of LDS
- *     of a gfx950 compute unit.  The mixed-radix grids H = 12, 22, 46 (both
+ *   - H must be a power of two with 8 <= H <= 256 (FP32) or 8 <= H <= 64
+ *     (FP64).  Up to H = 128 one yz-plane of the half spectrum is transformed
+ *     in the 160 KB of LDS of a gfx950 compute unit; at H = 256 the plane
+ *     passes split into row and column passes; sipf_adjoint and the direct
+ *     method take H <= 128.  The mixed-radix grids H = 12, 22, 46 (both
  *     precisions) and 90 (FP32) of the SIPF against SIPF-PIC comparison
  *     (Sec. 5.1) are also accepted; on them the tile side is any integer
  *     with at most 16 tiles per axis (the last may be partial), and

@@ -61,8 +61,15 @@ def slope(x, y):
     return float(np.polyfit(lx, ly, 1)[0])
 
 
+def grid_bytes(H, precision="fp32"):
+    """Device bytes of one 3-D instance's grids: deposit and 3 gradient grids
+    (H^3 reals each) and 5 half spectra (B1, alpha, 3 gradient spectra)."""
+    t = 4 if precision == "fp32" else 8
+    return 4 * H ** 3 * t + 5 * H * H * (H // 2 + 1) * 2 * t
+
+
 def run_study(configs, nsim, q_ref, steps=workloads.E1_STEPS, seed=0, precision="fp32",
-              max_particles=400_000_000, log=None):
+              max_particles=400_000_000, max_grid_bytes=160e9, log=None):
     """Run nsim independent simulations for each (P, H) in configs.
 
     q_ref: reference quantiles at probabilities() (length m + 1).
@@ -79,13 +86,15 @@ def run_study(configs, nsim, q_ref, steps=workloads.E1_STEPS, seed=0, precision=
     dt = np.float32 if precision == "fp32" else np.float64
     start = 0
     while start < len(jobs):
-        # largest prefix within the particle budget and the batch size limit
-        end, total = start, 0
+        # largest prefix within the particle and grid-memory budgets and the batch size limit
+        end, total, gbytes = start, 0, 0.0
         while end < len(jobs) and end - start < 1024:
-            P = configs[jobs[end][0]][0]
-            if end > start and total + P > max_particles:
+            P, H = configs[jobs[end][0]]
+            gb = grid_bytes(H, precision)
+            if end > start and (total + P > max_particles or gbytes + gb > max_grid_bytes):
                 break
             total += P
+            gbytes += gb
             end += 1
         if log:
             log(f"sampling {end - start} initial ensembles")
@@ -202,7 +211,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     q_ref = load_reference(a.reference)
     Ps = [2 ** e for e in range(a.pmin_log2, a.pmax_log2 + 1)]
-    Hs = [h for h in (8, 16, 32, 64, 128) if a.hmin <= h <= a.hmax]
+    Hs = [h for h in (8, 16, 32, 64, 128, 256) if a.hmin <= h <= a.hmax]
     configs = [(P, a.hmax) for P in Ps] + [(Ps[-1], H) for H in Hs if H != a.hmax]
     res, secs = run_study(configs, a.nsim, q_ref, steps=a.steps, seed=a.seed,
                           log=lambda s: print(s, flush=True))

@@ -59,7 +59,7 @@ int validate(const sipf_params* p, int64_t P) {
     if (p->precision != SIPF_FP32 && p->precision != SIPF_FP64) return fail(SIPF_EINVAL, "precision must be SIPF_FP32 or SIPF_FP64");
     if (p->dim != 0 && p->dim != 2 && p->dim != 3) return fail(SIPF_EINVAL, "dim must be 0, 2 or 3");
     if (dim_of(p) == 3 && !fft_size_supported(p->H, p->precision == SIPF_FP64))
-        return fail(SIPF_EINVAL, "H must be 8, 12, 16, 22, 32, 46, 64, 90 or 128 (FP32), or one of those up to 64 (FP64)");
+        return fail(SIPF_EINVAL, "H must be 8, 12, 16, 22, 32, 46, 64, 90, 128 or 256 (FP32), or one of those up to 64 (FP64)");
     if (dim_of(p) == 2 && !fft2d_size_supported(p->H))
         return fail(SIPF_EINVAL, "H must be a power of two in [8, 4096] in two dimensions");
     auto fin = [](double v) { return std::isfinite(v); };
@@ -79,6 +79,8 @@ int validate(const sipf_params* p, int64_t P) {
         return fail(SIPF_EINVAL, "method must be SIPF_METHOD_PIC or SIPF_METHOD_DIRECT");
     if (p->method == SIPF_METHOD_DIRECT && dim_of(p) != 3)
         return fail(SIPF_EINVAL, "the direct SIPF method is three-dimensional");
+    if (p->method == SIPF_METHOD_DIRECT && p->H > 128)
+        return fail(SIPF_EINVAL, "the direct SIPF method takes H <= 128");
     if (p->positivity != 0 && p->positivity != 1) return fail(SIPF_EINVAL, "positivity must be 0 or 1");
     if (p->positivity && (dim_of(p) != 3 || p->method != SIPF_METHOD_PIC))
         return fail(SIPF_EINVAL, "the positivity-preserving deposit is for the 3-D SIPF-PIC step");
@@ -1595,6 +1597,8 @@ int sipf_adjoint(sipf_ctx* c, int64_t nsteps, int32_t ckpt_every, const void* ph
     if (c->dim != 3) return fail(SIPF_EINVAL, "sipf_adjoint is available in three dimensions only");
     if (c->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "sipf_adjoint runs SIPF-PIC contexts only");
     if (!c->pow2) return fail(SIPF_EINVAL, "sipf_adjoint needs H a power of two");
+    for (const Inst& I : c->in)
+        if (I.H > 128) return fail(SIPF_EINVAL, "sipf_adjoint takes H <= 128");
     if (c->positivity) return fail(SIPF_EINVAL, "sipf_adjoint does not differentiate the positivity rounds");
     return c->prec == SIPF_FP32
                ? adjoint_typed<float>(c, nsteps, ckpt_every, (const float*)phi_bar, loss, dchi, dmu, (float*)dX0)

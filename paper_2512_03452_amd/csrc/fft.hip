@@ -6,7 +6,8 @@
 // Transform convention (Sec. 3.1): beta_q = L^-3 sum_j phi_j e^{-2 pi i q.j/H},
 // grad c(x_j) = sum_q i xi_q Phi_q alpha_q e^{+2 pi i q.j/H}.
 //
-// Three passes over HBM per step, each staged through LDS:
+// Three passes over HBM per step, each staged through LDS (five at H = 256,
+// where a plane pass splits into a row pass and a column pass, see below):
 //   fwd_planes  one workgroup per x-plane: each real row along z is read as
 //               H/2 complex values, transformed, and split into its half
 //               spectrum (kz = 0..H/2); then the plane is transformed along y.
@@ -44,12 +45,12 @@ int fft_perm(int N, int k) {
     return (k % N1) * N2 + k / N1;
 }
 
-// 3-D grids: powers of two 8 .. 128 and the mixed-radix sizes 12, 22, 46, 90;
+// 3-D grids: powers of two 8 .. 256 and the mixed-radix sizes 12, 22, 46, 90;
 // FP64 up to 64 (the plane passes' LDS)
 bool fft_size_supported(int H, bool fp64) {
     switch (H) {
         case 8: case 12: case 16: case 22: case 32: case 46: case 64: return true;
-        case 90: case 128: return !fp64;
+        case 90: case 128: case 256: return !fp64;
         default: return false;
     }
 }
@@ -431,11 +432,184 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
 }
 
 // ---------------------------------------------------------------------------
+// Grids whose yz-plane of half spectrum does not fit in LDS (H = 256: 264 KB
+// in FP32).  Each plane pass splits in two, with one more trip through HBM:
+//   fwd_zrows  ZROWS rows along z per workgroup: the half-length real
+//              transform of fwd_planes, written to B1 with y in natural
+//              order; consumes the deposit and advances the step counter.
+//   ycols      KB kz columns of one x-plane per workgroup, transformed along
+//              y in place (forward: natural -> digit-permuted y, as
+//              fwd_planes leaves it; inverse: permuted -> natural).
+//   inv_zrows  ZROWS rows per workgroup: the half-length complex-to-real
+//              inverse of inv_planes.
+// ---------------------------------------------------------------------------
+constexpr int ZROWS = 16;
+constexpr int ROW_THREADS = 256;
+
+template <typename T, int H>
+__global__ __launch_bounds__(ROW_THREADS) void k_fwd_zrows(const FieldDesc<T>* __restrict__ fds, int consume) {
+    using V = cplx_t<T>;
+    constexpr int M = H / 2;
+    constexpr int HH = M + 1;
+    constexpr int OP = HH;
+    constexpr int NP = M / 2 + 1;
+    constexpr int PPT = (ZROWS * NP + ROW_THREADS - 1) / ROW_THREADS;
+    constexpr int NRB = H * H / ZROWS;  // row blocks per component
+    __shared__ V buf[ZROWS * OP];
+    __shared__ V tw[H];
+    __shared__ V twm[M];
+    const FieldDesc<T>& fd = fds[blockIdx.y];
+    const int comp = blockIdx.x / NRB;
+    const size_t row0 = (size_t)(blockIdx.x % NRB) * ZROWS;  // row r = x H + y
+    const int tid = threadIdx.x, nt = blockDim.x;
+    make_twiddles<T, H>(tw);
+    make_twiddles<T, M>(twm);
+    T* rows = fd.phi + ((size_t)comp * H * H + row0) * H;
+    for (int u = tid; u < ZROWS * M; u += nt) {
+        const int row = u / M, m = u % M;
+        buf[row * OP + m] = cmake<V, T>(rows[row * H + 2 * m], rows[row * H + 2 * m + 1]);
+    }
+    __syncthreads();
+    if (consume) {
+        for (int u = tid; u < ZROWS * H; u += nt) rows[u] = (T)0;
+        if (blockIdx.x == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
+    }
+    lds_fft<T, M, -1>(buf, ZROWS, OP, 1, twm);
+    __syncthreads();
+    V za[PPT], zb[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * ROW_THREADS;
+        if (u < ZROWS * NP) {
+            const int row = u / NP, k = u % NP;
+            za[q] = buf[row * OP + perm_pos<M>(k % M)];
+            zb[q] = buf[row * OP + perm_pos<M>((M - k) % M)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * ROW_THREADS;
+        if (u < ZROWS * NP) {
+            const int row = u / NP, k = u % NP;
+            const V zc = cconj(zb[q]);
+            const V e = cscale(cadd(za[q], zc), (T)0.5);
+            const V dd = csub(za[q], zc);
+            const V o = cmake<V, T>(dd.y * (T)0.5, -dd.x * (T)0.5);
+            buf[row * OP + k] = cadd(e, cmul(tw[k], o));
+            if (k != M - k) buf[row * OP + (M - k)] = cadd(cconj(e), cmul(tw[M - k], cconj(o)));
+        }
+    }
+    __syncthreads();
+    V* out = fd.B1 + ((size_t)comp * H * H + row0) * HH;
+    for (int u = tid; u < ZROWS * HH; u += nt) out[u] = buf[u];
+}
+
+template <typename T, int H, int DIR>
+__global__ __launch_bounds__(PENCIL_THREADS) void k_ycols(const FieldDesc<T>* __restrict__ fds) {
+    using V = cplx_t<T>;
+    constexpr int HH = H / 2 + 1;
+    constexpr int NKB = (HH + KB - 1) / KB;
+    constexpr int BP = KB + 1;
+    __shared__ V buf[H * BP];
+    __shared__ V tw[H];
+    const FieldDesc<T>& fd = fds[blockIdx.y];
+    const int kb = blockIdx.x % NKB, rest = blockIdx.x / NKB;
+    const int x = rest % H, comp = rest / H;
+    const int kz0 = kb * KB;
+    const int ncol = min(KB, HH - kz0);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    V* base = (DIR < 0 ? fd.B1 : fd.gspec) + ((size_t)comp * H + x) * H * HH;
+    make_twiddles<T, H>(tw);
+    for (int u = tid; u < H * KB; u += nt) {
+        const int y = u / KB, j = u % KB;
+        buf[y * BP + j] = j < ncol ? base[(size_t)y * HH + kz0 + j] : cmake<V, T>(0, 0);
+    }
+    __syncthreads();
+    lds_fft<T, H, DIR>(buf, KB, 1, BP, tw);
+    __syncthreads();
+    for (int u = tid; u < H * KB; u += nt) {
+        const int y = u / KB, j = u % KB;
+        if (j < ncol) base[(size_t)y * HH + kz0 + j] = buf[y * BP + j];
+    }
+}
+
+template <typename T, int H>
+__global__ __launch_bounds__(ROW_THREADS) void k_inv_zrows(const FieldDesc<T>* __restrict__ fds) {
+    using V = cplx_t<T>;
+    constexpr int M = H / 2;
+    constexpr int HH = M + 1;
+    constexpr int OP = HH;
+    constexpr int NP = M / 2 + 1;
+    constexpr int PPT = (ZROWS * NP + ROW_THREADS - 1) / ROW_THREADS;
+    constexpr int NRB = H * H / ZROWS;
+    __shared__ V buf[ZROWS * OP];
+    __shared__ V tw[H];
+    __shared__ V twm[M];
+    const FieldDesc<T>& fd = fds[blockIdx.y];
+    const int d = blockIdx.x / NRB;
+    const size_t row0 = (size_t)(blockIdx.x % NRB) * ZROWS;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    make_twiddles<T, H>(tw);
+    make_twiddles<T, M>(twm);
+    const V* in = fd.gspec + ((size_t)d * H * H + row0) * HH;
+    for (int u = tid; u < ZROWS * HH; u += nt) buf[u] = in[u];
+    __syncthreads();
+    V xa[PPT], xb[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * ROW_THREADS;
+        if (u < ZROWS * NP) {
+            const int row = u / NP, k = u % NP;
+            xa[q] = buf[row * OP + k];
+            xb[q] = buf[row * OP + (M - k)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int u = tid + q * ROW_THREADS;
+        if (u < ZROWS * NP) {
+            const int row = u / NP, k = u % NP;
+            const V s1 = cadd(xa[q], cconj(xb[q])), d1 = csub(xa[q], cconj(xb[q]));
+            const V t1 = cmul(cconj(tw[k]), d1);
+            buf[row * OP + perm_pos<M>(k % M)] = cmake<V, T>(s1.x - t1.y, s1.y + t1.x);
+            if (k != 0 && k != M - k) {
+                const V s2 = cadd(xb[q], cconj(xa[q])), d2 = csub(xb[q], cconj(xa[q]));
+                const V t2 = cmul(cconj(tw[M - k]), d2);
+                buf[row * OP + perm_pos<M>(M - k)] = cmake<V, T>(s2.x - t2.y, s2.y + t2.x);
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<T, M, +1>(buf, ZROWS, OP, 1, twm);
+    __syncthreads();
+    T* outp = fd.G + ((size_t)d * H * H + row0) * H;
+    for (int u = tid; u < ZROWS * M; u += nt) {
+        const int row = u / M, m = u % M;
+        const V v = buf[row * OP + m];
+        outp[row * H + 2 * m] = v.x;
+        outp[row * H + 2 * m + 1] = v.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// grids above 128 take the split passes (a plane of half spectrum does not fit in LDS)
+constexpr int MAX_PLANE_H = 128;
+
 template <typename T, int H>
 static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s) {
-    launch_kernel((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(FWD_THREADS), 0, s, fd, consume ? 1 : 0);
+    if constexpr (H > MAX_PLANE_H) {
+        static_assert((H * H) % ZROWS == 0, "row blocks");
+        constexpr int NKB = (H / 2 + 1 + KB - 1) / KB;
+        launch_kernel((k_fwd_zrows<T, H>), dim3(ncomp * H * H / ZROWS, count), dim3(ROW_THREADS), 0, s, fd,
+                      consume ? 1 : 0);
+        launch_kernel((k_ycols<T, H, -1>), dim3(ncomp * H * NKB, count), dim3(PENCIL_THREADS), 0, s, fd);
+    } else {
+        launch_kernel((k_fwd_planes<T, H>), dim3(H * ncomp, count), dim3(FWD_THREADS), 0, s, fd, consume ? 1 : 0);
+    }
     return hipGetLastError();
 }
 template <typename T, int H>
@@ -454,7 +628,13 @@ static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStr
 }
 template <typename T, int H>
 static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, int ncomp, hipStream_t s) {
-    launch_kernel((k_inv_planes<T, H>), dim3(ncomp * H, count), dim3(PLANE_THREADS), 0, s, fd, ncomp);
+    if constexpr (H > MAX_PLANE_H) {
+        constexpr int NKB = (H / 2 + 1 + KB - 1) / KB;
+        launch_kernel((k_ycols<T, H, +1>), dim3(ncomp * H * NKB, count), dim3(PENCIL_THREADS), 0, s, fd);
+        launch_kernel((k_inv_zrows<T, H>), dim3(ncomp * H * H / ZROWS, count), dim3(ROW_THREADS), 0, s, fd);
+    } else {
+        launch_kernel((k_inv_planes<T, H>), dim3(ncomp * H, count), dim3(PLANE_THREADS), 0, s, fd, ncomp);
+    }
     return hipGetLastError();
 }
 
@@ -469,6 +649,7 @@ static hipError_t inv_planes_h(const FieldDesc<T>* fd, int count, int ncomp, hip
         case 64: return FN<T, 64>(__VA_ARGS__);           \
         case 90: if constexpr (sizeof(T) == 4) return FN<T, 90>(__VA_ARGS__); else return hipErrorInvalidValue; \
         case 128: if constexpr (sizeof(T) == 4) return FN<T, 128>(__VA_ARGS__); else return hipErrorInvalidValue; \
+        case 256: if constexpr (sizeof(T) == 4) return FN<T, 256>(__VA_ARGS__); else return hipErrorInvalidValue; \
         default: return hipErrorInvalidValue;             \
     }
 

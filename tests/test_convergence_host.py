@@ -53,3 +53,11 @@ def test_ball_sampler_is_uniform_in_the_unit_ball():
     assert abs(np.mean(r ** 3) - 0.5) < 3e-3
     assert np.abs(X.mean(axis=0)).max() < 5e-3
     assert not np.array_equal(X, workloads.ball(200_000, 1.0, seed=5))
+
+
+def test_grid_bytes_counts_the_instance_grids():
+    """Four H^3 real grids and five half spectra per 3-D instance (the batch
+    memory budget of the study)."""
+    from paper_2512_03452_amd import convergence
+    assert convergence.grid_bytes(256) == 4 * 256 ** 3 * 4 + 5 * 256 * 256 * 129 * 8
+    assert convergence.grid_bytes(64, "fp64") == 2 * convergence.grid_bytes(64)

@@ -146,6 +146,7 @@ def _positions(kind, P, seed):
     ("fp32", 32, 54321, "uniform"), ("fp32", 64, 100003, "blob"), ("fp32", 64, 20000, "faces"),
     ("fp32", 128, 200001, "blob"), ("fp32", 128, 50000, "corner"), ("fp32", 32, 4097, "corner"),
     ("fp64", 32, 30001, "blob"), ("fp64", 64, 10000, "uniform"), ("fp64", 8, 5, "corner"),
+    ("fp32", 256, 300001, "blob"), ("fp32", 256, 40000, "corner"),
 ])
 def test_deposit_parity(precision, H, P, kind):
     say("deposit", precision, H, P, kind)
@@ -171,6 +172,7 @@ def _state_np(sim):
     ("fp32", 8, 333, "strang"), ("fp32", 16, 4099, "strang"), ("fp32", 32, 20001, "em"),
     ("fp32", 64, 65537, "strang"), ("fp32", 128, 100000, "strang"),
     ("fp64", 16, 2001, "strang"), ("fp64", 32, 10000, "em"), ("fp64", 64, 5000, "strang"),
+    ("fp32", 256, 200003, "strang"),
 ])
 def test_one_step_parity(precision, H, P, scheme):
     say("step", precision, H, P, scheme)

@@ -61,7 +61,7 @@ def test_defaults():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("H", 48), ("H", 4), ("H", 256), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
+    ("H", 48), ("H", 4), ("H", 512), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
     ("chi", float("inf")), ("M0", -2.0), ("L", 0.0), ("p2g_order", 2), ("g2p_order", 4),
     ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4), ("propagator", 2), ("method", 2),
     ("positivity", 2), ("positivity", -1),
@@ -126,6 +126,17 @@ def test_positivity_option_is_for_the_3d_pic_step(kw):
     lib = L.load()
     sw, r = ctypes.c_int64(), ctypes.c_int32()
     assert lib.sipf_positivity_stats(None, ctypes.byref(sw), ctypes.byref(r)) == L.SIPF_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(H=256, precision="fp64"), dict(H=256, method="direct"), dict(H=512)])
+def test_h256_limits(kw):
+    """H = 256 runs SIPF-PIC in FP32 only; the direct method stops at 128."""
+    L = _lib()
+    p = L.default_params(**kw)
+    h = ctypes.c_void_p()
+    X = np.zeros((4, 3), np.float64 if kw.get("precision") == "fp64" else np.float32)
+    rc = L.load().sipf_init(ctypes.byref(p), 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h))
+    assert rc == L.SIPF_EINVAL and h.value is None
 
 
 def test_fp64_h128_rejected():
