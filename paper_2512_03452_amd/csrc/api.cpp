@@ -161,7 +161,7 @@ struct Inst {
     int nslices = 0, mslices = 0;
     // positivity-preserving deposit: per-particle switch tags, node flags
     uint32_t* pos_sw = nullptr;
-    uint8_t* pos_flag = nullptr;
+    uint8_t* pos_flag = nullptr;  // node flags, then two H^3-byte scratch grids
 };
 
 // Instances of one grid size: FieldDesc slots [first, first + count).
@@ -459,7 +459,9 @@ template <typename T> int positivity_rounds(Group* g) {
             const Inst& I = g->in[i];
             const T thresh = (T)(rel * I.prm.M0 / (double)I.P);
             HIPCHK(launch_pos_flag<T>((const T*)I.phi, (int64_t)grid_size(I.H, I.dim), thresh, I.pos_flag, g->stream));
-            HIPCHK(launch_pos_switch<T>(pd + i, I.P, I.pos_flag, I.pos_sw, tag, g->pos_count + i, g->stream));
+            const size_t ng = grid_size(I.H, I.dim);
+            HIPCHK(launch_pos_switch<T>(pd + i, I.P, I.H, I.pos_flag, I.pos_flag + ng, I.pos_flag + 2 * ng, I.pos_sw,
+                                        tag, g->pos_count + i, g->stream));
         }
         HIPCHK(hipMemcpyAsync(cnt.data(), g->pos_count, n * sizeof(int), hipMemcpyDeviceToHost, g->stream));
         HIPCHK(hipStreamSynchronize(g->stream));
@@ -736,7 +738,7 @@ template <typename T> int alloc_group(Group* g) {
         if ((rc = dalloc(g, (void**)&g->pos_count, n * sizeof(int)))) return rc;
         for (Inst& I : g->in) {
             if ((rc = dalloc(g, (void**)&I.pos_sw, I.P * sizeof(uint32_t)))) return rc;
-            if ((rc = dalloc(g, (void**)&I.pos_flag, grid_size(I.H, I.dim)))) return rc;
+            if ((rc = dalloc(g, (void**)&I.pos_flag, 3 * grid_size(I.H, I.dim)))) return rc;  // flags, 2 scratch
             HIPCHK(hipMemset(I.pos_sw, 0, I.P * sizeof(uint32_t)));
         }
     }

@@ -176,11 +176,12 @@ hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const 
                             bool push, int scheme, int win_bytes, bool pow2, hipStream_t s);
 // positivity-preserving deposit rounds (positivity.hip): flag nodes below
 // -thresh, switch the order-4 particles touching a flagged node to order 2
-// (count += switched; sw[i] = tag marks them), clamp negatives to zero
+// (count += switched; sw[i] = tag marks them), clamp negatives to zero; tmp
+// and touch are H^3-byte scratch grids for the per-cell dilation of the flags
 template <typename T> hipError_t launch_pos_flag(const T* phi, int64_t n, T thresh, uint8_t* flag, hipStream_t s);
 template <typename T>
-hipError_t launch_pos_switch(const PartDesc<T>* pd, int64_t P, const uint8_t* flag, uint32_t* sw, uint32_t tag,
-                             int* count, hipStream_t s);
+hipError_t launch_pos_switch(const PartDesc<T>* pd, int64_t P, int H, const uint8_t* flag, uint8_t* tmp,
+                             uint8_t* touch, uint32_t* sw, uint32_t tag, int* count, hipStream_t s);
 template <typename T> hipError_t launch_pos_clamp(T* phi, int64_t n, hipStream_t s);
 // 2-D particle pass (particles2d.hip)
 template <typename T>

@@ -19,6 +19,11 @@
 // truly negative or rounding of switched particles alone, which switches
 // nobody.  The flag grid is rebuilt before each switch pass, so the decisions
 // of one round do not depend on the order of its atomics.
+//
+// A particle in cell c touches nodes in c + {-1..2}^3 only, so before each
+// switch pass the flags are dilated over that box (three separable passes of
+// four reads) into a per-cell byte; a particle whose cell byte is clear stops
+// after that one read, the others check their 32 nodes exactly.
 #include "internal.h"
 #include "pass_common.h"
 
@@ -33,18 +38,37 @@ __global__ __launch_bounds__(POS_THREADS) void k_pos_flag(const T* __restrict__ 
         flag[j] = phi[j] < -thresh ? 1 : 0;
 }
 
-template <typename T>
+// out[c] = OR over t = -1..2 of in[c + t e_axis] (periodic)
+template <bool P2>
+__global__ __launch_bounds__(POS_THREADS) void k_pos_dilate(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                            int H, int axis) {
+    const Wrap<P2> wr{H, H - 1};
+    const int n = H * H * H;  // H <= 256: fits int
+    const int stride = axis == 0 ? H * H : (axis == 1 ? H : 1);
+    for (int j = blockIdx.x * POS_THREADS + threadIdx.x; j < n; j += gridDim.x * POS_THREADS) {
+        const int c = (j / stride) % H;  // coordinate along the axis
+        const int base = j - c * stride;
+        uint8_t v = 0;
+#pragma unroll
+        for (int t = -1; t <= 2; ++t) v |= in[base + wr(c + t) * stride];
+        out[j] = v;
+    }
+}
+
+template <typename T, bool P2>
 __global__ __launch_bounds__(POS_THREADS) void k_pos_switch(const PartDesc<T>* __restrict__ pd,
-                                                            const uint8_t* __restrict__ flag, uint32_t* __restrict__ sw,
+                                                            const uint8_t* __restrict__ flag,
+                                                            const uint8_t* __restrict__ touch, uint32_t* __restrict__ sw,
                                                             uint32_t tag, int* __restrict__ count) {
     const PartDesc<T>& a = *pd;
     const int64_t i = (int64_t)blockIdx.x * POS_THREADS + threadIdx.x;
-    if (i >= a.P || sw[i] == tag) return;
+    if (i >= a.P) return;
     const int H = a.H;
-    const Wrap<false> wr{H, H - 1};
+    const Wrap<P2> wr{H, H - 1};
     const T sx = a.x[i] * a.hl, sy = a.y[i] * a.hl, sz = a.z[i] * a.hl;
     const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
     const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
+    if (!touch[((size_t)wr(gx) * H + wr(gy)) * H + wr(gz)] || sw[i] == tag) return;
     int ix[4], iy[4], iz[4];  // nodes g - 1 .. g + 2 along each axis
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -104,11 +128,24 @@ template <typename T> hipError_t launch_pos_flag(const T* phi, int64_t n, T thre
 }
 
 template <typename T>
-hipError_t launch_pos_switch(const PartDesc<T>* pd, int64_t P, const uint8_t* flag, uint32_t* sw, uint32_t tag,
-                             int* count, hipStream_t s) {
+hipError_t launch_pos_switch(const PartDesc<T>* pd, int64_t P, int H, const uint8_t* flag, uint8_t* tmp,
+                             uint8_t* touch, uint32_t* sw, uint32_t tag, int* count, hipStream_t s) {
     if (P <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pos_switch<T>), dim3((unsigned)((P + POS_THREADS - 1) / POS_THREADS)), dim3(POS_THREADS), 0,
-                       s, pd, flag, sw, tag, count);
+    const bool p2 = (H & (H - 1)) == 0;
+    const int nb = grid_blocks((int64_t)H * H * H);
+    const unsigned pb = (unsigned)((P + POS_THREADS - 1) / POS_THREADS);
+    if (p2) {
+        hipLaunchKernelGGL((k_pos_dilate<true>), dim3(nb), dim3(POS_THREADS), 0, s, flag, touch, H, 0);
+        hipLaunchKernelGGL((k_pos_dilate<true>), dim3(nb), dim3(POS_THREADS), 0, s, touch, tmp, H, 1);
+        hipLaunchKernelGGL((k_pos_dilate<true>), dim3(nb), dim3(POS_THREADS), 0, s, tmp, touch, H, 2);
+        hipLaunchKernelGGL((k_pos_switch<T, true>), dim3(pb), dim3(POS_THREADS), 0, s, pd, flag, touch, sw, tag, count);
+    } else {
+        hipLaunchKernelGGL((k_pos_dilate<false>), dim3(nb), dim3(POS_THREADS), 0, s, flag, touch, H, 0);
+        hipLaunchKernelGGL((k_pos_dilate<false>), dim3(nb), dim3(POS_THREADS), 0, s, touch, tmp, H, 1);
+        hipLaunchKernelGGL((k_pos_dilate<false>), dim3(nb), dim3(POS_THREADS), 0, s, tmp, touch, H, 2);
+        hipLaunchKernelGGL((k_pos_switch<T, false>), dim3(pb), dim3(POS_THREADS), 0, s, pd, flag, touch, sw, tag,
+                           count);
+    }
     return hipGetLastError();
 }
 
@@ -120,8 +157,8 @@ template <typename T> hipError_t launch_pos_clamp(T* phi, int64_t n, hipStream_t
 
 #define SIPF_POS_INST(T)                                                                                     \
     template hipError_t launch_pos_flag<T>(const T*, int64_t, T, uint8_t*, hipStream_t);                     \
-    template hipError_t launch_pos_switch<T>(const PartDesc<T>*, int64_t, const uint8_t*, uint32_t*, uint32_t, \
-                                             int*, hipStream_t);                                             \
+    template hipError_t launch_pos_switch<T>(const PartDesc<T>*, int64_t, int, const uint8_t*, uint8_t*,    \
+                                             uint8_t*, uint32_t*, uint32_t, int*, hipStream_t);              \
     template hipError_t launch_pos_clamp<T>(T*, int64_t, hipStream_t);
 
 SIPF_POS_INST(float)
