@@ -247,6 +247,23 @@ def positivity_section(pkg, torch, X0, params, plain_ms, steps=20):
             "switched_last_step": switched, "rounds_last_step": rounds, "P": int(X0.shape[0])}
 
 
+def scheme_section(pkg, torch, X0, params, scheme, steps=100, warmup=20):
+    """The same workload stepped with another push scheme (graph-replayed
+    sipf_run, as the headline timing)."""
+    sim = pkg.Sim(X0, **dict(params, scheme=scheme))
+    sim.run(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.close()
+    return {"scheme": scheme, "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "particle_steps_per_s": X0.shape[0] * steps / el}
+
+
 def calibrate_copy(torch, nbytes=1 << 30, reps=5):
     """A plain device copy of nbytes, reps times: the reference whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) scale those of the step's kernels."""
@@ -312,6 +329,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-positivity", action="store_true")
+    ap.add_argument("--no-other-scheme", action="store_true")
     ap.add_argument("--e1", default="reduced", choices=["none", "reduced", "full"],
                     help="convergence study of Sec. 5.1: 8 runs of 6 configurations, or the full 30 x 14")
     ap.add_argument("--e2", default="quick", choices=["none", "quick", "full"],
@@ -416,6 +434,12 @@ def main():
         print("# positivity-preserving deposit on the same workload", file=sys.stderr, flush=True)
         X0 = cfg["init"](P).astype(np.float32 if fp32 else np.float64)  # the same seeded input as the timed run
         out["positivity"] = positivity_section(pkg, torch, X0, params, ms_per_step)
+        del X0
+    if not args.no_other_scheme:
+        other = "em" if args.scheme == "strang" else "strang"
+        print(f"# the same workload with the {other} push", file=sys.stderr, flush=True)
+        X0 = cfg["init"](P).astype(np.float32 if fp32 else np.float64)
+        out["other_scheme"] = scheme_section(pkg, torch, X0, params, other)
         del X0
     if args.e1 != "none":
         print(f"# convergence study of Sec. 5.1 ({args.e1})", file=sys.stderr, flush=True)
