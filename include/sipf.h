@@ -163,7 +163,8 @@ typedef struct sipf_params {
                               or any side when H is not one                      */
     int32_t  resort_every; /* re-sort period in steps; 0 = default: 4, or fewer when
                               sqrt(2 mu tau n) exceeds a quarter of a tile      */
-    int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = tuned */
+    int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = default:
+                              4096 in 2-D and from 6.3e6 particles per 3-D group, else 2048 */
     uint64_t seed;         /* Philox key                                          */
     uint32_t instance;     /* fourth Philox counter word                          */
     uint32_t dim;          /* space dimension: 3 (0 means 3) or 2                 */

@@ -106,7 +106,7 @@ double filter_h0(const sipf_params* p) {
 
 // Defaults where the parameters leave the tuning open (0): an 8-cell tile at
 // H = 128 and H/8 below (3-D), 16-cell tiles up to H = 1024 and H/64 above
-// (2-D), a re-sort every 4 steps, items of up to 4096.  A 3-D grid that is not
+// (2-D), a re-sort every 4 steps (items: default_chunk).  A 3-D grid that is not
 // a power of two takes the same rule with ceil(H / 8) below H = 128 (the last
 // tile of an axis may be partial; the whole axis below H = 16).
 int default_tile(const sipf_params* p) {
@@ -134,7 +134,17 @@ int default_resort(const sipf_params* p) {
     const double n = std::floor(q * q / spread);
     return (int)std::max(1.0, std::min(4.0, n));
 }
-int default_chunk(const sipf_params* p) { return p->chunk ? p->chunk : 4096; }
+// Work-item size: in 3-D, 4096 when the group's particles give at least
+// about two rounds of resident workgroups of the particle pass at that size
+// (~768 on the device: P >= 1536 x 4096), else 2048.  Measured (FP32, ms per
+// step): P = 1e7 torus 0.318 / 0.334 (4096 / 2048); P = 2e6 blob 0.159 /
+// 0.142; P = 1e6 mixed 0.087 / 0.072; 1024 is slower in all three.  The 2-D
+// pass keeps 4096 (P = 2^22 disk: 0.265 / 0.272).
+int default_chunk(const sipf_params* p, int64_t total_P) {
+    if (p->chunk) return p->chunk;
+    if (dim_of(p) == 2) return 4096;
+    return total_P >= (int64_t)1536 * 4096 ? 4096 : 2048;
+}
 
 }  // namespace
 
@@ -887,7 +897,9 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
     g->stream = (hipStream_t)hip_stream;
     g->resort = default_resort(&prm[0]);
     for (int i = 1; i < n; ++i) g->resort = std::min(g->resort, default_resort(&prm[i]));
-    g->chunk = default_chunk(&prm[0]);
+    int64_t total_P = 0;
+    for (int i = 0; i < n; ++i) total_P += P[i];
+    g->chunk = default_chunk(&prm[0], total_P);
     g->win_bytes = particle_window_bytes(g->prec == SIPF_FP64);
     g->in.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -1637,7 +1649,7 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
     if (prm->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "the direct SIPF method has nothing to tune");
     sipf_params cur = *prm;
     cur.tile = default_tile(prm);
-    cur.chunk = default_chunk(prm);
+    cur.chunk = default_chunk(prm, P);
     cur.resort_every = default_resort(prm);
     double t_best = 0;
     if ((rc = time_config(&cur, P, X0, x0_on_device, nsteps, hip_stream, &t_best))) return rc;
