@@ -429,17 +429,18 @@ __device__ __forceinline__ double block_sum_n(double v, double* sh, int nthreads
 #endif
 template <typename T, int SCHEME>
 __global__ __launch_bounds__(APT) ADJ_ATTR void k_adj_items(AdjDesc<T> a, const WorkItem* __restrict__ items,
-                                                   const int* __restrict__ nitems, int lds_bytes) {
+                                                   int* hdr, int lds_bytes) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int sh[8];
+    __shared__ int slot;
     __shared__ double shd[APT / 64];
-    const int n = *nitems;
+    const int n = hdr[0];
     double chib = 0, sb = 0;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = blockIdx.x; it < n; it = next_item(hdr, n, &slot)) {
         const WorkItem w = items[it];
         adj_item<T, SCHEME>(a, w.beg, w.cnt, lds, lds_bytes, sh, chib, sb);
-        __syncthreads();
     }
+    __syncthreads();
     const double tc = block_sum_n(chib, shd, APT);
     const double ts = block_sum_n(sb, shd, APT);
     if (threadIdx.x == 0) {
@@ -510,7 +511,7 @@ template <typename T> hipError_t launch_adj_seed(const AdjDesc<T>& a, hipStream_
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, const int* nitems, int grid, hipStream_t s) {
+hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, int* nitems, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     if (particle_chunk() > ACH) return hipErrorInvalidValue;  // a work item must fit one workgroup
     const int lds = adj_window_bytes(sizeof(T) == 8);
@@ -561,7 +562,7 @@ hipError_t launch_zero_f64(double* p, int n, hipStream_t s) {
 
 #define SIPF_ADJ_INST(T)                                                                \
     template hipError_t launch_adj_seed<T>(const AdjDesc<T>&, hipStream_t);            \
-    template hipError_t launch_adj_items<T>(const AdjDesc<T>&, const WorkItem*, const int*, int, hipStream_t); \
+    template hipError_t launch_adj_items<T>(const AdjDesc<T>&, const WorkItem*, int*, int, hipStream_t); \
     template hipError_t launch_copy_positions<T>(T*, T*, T*, uint32_t*, const T*, const T*, const T*,          \
                                                  const uint32_t*, int64_t, hipStream_t);                       \
     template hipError_t launch_xbar_order<T>(T*, T*, T*, T*, const uint32_t*, int64_t, bool, hipStream_t);     \

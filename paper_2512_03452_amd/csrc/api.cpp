@@ -212,7 +212,7 @@ struct Group {
     int* seg_off = nullptr;
     int* seg_n = nullptr;
     WorkItem* items = nullptr;  // concatenated work items of the particle pass
-    int* nitems = nullptr;
+    int* nitems = nullptr;  // [0] item count, [1] ticket counter of the persistent passes (zero between launches)
     int items_cap = 0;
     std::vector<void*> allocs;
     void* diag = nullptr;  // diagnostics scratch, allocated on first use

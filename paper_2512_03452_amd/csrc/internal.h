@@ -170,9 +170,11 @@ bool fft2d_size_supported(int H);
 int fft_perm(int N, int k);
 
 // --- particle pass (particles.hip) -------------------------------------------
+// nitems: the item list's header, [0] the count the sort writes and [1] the
+// ticket counter of the persistent passes (next_item in pass_common.h).
 template <typename T>
 // pow2: every instance's H is a power of two (index wraps by mask; else by remainder)
-hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
                             bool push, int scheme, int win_bytes, bool pow2, hipStream_t s);
 // positivity-preserving deposit rounds (positivity.hip): flag nodes below
 // -thresh, switch the order-4 particles touching a flagged node to order 2
@@ -185,7 +187,7 @@ hipError_t launch_pos_switch(const PartDesc<T>* pd, int64_t P, int H, const uint
 template <typename T> hipError_t launch_pos_clamp(T* phi, int64_t n, hipStream_t s);
 // 2-D particle pass (particles2d.hip)
 template <typename T>
-hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
                              bool push, int scheme, int win_bytes, hipStream_t s);
 template <typename T> int particle_resident_blocks2(int scheme, int win_bytes);
 template <typename T>
@@ -204,7 +206,7 @@ hipError_t launch_load_positions(const T* xyz, int64_t P, T L, PartDesc<T> pd_ho
 template <typename T> hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T> hipError_t launch_adj_seed(const AdjDesc<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, const int* nitems, int grid, hipStream_t s);
+hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, int* nitems, int grid, hipStream_t s);
 template <typename T>
 hipError_t launch_copy_positions(T* x, T* y, T* z, uint32_t* id, const T* sx, const T* sy, const T* sz,
                                  const uint32_t* sid, int64_t P, hipStream_t s);

@@ -564,18 +564,17 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
     }
 }
 
-// Persistent over the work items listed by the last sort (count in *nitems).
+// Persistent over the work items listed by the last sort (header: next_item).
 template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
 __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<T>* __restrict__ pds,
-                                                  const WorkItem* __restrict__ items, const int* __restrict__ nitems,
-                                                  int win_bytes) {
+                                                  const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[8];
-    const int n = *nitems;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    __shared__ int slot;
+    const int n = hdr[0];
+    for (int it = blockIdx.x; it < n; it = next_item(hdr, n, &slot)) {
         const WorkItem w = items[it];
         item_pass<T, DEP, PUSH, SCHEME, P2>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
-        __syncthreads();
     }
 }
 
@@ -600,7 +599,7 @@ template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
 }
 
 template <typename T, bool P2>
-static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, dim3 g, bool deposit,
+static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, int* nitems, dim3 g, bool deposit,
                          bool push, int scheme, int win_bytes, hipStream_t s) {
     const dim3 b(PT);
     const size_t shm = (size_t)win_bytes;
@@ -620,7 +619,7 @@ static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, const int
 }
 
 template <typename T>
-hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
                             bool push, int scheme, int win_bytes, bool pow2, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     if (pow2) particles_p2<T, true>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, s);
@@ -919,7 +918,7 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 
 #define SIPF_INST(T)                                                                                              \
     template int particle_resident_blocks<T>(int, int);                                                           \
-    template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, const int*, int, bool, bool, int, \
+    template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, int*, int, bool, bool, int, \
                                             int, bool, hipStream_t);                                              \
     template hipError_t launch_sort<T>(int, const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,   \
                                        uint32_t*, uint32_t*, WorkItem*, const int*, int*, WorkItem*, int*, int,    \

@@ -251,18 +251,17 @@ __device__ __forceinline__ void item_pass2(const PartDesc<T>& a, int64_t beg, in
     }
 }
 
-// Persistent over the work items listed by the last sort (count in *nitems).
+// Persistent over the work items listed by the last sort (header: next_item).
 template <typename T, bool DEP, bool PUSH, int SCHEME>
 __global__ __launch_bounds__(PT2) void k_particles2(const PartDesc<T>* __restrict__ pds,
-                                                    const WorkItem* __restrict__ items,
-                                                    const int* __restrict__ nitems, int win_bytes) {
+                                                    const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw2[];
     __shared__ int sh[4];
-    const int n = *nitems;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    __shared__ int slot;
+    const int n = hdr[0];
+    for (int it = blockIdx.x; it < n; it = next_item(hdr, n, &slot)) {
         const WorkItem w = items[it];
         item_pass2<T, DEP, PUSH, SCHEME>(pds[w.inst], w.beg, w.cnt, smem_raw2, win_bytes, sh);
-        __syncthreads();
     }
 }
 
@@ -283,7 +282,7 @@ template <typename T> int particle_resident_blocks2(int scheme, int win_bytes) {
 }
 
 template <typename T>
-hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, const int* nitems, int grid, bool deposit,
+hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
                              bool push, int scheme, int win_bytes, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     const size_t shm = (size_t)win_bytes;
@@ -306,9 +305,9 @@ hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, const
 
 template int particle_resident_blocks2<float>(int, int);
 template int particle_resident_blocks2<double>(int, int);
-template hipError_t launch_particles2<float>(const PartDesc<float>*, const WorkItem*, const int*, int, bool, bool, int,
+template hipError_t launch_particles2<float>(const PartDesc<float>*, const WorkItem*, int*, int, bool, bool, int,
                                              int, hipStream_t);
-template hipError_t launch_particles2<double>(const PartDesc<double>*, const WorkItem*, const int*, int, bool, bool,
+template hipError_t launch_particles2<double>(const PartDesc<double>*, const WorkItem*, int*, int, bool, bool,
                                               int, int, hipStream_t);
 
 }  // namespace sipf

@@ -126,4 +126,27 @@ __device__ __forceinline__ void axis_window(int r, int lo, int hi, const Wrap<P2
     }
 }
 
+// Work queue of the persistent item passes.  The item list's header holds the
+// item count n (hdr[0], written by the sort) and a ticket counter (hdr[1],
+// zero between launches).  Workgroup b takes item b first; with more items
+// than workgroups it then draws tickets t for item grid + t, in list order,
+// until a draw is past the end, so items of uneven cost spread over the
+// workgroups that free up first.  Each workgroup's last draw is that failing
+// one, hence a launch draws exactly n tickets and the draw that returns n - 1
+// is its last: it puts the counter back to zero.  Launches that share a
+// header must not overlap (they run on one stream).  Call with the whole
+// workgroup after an item; returns the next item (>= n: none).
+__device__ __forceinline__ int next_item(int* hdr, int n, int* slot) {
+    const int grid = (int)gridDim.x;
+    if (n <= grid) return n;
+    __syncthreads();  // the item's use of LDS has ended
+    if (threadIdx.x == 0) {
+        const int t = atomicAdd(hdr + 1, 1);
+        if (t == n - 1) atomicExch(hdr + 1, 0);
+        *slot = grid + t;
+    }
+    __syncthreads();
+    return *slot;
+}
+
 }  // namespace sipf
