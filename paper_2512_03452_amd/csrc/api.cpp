@@ -134,17 +134,22 @@ int default_resort(const sipf_params* p) {
     const double n = std::floor(q * q / spread);
     return (int)std::max(1.0, std::min(4.0, n));
 }
-// Work-item size: in 3-D, 4096 when the group's particles give at least
-// about two rounds of resident workgroups of the particle pass at that size
-// (~768 on the device: P >= 1536 x 4096), else 2048.  Measured (FP32, ms per
-// step): P = 1e7 torus 0.318 / 0.334 (4096 / 2048); P = 2e6 blob 0.159 /
-// 0.142; P = 1e6 mixed 0.087 / 0.072; 1024 is slower in all three.  The 2-D
-// pass keeps 4096 (P = 2^22 disk: 0.265 / 0.272).
+// Work-item size: in 3-D, 3072, and 4096 from 2^23 particles per group; 2-D
+// keeps 4096.  The particle pass draws items from a ticket queue, so the size
+// trades per-item set-up (windows, barriers) against balance.  Measured
+// (FP32, ms per step, items of 4096 / 3072 / 2048): torus P = 1e7 0.289 /
+// 0.292 / 0.315; torus P = 6.5e6 0.224 / 0.215 / 0.231; blob P = 2e6 0.130 /
+// 0.119 / 0.132; mixed P = 1e6 0.087 / 0.070 / 0.072; 64-instance ensemble
+// 0.687 / 0.688 / 0.711.  2-D: P = 2^22 disk 0.265 / 0.272 (4096 / 2048).
 int default_chunk(const sipf_params* p, int64_t total_P) {
     if (p->chunk) return p->chunk;
     if (dim_of(p) == 2) return 4096;
-    return total_P >= (int64_t)1536 * 4096 ? 4096 : 2048;
+    return total_P >= (int64_t(1) << 23) ? 4096 : 3072;
 }
+// Work-item size of the adjoint's per-segment sorts: its reverse item pass
+// holds one 512-thread workgroup per CU and prefers smaller items (adjoint
+// workload, P = 2e6: reverse sweep ~0.75 ms shorter at 2048 than at 3072).
+int default_adj_chunk(const sipf_params* p, int chunk) { return p->chunk ? p->chunk : std::min(chunk, 2048); }
 
 }  // namespace
 
@@ -193,7 +198,7 @@ struct Group {
     int scheme = SIPF_STRANG;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
-    int resort = 4, chunk = 4096, win_bytes = 65536, pgrid = 1024;
+    int resort = 4, chunk = 4096, adj_chunk = 2048, win_bytes = 65536, pgrid = 1024;
     int since_sort = 0;
     int cur = 0;  // which of the two particle buffer sets holds the current positions
     int64_t n_host = 0;
@@ -720,7 +725,8 @@ template <typename T> int alloc_group(Group* g) {
         for (int64_t b = 0; b < P; b += sc) chunks.push_back(SortChunk{b, i, 0});
         const int nt = (I.H + I.tile - 1) / I.tile;  // tiles per axis, the last may be partial
         seg_off[i] = (int)cap;
-        cap += (P + g->chunk - 1) / g->chunk + (d == 2 ? (int64_t)nt * nt : (int64_t)nt * nt * nt);
+        const int64_t ch = std::min(g->chunk, g->adj_chunk);  // the smaller item size gives more items
+        cap += (P + ch - 1) / ch + (d == 2 ? (int64_t)nt * nt : (int64_t)nt * nt * nt);
     }
     if (cap >= (int64_t(1) << 31) || chunks.size() >= (size_t(1) << 31))
         return fail(SIPF_EINVAL, "too many particles in one group");
@@ -900,6 +906,7 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
     int64_t total_P = 0;
     for (int i = 0; i < n; ++i) total_P += P[i];
     g->chunk = default_chunk(&prm[0], total_P);
+    g->adj_chunk = default_adj_chunk(&prm[0], g->chunk);
     g->win_bytes = particle_window_bytes(g->prec == SIPF_FP64);
     g->in.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -1321,7 +1328,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         const int64_t base = sgi * K;
         const int len = (int)std::min<int64_t>(K, N - base);
         HIPCHK(launch_sort<T>(3, ps_dev + sgi, ps_dev + nseg, c->chunks, c->nchunks, 1, c->counts, c->cursor, c->seg,
-                              c->seg_off, c->seg_n, c->items, c->nitems, c->chunk, c->stream));
+                              c->seg_off, c->seg_n, c->items, c->nitems, c->adj_chunk, c->stream));
         if ((rc = grad_of_tape(base))) return rc;
         for (int m = 1; m < len; ++m) {
             // X^(base+m) = push of X^(base+m-1) (slot m-1 -> slot m) with G^(base+m-1)
@@ -1681,7 +1688,7 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
             if (t <= prm->H && (prm->H + t - 1) / t <= 16) tiles.push_back(t);
     }
     if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
-    if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 4096}))) return rc;
+    if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 3072, 4096}))) return rc;
     if ((rc = try_axis(&sipf_params::resort_every, {2, 4, 8, 16}))) return rc;
     *best = cur;
     *ms_per_step = t_best;
