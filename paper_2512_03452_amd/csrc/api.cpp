@@ -1323,6 +1323,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     HIPCHK(launch_fill<T>((T*)abar.p, (int64_t)(2 * nspec), (T)0, c->stream));
 
     // ---- reverse sweep, one checkpoint segment at a time
+    HIPCHK(launch_fill<T>((T*)Gbar.p, (int64_t)(3 * H3), (T)0, c->stream));
     const PartDesc<T>* ps_dev = (const PartDesc<T>*)pdS.p;
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
         const int64_t base = sgi * K;
@@ -1350,8 +1351,8 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
                 HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdS.p, 1, XP_ADJ_SRC, c->stream));
                 HIPCHK(launch_inv_planes<T>(H, (const FieldDesc<T>*)fdS.p, 1, 1, c->stream));
             }
-            // (b) particles of X^(n-1) with G^(n-1)
-            HIPCHK(launch_fill<T>((T*)Gbar.p, (int64_t)(3 * H3), (T)0, c->stream));
+            // (b) particles of X^(n-1) with G^(n-1) (Gbar is zero: cleared once before the
+            // sweep, then by the forward plane pass that consumes it)
             T *x, *y, *z;
             uint32_t* id;
             slot(seg.p, n - 1 - base, x, y, z, id);
@@ -1364,7 +1365,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
             ad.n = (uint32_t)n;
             HIPCHK(launch_adj_items<T>(ad, c->items, c->nitems, c->pgrid, c->stream));
             // (c) abar^(n-1) = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d)
-            HIPCHK(launch_fwd_planes<T>(H, (const FieldDesc<T>*)fdA.p, 1, 3, false, c->stream));
+            HIPCHK(launch_fwd_planes<T>(H, (const FieldDesc<T>*)fdA.p, 1, 3, true, c->stream));
             HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdA.p, 1, XP_ADJ_ACC, c->stream));
         }
         {
