@@ -161,8 +161,8 @@ typedef struct sipf_params {
     int32_t  tile;         /* binning tile side in cells; 0 = tuned default; at most
                               16 (3-D) or 64 (2-D) tiles per axis; a power of two,
                               or any side when H is not one                      */
-    int32_t  resort_every; /* re-sort period in steps; 0 = default: 4, or fewer when
-                              sqrt(2 mu tau n) exceeds a quarter of a tile      */
+    int32_t  resort_every; /* re-sort period in steps; 0 = default: 6 in 3-D, 4 in 2-D,
+                              or fewer when sqrt(2 mu tau n) exceeds a quarter of a tile */
     int32_t  chunk;        /* max particles per work item of the particle pass (256..4096); 0 = default:
                               4096 in 2-D and from 2^23 particles per 3-D group, else 3072;
                               the adjoint's reverse pass then uses items of at most 2048 */
@@ -331,7 +331,7 @@ const char* sipf_last_error(void);
  * meaning as in sipf_init), searching one axis at a time: the binning tile
  * (powers of two from 4 to 32, or 4, 6, 8, 12, 16, 24, 32 when H is not a
  * power of two, within the limits of sipf_params.tile), the
- * work-item size (1024, 2048, 3072, 4096) and the re-sort period (2, 4, 8, 16),
+ * work-item size (1024, 2048, 3072, 4096) and the re-sort period (2, 4, 6, 8, 16),
  * starting from the defaults.  *best receives prm with tile, chunk and
  * resort_every set to the fastest combination found, *ms_per_step its time.
  * Every trial context is destroyed before return; each needs the memory of

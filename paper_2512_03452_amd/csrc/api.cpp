@@ -123,16 +123,20 @@ int default_tile(const sipf_params* p) {
     if (p->H / t > 16) t = p->H / 16;
     return t;
 }
-// Re-sort period: every 4 steps, or more often when the Brownian spread over
-// the period, sqrt(2 mu tau n), would exceed a quarter of a tile (item boxes
-// then outgrow their LDS windows and the pass falls back to global atomics).
+// Re-sort period: every 6 steps in 3-D (4 in 2-D), or more often when the
+// Brownian spread over the period, sqrt(2 mu tau n), would exceed a quarter of
+// a tile (item boxes then outgrow their LDS windows and the pass falls back to
+// global atomics).  3-D, FP32 ms per step at periods 4 / 6 / 8: torus P = 1e7
+// 0.283 / 0.277 / 0.302 (the collapsing ring's drift outgrows the windows at
+// 8); blob P = 2e6 0.138 / 0.124 / 0.115; mixed P = 1e6 0.069 / 0.067 / 0.067.
 int default_resort(const sipf_params* p) {
     if (p->resort_every) return p->resort_every;
+    const double cap = dim_of(p) == 2 ? 4.0 : 6.0;
     const double q = default_tile(p) * p->L / p->H / 4.0;
     const double spread = 2.0 * p->mu * p->dt;
-    if (spread <= 0) return 4;
+    if (spread <= 0) return (int)cap;
     const double n = std::floor(q * q / spread);
-    return (int)std::max(1.0, std::min(4.0, n));
+    return (int)std::max(1.0, std::min(cap, n));
 }
 // Work-item size: in 3-D, 3072, and 4096 from 2^23 particles per group; 2-D
 // keeps 4096.  The particle pass draws items from a ticket queue, so the size
@@ -1690,7 +1694,7 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
     }
     if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
     if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 3072, 4096}))) return rc;
-    if ((rc = try_axis(&sipf_params::resort_every, {2, 4, 8, 16}))) return rc;
+    if ((rc = try_axis(&sipf_params::resort_every, {2, 4, 6, 8, 16}))) return rc;
     *best = cur;
     *ms_per_step = t_best;
     return SIPF_OK;

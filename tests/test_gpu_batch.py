@@ -216,7 +216,7 @@ def test_autotune_picks_valid_settings_that_keep_results():
     assert ms > 0
     assert tuned["tile"] in (4, 8, 16, 32) and 32 // tuned["tile"] <= 16
     assert tuned["chunk"] in (1024, 2048, 3072, 4096)
-    assert tuned["resort_every"] in (2, 4, 8, 16)
+    assert tuned["resort_every"] in (2, 4, 6, 8, 16)
     a = pkg.Sim(X0, **kw)
     t = pkg.Sim(X0, **kw, **tuned)
     a.run(10)
