@@ -121,7 +121,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------------------
 // Reverse particle pass over the work items of a tile sort (one item = up to
-// ACH particles of one tile, consecutive in the segment's order).  Per item,
+// AdjShape<T>::PT x PPT particles of one tile, consecutive in the segment's order).  Per item,
 // the cells of X bound a window of the grid that covers the trilinear stencil
 // at Y = X + W^- (margin gmargin):
 //   G window     the gradient grids, staged once from HBM (gather of v, J);
@@ -133,13 +133,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // deposit at X gathers the deposit cotangent from a third window (order-4
 // stencil around the cells of X).
 // ---------------------------------------------------------------------------
-constexpr int APT = 512;  // threads per workgroup
+// Launch shape per precision: threads per workgroup and particles per thread
+// (an item holds up to PT x PPT particles).  The pass needs ~166 VGPRs: one
+// 768-thread workgroup is three waves per SIMD (measured FP32 forward +
+// adjoint 37.6 against 38.7 ms with 512 threads); FP64 at 768 threads would
+// spill, so it keeps 512 (two waves per SIMD).
+template <typename T> struct AdjShape;
+template <> struct AdjShape<float> { static constexpr int PT = 768, PPT = 6; };
+template <> struct AdjShape<double> { static constexpr int PT = 512, PPT = 8; };
 #ifndef ADJ_UNROLL
 #define ADJ_UNROLL 1
 #endif
-
-constexpr int APPT = 8;   // particles per thread
-constexpr int ACH = APT * APPT;
 
 // Gbar accumulator: a term t (already scaled by 2^S) is added as round(t); S is
 // chosen per item so that every node sum stays below 2^E in magnitude.
@@ -164,6 +168,7 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
                                          int* sh, double& chib, double& sb) {
     using I = typename AdjFixed<T>::I;
     using U = typename AdjFixed<T>::U;
+    constexpr int APT = AdjShape<T>::PT, APPT = AdjShape<T>::PPT;
     const int tid = threadIdx.x;
     const int H = a.H, Hm = H - 1, Hh = H / 2;
     const T hl = a.hl;
@@ -428,8 +433,10 @@ __device__ __forceinline__ double block_sum_n(double v, double* sh, int nthreads
 #define ADJ_ATTR
 #endif
 template <typename T, int SCHEME>
-__global__ __launch_bounds__(APT) ADJ_ATTR void k_adj_items(AdjDesc<T> a, const WorkItem* __restrict__ items,
-                                                   int* hdr, int lds_bytes) {
+__global__ __launch_bounds__(AdjShape<T>::PT) ADJ_ATTR void k_adj_items(AdjDesc<T> a,
+                                                                      const WorkItem* __restrict__ items, int* hdr,
+                                                                      int lds_bytes) {
+    constexpr int APT = AdjShape<T>::PT;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int sh[8];
     __shared__ int slot;
@@ -513,7 +520,8 @@ template <typename T> hipError_t launch_adj_seed(const AdjDesc<T>& a, hipStream_
 template <typename T>
 hipError_t launch_adj_items(const AdjDesc<T>& a, const WorkItem* items, int* nitems, int grid, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
-    if (particle_chunk() > ACH) return hipErrorInvalidValue;  // a work item must fit one workgroup
+    constexpr int APT = AdjShape<T>::PT;
+    if (particle_chunk() > APT * AdjShape<T>::PPT) return hipErrorInvalidValue;  // an item must fit one workgroup
     const int lds = adj_window_bytes(sizeof(T) == 8);
     if (a.scheme == SIPF_STRANG) {
         (void)hipFuncSetAttribute((const void*)k_adj_items<T, SIPF_STRANG>,
