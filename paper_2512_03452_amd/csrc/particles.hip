@@ -676,7 +676,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* p
 // One workgroup per instance: exclusive scan of the tile counts into the
 // cursors (tile starts) and the instance's work items (each non-empty tile
 // split into ceil(count / chunk) contiguous items of near-equal size) into
-// its segment of `seg`.  Clears the counts for the next sort.
+// its segment of `seg`.  Items of at least chunk / 2 particles come first and
+// the single items of sparser tiles last, so that the persistent passes, which
+// draw items in list order, end on the small ones.  Clears the counts for the
+// next sort.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restrict__ pds, uint32_t* counts,
                                                     uint32_t* cursor, WorkItem* seg, const int* __restrict__ seg_off,
@@ -689,19 +692,22 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
     WorkItem* items = seg + seg_off[inst];
     const int tid = threadIdx.x;
     constexpr int PER = MAX_KEYS / 1024;  // keys per thread, consecutive in key order
+    const uint32_t half = ((uint32_t)chunk + 1u) / 2u;
     uint32_t loc[PER], nit[PER];
-    uint32_t sum = 0, isum = 0;
+    uint32_t sum = 0, ibig = 0, ismall = 0;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int i = tid * PER + j;
         loc[j] = i < nk ? cnt[i] : 0u;
         nit[j] = (loc[j] + chunk - 1) / chunk;
         sum += loc[j];
-        isum += nit[j];
+        if (loc[j] >= half) ibig += nit[j];
+        else if (loc[j] > 0) ismall += 1u;
     }
-    uint32_t total, itotal;
+    uint32_t total, tbig, tsmall;
     uint32_t run = block_exclusive_scan(sum, part, total);
-    uint32_t irun = block_exclusive_scan(isum, part, itotal);
+    uint32_t rbig = block_exclusive_scan(ibig, part, tbig);
+    uint32_t rsmall = tbig + block_exclusive_scan(ismall, part, tsmall);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int i = tid * PER + j;
@@ -711,6 +717,8 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
             if (nit[j] > 0) {
                 // nit items: the first rem of base + 1 particles, the rest of base
                 const uint32_t base = loc[j] / nit[j], rem = loc[j] - base * nit[j];
+                const bool big = loc[j] >= half;
+                const uint32_t at = big ? rbig : rsmall;
                 uint32_t b = run;
                 for (uint32_t k = 0; k < nit[j]; ++k) {
                     const uint32_t c = base + (k < rem ? 1u : 0u);
@@ -718,15 +726,16 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
                     w.beg = (int64_t)b;
                     w.cnt = (int32_t)c;
                     w.inst = inst;
-                    items[irun + k] = w;
+                    items[at + k] = w;
                     b += c;
                 }
+                if (big) rbig += nit[j];
+                else rsmall += 1u;
             }
         }
         run += loc[j];
-        irun += nit[j];
     }
-    if (tid == 0) seg_n[inst] = (int)itotal;
+    if (tid == 0) seg_n[inst] = (int)(tbig + tsmall);
 }
 
 // Concatenate the instances' item segments into one list (one workgroup).
