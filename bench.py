@@ -24,20 +24,44 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(phase, P, H, tsize):
-    """Bytes each pass must move (every array read or written once)."""
-    spec = 2 * tsize * H * H * (H // 2 + 1)   # one half spectrum
+    """Bytes the method itself must move per launch of a pass (every array of
+    the step read or written once; the byte model of the step, Sec. 3.2's
+    O(P + H^3 log H) count): 24 P + 40 H^3 per FP32 step in all.  Particle
+    ids, the re-sort and the intermediate spectra of the transforms are
+    implementation overhead and are not counted here."""
     grid = tsize * H ** 3
     if phase == "particles":
-        # X read + write, particle id read (noise counter), deposit out, gradient in
+        return 6 * tsize * P + grid + 3 * grid     # X read + write, deposit out, 3 gradient grids in
+    if phase == "fwd_planes":
+        return grid                                # deposit in
+    if phase == "xpencils":
+        return 2 * 2 * tsize * H * H * (H // 2 + 1)  # alpha read + write (half spectrum)
+    if phase == "inv_planes":
+        return 3 * grid                            # 3 gradient grids out
+    return 0                                       # the re-sort moves no algorithmic bytes
+
+
+def step_algorithmic_bytes(P, H, tsize):
+    """24 P + 40 H^3 (FP32): X read + write, deposit write + read, alpha
+    read + write, three gradient grids write + read."""
+    return 6 * tsize * P + 2 * tsize * H ** 3 + 2 * 2 * tsize * H * H * (H // 2 + 1) + 6 * tsize * H ** 3
+
+
+def implementation_bytes(phase, P, H, tsize):
+    """Bytes each pass of this implementation touches at least once: the
+    algorithmic bytes plus ids (the noise counter), the half spectra passed
+    between the transform passes, and the re-sort's reads and writes."""
+    spec = 2 * tsize * H * H * (H // 2 + 1)
+    grid = tsize * H ** 3
+    if phase == "particles":
         return 6 * tsize * P + 4 * P + grid + 3 * grid
     if phase == "fwd_planes":
-        return grid + spec                         # deposit in, y/z-transformed spectrum out
+        return grid + spec
     if phase == "xpencils":
-        return spec + 2 * spec + 3 * spec          # spectrum in, alpha r/w, 3 gradient spectra out
+        return spec + 2 * spec + 3 * spec
     if phase == "inv_planes":
-        return 3 * spec + 3 * grid                 # 3 spectra in, 3 gradient grids out
+        return 3 * spec + 3 * grid
     if phase == "sort":
-        # histogram reads X; scatter reads X and id and writes both to the other set
         return 3 * tsize * P + 2 * (3 * tsize + 4) * P
     return 0
 
@@ -67,27 +91,70 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def cpu_baseline(cfg, sample_P, steps):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_worker(args):
+    """One oracle run on its own sample: an untimed first step, then `steps`
+    timed steps (started together with the other workers)."""
+    workload, sample_P, steps, seed, barrier = args
     import numpy as np
     from oracle import sipf as osipf
+    from paper_2512_03452_amd import workloads
+    cfg = workloads.CONFIGS[workload]
     prm = dict(cfg["params"])
     prm.pop("precision", None)
     p = osipf.Params(**prm)
-    X = cfg["init"](sample_P, seed=1)
-    H = p.H
-    alpha = np.zeros((H, H, H), dtype=np.complex128)
+    X = cfg["init"](sample_P, seed=seed)
+    alpha = np.zeros((p.H, p.H, p.H), dtype=np.complex128)
     ids = np.arange(sample_P, dtype=np.uint64)
-    X, alpha = osipf.step(X, alpha, 1, p, ids)  # untimed first step (imports, page-in)
-    c0, t0 = time.process_time(), time.perf_counter()
+    X, alpha = osipf.step(X, alpha, 1, p, ids)
+    if barrier is not None:
+        barrier.wait()
+    t0 = time.perf_counter()
     for n in range(2, 2 + steps):
         X, alpha = osipf.step(X, alpha, n, p, ids)
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    return dict(value=sample_P * steps / wall, unit="particle-steps/s",
-                cores=max(1, int(round(cpu / wall))), kind="oracle",
-                sample=f"{sample_P} particles of the same workload, H={H}, {steps} steps after 1 untimed step; "
-                       f"{wall:.1f} s wall")
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(workload, H, sample_P, steps, workers):
+    """The FP64 oracle on the host: `workers` concurrent processes (the host's
+    cores), each stepping its own sample of sample_P particles of the same
+    workload on the full grid, and one process alone.  numpy's FFT and
+    bincount in the oracle are single-threaded, so one process uses one core."""
+    import multiprocessing as mp
+    nproc = os.cpu_count()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    ctx = mp.get_context("spawn")
+    one = _oracle_worker((workload, sample_P, steps, 1, None))
+    out = {"unit": "particle-steps/s", "kind": "oracle", "cpu_model": _cpu_model(), "nproc": nproc,
+           "cores_available": avail,
+           "one_core": {"value": sample_P * steps / one, "cores": 1, "wall_s": one}}
+    if workers > 1:
+        with ctx.Manager() as man:
+            bar = man.Barrier(workers)
+            with ctx.Pool(workers) as pool:
+                walls = pool.map(_oracle_worker, [(workload, sample_P, steps, 1 + w, bar) for w in range(workers)])
+        wall = max(walls)
+        out.update(value=workers * sample_P * steps / wall, cores=workers, wall_s=wall)
+    else:
+        out.update(value=sample_P * steps / one, cores=1, wall_s=one)
+    out["sample"] = (f"{out['cores']} concurrent oracle processes, each {sample_P} particles of the {workload} "
+                     f"workload on the H={H} grid (own seed), {steps} timed steps after 1 untimed step; "
+                     f"one_core: one process alone on the same sample")
+    return out
 
 
 def adjoint_ratio(pkg, workloads, np, torch):
@@ -325,6 +392,10 @@ def main():
     ap.add_argument("--scheme", default="strang", choices=["strang", "em"])
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="concurrent oracle processes (default: the usable host cores, at most 16)")
+    ap.add_argument("--steady-steps", type=int, default=0,
+                    help="steps of the steady-state reference run after the timed one (default: 4 graph periods)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
@@ -343,6 +414,14 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design note, not an implemented path.", file=sys.stderr)
         sys.exit(2)
+
+    if args.steady_steps <= 0:
+        args.steady_steps = 96
+    if args.cpu_workers <= 0:
+        try:
+            args.cpu_workers = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            args.cpu_workers = min(16, os.cpu_count() or 1)
 
     import numpy as np
     import torch
@@ -367,6 +446,9 @@ def main():
     del X0
 
     sim.run(args.warmup)
+    # capture the HIP graphs the timed run replays (runs no step), so that the
+    # timed window holds graph replays only
+    sim.prepare_run(args.steps)
     sim.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -375,6 +457,13 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"# timed {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    # steady state for reference: whole graph periods after the timed run
+    sim.prepare_run(args.steady_steps)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.run(args.steady_steps)
+    sim.sync()
+    steady = time.perf_counter() - t0
 
     # per-kernel durations with HIP events on the library's stream, same steps again
     sim.profile(True)
@@ -392,7 +481,10 @@ def main():
           file=sys.stderr, flush=True)
 
     ms_per_step = 1e3 * elapsed / args.steps
-    step_bytes = sum(algorithmic_bytes(k, P, H, tsize) * v["launches"] / args.steps for k, v in phases.items())
+    step_bytes = step_algorithmic_bytes(P, H, tsize)
+    impl_step_bytes = sum(implementation_bytes(k, P, H, tsize) * v["launches"] / args.steps
+                          for k, v in phases.items())
+    traffic = measured_traffic(dom, args.workload)
     out = {
         "metric": METRIC,
         "value": P * args.steps / elapsed,
@@ -409,17 +501,27 @@ def main():
         "config": {"workload": args.workload, "P": P, "H": H, "scheme": args.scheme,
                    "dt": params["dt"], "M0": params["M0"], "init": "torus R=0.5 sd=0.05"
                    if "ring" in args.workload else args.workload},
+        # dominant kernel: algorithmic bytes per launch (24 P + 16 H^3 for the
+        # particle pass) over its average launch time (HIP events on the
+        # library's stream); traffic = counter-measured HBM bytes per launch
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.workload),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_over_algorithmic": (traffic / abytes) if traffic else None,
                      "algorithmic_bytes_per_launch": abytes, "avg_launch_us": avg_s * 1e6},
-        # per step: each pass's bytes times its launches per step (the sort runs every few steps)
+        # the whole step: 24 P + 40 H^3 over the timed ms per step
         "step_roofline": {"algorithmic_bytes_per_step": step_bytes,
-                          "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+                          "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "implementation_bytes_per_step": impl_step_bytes,
+                          "overhead_bytes_per_step": impl_step_bytes - step_bytes},
+        "steady_state": {"steps": args.steady_steps, "ms_per_step": 1e3 * steady / args.steady_steps,
+                         "particle_steps_per_s": P * args.steady_steps / steady},
         "phases": phases,
-        # every pass against the HBM peak: algorithmic bytes per launch over its average duration
+        # every pass: algorithmic and implementation bytes per launch over its average duration
         "phase_roofline": {k: {"algorithmic_bytes": algorithmic_bytes(k, P, H, tsize),
+                               "implementation_bytes": implementation_bytes(k, P, H, tsize),
                                "GB_s": algorithmic_bytes(k, P, H, tsize) / (v["us_avg"] * 1e3),
-                               "frac": algorithmic_bytes(k, P, H, tsize) / (v["us_avg"] * 1e3) / HBM_PEAK_GBS}
+                               "frac": algorithmic_bytes(k, P, H, tsize) / (v["us_avg"] * 1e3) / HBM_PEAK_GBS,
+                               "implementation_GB_s": implementation_bytes(k, P, H, tsize) / (v["us_avg"] * 1e3)}
                            for k, v in phases.items() if v["launches"]},
     }
     # run-time diagnostics of the state (one call = deposit, three FFT passes, reductions)
@@ -458,7 +560,8 @@ def main():
         out["ensemble"] = ensemble_throughput(pkg, workloads, np, torch)
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, P), args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.workload, H, min(args.cpu_sample, P), args.cpu_steps,
+                                           args.cpu_workers)
     print(json.dumps(out), flush=True)
 
 

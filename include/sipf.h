@@ -201,11 +201,20 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
 /* Advance one step n-1 -> n (Algorithm 4).  Asynchronous. */
 int sipf_step(sipf_ctx* ctx);
 
-/* Advance nsteps >= 0 steps.  Asynchronous.  Whole runs of two re-sort
- * periods replay a HIP graph captured on first use (kernels only, no memset
- * or copy nodes); the remaining steps are enqueued one by one.  Graph replay
- * and eager stepping enqueue the same kernels with the same arguments. */
+/* Advance nsteps >= 0 steps.  Asynchronous.  The run is cut into segments
+ * (up to the next due re-sort; from a due re-sort, two re-sort periods) and
+ * each segment replays a HIP graph captured on its first use (kernels only,
+ * no memset or copy nodes), cached by (particle buffer set, steps since the
+ * last re-sort, length).  Graph replay and eager stepping enqueue the same
+ * kernels with the same arguments.  With graphs off, or while phase
+ * profiling is on, every step is enqueued eagerly. */
 int sipf_run(sipf_ctx* ctx, int64_t nsteps);
+
+/* Capture, without running anything, every graph that sipf_run(ctx, nsteps)
+ * issued next would replay, so that the run itself only replays.  The
+ * context's state is unchanged.  Errors: SIPF_EINVAL (nsteps < 0),
+ * SIPF_EDEVICE (capture or instantiation failed). */
+int sipf_prepare_run(sipf_ctx* ctx, int64_t nsteps);
 
 /* Switch graph replay in sipf_run on (1, the default) or off (0). */
 int sipf_use_graphs(sipf_ctx* ctx, int enable);
@@ -363,6 +372,7 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
 int sipf_batch_init(int32_t n, const sipf_params* prm, const int64_t* P, const void* const* X0,
                     int x0_on_device, void* hip_stream, sipf_batch** out);
 int sipf_batch_run(sipf_batch* b, int64_t nsteps);
+int sipf_batch_prepare_run(sipf_batch* b, int64_t nsteps);  /* as sipf_prepare_run */
 int sipf_batch_use_graphs(sipf_batch* b, int enable);
 int sipf_batch_sync(sipf_batch* b);
 int sipf_batch_get_step(sipf_batch* b, int32_t i, int64_t* n);

@@ -79,6 +79,7 @@ SIGNATURES = {
     "sipf_init": [_pp, _i64, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "sipf_step": [_vp],
     "sipf_run": [_vp, _i64],
+    "sipf_prepare_run": [_vp, _i64],
     "sipf_sync": [_vp],
     "sipf_get_step": [_vp, ctypes.POINTER(_i64)],
     "sipf_get_positions": [_vp, _vp, ctypes.c_int],
@@ -99,6 +100,7 @@ SIGNATURES = {
     "sipf_batch_init": [_i32, _pp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.c_int, _vp,
                         ctypes.POINTER(_vp)],
     "sipf_batch_run": [_vp, _i64],
+    "sipf_batch_prepare_run": [_vp, _i64],
     "sipf_batch_use_graphs": [_vp, ctypes.c_int],
     "sipf_batch_sync": [_vp],
     "sipf_batch_get_step": [_vp, _i32, ctypes.POINTER(_i64)],

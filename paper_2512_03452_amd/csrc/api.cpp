@@ -225,9 +225,14 @@ struct Group {
     int items_cap = 0;
     std::vector<void*> allocs;
     void* diag = nullptr;  // diagnostics scratch, allocated on first use
-    // captured graphs of two sort periods, by starting buffer set
+    // captured graphs of run segments, by (buffer set, steps since the last
+    // sort, segment length): the only host state a step's launches depend on
     bool graphs = true;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    struct GraphSeg {
+        int cur, since, len;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphSeg> gcache;
     // per-phase event timing
     bool prof = false;
     struct Mark {
@@ -536,10 +541,11 @@ template <typename T> int enqueue_step(Group* g) {
     return SIPF_OK;
 }
 
-// Capture two sort periods (starting at a due sort from buffer set g->cur) on
-// the private stream.  Nothing runs during capture; the host-side stepping
-// state is put back afterwards.
-template <typename T> int capture_graph(Group* g, hipGraphExec_t* out) {
+// Capture `len` steps from the current host stepping state (buffer set
+// g->cur, g->since_sort steps since the last sort) on the private stream.
+// Nothing runs during capture; the host-side stepping state is put back
+// afterwards.
+template <typename T> int capture_graph(Group* g, int len, hipGraphExec_t* out) {
     *out = nullptr;
     if (!g->cap) HIPCHK(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
     const int since = g->since_sort, cur = g->cur;
@@ -548,7 +554,7 @@ template <typename T> int capture_graph(Group* g, hipGraphExec_t* out) {
     g->stream = g->cap;
     HIPCHK(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
     int rc = SIPF_OK;
-    for (int k = 0; k < 2 * g->resort && rc == SIPF_OK; ++k) rc = enqueue_step<T>(g);
+    for (int k = 0; k < len && rc == SIPF_OK; ++k) rc = enqueue_step<T>(g);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(g->cap, &graph);
     g->stream = user;
@@ -569,19 +575,58 @@ template <typename T> int capture_graph(Group* g, hipGraphExec_t* out) {
     return SIPF_OK;
 }
 
+// Length of the next graph segment of a run with `left` steps to go: up to
+// the next due sort, or, from a due sort, two sort periods (which end on the
+// starting buffer set with a sort due again, so one graph serves a long run).
+int segment_len(const Group* g, int64_t left) {
+    const int64_t to_sort = g->resort - g->since_sort;
+    const int64_t len = to_sort > 0 ? to_sort : 2 * (int64_t)g->resort;
+    return (int)std::min(left, len);
+}
+
+// Host stepping state after a segment of len steps (the sorts it holds).
+void advance_state(Group* g, int len) {
+    for (int k = 0; k < len; ++k) {
+        if (g->since_sort >= g->resort) {
+            g->cur = 1 - g->cur;
+            g->since_sort = 0;
+        }
+        g->since_sort++;
+    }
+    g->n_host += len;
+}
+
+constexpr size_t GRAPH_CACHE_MAX = 16;
+
+// The cached graph of a segment of len steps from the current state; captured
+// on first use.
+template <typename T> int segment_graph(Group* g, int len, hipGraphExec_t* out) {
+    for (const auto& gs : g->gcache)
+        if (gs.cur == g->cur && gs.since == g->since_sort && gs.len == len) {
+            *out = gs.exec;
+            return SIPF_OK;
+        }
+    if (g->gcache.size() >= GRAPH_CACHE_MAX) {
+        (void)hipGraphExecDestroy(g->gcache.front().exec);
+        g->gcache.erase(g->gcache.begin());
+    }
+    int rc = capture_graph<T>(g, len, out);
+    if (rc) return rc;
+    g->gcache.push_back({g->cur, g->since_sort, len, *out});
+    return SIPF_OK;
+}
+
 template <typename T> int run_typed(Group* g, int64_t nsteps) {
     int64_t left = nsteps;
-    const int period = 2 * g->resort;
     while (left > 0) {
-        if (g->graphs && !g->prof && g->n_host > 0 && g->since_sort >= g->resort && left >= period) {
-            hipGraphExec_t& ge = g->gexec[g->cur];
-            if (!ge) {
-                int rc = capture_graph<T>(g, &ge);
-                if (rc) return rc;
-            }
+        if (g->graphs && !g->prof) {
+            const int len = segment_len(g, left);
+            hipGraphExec_t ge = nullptr;
+            int rc = segment_graph<T>(g, len, &ge);
+            if (rc) return rc;
             HIPCHK(hipGraphLaunch(ge, g->stream));
-            g->n_host += period;  // the graph ends where it started: set cur, sort due
-            left -= period;
+            advance_state(g, len);
+            left -= len;
             continue;
         }
         int rc = enqueue_step<T>(g);
@@ -589,6 +634,30 @@ template <typename T> int run_typed(Group* g, int64_t nsteps) {
         --left;
     }
     return SIPF_OK;
+}
+
+// Capture (without running) every graph that a run of nsteps from the
+// current state will replay.
+template <typename T> int prepare_typed(Group* g, int64_t nsteps) {
+    if (!g->graphs) return SIPF_OK;
+    const int since = g->since_sort, cur = g->cur;
+    const int64_t nh = g->n_host;
+    int rc = SIPF_OK;
+    for (int64_t left = nsteps; left > 0 && rc == SIPF_OK;) {
+        const int len = segment_len(g, left);
+        hipGraphExec_t ge = nullptr;
+        rc = segment_graph<T>(g, len, &ge);
+        advance_state(g, len);
+        left -= len;
+    }
+    g->since_sort = since;
+    g->cur = cur;
+    g->n_host = nh;
+    return rc;
+}
+
+int prepare_group(Group* g, int64_t nsteps) {
+    return g->prec == SIPF_FP32 ? prepare_typed<float>(g, nsteps) : prepare_typed<double>(g, nsteps);
 }
 
 int run_group(Group* g, int64_t nsteps) {
@@ -864,8 +933,9 @@ int init_group(Group* g, const void* const* X0, int x0_on_device, const void* al
 void free_group(Group* g) {
     if (!g) return;
     release_marks(g);
-    for (auto& ge : g->gexec)
-        if (ge) (void)hipGraphExecDestroy(ge);
+    for (auto& gs : g->gcache)
+        if (gs.exec) (void)hipGraphExecDestroy(gs.exec);
+    g->gcache.clear();
     if (g->cap) (void)hipStreamDestroy(g->cap);
     for (void* p : g->allocs) (void)hipFree(p);
 }
@@ -1484,14 +1554,20 @@ int time_config(const sipf_params* prm, int64_t P, const void* X0, int x0_on_dev
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     if (e == hipSuccess) {
-        rc = run_group(c, 2 * c->resort + 1);  // warm-up, including graph capture
+        // Timed window: whole multiples of two sort periods starting at a due
+        // sort, so that every candidate period pays its sorts in proportion;
+        // one untimed window first captures the graphs the timed one replays.
+        const int64_t period = 2 * (int64_t)c->resort;
+        const int64_t T = (nsteps + period - 1) / period * period;
+        rc = run_group(c, c->resort);  // to the first due sort
+        if (!rc) rc = run_group(c, T);
         if (!rc) e = hipEventRecord(a, c->stream);
-        if (!rc && e == hipSuccess) rc = run_group(c, nsteps);
+        if (!rc && e == hipSuccess) rc = run_group(c, T);
         if (!rc && e == hipSuccess) e = hipEventRecord(b, c->stream);
         if (!rc && e == hipSuccess) e = hipEventSynchronize(b);
         float f = 0.f;
         if (!rc && e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
-        *ms = f / nsteps;
+        *ms = f / (double)T;
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
@@ -1553,6 +1629,12 @@ int sipf_init(const sipf_params* prm, int64_t P, const void* X0, int x0_on_devic
     }
     *out = c;
     return SIPF_OK;
+}
+
+int sipf_prepare_run(sipf_ctx* c, int64_t nsteps) {
+    if (!c) return fail(SIPF_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+    return prepare_group(c, nsteps);
 }
 
 int sipf_step(sipf_ctx* c) {
@@ -1717,6 +1799,12 @@ int sipf_batch_init(int32_t n, const sipf_params* prm, const int64_t* P, const v
     }
     *out = b;
     return SIPF_OK;
+}
+
+int sipf_batch_prepare_run(sipf_batch* b, int64_t nsteps) {
+    if (!b) return fail(SIPF_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+    return prepare_group(b, nsteps);
 }
 
 int sipf_batch_run(sipf_batch* b, int64_t nsteps) {

@@ -75,6 +75,10 @@ class Sim:
     def run(self, nsteps):
         check(_lib.load().sipf_run(self._h, int(nsteps)))
 
+    def prepare_run(self, nsteps):
+        """Capture every graph that run(nsteps) issued next would replay (runs nothing)."""
+        check(_lib.load().sipf_prepare_run(self._h, int(nsteps)))
+
     def sync(self):
         check(_lib.load().sipf_sync(self._h))
 
@@ -245,6 +249,10 @@ class Batch:
 
     def run(self, nsteps):
         check(_lib.load().sipf_batch_run(self._h, int(nsteps)))
+
+    def prepare_run(self, nsteps):
+        """Capture every graph that run(nsteps) issued next would replay (runs nothing)."""
+        check(_lib.load().sipf_batch_prepare_run(self._h, int(nsteps)))
 
     def use_graphs(self, enable=True):
         check(_lib.load().sipf_batch_use_graphs(self._h, 1 if enable else 0))

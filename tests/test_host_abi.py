@@ -159,6 +159,7 @@ def test_bad_particle_count_and_null_pointers():
     assert lib.sipf_init(None, 4, X.ctypes.data_as(ctypes.c_void_p), 0, None, 0, None, ctypes.byref(h)) == L.SIPF_EINVAL
     assert lib.sipf_step(None) == L.SIPF_EINVAL
     assert lib.sipf_run(None, 3) == L.SIPF_EINVAL
+    assert lib.sipf_prepare_run(None, 3) == L.SIPF_EINVAL
     assert lib.sipf_destroy(None) == L.SIPF_OK
 
 
@@ -264,6 +265,7 @@ def test_batch_and_tuning_null_handles():
     lib = L.load()
     n = ctypes.c_int64()
     assert lib.sipf_batch_run(None, 1) == L.SIPF_EINVAL
+    assert lib.sipf_batch_prepare_run(None, 1) == L.SIPF_EINVAL
     assert lib.sipf_batch_sync(None) == L.SIPF_EINVAL
     assert lib.sipf_batch_get_step(None, 0, ctypes.byref(n)) == L.SIPF_EINVAL
     assert lib.sipf_batch_get_positions(None, 0, None, 1) == L.SIPF_EINVAL
