@@ -70,17 +70,27 @@ __device__ __forceinline__ void fields21(u32x4 r, uint32_t f[6]) {
     f[4] = ((r.v0 & 0x7FFu) << 10) | (r.v1 & 0x3FFu);
     f[5] = ((r.v2 & 0x7FFu) << 10) | (r.v3 & 0x3FFu);
 }
-// float: the hardware transcendentals (v_log_f32 is log2; v_sin/v_cos take
-// revolutions, so cos 2 pi u is one instruction); u in [2^-22, 1) keeps every
-// argument in range.
+// float: u = (f + 1/2) 2^-21 is formed from bits as the float 1 + (f + 1/2)
+// 2^-21 (mantissa 4 f + 2) minus 1, both steps exact, so it equals
+// u01_21<float>(f) without an integer-to-float conversion.  The hardware
+// transcendentals follow (v_log_f32 is log2; v_sin/v_cos take revolutions,
+// so cos 2 pi u is one instruction); u in [2^-22, 1) keeps every argument in
+// range.
+__device__ __forceinline__ float u01_21_bits(uint32_t mant) { return __uint_as_float(0x3F800000u | mant) - 1.0f; }
 template <int NPAIR> __device__ __forceinline__ void normals6(u32x4 r, float z[6]) {
-    uint32_t f[6];
-    fields21(r, f);
+    // mantissas 4 f_i + 2 of the six fields (see fields21)
+    uint32_t m[6];
+    m[0] = ((r.v0 >> 9) & 0x7FFFFCu) | 2u;
+    m[1] = ((r.v1 >> 9) & 0x7FFFFCu) | 2u;
+    m[2] = ((r.v2 >> 9) & 0x7FFFFCu) | 2u;
+    m[3] = ((r.v3 >> 9) & 0x7FFFFCu) | 2u;
+    m[4] = ((r.v0 << 12) & 0x7FF000u) | ((r.v1 << 2) & 0xFFCu) | 2u;
+    m[5] = ((r.v2 << 12) & 0x7FF000u) | ((r.v3 << 2) & 0xFFCu) | 2u;
     constexpr float m2ln2 = -1.3862943611198906f;  // -2 ln 2
 #pragma unroll
     for (int j = 0; j < NPAIR; ++j) {
-        const float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01_21<float>(f[2 * j])));
-        const float b = u01_21<float>(f[2 * j + 1]);
+        const float a = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01_21_bits(m[2 * j])));
+        const float b = u01_21_bits(m[2 * j + 1]);
         z[2 * j] = a * __builtin_amdgcn_cosf(b);
         z[2 * j + 1] = a * __builtin_amdgcn_sinf(b);
     }

@@ -189,6 +189,24 @@ template <> struct Win<double> { static constexpr int D = 15, G = 11; };
 static_assert(Win<float>::D * Win<float>::D <= PT && Win<double>::D * Win<double>::D <= PT, "window plane");
 static_assert(Win<float>::G * Win<float>::G <= PT && Win<double>::G * Win<double>::G <= PT, "window plane");
 
+// Fused FP32 pass: both fast windows are live at once, the deposit window first.
+template <typename T> constexpr int fused_dep_bytes() {
+    return (Win<T>::D * Win<T>::D * Win<T>::D * (int)sizeof(typename Fixed<T>::I) + 255) / 256 * 256;
+}
+template <typename T> constexpr int fused_win_bytes() {
+    return fused_dep_bytes<T>() + (3 * Win<T>::G * Win<T>::G * Win<T>::G * (int)sizeof(T) + 255) / 256 * 256;
+}
+// FP32 items are also counting-sorted by cell when they are written back:
+// 16-bit counts packed in pairs for the (D - 3)^3 cells of the largest box
+// plus one overflow key, and eight wave totals.
+constexpr int SORT_KEYS_MAX = (Win<float>::D - 3) * (Win<float>::D - 3) * (Win<float>::D - 3) + 1;
+constexpr int SORT_WORDS_MAX = (SORT_KEYS_MAX + 1) / 2;
+template <typename T> constexpr int fused_bytes() {
+    return fused_win_bytes<T>() + ((SORT_WORDS_MAX + PT / 64) * 4 + 255) / 256 * 256;
+}
+// the write-out staging (one float4 per particle) fits in the two windows
+static_assert(CH * 16 <= fused_win_bytes<float>(), "staging");
+
 // LDS bytes the particle pass needs per workgroup (the larger fast window)
 int particle_window_bytes(bool fp64) {
     const int d32 = Win<float>::D * Win<float>::D * Win<float>::D * 4;
@@ -276,7 +294,7 @@ __device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz,
     constexpr int G3 = G * G * G;
     const int ix = wr(gx - ox), iy = wr(gy - oy), iz = wr(gz - oz);
     if (ix > ex - 2 || iy > ey - 2 || iz > ez - 2) return false;
-    const T* p = Gw + (ix * G + iy) * G + iz;
+    const T* p = Gw + mad24(mad24(ix, G, iy), G, iz);
     const T wx[2] = {(T)1 - lx, lx}, wy[2] = {(T)1 - ly, ly}, wz[2] = {(T)1 - lz, lz};
     T ax = 0, ay = 0, az = 0;
 #pragma unroll
@@ -565,17 +583,408 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
 }
 
 // Persistent over the work items listed by the last sort (header: next_item).
+// Lane layout of an FP32 item of cnt particles: ppe = ceil(cnt / PT)
+// particles per lane on lact = ceil(cnt / ppe) lanes; lane t holds the
+// particles of ranks t ppe .. t ppe + ppe - 1 of the item, and rank
+// s = t ppe + k is stored at column k, row t: position col(k) + t with
+// col(k) = k lact - max(0, k - rlast), where rlast = cnt - (lact - 1) ppe is
+// the length of the last lane's run (columns k >= rlast are one row short).
+// Loads of one column are contiguous; a lane's ranks are consecutive.
+struct ColLayout {
+    int ppe, lact, rlast;
+    __device__ __forceinline__ ColLayout(int cnt) {
+        ppe = (cnt + PT - 1) / PT;
+        lact = (cnt + ppe - 1) / ppe;
+        rlast = cnt - (lact - 1) * ppe;
+    }
+    __device__ __forceinline__ int col(int k) const { return k * lact - max(0, k - rlast); }
+    __device__ __forceinline__ bool valid(int t, int k) const {
+        return k < ppe && t < lact && (t < lact - 1 || k < rlast);
+    }
+};
+
+// The sorted FP32 pass accumulates its deposit window in fixed point with
+// integer LDS atomics: on gfx950 a float LDS atomic add (ds_add_f32) issues
+// about fifty times slower than the integer one.
+using RunWin = int32_t;
+
+// The 32 weights of eq. 4ord of one particle times the window scale 2^S,
+// added to a run accumulator (slots in the order of flush_run4).
+__device__ __forceinline__ void add_weights4(float* acc, const Axis4<float>& ax, const Axis4<float>& ay,
+                                             const Axis4<float>& az, float S, float scale) {
+    const float X[4] = {ax.wm * scale, ax.w0 * scale, ax.w1 * scale, ax.wp * scale};
+    const float Y[4] = {ay.wm, ay.w0, ay.w1, ay.wp};
+    const float Z[4] = {az.wm, az.w0, az.w1, az.wp};
+    int q = 0;
+#pragma unroll
+    for (int j = 1; j <= 2; ++j)
+#pragma unroll
+        for (int k = 1; k <= 2; ++k) {
+            const float yz = Y[j] * Z[k];
+            const float Syz = S * yz;
+            acc[q] = fmaf(X[1], Syz, acc[q]); ++q;  // inner nodes (1, j, k), (2, j, k)
+            acc[q] = fmaf(X[2], Syz, acc[q]); ++q;
+            acc[q] = fmaf(X[0], yz, acc[q]); ++q;   // outer nodes on x: (0, j, k), (3, j, k)
+            acc[q] = fmaf(X[3], yz, acc[q]); ++q;
+        }
+#pragma unroll
+    for (int i = 1; i <= 2; ++i)
+#pragma unroll
+        for (int k = 1; k <= 2; ++k) {
+            const float xz = X[i] * Z[k];
+            acc[q] = fmaf(Y[0], xz, acc[q]); ++q;   // outer nodes on y: (i, 0, k), (i, 3, k)
+            acc[q] = fmaf(Y[3], xz, acc[q]); ++q;
+        }
+#pragma unroll
+    for (int i = 1; i <= 2; ++i)
+#pragma unroll
+        for (int j = 1; j <= 2; ++j) {
+            const float xy = X[i] * Y[j];
+            acc[q] = fmaf(Z[0], xy, acc[q]); ++q;   // outer nodes on z: (i, j, 0), (i, j, 3)
+            acc[q] = fmaf(Z[3], xy, acc[q]); ++q;
+        }
+}
+
+// Adds a run accumulator (already at the window scale 2^S), rounded to
+// integers, to the fixed-point deposit window at the run's base node
+// (cell - (1,1,1)); node (i, j, k) at (i D + j) D + k.
+__device__ __forceinline__ void flush_run4(RunWin* win, int base, const float* acc) {
+    constexpr int D = Win<float>::D;
+    uint32_t* w = reinterpret_cast<uint32_t*>(win) + base;
+#define SIPF_FL(q, i, j, k) atomicAdd(w + ((i) * D + (j)) * D + (k), (uint32_t)round_half_up(acc[q]))
+    int q = 0;
+#pragma unroll
+    for (int j = 1; j <= 2; ++j)
+#pragma unroll
+        for (int k = 1; k <= 2; ++k) {
+            SIPF_FL(q, 1, j, k); ++q;
+            SIPF_FL(q, 2, j, k); ++q;
+            SIPF_FL(q, 0, j, k); ++q;
+            SIPF_FL(q, 3, j, k); ++q;
+        }
+#pragma unroll
+    for (int i = 1; i <= 2; ++i)
+#pragma unroll
+        for (int k = 1; k <= 2; ++k) {
+            SIPF_FL(q, i, 0, k); ++q;
+            SIPF_FL(q, i, 3, k); ++q;
+        }
+#pragma unroll
+    for (int i = 1; i <= 2; ++i)
+#pragma unroll
+        for (int j = 1; j <= 2; ++j) {
+            SIPF_FL(q, i, j, 0); ++q;
+            SIPF_FL(q, i, j, 3); ++q;
+        }
+#undef SIPF_FL
+}
+
+// FP32 work item in one loop, with the item kept sorted by cell between
+// steps.  The particles arrive in the lane layout above, sorted by cell by
+// the previous step's write-out (in the order of the re-sort right after
+// one).  Each particle deposits its position X^(n-1) (Algorithm 4 reads only
+// the state after step n-1 in both branches, so the deposit and the push of a
+// particle are independent and one pass serves both): a lane adds the
+// weights of its consecutive particles into registers while they share a
+// cell and adds each run to the deposit window once (one set of 32 LDS
+// atomics per run instead of per particle; the lanes of a wave then work on
+// neighbouring cells, so those atomics spread over the LDS banks).  The
+// particle then draws its noise, gathers the gradient at Y from the gradient
+// window (neighbouring lanes read neighbouring rows) and is pushed.  The
+// pushed particles are counting-sorted by
+// their new cell inside the item's box (cells that left it go last) and
+// written back to the item's segment in the lane layout, which keeps the
+// order for the next step.  Returns false, touching nothing, when the item
+// does not fit the windows.
+// Particles of an FP32 item in the lane layout, loaded into registers.
+__device__ __forceinline__ void load_cols(const PartDesc<float>& a, int64_t beg, int cnt, float* px, float* py,
+                                          float* pz, uint32_t* pid) {
+    const ColLayout cl(cnt);
+    const int tid = threadIdx.x;
+    const float* ix = a.x + beg;
+    const float* iy = a.y + beg;
+    const float* iz = a.z + beg;
+    const uint32_t* iid = a.id + beg;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t jj = (uint32_t)(cl.valid(tid, k) ? cl.col(k) + tid : 0);
+        px[k] = gp(ix)[jj];
+        py[k] = gp(iy)[jj];
+        pz[k] = gp(iz)[jj];
+        pid[k] = gp(iid)[jj];
+    }
+}
+
+// Whether an FP32 item can take the sorted pass (its box is checked there).
+__device__ __forceinline__ bool sorted_candidate(const PartDesc<float>& a, const WorkItem& w, int win_bytes) {
+    return a.ox == nullptr && w.cnt >= MIN_WINDOW_ITEM && a.H > Win<float>::D && a.H > Win<float>::G &&
+           win_bytes >= fused_bytes<float>();
+}
+
+template <int SCHEME, bool P2>
+__device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t beg, int cnt, unsigned char* lds,
+                                            int* sh) {
+    float px[PPT], py[PPT], pz[PPT];
+    uint32_t pid[PPT];
+    load_cols(a, beg, cnt, px, py, pz, pid);
+    constexpr int D = Win<float>::D, G = Win<float>::G, G3 = G * G * G;
+    const int tid = threadIdx.x;
+    const int H = a.H, Hh = H / 2;
+    const Wrap<P2> wr{H, H - 1};
+    const float hl = a.hl;
+    const ColLayout cl(cnt);
+    // bounding box of the item's cells, relative to the cell of its first particle (thread 0, k = 0)
+    if (tid < 3) sh[tid] = INT_MAX;
+    else if (tid < 6) sh[tid] = INT_MIN;
+    if (tid == 0) {
+        sh[8] = wr(ifloor(px[0] * hl));
+        sh[9] = wr(ifloor(py[0] * hl));
+        sh[10] = wr(ifloor(pz[0] * hl));
+    }
+    __syncthreads();
+    const int rx = sh[8], ry = sh[9], rz = sh[10];
+    {
+        int mnx = INT_MAX, mny = INT_MAX, mnz = INT_MAX, mxx = INT_MIN, mxy = INT_MIN, mxz = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (cl.valid(tid, k)) {
+                const int cx = wr(wr(ifloor(px[k] * hl)) - rx + Hh) - Hh;
+                const int cy = wr(wr(ifloor(py[k] * hl)) - ry + Hh) - Hh;
+                const int cz = wr(wr(ifloor(pz[k] * hl)) - rz + Hh) - Hh;
+                mnx = min(mnx, cx); mxx = max(mxx, cx);
+                mny = min(mny, cy); mxy = max(mxy, cy);
+                mnz = min(mnz, cz); mxz = max(mxz, cz);
+            }
+        }
+        mnx = wave_min(mnx); mny = wave_min(mny); mnz = wave_min(mnz);
+        mxx = wave_max(mxx); mxy = wave_max(mxy); mxz = wave_max(mxz);
+        if ((tid & 63) == 0) {
+            atomicMin(&sh[0], mnx); atomicMin(&sh[1], mny); atomicMin(&sh[2], mnz);
+            atomicMax(&sh[3], mxx); atomicMax(&sh[4], mxy); atomicMax(&sh[5], mxz);
+        }
+    }
+    __syncthreads();
+    const int bx0 = sh[0], by0 = sh[1], bz0 = sh[2];
+    const int nbx = sh[3] - bx0 + 1, nby = sh[4] - by0 + 1, nbz = sh[5] - bz0 + 1;
+    int m = a.gmargin;
+    while (m >= 0 && (nbx + 1 + 2 * m > G || nby + 1 + 2 * m > G || nbz + 1 + 2 * m > G)) --m;
+    if (nbx + 3 > D || nby + 3 > D || nbz + 3 > D || m < 0) {
+        __syncthreads();  // sh is rewritten by the caller's fallback
+        return false;
+    }
+    RunWin* win = reinterpret_cast<RunWin*>(lds);
+    float* Gw = reinterpret_cast<float*>(lds + fused_dep_bytes<float>());
+    uint32_t* cw = reinterpret_cast<uint32_t*>(lds + fused_win_bytes<float>());
+    uint32_t* wtot = cw + SORT_WORDS_MAX;
+    const int nkeys = nbx * nby * nbz + 1, nwords = (nkeys + 1) / 2;
+    // deposit window: nodes -1..+2 around the box; sort counters
+    const int dox = wr(rx + bx0 - 1), doy = wr(ry + by0 - 1), doz = wr(rz + bz0 - 1);
+    {
+        int i0, wj, wk, nrep;
+        plane_map(nby + 3, nbz + 3, i0, wj, wk, nrep);
+        for (int i = i0; i < nbx + 3; i += nrep) win[(i * D + wj) * D + wk] = (RunWin)0;
+        for (int w = tid; w < nwords; w += PT) cw[w] = 0u;
+    }
+    // gradient window: the box, the W^- margin m and the trilinear reach
+    const int gox = wr(rx + bx0 - m), goy = wr(ry + by0 - m), goz = wr(rz + bz0 - m);
+    const int gWx = nbx + 1 + 2 * m, gWy = nby + 1 + 2 * m, gWz = nbz + 1 + 2 * m;
+    {
+        const int H3 = H * H * H;
+        int i0, wj, wk, nrep;
+        plane_map(gWy, gWz, i0, wj, wk, nrep);
+        const int nyz = wr(goy + wj) * H + wr(goz + wk);
+        for (int i = i0; i < gWx; i += nrep) {
+            const int node = wr(gox + i) * H * H + nyz;
+            const int o = (i * G + wj) * G + wk;
+            Gw[o] = gp(a.G)[node];
+            Gw[G3 + o] = gp(a.G)[H3 + node];
+            Gw[2 * G3 + o] = gp(a.G)[2 * H3 + node];
+        }
+    }
+    const int need = (11 * cnt + 7) / 8;
+    const int S = min(Magic<float>::MAXS, Fixed<float>::BITS - (32 - __clz(need)));
+    const float scale = ldexpf(1.0f, S);
+    const uint32_t step_n = *a.step + 1u;
+    const size_t H3 = (size_t)H * H * H;
+    __syncthreads();
+
+    float acc[32];
+    int run = -1;  // window base node of the run in acc
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!cl.valid(tid, k)) continue;
+        const float x = px[k], y = py[k], z = pz[k];
+        {
+            const float sx = x * hl, sy = y * hl, sz = z * hl;
+            const float fx = floorf(sx), fy = floorf(sy), fz = floorf(sz);
+            const int base =
+                mad24(mad24(wr((int)fx - 1 - dox), D, wr((int)fy - 1 - doy)), D, wr((int)fz - 1 - doz));
+            if (base != run) {
+                if (run >= 0) flush_run4(win, run, acc);
+#pragma unroll
+                for (int q = 0; q < 32; ++q) acc[q] = 0.0f;
+                run = base;
+            }
+            const Axis4<float> ax = axis4(sx - fx), ay = axis4(sy - fy), az = axis4(sz - fz);
+            add_weights4(acc, ax, ay, az, 1.0f + (ax.w0 * ax.w1 + ay.w0 * ay.w1 + az.w0 * az.w1) * 0.5f, scale);
+        }
+        float yx, yy, yz, w0, w1, w2;
+        float zn[6];
+        if (SCHEME == SIPF_STRANG) {
+            noise6<3, float>(pid[k], step_n, a.inst, a.k0, a.k1, zn);
+            yx = x + a.s * zn[0];
+            yy = y + a.s * zn[1];
+            yz = z + a.s * zn[2];
+            w0 = zn[3];
+            w1 = zn[4];
+            w2 = zn[5];
+        } else {
+            noise6<2, float>(pid[k], step_n, a.inst, a.k0, a.k1, zn);
+            w0 = zn[0];
+            w1 = zn[1];
+            w2 = zn[2];
+            yx = x;
+            yy = y;
+            yz = z;
+        }
+        const float sx = yx * hl, sy = yy * hl, sz = yz * hl;
+        const float fx = floorf(sx), fy = floorf(sy), fz = floorf(sz);
+        const int gx = (int)fx, gy = (int)fy, gz = (int)fz;
+        float vx, vy, vz;
+        if (!gather_fast<float>(Gw, gx, gy, gz, sx - fx, sy - fy, sz - fz, wr, gox, goy, goz, gWx, gWy, gWz, vx,
+                                vy, vz)) {
+            const int jx[2] = {wr(gx), wr(gx + 1)};
+            const int jy[2] = {wr(gy), wr(gy + 1)};
+            const int jz[2] = {wr(gz), wr(gz + 1)};
+            trilinear3<float>(gp(a.G), H3, H, H, jx, jy, jz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
+        }
+        px[k] = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
+        py[k] = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
+        pz[k] = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
+        if (!(isfinite(px[k]) && isfinite(py[k]) && isfinite(pz[k]))) atomicOr(a.err, 1);
+    }
+    if (run >= 0) flush_run4(win, run, acc);
+    // ranks of the pushed particles among those of the same new cell
+    uint32_t kr[PPT];  // key << 16 | rank
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        kr[k] = 0u;
+        if (!cl.valid(tid, k)) continue;
+        const int cx = wr(wr(ifloor(px[k] * hl)) - rx + Hh) - Hh - bx0;
+        const int cy = wr(wr(ifloor(py[k] * hl)) - ry + Hh) - Hh - by0;
+        const int cz = wr(wr(ifloor(pz[k] * hl)) - rz + Hh) - Hh - bz0;
+        const bool in = (unsigned)cx < (unsigned)nbx && (unsigned)cy < (unsigned)nby && (unsigned)cz < (unsigned)nbz;
+        const uint32_t kk = in ? (uint32_t)mad24(mad24(cx, nby, cy), nbz, cz) : (uint32_t)(nkeys - 1);
+        const uint32_t sft = 16u * (kk & 1u);
+        kr[k] = (kk << 16) | ((atomicAdd(&cw[kk >> 1], 1u << sft) >> sft) & 0xFFFFu);
+    }
+    __syncthreads();
+    // the deposit window into the grid
+    {
+        const float back = a.wmass * ldexpf(1.0f, -S);
+        int i0, wj, wk, nrep;
+        plane_map(nby + 3, nbz + 3, i0, wj, wk, nrep);
+        const int nyz = wr(doy + wj) * H + wr(doz + wk);
+        for (int i = i0; i < nbx + 3; i += nrep) {
+            const RunWin v = win[(i * D + wj) * D + wk];
+            if (v != (RunWin)0) gatomic_add(a.phi + wr(dox + i) * H * H + nyz, (float)v * back);
+        }
+    }
+    // exclusive scan of the counts: thread t owns words [t wp, t wp + wp)
+    const int wp = (nwords + PT - 1) / PT;
+    uint32_t loc = 0;
+    for (int i = 0; i < wp; ++i) {
+        const int w = tid * wp + i;
+        if (w < nwords) {
+            const uint32_t v = cw[w];
+            loc += (v & 0xFFFFu) + (v >> 16);
+        }
+    }
+    uint32_t incl = loc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(incl, off, 64);
+        if ((tid & 63) >= off) incl += u;
+    }
+    if ((tid & 63) == 63) wtot[tid >> 6] = incl;
+    __syncthreads();
+    {
+        uint32_t b = incl - loc;
+        for (int w = 0; w < (tid >> 6); ++w) b += wtot[w];
+        for (int i = 0; i < wp; ++i) {
+            const int w = tid * wp + i;
+            if (w < nwords) {
+                const uint32_t v = cw[w], lo = v & 0xFFFFu;
+                cw[w] = b | ((b + lo) << 16);
+                b += lo + (v >> 16);
+            }
+        }
+    }
+    __syncthreads();
+    // stage in the lane layout (over the dead windows), then write back
+    float4* stg = reinterpret_cast<float4*>(lds);
+    const float inv_ppe = 1.0f / (float)cl.ppe;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!cl.valid(tid, k)) continue;
+        const uint32_t kk = kr[k] >> 16, sft = 16u * (kk & 1u);
+        const int s = (int)(((cw[kk >> 1] >> sft) & 0xFFFFu) + (kr[k] & 0xFFFFu));
+        int t2, k2;
+        divmod_small(s, cl.ppe, inv_ppe, t2, k2);
+        stg[cl.col(k2) + t2] = make_float4(px[k], py[k], pz[k], __uint_as_float(pid[k]));
+    }
+    __syncthreads();
+    for (int g = tid; g < cnt; g += PT) {
+        const float4 v = stg[g];
+        gp(a.x + beg)[g] = v.x;
+        gp(a.y + beg)[g] = v.y;
+        gp(a.z + beg)[g] = v.z;
+        gp(a.id + beg)[g] = __float_as_uint(v.w);
+    }
+    return true;
+}
+
+template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
+__device__ __forceinline__ void particles_body(const PartDesc<T>* __restrict__ pds,
+                                               const WorkItem* __restrict__ items, int* hdr, int win_bytes,
+                                               unsigned char* smem_raw, int* sh, int* slot_p) {
+    const int n = hdr[0];
+    for (int it = blockIdx.x; it < n; it = next_item(hdr, n, slot_p)) {
+        const WorkItem w = items[it];
+        if constexpr (sizeof(T) == 4 && DEP && PUSH) {
+            const PartDesc<T>& a = pds[w.inst];
+            if (sorted_candidate(a, w, win_bytes) && item_sorted<SCHEME, P2>(a, w.beg, w.cnt, smem_raw, sh))
+                continue;
+        }
+        item_pass<T, DEP, PUSH, SCHEME, P2>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
+    }
+}
+
+// Deposit-only and push-only passes (six waves per SIMD).
 template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
 __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<T>* __restrict__ pds,
                                                   const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[8];
     __shared__ int slot;
-    const int n = hdr[0];
-    for (int it = blockIdx.x; it < n; it = next_item(hdr, n, &slot)) {
-        const WorkItem w = items[it];
-        item_pass<T, DEP, PUSH, SCHEME, P2>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
-    }
+    particles_body<T, DEP, PUSH, SCHEME, P2>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+}
+
+// The fused deposit + push pass: its two windows (and, in FP32, the sort
+// counters) allow two workgroups per CU, i.e. four waves per SIMD, so the
+// registers are budgeted for four.
+#ifndef SIPF_FUSED_WAVES
+#define SIPF_FUSED_WAVES 4
+#endif
+template <typename T, int SCHEME, bool P2>
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(SIPF_FUSED_WAVES))) void k_particles_fused(
+    const PartDesc<T>* __restrict__ pds, const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int sh[12];
+    __shared__ int slot;
+    particles_body<T, true, true, SCHEME, P2>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
 }
 
 // Workgroups of the fused particle pass that are resident on the whole device
@@ -584,11 +993,20 @@ __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<
 // before it can start its share of the work items.
 template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
     int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = scheme == SIPF_STRANG
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &per_cu, (const void*)k_particles<T, true, true, SIPF_STRANG, true>, PT, win_bytes)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &per_cu, (const void*)k_particles<T, true, true, SIPF_EM, true>, PT, win_bytes);
+    hipError_t e;
+    if constexpr (sizeof(T) == 4) {
+        if (win_bytes < fused_bytes<T>()) win_bytes = fused_bytes<T>();
+        e = scheme == SIPF_STRANG ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                        &per_cu, (const void*)k_particles_fused<T, SIPF_STRANG, true>, PT, win_bytes)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                        &per_cu, (const void*)k_particles_fused<T, SIPF_EM, true>, PT, win_bytes);
+    } else {
+        e = scheme == SIPF_STRANG
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, (const void*)k_particles<T, true, true, SIPF_STRANG, true>, PT, win_bytes)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, (const void*)k_particles<T, true, true, SIPF_EM, true>, PT, win_bytes);
+    }
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess || per_cu < 1 || cus < 1) {
@@ -602,12 +1020,27 @@ template <typename T, bool P2>
 static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, int* nitems, dim3 g, bool deposit,
                          bool push, int scheme, int win_bytes, hipStream_t s) {
     const dim3 b(PT);
+    if (deposit && push) {
+        if constexpr (sizeof(T) == 4) {
+            // the fused FP32 pass holds both windows and the sort counters at once
+            if (win_bytes < fused_bytes<T>()) win_bytes = fused_bytes<T>();
+            const size_t shm = (size_t)win_bytes;
+            if (scheme == SIPF_STRANG)
+                launch_kernel((k_particles_fused<T, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+            else
+                launch_kernel((k_particles_fused<T, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+            return;
+        }
+    }
     const size_t shm = (size_t)win_bytes;
     if (deposit && push) {
-        if (scheme == SIPF_STRANG)
-            launch_kernel((k_particles<T, true, true, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
-        else
-            launch_kernel((k_particles<T, true, true, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+        if constexpr (sizeof(T) == 8) {
+            if (scheme == SIPF_STRANG)
+                launch_kernel((k_particles<T, true, true, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems,
+                              win_bytes);
+            else
+                launch_kernel((k_particles<T, true, true, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+        }
     } else if (deposit) {
         launch_kernel((k_particles<T, true, false, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
     } else if (push) {

@@ -53,6 +53,16 @@ template <> struct Magic<double> {
     __device__ static long long take(double v) { return __double_as_longlong(v) - 0x4338000000000000LL; }
 };
 
+// floor(v + 1/2) as an integer in one instruction (|v| < 2^31).
+__device__ __forceinline__ int round_half_up(float v) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// a * b + c for 0 <= a, b < 2^24 (24-bit multiply, full rate)
+__device__ __forceinline__ int mad24(int a, int b, int c) { return (int)__umul24((unsigned)a, (unsigned)b) + c; }
+
 // q = e / d, r = e % d for 0 <= e < 2^20, 0 < d < 2^10: float reciprocal
 // estimate, corrected by one step.
 __device__ __forceinline__ void divmod_small(int e, int d, float inv_d, int& q, int& r) {
