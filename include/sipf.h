@@ -404,6 +404,27 @@ int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t
 int sipf_dbg_deposit(const sipf_params* prm, int64_t count, const void* X, void* phi,
                      void* hip_stream);
 
+/*
+ * Allocation-free deposit, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation and kernels as sipf_dbg_deposit, i.e.
+ * phi = I(sum_p w delta_{X_p}) with w = M0/count on the H^3 grid, but every
+ * intermediate (particle copies in two sort buffer sets, tile counts and
+ * cursors, work items, descriptors) lives in a fixed-size static device
+ * array of 32 MiB that each GPU the library runs on holds until the process
+ * ends.  The call allocates nothing and does not synchronise: it only
+ * enqueues kernels on hip_stream.  prm: three-dimensional, any precision,
+ * no positivity option; count in [1, 524288]; X: count x 3 positions on the
+ * device (precision of prm), read only; phi: H^3 device grid (precision of
+ * prm), overwritten.  Non-finite positions are not reported.  All calls on
+ * one GPU share that GPU's array, so calls that overlap in time on one GPU
+ * (different streams or threads) race; serialise them.  Errors: SIPF_EINVAL
+ * (NULL pointer, invalid parameters, count out of range), SIPF_EDEVICE (a HIP
+ * launch failed or the scratch array's address could not be obtained).
+ */
+int sipf_deposit_noalloc(const sipf_params* prm, int64_t count, const void* X, void* phi,
+                         void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

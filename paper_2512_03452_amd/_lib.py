@@ -112,6 +112,7 @@ SIGNATURES = {
     "sipf_dbg_philox": [_u64, _i64, _vp, _vp, _vp, ctypes.c_int, _vp],
     "sipf_dbg_cells": [_pp, _i64, _vp, _vp, _vp],
     "sipf_dbg_deposit": [_pp, _i64, _vp, _vp, _vp],
+    "sipf_deposit_noalloc": [_pp, _i64, _vp, _vp, _vp],
 }
 _RESTYPES = {"sipf_last_error": ctypes.c_char_p}
 

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsipf.so")
-SOURCES = ["fft.hip", "field2d.hip", "particles.hip", "particles2d.hip", "adjoint.hip", "diag.hip", "direct.hip", "positivity.hip", "api.cpp"]
+SOURCES = ["fft.hip", "field2d.hip", "particles.hip", "particles2d.hip", "adjoint.hip", "diag.hip", "direct.hip", "positivity.hip", "noalloc.hip", "api.cpp"]
 ARCH = os.environ.get("SIPF_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -264,27 +264,18 @@ int dalloc(Group* g, void** p, size_t bytes) {
     return SIPF_OK;
 }
 
-template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
-    const Inst& I = g->in[i];
-    const sipf_params& p = I.prm;
+// The parameter-derived fields of a particle descriptor (buffers left null).
+template <typename T> PartDesc<T> pdesc_params(const sipf_params& p, int64_t P, int H, int dim, int tile) {
     PartDesc<T> d{};
-    d.x = (T*)I.xs[set];
-    d.y = (T*)I.ys[set];
-    d.z = (T*)I.zs[set];
-    d.id = I.ids[set];
-    d.P = I.P;
-    d.phi = (T*)I.phi;
-    d.G = (const T*)I.G;
-    d.step = g->steps + i;
-    d.err = g->errs + i;
-    d.H = I.H;
-    d.dim = I.dim;
+    d.P = P;
+    d.H = H;
+    d.dim = dim;
     d.scheme = p.scheme;
-    d.hl = (T)(I.H / p.L);
+    d.hl = (T)(H / p.L);
     d.L = (T)p.L;
     d.halfL = (T)(p.L / 2);
     d.invL = (T)(1.0 / p.L);
-    d.wmass = (T)(p.M0 / (double)I.P);
+    d.wmass = (T)(p.M0 / (double)P);
     d.chitau = (T)(p.chi * p.dt);
     d.s = (T)(p.scheme == SIPF_STRANG ? std::sqrt(p.mu * p.dt) : std::sqrt(2.0 * p.mu * p.dt));
     d.k0 = (uint32_t)p.seed;
@@ -293,10 +284,24 @@ template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
     // |W^-| <= s max|z| with max|z| = sqrt(-2 ln 2^-22) = 5.5176 (uniforms are >= 2^-22)
     d.gmargin = p.scheme == SIPF_STRANG ? (int)std::ceil((double)d.s * 5.52 * (double)d.hl) : 0;
     // the Morton key space is a power of two per axis; tiles past H / tile stay empty
-    d.tshift = is_pow2(I.H) && is_pow2(I.tile) ? ilog2(I.tile) : -1;
-    d.tile = I.tile;
-    const int nt = 1 << ilog2((I.H + I.tile - 1) / I.tile);
-    d.nkeys = I.dim == 2 ? nt * nt : nt * nt * nt;
+    d.tshift = is_pow2(H) && is_pow2(tile) ? ilog2(tile) : -1;
+    d.tile = tile;
+    const int nt = 1 << ilog2((H + tile - 1) / tile);
+    d.nkeys = dim == 2 ? nt * nt : nt * nt * nt;
+    return d;
+}
+
+template <typename T> PartDesc<T> make_pdesc(const Group* g, int i, int set) {
+    const Inst& I = g->in[i];
+    PartDesc<T> d = pdesc_params<T>(I.prm, I.P, I.H, I.dim, I.tile);
+    d.x = (T*)I.xs[set];
+    d.y = (T*)I.ys[set];
+    d.z = (T*)I.zs[set];
+    d.id = I.ids[set];
+    d.phi = (T*)I.phi;
+    d.G = (const T*)I.G;
+    d.step = g->steps + i;
+    d.err = g->errs + i;
     return d;
 }
 
@@ -1545,6 +1550,61 @@ int load_ctx(const char* path, void* hip_stream, sipf_ctx** out) {
 // ---------------------------------------------------------------------------
 // autotuner: coordinate search over (tile, chunk, resort period)
 // ---------------------------------------------------------------------------
+// The deposit of Algorithm 2 (load, tile sort, deposit-only particle pass)
+// on caller buffers, with every intermediate in the device's static scratch
+// array (noalloc.hip) instead of allocated memory.
+constexpr int64_t NOALLOC_MAX_P = int64_t(1) << 19;
+
+template <typename T> int deposit_noalloc_typed(const sipf_params* p, int64_t P, const void* X, void* phi, hipStream_t s) {
+    void* base = nullptr;
+    size_t bytes = 0;
+    HIPCHK(noalloc_scratch(&base, &bytes));
+    const int H = p->H, tile = default_tile(p), chunk = default_chunk(p, P);
+    const int mk = sort_max_keys(), sc = sort_chunk();
+    const int nchunks = (int)((P + sc - 1) / sc);
+    const int nt = (H + tile - 1) / tile;
+    const int cap = (int)((P + chunk - 1) / chunk) + nt * nt * nt;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        unsigned char* q = (unsigned char*)base + off;
+        off += (n + 255) / 256 * 256;
+        return q;
+    };
+    PartDesc<T> d[2];
+    for (int set = 0; set < 2; ++set) {
+        d[set] = pdesc_params<T>(*p, P, H, 3, tile);
+        d[set].x = (T*)take(P * sizeof(T));
+        d[set].y = (T*)take(P * sizeof(T));
+        d[set].z = (T*)take(P * sizeof(T));
+        d[set].id = (uint32_t*)take(P * sizeof(uint32_t));
+        d[set].phi = (T*)phi;
+    }
+    uint32_t* counts = (uint32_t*)take(mk * sizeof(uint32_t));
+    uint32_t* cursor = (uint32_t*)take(mk * sizeof(uint32_t));
+    PartDesc<T>* pd = (PartDesc<T>*)take(2 * sizeof(PartDesc<T>));
+    SortChunk* chunks = (SortChunk*)take(nchunks * sizeof(SortChunk));
+    WorkItem* seg = (WorkItem*)take(cap * sizeof(WorkItem));
+    int* seg_off = (int*)take(sizeof(int));
+    int* seg_n = (int*)take(sizeof(int));
+    WorkItem* items = (WorkItem*)take(cap * sizeof(WorkItem));
+    int* nitems = (int*)take(16);
+    int* err = (int*)take(sizeof(int));
+    uint32_t* step = (uint32_t*)take(sizeof(uint32_t));
+    if (off > bytes) return fail(SIPF_EINVAL, "the allocation-free scratch is too small for this call");
+    for (int set = 0; set < 2; ++set) {
+        d[set].step = step;
+        d[set].err = err;
+    }
+    HIPCHK(launch_noalloc_setup<T>(d[0], d[1], pd, chunks, nchunks, sc, seg_off, counts, mk, nitems, err, step, s));
+    HIPCHK(launch_fill<T>((T*)phi, (int64_t)H * H * H, (T)0, s));
+    HIPCHK(launch_load_positions<T>((const T*)X, P, (T)p->L, d[0], err, s));
+    HIPCHK(launch_sort<T>(3, pd, pd + 1, chunks, nchunks, 1, counts, cursor, seg, seg_off, seg_n, items, nitems, chunk, s));
+    const int win = particle_window_bytes(sizeof(T) == 8);
+    const int grid = std::max(1, std::min(cap, particle_resident_blocks<T>(p->scheme, win)));
+    HIPCHK(launch_particles<T>(pd + 1, items, nitems, grid, true, false, p->scheme, win, is_pow2(H), s));
+    return SIPF_OK;
+}
+
 int time_config(const sipf_params* prm, int64_t P, const void* X0, int x0_on_device, int nsteps, void* hip_stream,
                 double* ms) {
     sipf_ctx* c = nullptr;
@@ -1894,6 +1954,21 @@ int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t
         HIPCHK(launch_cells<double>((const double*)X, count, prm->H, (double)(prm->H / prm->L), cells, s));
     HIPCHK(hipStreamSynchronize(s));
     return SIPF_OK;
+}
+
+int sipf_deposit_noalloc(const sipf_params* prm, int64_t count, const void* X, void* phi, void* hip_stream) {
+    if (!prm || !X || !phi) return fail(SIPF_EINVAL, "NULL argument");
+    int rc = validate(prm, count);
+    if (rc) return rc;
+    if (dim_of(prm) != 3) return fail(SIPF_EINVAL, "the allocation-free deposit is three-dimensional");
+    if (prm->method == SIPF_METHOD_DIRECT) return fail(SIPF_EINVAL, "the direct SIPF method has no grid deposit");
+    if (prm->positivity) return fail(SIPF_EINVAL, "the allocation-free deposit has no positivity option");
+    if (count < 1 || count > NOALLOC_MAX_P)
+        return fail(SIPF_EINVAL, "count must be in [1, " + std::to_string(NOALLOC_MAX_P) +
+                                     "] for the allocation-free deposit (its scratch is a fixed-size device array)");
+    hipStream_t s = (hipStream_t)hip_stream;
+    return prm->precision == SIPF_FP32 ? deposit_noalloc_typed<float>(prm, count, X, phi, s)
+                                       : deposit_noalloc_typed<double>(prm, count, X, phi, s);
 }
 
 int sipf_dbg_deposit(const sipf_params* prm, int64_t count, const void* X, void* phi, void* hip_stream) {

@@ -276,6 +276,12 @@ template <typename T> hipError_t launch_axpby(T* y, const T* x, T a, T b, int64_
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int n, hipStream_t s);
 int sort_max_keys();
+// allocation-free deposit (noalloc.hip): this device's static scratch array
+hipError_t noalloc_scratch(void** out, size_t* bytes);
+template <typename T>
+hipError_t launch_noalloc_setup(const PartDesc<T>& d0, const PartDesc<T>& d1, PartDesc<T>* pd, SortChunk* chunks,
+                                int nchunks, int sort_chunk_size, int* seg_off, uint32_t* counts, int nkeys,
+                                int* nitems, int* err, uint32_t* step, hipStream_t s);
 int particle_threads();
 int particle_chunk();
 int particle_window_bytes(bool fp64);
