@@ -91,3 +91,42 @@ def test_adjoint_requires_initial_state():
     with pytest.raises(_lib.SipfError) as e:
         sim.adjoint(2, 1)
     assert e.value.code == _lib.SIPF_ESTATE
+
+
+# The adjoint workload's shape (H = 64, blob of sd 0.1, M0 = 80, tau = 5e-5,
+# N = 100 steps, a checkpoint every K = 10), with 1e5 particles in FP64 and
+# 2e4 in FP32 so that the FP64 oracle finishes within a minute.  Over 100
+# steps this collapsing run
+# amplifies input perturbations about 1e7-fold in dL/dX0 (two FP64 runs from
+# X0 and from X0 perturbed by 1e-12 differ by 2e-5 relative; from X0 rounded
+# through float32 they differ by O(1)), so FP32 forward rounding alone
+# decides its gradient: there the FP32 path is compared only in the two
+# conditioned variants below (N = 50; M0 = 20 at N = 100), where FP32 and FP64
+# agree to 3e-5.  FP64 against the FP64 oracle: rounding-order differences of
+# order 1e-16 amplified 1e7-fold give about 1e-9; 1e-8 bounds them (the
+# stated gradient tolerance is 1e-3).
+@pytest.mark.parametrize("precision,P,N,M0,tol", [
+    ("fp64", 100000, 100, 80.0, 1e-8),
+    ("fp32", 20000, 50, 80.0, 1e-3),
+    ("fp32", 20000, 100, 20.0, 1e-3),
+])
+def test_adjoint_at_the_adjoint_workload_shape(precision, P, N, M0, tol):
+    from paper_2512_03452_amd import workloads
+    cfg = workloads.CONFIGS["fp32_adjoint_h64"]
+    K = 10
+    kw = dict(cfg["params"], M0=M0)
+    kw.pop("precision")
+    say("adjoint workload shape", precision, "P", P, "N", N, "K", K, "M0", M0)
+    X0 = cfg["init"](P, seed=7).astype(np.float32 if precision == "fp32" else np.float64)
+    sim = pkg.Sim(X0, precision=precision, **kw)
+    loss, dchi, dmu, dX0 = sim.adjoint(N, K)
+    dX0 = dX0.cpu().numpy()
+    sim.close()
+    say("  gpu", loss, dchi, dmu)
+    ol, odX, ochi, omu = oadj.loss_and_grad(X0.astype(np.float64), osipf.Params(**kw), N)
+    say("  oracle", ol, ochi, omu, "rel dX0", rel(dX0, odX), "rel dchi", abs(dchi - ochi) / abs(ochi),
+        "rel dmu", abs(dmu - omu) / abs(omu))
+    assert abs(loss - ol) < tol * abs(ol)
+    assert abs(dchi - ochi) < tol * abs(ochi)
+    assert abs(dmu - omu) < tol * abs(omu)
+    assert rel(dX0, odX) < tol
