@@ -159,13 +159,17 @@ def cpu_baseline(workload, H, sample_P, steps, workers):
 
 def adjoint_ratio(pkg, workloads, np, torch):
     """fwd+adjoint time over forward time on the adjoint workload (same GPU),
-    in the workload's FP32 and in FP64.  Each adjoint runs twice from the same
-    inputs: the relative difference of the two dL/dX0 shows how far rounding
-    (summation order of the deposit) is amplified along the trajectory."""
+    in FP64 and in the workload's FP32.  Each adjoint runs twice from the same
+    inputs (the faster run is timed): the relative difference of the two dL/dX0
+    shows how far rounding (summation order of the deposit) is amplified along
+    the trajectory.  The headline ratio is FP64's: over these 100 steps the
+    gradient is ill-conditioned (inputs perturbed at the float32 rounding level
+    change it by O(1) even in FP64), so only FP64 gives it reproducibly and at
+    the oracle's accuracy."""
     cfg = workloads.CONFIGS["fp32_adjoint_h64"]
     P, N, K = cfg["P"], cfg["steps"], 10
     out = {"workload": "fp32_adjoint_h64", "P": P, "H": cfg["params"]["H"], "steps": N, "ckpt_every": K}
-    for prec in ("fp32", "fp64"):
+    for prec in ("fp64", "fp32"):
         params = dict(cfg["params"], precision=prec)
         X0 = cfg["init"](P).astype(np.float32 if prec == "fp32" else np.float64)
         sim = pkg.Sim(X0, **params)
@@ -194,7 +198,8 @@ def adjoint_ratio(pkg, workloads, np, torch):
                      "loss": runs[0][1], "dchi": [runs[0][2], runs[1][2]], "dmu": [runs[0][3], runs[1][3]],
                      "dX0_rel_diff_between_runs": float(torch.linalg.norm(a - b) / torch.linalg.norm(a)),
                      "grad_finite": bool(np.isfinite(runs[0][2]) and torch.isfinite(a).all().item())}
-    out["ratio"] = out["fp32"]["ratio"]
+    out["ratio"] = out["fp64"]["ratio"]
+    out["ratio_precision"] = "fp64"
     return out
 
 

@@ -404,6 +404,10 @@ int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t
 int sipf_dbg_deposit(const sipf_params* prm, int64_t count, const void* X, void* phi,
                      void* hip_stream);
 
+/* Return to the device the work buffers that sipf_adjoint keeps between
+ * calls (on every device).  Call with no adjoint running. */
+int sipf_release_cached_memory(void);
+
 /*
  * Allocation-free deposit, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -113,6 +113,7 @@ SIGNATURES = {
     "sipf_dbg_cells": [_pp, _i64, _vp, _vp, _vp],
     "sipf_dbg_deposit": [_pp, _i64, _vp, _vp, _vp],
     "sipf_deposit_noalloc": [_pp, _i64, _vp, _vp, _vp],
+    "sipf_release_cached_memory": [],
 }
 _RESTYPES = {"sipf_last_error": ctypes.c_char_p}
 

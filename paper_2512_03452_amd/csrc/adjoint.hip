@@ -144,6 +144,9 @@ template <> struct AdjShape<double> { static constexpr int PT = 512, PPT = 8; };
 #ifndef ADJ_UNROLL
 #define ADJ_UNROLL 1
 #endif
+#ifndef ADJ_BATCH
+#define ADJ_BATCH 4
+#endif
 
 // Gbar accumulator: a term t (already scaled by 2^S) is added as round(t); S is
 // chosen per item so that every node sum stays below 2^E in magnitude.
@@ -175,7 +178,6 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
     const size_t H3 = (size_t)H * H * H;
     // the load phase keeps the particles only long enough for the bounding box
     // and the cotangent bound; the main loop re-reads each one from L2
-    T px[APPT], py[APPT], pz[APPT], qx[APPT], qy[APPT], qz[APPT];
     if (tid < 3) sh[tid] = INT_MAX;
     else if (tid < 6) sh[tid] = INT_MIN;
     else if (tid == 6) sh[6] = 0;
@@ -183,30 +185,37 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
     const int rx = ifloor(a.x[beg] * hl) & Hm, ry = ifloor(a.y[beg] * hl) & Hm, rz = ifloor(a.z[beg] * hl) & Hm;
     int mnx = INT_MAX, mny = INT_MAX, mnz = INT_MAX, mxx = INT_MIN, mxy = INT_MIN, mxz = INT_MIN;
     float bmax = 0.f;
+    // in batches of ADJ_BATCH particles per thread, to bound the registers held
+    constexpr int NB = APPT < ADJ_BATCH ? APPT : ADJ_BATCH;
 #pragma unroll
-    for (int k = 0; k < APPT; ++k) {
-        const int j = tid + k * APT;
-        const uint32_t jj = (uint32_t)(j < cnt ? j : cnt - 1);  // in-item index for every lane: branch-free loads
-        px[k] = gp(a.x + beg)[jj];
-        py[k] = gp(a.y + beg)[jj];
-        pz[k] = gp(a.z + beg)[jj];
-        qx[k] = gp(a.xbx + beg)[jj];
-        qy[k] = gp(a.xby + beg)[jj];
-        qz[k] = gp(a.xbz + beg)[jj];
-    }
+    for (int k0 = 0; k0 < APPT; k0 += NB) {
+        T px[NB], py[NB], pz[NB], qx[NB], qy[NB], qz[NB];
 #pragma unroll
-    for (int k = 0; k < APPT; ++k) {
-        const int j = tid + k * APT;
-        if (j < cnt) {
-            const int cx = (((ifloor(px[k] * hl) & Hm) - rx + Hh) & Hm) - Hh;
-            const int cy = (((ifloor(py[k] * hl) & Hm) - ry + Hh) & Hm) - Hh;
-            const int cz = (((ifloor(pz[k] * hl) & Hm) - rz + Hh) & Hm) - Hh;
-            mnx = min(mnx, cx); mxx = max(mxx, cx);
-            mny = min(mny, cy); mxy = max(mxy, cy);
-            mnz = min(mnz, cz); mxz = max(mxz, cz);
-            // |x| rounded up to float (values beyond float range give +inf)
-            const float m3 = (float)fmax(fmax(fabs((double)qx[k]), fabs((double)qy[k])), fabs((double)qz[k]));
-            bmax = fmaxf(bmax, m3 * 1.0000002f);
+        for (int kk = 0; kk < NB; ++kk) {
+            const int j = tid + (k0 + kk) * APT;
+            const uint32_t jj = (uint32_t)(j < cnt ? j : cnt - 1);  // in-item index for every lane: branch-free loads
+            px[kk] = gp(a.x + beg)[jj];
+            py[kk] = gp(a.y + beg)[jj];
+            pz[kk] = gp(a.z + beg)[jj];
+            qx[kk] = gp(a.xbx + beg)[jj];
+            qy[kk] = gp(a.xby + beg)[jj];
+            qz[kk] = gp(a.xbz + beg)[jj];
+        }
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) {
+            const int j = tid + (k0 + kk) * APT;
+            if (j < cnt) {
+                const int cx = (((ifloor(px[kk] * hl) & Hm) - rx + Hh) & Hm) - Hh;
+                const int cy = (((ifloor(py[kk] * hl) & Hm) - ry + Hh) & Hm) - Hh;
+                const int cz = (((ifloor(pz[kk] * hl) & Hm) - rz + Hh) & Hm) - Hh;
+                mnx = min(mnx, cx); mxx = max(mxx, cx);
+                mny = min(mny, cy); mxy = max(mxy, cy);
+                mnz = min(mnz, cz); mxz = max(mxz, cz);
+                // |x| rounded up to float (values beyond float range give +inf)
+                const float m3 =
+                    (float)fmax(fmax(fabs((double)qx[kk]), fabs((double)qy[kk])), fabs((double)qz[kk]));
+                bmax = fmaxf(bmax, m3 * 1.0000002f);
+            }
         }
     }
     mnx = wave_min(mnx); mny = wave_min(mny); mnz = wave_min(mnz);
@@ -284,15 +293,23 @@ __device__ __forceinline__ void adj_item(const AdjDesc<T>& a, int64_t beg, int c
         const T xb[3] = {gp(a.xbx + beg)[j], gp(a.xby + beg)[j], gp(a.xbz + beg)[j]};
         const uint32_t pidk = gp(a.id + beg)[j];
         T zm[3], zp[3], Y[3], zn[6];
-        if (SCHEME == SIPF_STRANG) {
+        if (a.zin != nullptr) {
+            // the normals kept by the segment's forward recompute
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                zn[q] = (SCHEME == SIPF_STRANG || q < 3) ? gp(a.zin + q * a.P + beg)[j] : (T)0;
+        } else if (SCHEME == SIPF_STRANG) {
             noise6<3, T>(pidk, a.n, a.inst, a.k0, a.k1, zn);
+        } else {
+            noise6<2, T>(pidk, a.n, a.inst, a.k0, a.k1, zn);
+        }
+        if (SCHEME == SIPF_STRANG) {
             for (int d = 0; d < 3; ++d) {
                 zm[d] = zn[d];
                 zp[d] = zn[3 + d];
                 Y[d] = X[d] + a.s * zm[d];
             }
         } else {
-            noise6<2, T>(pidk, a.n, a.inst, a.k0, a.k1, zn);
             for (int d = 0; d < 3; ++d) {
                 zp[d] = zn[d];
                 zm[d] = 0;

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1195,12 +1196,79 @@ int destroy_any(Group* g) {
 // ---------------------------------------------------------------------------
 
 // Device buffer freed when it goes out of scope (adjoint temporaries).
+// Device work buffers of the adjoint are kept for later calls instead of
+// freed: an FP64 adjoint of 2e6 particles holds about 2 GB of tape, segment
+// and noise buffers, and hipMalloc + hipFree of those cost milliseconds per
+// call (hipFree also waits for the device).  Cached blocks are reused by any
+// later adjoint on the same device whose request fits (best fit, at most
+// twice the request) and returned by sipf_release_cached_memory.
+struct BufCache {
+    struct Blk {
+        int dev;
+        size_t n;
+        void* p;
+    };
+    std::mutex mu;
+    std::vector<Blk> free_blocks;
+    hipError_t get(size_t n, void** out) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            int best = -1;
+            for (int i = 0; i < (int)free_blocks.size(); ++i) {
+                const Blk& b = free_blocks[i];
+                if (b.dev == dev && b.n >= n && b.n <= 2 * n && (best < 0 || b.n < free_blocks[best].n)) best = i;
+            }
+            if (best >= 0) {
+                *out = free_blocks[best].p;
+                free_blocks.erase(free_blocks.begin() + best);
+                return hipSuccess;
+            }
+        }
+        return hipMalloc(out, n);
+    }
+    void put(void* p, size_t n) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p);
+            return;
+        }
+        std::lock_guard<std::mutex> lock(mu);
+        free_blocks.push_back({dev, n, p});
+    }
+    void release() {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const Blk& b : free_blocks) {
+            int cur = 0;
+            if (hipGetDevice(&cur) == hipSuccess && cur != b.dev) (void)hipSetDevice(b.dev);
+            (void)hipFree(b.p);
+            if (cur != b.dev) (void)hipSetDevice(cur);
+        }
+        free_blocks.clear();
+    }
+};
+BufCache g_buf_cache;
+
 struct DevBuf {
     void* p = nullptr;
+    size_t n = 0;
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p) g_buf_cache.put(p, n);
     }
-    hipError_t alloc(size_t n) { return hipMalloc(&p, n ? n : 16); }
+    hipError_t alloc(size_t bytes) {
+        n = bytes ? bytes : 16;
+        return g_buf_cache.get(n, &p);
+    }
+};
+
+// Waits for a stream when it goes out of scope (declared after a function's
+// DevBufs, it runs before they return to the cache, on every exit path).
+struct StreamSync {
+    hipStream_t s;
+    ~StreamSync() { (void)hipStreamSynchronize(s); }
 };
 
 template <typename T> PartDesc<T> pdesc_on(const Group* g, T* x, T* y, T* z, uint32_t* id) {
@@ -1255,7 +1323,15 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         }
         return SIPF_OK;
     };
-    DevBuf tape, ckpt, seg, Gseg, xbar, xbs, Gbar, phibar, abar, aN, scr, gs1, fdS, fdA, fdR, pdR, pdS, consts, acc;
+    DevBuf tape, ckpt, seg, Gseg, xbar, xbs, Gbar, phibar, abar, aN, scr, gs1, fdS, fdA, fdR, pdR, pdS, consts, acc,
+        zseg;
+    const StreamSync drain{c->stream};  // no work on these buffers is pending when they go back to the cache
+    // FP64: the segment's forward recompute keeps each step's normals for the
+    // reverse pass, whose double-precision Box-Muller would otherwise redraw
+    // them (about 0.1 ms per step on the adjoint workload; the normals cost
+    // 48 bytes per particle written and read once).  FP32 redraws them: there
+    // the draw hides under the pass's other work.
+    const bool keep_noise = sizeof(T) == 8 && K > 1;
     if ((rc = need(tape, (size_t)N * nspec * sizeof(V)))) return rc;
     if ((rc = need(ckpt, (size_t)nseg * pos_bytes))) return rc;
     if ((rc = need(seg, (size_t)K * pos_bytes))) return rc;
@@ -1275,6 +1351,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     if ((rc = need(pdS, (size_t)(nseg + 1) * sizeof(PartDesc<T>)))) return rc;
     if ((rc = need(consts, (size_t)N * sizeof(uint32_t)))) return rc;
     if ((rc = need(acc, 4 * sizeof(double)))) return rc;
+    if (keep_noise && (rc = need(zseg, (size_t)(K - 1) * 6 * P * sizeof(T)))) return rc;
     // position slot j of a buffer: x, y, z, id
     auto slot = [&](void* base, int64_t j, T*& x, T*& y, T*& z, uint32_t*& id) {
         char* b = (char*)base + (size_t)j * pos_bytes;
@@ -1296,6 +1373,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         f.phi = (T*)Gbar.p;
         f.B1 = (V*)scr.p;
         f.alpha = (V*)abar.p;
+        f.gspec = (V*)gs1.p;  // the fused accumulation + source pass writes the source spectrum here
         f.step = nullptr;
         HIPCHK(hipMemcpy(fdA.p, &f, sizeof(f), hipMemcpyHostToDevice));
         // per step t: gradient grids of the taped alpha^(t) into the segment store,
@@ -1321,6 +1399,8 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
             pr[t].oid = id1;
             pr[t].G = gseg + (size_t)(t % K) * 3 * H3;
             pr[t].step = (const uint32_t*)consts.p + t;
+            // the normals of step t + 1, read back by the reverse pass of that step
+            pr[t].zout = keep_noise && (int)(t % K) + 1 < K ? (T*)zseg.p + (size_t)(t % K) * 6 * P : nullptr;
         }
         HIPCHK(hipMemcpy(fdR.p, fr.data(), fr.size() * sizeof(FieldDesc<T>), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(pdR.p, pr.data(), pr.size() * sizeof(PartDesc<T>), hipMemcpyHostToDevice));
@@ -1404,6 +1484,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     // ---- reverse sweep, one checkpoint segment at a time
     HIPCHK(launch_fill<T>((T*)Gbar.p, (int64_t)(3 * H3), (T)0, c->stream));
     const PartDesc<T>* ps_dev = (const PartDesc<T>*)pdS.p;
+    bool src_ready = false;  // phibar^(n-1) already made by the fused pass of step n + 1
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
         const int64_t base = sgi * K;
         const int len = (int)std::min<int64_t>(K, N - base);
@@ -1426,10 +1507,11 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         for (int64_t n = base + len; n > base; --n) {
             // (a) phibar^(n-1) = L^-3 C2R(B abar^(n)); zero at n = N (abar^(N) = 0)
             const bool src = n < N;
-            if (src) {
+            if (src && !src_ready) {
                 HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdS.p, 1, XP_ADJ_SRC, c->stream));
                 HIPCHK(launch_inv_planes<T>(H, (const FieldDesc<T>*)fdS.p, 1, 1, c->stream));
             }
+            src_ready = false;
             // (b) particles of X^(n-1) with G^(n-1) (Gbar is zero: cleared once before the
             // sweep, then by the forward plane pass that consumes it)
             T *x, *y, *z;
@@ -1442,10 +1524,19 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
             ad.G = gseg + (size_t)(n - 1 - base) * 3 * H3;
             ad.phibar = src ? (const T*)phibar.p : nullptr;
             ad.n = (uint32_t)n;
+            // steps base+1 .. base+len-1 were pushed by the recompute, which kept their normals
+            ad.zin = keep_noise && n < base + len ? (const T*)zseg.p + (size_t)(n - base - 1) * 6 * P : nullptr;
             HIPCHK(launch_adj_items<T>(ad, c->items, c->nitems, c->pgrid, c->stream));
-            // (c) abar^(n-1) = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d)
+            // (c) abar^(n-1) = A abar^(n) + sum_d (-i xi_d Phi) R2C(Gbar_d); for n > 1 the
+            // same pass also makes the source term of abar^(n-1), i.e. phibar^(n-2) of step n - 1
             HIPCHK(launch_fwd_planes<T>(H, (const FieldDesc<T>*)fdA.p, 1, 3, true, c->stream));
-            HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdA.p, 1, XP_ADJ_ACC, c->stream));
+            if (n > 1) {
+                HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdA.p, 1, XP_ADJ_ACC_SRC, c->stream));
+                HIPCHK(launch_inv_planes<T>(H, (const FieldDesc<T>*)fdS.p, 1, 1, c->stream));
+                src_ready = true;
+            } else {
+                HIPCHK(launch_xpencils<T>(H, (const FieldDesc<T>*)fdA.p, 1, XP_ADJ_ACC, c->stream));
+            }
         }
         {
             T *x, *y, *z;
@@ -1953,6 +2044,11 @@ int sipf_dbg_cells(const sipf_params* prm, int64_t count, const void* X, int32_t
     else
         HIPCHK(launch_cells<double>((const double*)X, count, prm->H, (double)(prm->H / prm->L), cells, s));
     HIPCHK(hipStreamSynchronize(s));
+    return SIPF_OK;
+}
+
+int sipf_release_cached_memory(void) {
+    g_buf_cache.release();
     return SIPF_OK;
 }
 

@@ -160,7 +160,10 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
 // MODE_RHO:  forward x of B1 (a deposit), Gaussian factor Phi and L^-3, inverse x
 //            into gspec component 0: the regularised density rho_hat * G0 after
 //            the inverse plane pass.
-enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3, MODE_RHO = 4 };
+// MODE_ADJ_ACC_SRC: MODE_ADJ_ACC, then MODE_ADJ_SRC of the updated abar in the
+//            same pass (the reverse sweep needs the source term of abar^(n-1)
+//            right after accumulating it).
+enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3, MODE_RHO = 4, MODE_ADJ_ACC_SRC = 5 };
 
 template <typename T, int H, int MODE>
 __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>* __restrict__ fds) {
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
     make_twiddles<T, H>(tw);
     const int ky = perm_freq<H>(kyp);
     const T qy = (T)(ky < H / 2 ? ky : ky - H);
-    if constexpr (MODE == MODE_ADJ_SRC || MODE == MODE_ADJ_ACC) {
+    if constexpr (MODE == MODE_ADJ_SRC || MODE == MODE_ADJ_ACC || MODE == MODE_ADJ_ACC_SRC) {
         adjoint_pencils<T, H, MODE>(fd, kyp, kz0, ncol, qy, ky, buf, abuf, tw);
         return;
     }
@@ -343,13 +346,30 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
         __syncthreads();
         for (int u = tid; u < H * KB; u += nt) {
             const int p = u / KB, j = u % KB;
-            if (j >= ncol) continue;
+            if (j >= ncol) {
+                if (MODE == MODE_ADJ_ACC_SRC) buf[p * BP + j] = cmake<V, T>(0, 0);
+                continue;
+            }
             T A, B, phi, xi[3];
             factors(p, j, A, B, phi, xi);
             const size_t ai = ((size_t)p * H + kyp) * HH + kz0 + j;
             const V a = fd.alpha[ai];
             const V acc = abuf[p * BP + j];
-            fd.alpha[ai] = cmake<V, T>(A * a.x + acc.x, A * a.y + acc.y);
+            const V na = cmake<V, T>(A * a.x + acc.x, A * a.y + acc.y);
+            fd.alpha[ai] = na;
+            if (MODE == MODE_ADJ_ACC_SRC) {
+                const T sc = B * fd.inv_Ld;
+                buf[p * BP + j] = cmake<V, T>(na.x * sc, na.y * sc);
+            }
+        }
+        if constexpr (MODE == MODE_ADJ_ACC_SRC) {
+            __syncthreads();
+            lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
+            __syncthreads();
+            for (int u = tid; u < H * KB; u += nt) {
+                const int ix = u / KB, j = u % KB;
+                if (j < ncol) fd.gspec[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
+            }
         }
     }
 }
@@ -623,6 +643,7 @@ static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStr
         case MODE_GRAD: launch_kernel((k_xpencils<T, H, MODE_GRAD>), g, b, 0, s, fd); break;
         case MODE_ADJ_SRC: launch_kernel((k_xpencils<T, H, MODE_ADJ_SRC>), g, b, 0, s, fd); break;
         case MODE_ADJ_ACC: launch_kernel((k_xpencils<T, H, MODE_ADJ_ACC>), g, b, 0, s, fd); break;
+        case MODE_ADJ_ACC_SRC: launch_kernel((k_xpencils<T, H, MODE_ADJ_ACC_SRC>), g, b, 0, s, fd); break;
         case MODE_RHO: launch_kernel((k_xpencils<T, H, MODE_RHO>), g, b, 0, s, fd); break;
         default: return hipErrorInvalidValue;
     }

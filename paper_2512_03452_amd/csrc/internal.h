@@ -104,6 +104,7 @@ template <typename T> struct PartDesc {
     T* oy;
     T* oz;
     uint32_t* oid;
+    T* zout;                // push-only passes: the step's normals out (SoA, 6 x P in particle order), or null
 };
 
 // A run of sort-chunk particles of one instance (sort kernels).
@@ -137,6 +138,7 @@ template <typename T> struct AdjDesc {
     T s;
     uint32_t k0, k1, inst, n;
     int gmargin;            // cells the W^- displacement can reach
+    const T* zin;           // the step's normals (SoA, 6 x P in the order of x), or null: drawn here
 };
 
 // Work item of the particle pass: particles [beg, beg + cnt) of instance inst.
@@ -153,7 +155,7 @@ struct WorkItem {
 //             the input and advance the step counter (the step's deposit).
 // xpencils:   mode MODE_STEP / MODE_GRAD / MODE_ADJ_SRC / MODE_ADJ_ACC / MODE_RHO (fft.hip).
 // inv_planes: C2R of ncomp spectra (gspec + c spectrum -> G + c H^3).
-enum { XP_STEP = 0, XP_GRAD = 1, XP_ADJ_SRC = 2, XP_ADJ_ACC = 3, XP_RHO = 4 };
+enum { XP_STEP = 0, XP_GRAD = 1, XP_ADJ_SRC = 2, XP_ADJ_ACC = 3, XP_RHO = 4, XP_ADJ_ACC_SRC = 5 };
 template <typename T>
 hipError_t launch_fwd_planes(int H, const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s);
 template <typename T> hipError_t launch_xpencils(int H, const FieldDesc<T>* fd, int count, int mode, hipStream_t s);

@@ -38,11 +38,15 @@ constexpr int MIN_WINDOW_ITEM = 64;  // smaller items deposit and gather straigh
 #ifndef SIPF_PUSH_UNROLL
 #define SIPF_PUSH_UNROLL 8
 #endif
-// Minimum waves per SIMD the register allocation must leave room for
-// (0: the compiler's choice).  Six waves per SIMD hold three 512-thread
-// workgroups per CU, which the LDS windows also allow.
+// Minimum waves per SIMD the register allocation of the two-phase passes
+// (FP64 steps, and the deposit-only and push-only passes of both precisions)
+// must leave room for; 0 leaves it to the compiler.  A budget of six waves
+// spilled 50-105 VGPRs in FP64: on the adjoint workload (P = 2e6, H = 64, 100
+// steps) the compiler's choice took the FP64 forward from 27.1 to 22.8 ms and
+// forward + adjoint from 87.5 to 73.5 ms (a budget of four: 24.8 and 76.2 ms);
+// FP32 forward + adjoint 36.9 -> 36.5 ms.
 #ifndef SIPF_PART_WAVES
-#define SIPF_PART_WAVES 6
+#define SIPF_PART_WAVES 0
 #endif
 #if SIPF_PART_WAVES > 0
 #define SIPF_PART_ATTR __attribute__((amdgpu_waves_per_eu(SIPF_PART_WAVES)))
@@ -566,6 +570,11 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
             const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
             const T ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
             const T nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
+            if (!DEP && a.zout != nullptr) {
+                // keep the normals of this step for the reverse pass (adjoint recompute)
+                const int nz6 = SCHEME == SIPF_STRANG ? 6 : 3;
+                for (int q = 0; q < nz6; ++q) gp(a.zout + q * a.P + beg)[j] = zn[q];
+            }
             if (!DEP && a.ox != nullptr) {
                 // out of place (push-only passes): positions and ids to the output set
                 gp(a.ox + beg)[j] = nx;
@@ -1089,21 +1098,48 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* _
         if (h[i]) atomicAdd(&cnt[i], h[i]);
 }
 
+// Block-wide exclusive scans of NV values per thread (1024 threads = 16
+// waves): inclusive scans inside each wave with lane shuffles, the wave
+// totals through LDS (part: at least 16 NV words), one barrier between.
+// totals[v] receives the block sum of value v.
+template <int NV>
+__device__ __forceinline__ void block_exclusive_scan_n(uint32_t* v, uint32_t* part, uint32_t* totals) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t inc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) inc[q] = v[q];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const uint32_t u = __shfl_up(inc[q], off, 64);
+            if (lane >= off) inc[q] += u;
+        }
+    }
+    __syncthreads();  // part may still be read by a previous scan
+    if (lane == 63)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) part[q * 16 + w] = inc[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        uint32_t before = 0, all = 0;
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t t = part[q * 16 + k];
+            before += k < w ? t : 0u;
+            all += t;
+        }
+        totals[q] = all;
+        v[q] = before + inc[q] - v[q];
+    }
+}
+
 // Block-wide exclusive scan of one value per thread (1024 threads).
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* part, uint32_t& total) {
-    const int tid = threadIdx.x;
-    part[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t u = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += u;
-        __syncthreads();
-    }
-    total = part[1023];
-    const uint32_t r = part[tid] - v;
-    __syncthreads();
-    return r;
+    uint32_t x[1] = {v}, t[1];
+    block_exclusive_scan_n<1>(x, part, t);
+    total = t[0];
+    return x[0];
 }
 
 // One workgroup per instance: exclusive scan of the tile counts into the
@@ -1137,10 +1173,12 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
         if (loc[j] >= half) ibig += nit[j];
         else if (loc[j] > 0) ismall += 1u;
     }
-    uint32_t total, tbig, tsmall;
-    uint32_t run = block_exclusive_scan(sum, part, total);
-    uint32_t rbig = block_exclusive_scan(ibig, part, tbig);
-    uint32_t rsmall = tbig + block_exclusive_scan(ismall, part, tsmall);
+    uint32_t sc[3] = {sum, ibig, ismall}, tot[3];
+    block_exclusive_scan_n<3>(sc, part, tot);
+    const uint32_t tbig = tot[1], tsmall = tot[2];
+    uint32_t run = sc[0];
+    uint32_t rbig = sc[1];
+    uint32_t rsmall = tbig + sc[2];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int i = tid * PER + j;
