@@ -130,6 +130,22 @@ extern "C" {
  * batch share it; sipf_adjoint returns SIPF_EINVAL.  It applies to the step's
  * deposit, sipf_get_field(SIPF_FIELD_RHO) and sipf_diagnostics. */
 
+/* sipf_params.particle_pass: how the FP32 3-D step runs its particle pass
+ * (deposit of Algorithm 2, then gather and push of Algorithm 3).  Both give
+ * the same deposit up to the rounding of the weights' fixed-point sums, and
+ * the same positions; they differ in speed, which depends on the workload.
+ *   SIPF_PASS_TWO_PHASE  each work item (particles of one tile) deposits all
+ *                        its particles, then gathers and pushes them;
+ *   SIPF_PASS_SORTED     each work item keeps its particles sorted by cell,
+ *                        deposits runs of equal cells as one sum, and pushes
+ *                        particles while it deposits (both LDS windows live);
+ *   SIPF_PASS_DEFAULT    the two-phase pass for a single instance, the sorted
+ *                        pass for a batch of several.
+ * FP64 and 2-D steps always take the two-phase pass. */
+#define SIPF_PASS_DEFAULT   0
+#define SIPF_PASS_SORTED    1
+#define SIPF_PASS_TWO_PHASE 2
+
 /* arithmetic precision of particles, grids and spectra */
 #define SIPF_FP32 0
 #define SIPF_FP64 1
@@ -172,6 +188,8 @@ typedef struct sipf_params {
     int32_t  propagator;   /* SIPF_PROP_IMPLICIT (default) or SIPF_PROP_EXP (needs eps > 0) */
     int32_t  method;       /* SIPF_METHOD_PIC (default, Algorithm 4) or SIPF_METHOD_DIRECT */
     int32_t  positivity;   /* 1: positivity-preserving deposit (see below), 0: plain order 4 */
+    int32_t  particle_pass; /* FP32 3-D deposit + push pass: SIPF_PASS_DEFAULT, SIPF_PASS_SORTED
+                               or SIPF_PASS_TWO_PHASE (see below); ignored elsewhere          */
 } sipf_params;
 
 typedef struct sipf_ctx sipf_ctx;
@@ -340,9 +358,10 @@ const char* sipf_last_error(void);
  * meaning as in sipf_init), searching one axis at a time: the binning tile
  * (powers of two from 4 to 32, or 4, 6, 8, 12, 16, 24, 32 when H is not a
  * power of two, within the limits of sipf_params.tile), the
- * work-item size (1024, 2048, 3072, 4096) and the re-sort period (2, 4, 6, 8, 16),
- * starting from the defaults.  *best receives prm with tile, chunk and
- * resort_every set to the fastest combination found, *ms_per_step its time.
+ * work-item size (1024, 2048, 3072, 4096), the re-sort period (2, 4, 6, 8, 16)
+ * and, for FP32 3-D steps, the particle pass (sorted, two-phase), starting
+ * from the defaults.  *best receives prm with tile, chunk, resort_every and
+ * particle_pass set to the fastest combination found, *ms_per_step its time.
  * Every trial context is destroyed before return; each needs the memory of
  * one sipf_init.  Synchronises.  Errors: those of sipf_init.
  */

@@ -28,6 +28,9 @@ SIPF_PROP_IMPLICIT = 0
 SIPF_PROP_EXP = 1
 SIPF_METHOD_PIC = 0
 SIPF_METHOD_DIRECT = 1
+SIPF_PASS_DEFAULT = 0
+SIPF_PASS_SORTED = 1
+SIPF_PASS_TWO_PHASE = 2
 SIPF_FIELD_RHO = 0
 SIPF_FIELD_ALPHA = 1
 SIPF_FIELD_GRAD = 2
@@ -45,6 +48,7 @@ class SipfParams(ctypes.Structure):
         ("resort_every", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32), ("dim", ctypes.c_uint32),
         ("propagator", ctypes.c_int32), ("method", ctypes.c_int32), ("positivity", ctypes.c_int32),
+        ("particle_pass", ctypes.c_int32),
     ]
 
 
@@ -156,6 +160,8 @@ def default_params(**overrides):
             v = {"implicit": SIPF_PROP_IMPLICIT, "exp": SIPF_PROP_EXP}[v]
         if k == "method" and isinstance(v, str):
             v = {"pic": SIPF_METHOD_PIC, "direct": SIPF_METHOD_DIRECT}[v]
+        if k == "particle_pass" and isinstance(v, str):
+            v = {"default": SIPF_PASS_DEFAULT, "sorted": SIPF_PASS_SORTED, "two_phase": SIPF_PASS_TWO_PHASE}[v]
         if not hasattr(p, k):
             raise KeyError(f"unknown parameter {k}")
         setattr(p, k, v)

@@ -83,6 +83,8 @@ int validate(const sipf_params* p, int64_t P) {
     if (p->method == SIPF_METHOD_DIRECT && p->H > 128)
         return fail(SIPF_EINVAL, "the direct SIPF method takes H <= 128");
     if (p->positivity != 0 && p->positivity != 1) return fail(SIPF_EINVAL, "positivity must be 0 or 1");
+    if (p->particle_pass < SIPF_PASS_DEFAULT || p->particle_pass > SIPF_PASS_TWO_PHASE)
+        return fail(SIPF_EINVAL, "particle_pass must be SIPF_PASS_DEFAULT, SIPF_PASS_SORTED or SIPF_PASS_TWO_PHASE");
     if (p->positivity && (dim_of(p) != 3 || p->method != SIPF_METHOD_PIC))
         return fail(SIPF_EINVAL, "the positivity-preserving deposit is for the 3-D SIPF-PIC step");
     if (p->p2g_order != 4) return fail(SIPF_EINVAL, "p2g_order must be 4");
@@ -155,6 +157,12 @@ int default_chunk(const sipf_params* p, int64_t total_P) {
 // holds one 512-thread workgroup per CU and prefers smaller items (adjoint
 // workload, P = 2e6: reverse sweep ~0.75 ms shorter at 2048 than at 3072).
 int default_adj_chunk(const sipf_params* p, int chunk) { return p->chunk ? p->chunk : std::min(chunk, 2048); }
+// FP32 3-D deposit + push pass: sorted items or the two-phase pass (the
+// choice is shared by a group's instances).
+bool sorted_pass(const sipf_params* p, int n) {
+    if (p->particle_pass) return p->particle_pass == SIPF_PASS_SORTED;
+    return n > 1;
+}
 
 }  // namespace
 
@@ -204,6 +212,7 @@ struct Group {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     int resort = 4, chunk = 4096, adj_chunk = 2048, win_bytes = 65536, pgrid = 1024;
+    bool sorted = false;  // FP32 3-D deposit + push: the sorted pass (else two-phase)
     int since_sort = 0;
     int cur = 0;  // which of the two particle buffer sets holds the current positions
     int64_t n_host = 0;
@@ -420,7 +429,7 @@ hipError_t particles_any(const Group* g, const PartDesc<T>* pd, bool deposit, bo
     return g->dim == 2 ? launch_particles2<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
                                               g->win_bytes, g->stream)
                        : launch_particles<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
-                                             g->win_bytes, g->pow2, g->stream);
+                                             g->win_bytes, g->pow2, g->sorted, g->stream);
 }
 template <typename T> hipError_t field_fwd(const Group* g, int H, const FieldDesc<T>* fd, int count, bool consume) {
     return g->dim == 2 ? launch_fwd_rows2<T>(H, fd, count, consume, g->stream)
@@ -838,7 +847,8 @@ template <typename T> int alloc_group(Group* g) {
         }
     }
     g->pgrid = std::max(1, std::min(g->items_cap, g->dim == 2 ? particle_resident_blocks2<T>(g->scheme, g->win_bytes)
-                                                                : particle_resident_blocks<T>(g->scheme, g->win_bytes)));
+                                                                : particle_resident_blocks<T>(g->scheme, g->win_bytes,
+                                                                                              g->sorted)));
     return upload_descs<T>(g);
 }
 
@@ -960,6 +970,8 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
         if (dim_of(&prm[i]) != dim_of(&prm[0])) return fail(SIPF_EINVAL, "all instances must share the dimension");
         if (prm[i].positivity != prm[0].positivity)
             return fail(SIPF_EINVAL, "all instances must share the positivity option");
+        if (prm[i].particle_pass != prm[0].particle_pass)
+            return fail(SIPF_EINVAL, "all instances must share the particle pass");
     }
     if (prm[0].method == SIPF_METHOD_DIRECT && n != 1)
         return fail(SIPF_EINVAL, "the direct SIPF method runs single contexts, not batches");
@@ -988,6 +1000,7 @@ int setup_group(Group* g, int32_t n, const sipf_params* prm, const int64_t* P, c
     g->chunk = default_chunk(&prm[0], total_P);
     g->adj_chunk = default_adj_chunk(&prm[0], g->chunk);
     g->win_bytes = particle_window_bytes(g->prec == SIPF_FP64);
+    g->sorted = sorted_pass(&prm[0], n);
     g->in.resize(n);
     for (int i = 0; i < n; ++i) {
         Inst& I = g->in[i];
@@ -1440,7 +1453,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     // ---- loss and its cotangent phibar^(N)
     HIPCHK(launch_zero_f64((double*)acc.p, 4, c->stream));
     HIPCHK(launch_particles<T>(pdesc_dev<T>(c, c->cur), c->items, c->nitems, c->pgrid, true, false, c->scheme,
-                               c->win_bytes, c->pow2, c->stream));
+                               c->win_bytes, c->pow2, c->sorted, c->stream));
     if (phibar_in) {
         HIPCHK(launch_dot<T>(phibar_in, (const T*)I.phi, (int64_t)H3, (double*)acc.p + 2, c->stream));
         HIPCHK(hipMemcpyAsync(phibar.p, phibar_in, H3 * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
@@ -1495,7 +1508,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
             // X^(base+m) = push of X^(base+m-1) (slot m-1 -> slot m) with G^(base+m-1)
             // (step base+m), then G^(base+m)
             HIPCHK(launch_particles<T>((const PartDesc<T>*)pdR.p + (base + m - 1), c->items, c->nitems, c->pgrid,
-                                       false, true, c->scheme, c->win_bytes, c->pow2, c->stream));
+                                       false, true, c->scheme, c->win_bytes, c->pow2, c->sorted, c->stream));
             if ((rc = grad_of_tape(base + m))) return rc;
         }
         {
@@ -1567,7 +1580,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
 // snapshots: header, positions in original order, alpha in natural order
 // ---------------------------------------------------------------------------
 const char kMagic[8] = {'S', 'I', 'P', 'F', 'S', 'N', 'A', 'P'};
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 
 struct SnapHeader {
     char magic[8];
@@ -1691,8 +1704,8 @@ template <typename T> int deposit_noalloc_typed(const sipf_params* p, int64_t P,
     HIPCHK(launch_load_positions<T>((const T*)X, P, (T)p->L, d[0], err, s));
     HIPCHK(launch_sort<T>(3, pd, pd + 1, chunks, nchunks, 1, counts, cursor, seg, seg_off, seg_n, items, nitems, chunk, s));
     const int win = particle_window_bytes(sizeof(T) == 8);
-    const int grid = std::max(1, std::min(cap, particle_resident_blocks<T>(p->scheme, win)));
-    HIPCHK(launch_particles<T>(pd + 1, items, nitems, grid, true, false, p->scheme, win, is_pow2(H), s));
+    const int grid = std::max(1, std::min(cap, particle_resident_blocks<T>(p->scheme, win, false)));
+    HIPCHK(launch_particles<T>(pd + 1, items, nitems, grid, true, false, p->scheme, win, is_pow2(H), false, s));
     return SIPF_OK;
 }
 
@@ -1928,6 +1941,10 @@ int sipf_autotune(const sipf_params* prm, int64_t P, const void* X0, int x0_on_d
     if ((rc = try_axis(&sipf_params::tile, tiles))) return rc;
     if ((rc = try_axis(&sipf_params::chunk, {1024, 2048, 3072, 4096}))) return rc;
     if ((rc = try_axis(&sipf_params::resort_every, {2, 4, 6, 8, 16}))) return rc;
+    if (prm->precision == SIPF_FP32 && dim_of(prm) == 3) {
+        cur.particle_pass = sorted_pass(&cur, 1) ? SIPF_PASS_SORTED : SIPF_PASS_TWO_PHASE;
+        if ((rc = try_axis(&sipf_params::particle_pass, {SIPF_PASS_SORTED, SIPF_PASS_TWO_PHASE}))) return rc;
+    }
     *best = cur;
     *ms_per_step = t_best;
     return SIPF_OK;

@@ -176,8 +176,11 @@ int fft_perm(int N, int k);
 // ticket counter of the persistent passes (next_item in pass_common.h).
 template <typename T>
 // pow2: every instance's H is a power of two (index wraps by mask; else by remainder)
+// sorted: the FP32 deposit + push pass keeps each item sorted by cell and
+// accumulates runs of equal cells (else the two-phase pass; FP64 and the
+// single-phase passes ignore it)
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
-                            bool push, int scheme, int win_bytes, bool pow2, hipStream_t s);
+                            bool push, int scheme, int win_bytes, bool pow2, bool sorted, hipStream_t s);
 // positivity-preserving deposit rounds (positivity.hip): flag nodes below
 // -thresh, switch the order-4 particles touching a flagged node to order 2
 // (count += switched; sw[i] = tag marks them), clamp negatives to zero; tmp
@@ -287,6 +290,6 @@ hipError_t launch_noalloc_setup(const PartDesc<T>& d0, const PartDesc<T>& d1, Pa
 int particle_threads();
 int particle_chunk();
 int particle_window_bytes(bool fp64);
-template <typename T> int particle_resident_blocks(int scheme, int win_bytes);
+template <typename T> int particle_resident_blocks(int scheme, int win_bytes, bool sorted);
 
 }  // namespace sipf

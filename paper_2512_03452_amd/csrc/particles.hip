@@ -955,14 +955,14 @@ __device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t be
     return true;
 }
 
-template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
+template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2, bool SORTED>
 __device__ __forceinline__ void particles_body(const PartDesc<T>* __restrict__ pds,
                                                const WorkItem* __restrict__ items, int* hdr, int win_bytes,
                                                unsigned char* smem_raw, int* sh, int* slot_p) {
     const int n = hdr[0];
     for (int it = blockIdx.x; it < n; it = next_item(hdr, n, slot_p)) {
         const WorkItem w = items[it];
-        if constexpr (sizeof(T) == 4 && DEP && PUSH) {
+        if constexpr (SORTED) {
             const PartDesc<T>& a = pds[w.inst];
             if (sorted_candidate(a, w, win_bytes) && item_sorted<SCHEME, P2>(a, w.beg, w.cnt, smem_raw, sh))
                 continue;
@@ -971,14 +971,30 @@ __device__ __forceinline__ void particles_body(const PartDesc<T>* __restrict__ p
     }
 }
 
-// Deposit-only and push-only passes (six waves per SIMD).
+// Two-phase passes: FP64 deposit + push, and the deposit-only and push-only
+// passes of both precisions.
 template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
 __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<T>* __restrict__ pds,
                                                   const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[8];
     __shared__ int slot;
-    particles_body<T, DEP, PUSH, SCHEME, P2>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+    particles_body<T, DEP, PUSH, SCHEME, P2, false>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+}
+
+// The FP32 two-phase deposit + push pass (items kept in tile order, not
+// sorted by cell): one window at a time, so three workgroups fit a CU and the
+// registers are budgeted for six waves per SIMD.
+#ifndef SIPF_TWO_WAVES
+#define SIPF_TWO_WAVES 6
+#endif
+template <int SCHEME, bool P2>
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(SIPF_TWO_WAVES))) void k_particles_two(
+    const PartDesc<float>* __restrict__ pds, const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int sh[8];
+    __shared__ int slot;
+    particles_body<float, true, true, SCHEME, P2, false>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
 }
 
 // The fused deposit + push pass: its two windows (and, in FP32, the sort
@@ -993,22 +1009,29 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(SIPF_FUSED_W
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[12];
     __shared__ int slot;
-    particles_body<T, true, true, SCHEME, P2>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+    particles_body<T, true, true, SCHEME, P2, true>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
 }
 
 // Workgroups of the fused particle pass that are resident on the whole device
 // at once (occupancy from its registers and its LDS window): the persistent
 // grid is sized to this, so that no workgroup waits for another to finish
 // before it can start its share of the work items.
-template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
+template <typename T> int particle_resident_blocks(int scheme, int win_bytes, bool sorted) {
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e;
     if constexpr (sizeof(T) == 4) {
-        if (win_bytes < fused_bytes<T>()) win_bytes = fused_bytes<T>();
+        if (!sorted) {
+            e = scheme == SIPF_STRANG ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                            &per_cu, (const void*)k_particles_two<SIPF_STRANG, true>, PT, win_bytes)
+                                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                            &per_cu, (const void*)k_particles_two<SIPF_EM, true>, PT, win_bytes);
+        } else {
+            if (win_bytes < fused_bytes<T>()) win_bytes = fused_bytes<T>();
         e = scheme == SIPF_STRANG ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                                         &per_cu, (const void*)k_particles_fused<T, SIPF_STRANG, true>, PT, win_bytes)
                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
                                         &per_cu, (const void*)k_particles_fused<T, SIPF_EM, true>, PT, win_bytes);
+        }
     } else {
         e = scheme == SIPF_STRANG
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -1027,11 +1050,19 @@ template <typename T> int particle_resident_blocks(int scheme, int win_bytes) {
 
 template <typename T, bool P2>
 static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, int* nitems, dim3 g, bool deposit,
-                         bool push, int scheme, int win_bytes, hipStream_t s) {
+                         bool push, int scheme, int win_bytes, bool sorted, hipStream_t s) {
     const dim3 b(PT);
     if (deposit && push) {
         if constexpr (sizeof(T) == 4) {
-            // the fused FP32 pass holds both windows and the sort counters at once
+            if (!sorted) {
+                const size_t shm = (size_t)win_bytes;
+                if (scheme == SIPF_STRANG)
+                    launch_kernel((k_particles_two<SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+                else
+                    launch_kernel((k_particles_two<SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+                return;
+            }
+            // the sorted pass holds both windows and the sort counters at once
             if (win_bytes < fused_bytes<T>()) win_bytes = fused_bytes<T>();
             const size_t shm = (size_t)win_bytes;
             if (scheme == SIPF_STRANG)
@@ -1062,10 +1093,10 @@ static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, int* nite
 
 template <typename T>
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
-                            bool push, int scheme, int win_bytes, bool pow2, hipStream_t s) {
+                            bool push, int scheme, int win_bytes, bool pow2, bool sorted, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
-    if (pow2) particles_p2<T, true>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, s);
-    else particles_p2<T, false>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, s);
+    if (pow2) particles_p2<T, true>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, sorted, s);
+    else particles_p2<T, false>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, sorted, s);
     return hipGetLastError();
 }
 
@@ -1397,9 +1428,9 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 }
 
 #define SIPF_INST(T)                                                                                              \
-    template int particle_resident_blocks<T>(int, int);                                                           \
+    template int particle_resident_blocks<T>(int, int, bool);                                                     \
     template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, int*, int, bool, bool, int, \
-                                            int, bool, hipStream_t);                                              \
+                                            int, bool, bool, hipStream_t);                                        \
     template hipError_t launch_sort<T>(int, const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,   \
                                        uint32_t*, uint32_t*, WorkItem*, const int*, int*, WorkItem*, int*, int,    \
                                        hipStream_t);                                                               \

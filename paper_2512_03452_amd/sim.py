@@ -310,7 +310,7 @@ class Batch:
 
 
 def autotune(X0, nsteps=8, stream=None, **params):
-    """Run the library's tile / chunk / re-sort search (sipf_autotune) for
+    """Run the library's tile / chunk / re-sort / particle-pass search (sipf_autotune) for
     positions X0 and parameters ``params``; returns (tuned params dict, ms/step)."""
     p = _lib.default_params(**params)
     X = torch.as_tensor(np.asarray(X0) if not torch.is_tensor(X0) else X0)
@@ -320,7 +320,8 @@ def autotune(X0, nsteps=8, stream=None, **params):
     torch.cuda.synchronize()
     check(_lib.load().sipf_autotune(ctypes.byref(p), int(X.shape[0]), ctypes.c_void_p(X.data_ptr()), 1,
                                     int(nsteps), _stream_handle(stream), ctypes.byref(best), ctypes.byref(ms)))
-    return {"tile": best.tile, "chunk": best.chunk, "resort_every": best.resort_every}, ms.value
+    return ({"tile": best.tile, "chunk": best.chunk, "resort_every": best.resort_every,
+             "particle_pass": best.particle_pass}, ms.value)
 
 
 def dbg_philox(ctr, seed, precision="fp32"):

@@ -41,7 +41,7 @@ def rel_l2(a, b):
 def oparams(**kw):
     kw = dict(kw)
     kw.pop("precision", None)
-    for k in ("tile", "resort_every", "chunk"):
+    for k in ("tile", "resort_every", "chunk", "particle_pass"):
         kw.pop(k, None)
     return osipf.Params(**kw)
 
@@ -50,14 +50,14 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-def _instances(precision, specs, seed=0):
+def _instances(precision, specs, seed=0, pp="default"):
     """specs: (H, P, chi, M0, mu) per instance; blob initial data, distinct streams."""
     out = []
     for i, (H, P, chi, M0, mu) in enumerate(specs):
         X0 = workloads.blob(P, 0.15, seed=100 + i)
         X0 = X0.astype(np.float32 if precision == "fp32" else np.float64)
         prm = dict(L=2.0, chi=chi, mu=mu, eps=1.0, k=1.0, M0=M0, dt=1e-3 if precision == "fp64" else 5e-5, H=H,
-                   precision=precision, seed=seed + 7, instance=i)
+                   precision=precision, seed=seed + 7, instance=i, particle_pass=pp)
         out.append(dict(params=prm, X0=X0))
     return out
 
@@ -86,11 +86,12 @@ def test_batch_fp64_each_instance_matches_oracle():
     b.close()
 
 
-def test_batch_fp32_instances_match_standalone_contexts():
+@pytest.mark.parametrize("pp", ["sorted", "two_phase"])
+def test_batch_fp32_instances_match_standalone_contexts(pp):
     specs = [(32, 50000, 0.5, 40.0, 1.0), (64, 12345, 2.0, 120.0, 1.0), (32, 777, 1.2, 90.0, 1.0),
              (64, 65537, 1.0, 60.0, 1.0), (32, 20000, 1.8, 100.0, 1.0), (64, 3001, 0.7, 70.0, 1.0)]
-    say("batch fp32 vs standalone", len(specs), "instances")
-    inst = _instances("fp32", specs)
+    say("batch fp32 vs standalone", len(specs), "instances", pp)
+    inst = _instances("fp32", specs, pp=pp)
     b = pkg.Batch(inst)
     b.run(20)
     for i, it in enumerate(inst):
@@ -106,11 +107,12 @@ def test_batch_fp32_instances_match_standalone_contexts():
     b.close()
 
 
-def test_batch_fp32_against_oracle_stepwise():
+@pytest.mark.parametrize("pp", ["sorted", "two_phase"])
+def test_batch_fp32_against_oracle_stepwise(pp):
     """Two instances of different H in one batch; the oracle advances the GPU
     state of each by one step at steps 1 and 10."""
     specs = [(32, 20001, 1.5, 100.0, 1.0), (64, 30000, 0.8, 60.0, 1.0)]
-    inst = _instances("fp32", specs)
+    inst = _instances("fp32", specs, pp=pp)
     b = pkg.Batch(inst)
     done = 0
     for n in (1, 10):
@@ -217,6 +219,7 @@ def test_autotune_picks_valid_settings_that_keep_results():
     assert tuned["tile"] in (4, 8, 16, 32) and 32 // tuned["tile"] <= 16
     assert tuned["chunk"] in (1024, 2048, 3072, 4096)
     assert tuned["resort_every"] in (2, 4, 6, 8, 16)
+    assert tuned["particle_pass"] in (1, 2)
     a = pkg.Sim(X0, **kw)
     t = pkg.Sim(X0, **kw, **tuned)
     a.run(10)

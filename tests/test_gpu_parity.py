@@ -43,7 +43,7 @@ def oparams(**kw):
     """Oracle parameters from library keyword arguments."""
     kw = dict(kw)
     kw.pop("precision", None)
-    for k in ("tile", "resort_every", "chunk"):
+    for k in ("tile", "resort_every", "chunk", "particle_pass"):
         kw.pop(k, None)
     sch = kw.pop("scheme", "strang")
     return osipf.Params(scheme=sch if isinstance(sch, str) else ("strang" if sch == 0 else "em"), **kw)
@@ -168,15 +168,22 @@ def _state_np(sim):
     return to_np(sim.positions()).astype(np.float64), to_np(sim.field("alpha")).astype(np.complex128)
 
 
-@pytest.mark.parametrize("precision,H,P,scheme", [
+# FP32 3-D steps have two particle passes (sorted items, two-phase): each
+# FP32 case runs both.
+_STEP_CASES = [
     ("fp32", 8, 333, "strang"), ("fp32", 16, 4099, "strang"), ("fp32", 32, 20001, "em"),
     ("fp32", 64, 65537, "strang"), ("fp32", 128, 100000, "strang"),
     ("fp64", 16, 2001, "strang"), ("fp64", 32, 10000, "em"), ("fp64", 64, 5000, "strang"),
     ("fp32", 256, 200003, "strang"),
-])
-def test_one_step_parity(precision, H, P, scheme):
-    say("step", precision, H, P, scheme)
-    kw = dict(L=2.0, chi=3.0, mu=0.5, eps=1.0, k=1.0, M0=50.0, dt=1e-3, H=H, seed=11, scheme=scheme)
+]
+
+
+@pytest.mark.parametrize("precision,H,P,scheme,pp", [
+    c + (pp,) for c in _STEP_CASES for pp in (("sorted", "two_phase") if c[0] == "fp32" else ("default",))])
+def test_one_step_parity(precision, H, P, scheme, pp):
+    say("step", precision, H, P, scheme, pp)
+    kw = dict(L=2.0, chi=3.0, mu=0.5, eps=1.0, k=1.0, M0=50.0, dt=1e-3, H=H, seed=11, scheme=scheme,
+              particle_pass=pp)
     X0 = osipf.wrap(np.random.default_rng(H).normal(0, 0.3, (P, 3)), 2.0)
     X0 = X0.astype(np.float32 if precision == "fp32" else np.float64)
     a0 = hermitian_alpha(H, seed=H, scale=40.0, dtype=precision)
@@ -223,14 +230,15 @@ def test_trajectory_fp64_h32_blob_100_steps():
     assert abs(A[0, 0, 0].real - a00) < 1e-13 * a00
 
 
-@pytest.mark.parametrize("scheme", ["strang", "em"])
-def test_trajectory_fp32_h64_mix_100_steps(scheme):
+@pytest.mark.parametrize("scheme,pp", [("strang", "sorted"), ("strang", "two_phase"), ("em", "sorted"),
+                                       ("em", "two_phase")])
+def test_trajectory_fp32_h64_mix_100_steps(scheme, pp):
     """Parameters of the H=64 mixed workload (M0 = 80, dt = 5e-5) at P = 30000."""
-    say("trajectory fp32 H=64", scheme)
+    say("trajectory fp32 H=64", scheme, pp)
     cfg = workloads.CONFIGS["fp32_mix_h64"]
     P = 30000
     X0 = cfg["init"](P).astype(np.float32)
-    kw = dict(cfg["params"], scheme=scheme)
+    kw = dict(cfg["params"], scheme=scheme, particle_pass=pp)
     sim = pkg.Sim(X0, **kw)
     sim.run(100)
     X, A = _state_np(sim)
@@ -272,13 +280,14 @@ def test_stepwise_parity_strong_aggregation(scheme):
 # full-size configurations in the bench launch configuration (sampled checks)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name,nsteps", [("fp32_mix_h64", 3), ("fp32_ring_h128", 3)])
-def test_full_size_sampled(name, nsteps):
+@pytest.mark.parametrize("name,nsteps,pp", [("fp32_mix_h64", 3, "sorted"), ("fp32_mix_h64", 3, "two_phase"),
+                                            ("fp32_ring_h128", 3, "sorted"), ("fp32_ring_h128", 3, "two_phase")])
+def test_full_size_sampled(name, nsteps, pp):
     cfg = workloads.CONFIGS[name]
     P = cfg["P"]
-    say("full size", name, P)
+    say("full size", name, P, pp)
     X0 = cfg["init"](P).astype(np.float32)
-    sim = pkg.Sim(X0, **cfg["params"])
+    sim = pkg.Sim(X0, **dict(cfg["params"], particle_pass=pp))
     sim.run(nsteps)
     prm = oparams(**cfg["params"])
     Xk, Ak = _state_np(sim)

@@ -64,7 +64,7 @@ def test_defaults():
     ("H", 48), ("H", 4), ("H", 512), ("dt", 0.0), ("dt", float("nan")), ("eps", -1.0), ("mu", -1.0),
     ("chi", float("inf")), ("M0", -2.0), ("L", 0.0), ("p2g_order", 2), ("g2p_order", 4),
     ("scheme", 7), ("precision", 3), ("tile", 3), ("tile", 4096), ("chunk", 17), ("dim", 1), ("dim", 4), ("propagator", 2), ("method", 2),
-    ("positivity", 2), ("positivity", -1),
+    ("positivity", 2), ("positivity", -1), ("particle_pass", 3), ("particle_pass", -1),
 ])
 def test_invalid_parameters_rejected_before_device(field, value):
     L = _lib()
@@ -197,12 +197,12 @@ def test_load_of_corrupt_snapshot_is_eio(tmp_path, damage):
     Hdr = _snap_header_type()
     p = L.default_params(H=8)
     P = 10
-    h = Hdr(b"SIPFSNAP", 3, 4, p, P, 3)
+    h = Hdr(b"SIPFSNAP", 4, 4, p, P, 3)
     payload = bytes(P * 3 * 4 + 8 * 8 * 5 * 2 * 4)
     if damage == "magic":
         h.magic = b"SIPFSNAQ"
     elif damage == "version":
-        h.version = 2  # the layout before the positivity field
+        h.version = 3  # the layout before the particle_pass field
     elif damage == "tsize":
         h.tsize = 8
     elif damage == "truncated":
@@ -230,7 +230,7 @@ def _batch_init(L, prms, Ps, Xs, on_device=0):
 
 
 @pytest.mark.parametrize("case", ["empty", "mixed_precision", "mixed_scheme", "bad_instance", "bad_count",
-                                  "non_finite", "mixed_positivity"])
+                                  "non_finite", "mixed_positivity", "mixed_pass"])
 def test_batch_init_rejects_before_device(case):
     L = _lib()
     a = L.default_params(H=16)
@@ -251,6 +251,8 @@ def test_batch_init_rejects_before_device(case):
         Ps[0] = 0
     elif case == "mixed_positivity":
         prms[1] = L.default_params(H=32, positivity=1)
+    elif case == "mixed_pass":
+        prms[1] = L.default_params(H=32, particle_pass="two_phase")
     elif case == "non_finite":
         Xb[4, 2] = np.inf
         want = L.SIPF_ENUMERIC
