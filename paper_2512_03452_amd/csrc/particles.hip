@@ -24,8 +24,14 @@ namespace sipf {
 constexpr int PT = 512;            // threads per particle-pass workgroup
 constexpr int PPT = 8;             // particles held in registers per thread
 constexpr int CH = PT * PPT;       // particles per work item at most
-constexpr int SORT_THREADS = 512;  // threads per sort workgroup
-constexpr int SORT_PER_THREAD = 8;
+#ifndef SIPF_SORT_THREADS
+#define SIPF_SORT_THREADS 512
+#endif
+#ifndef SIPF_SORT_PER_THREAD
+#define SIPF_SORT_PER_THREAD 8
+#endif
+constexpr int SORT_THREADS = SIPF_SORT_THREADS;  // threads per sort workgroup
+constexpr int SORT_PER_THREAD = SIPF_SORT_PER_THREAD;
 constexpr int SORT_CHUNK = SORT_THREADS * SORT_PER_THREAD;
 constexpr int MAX_KEYS = 4096;     // (H / tile)^3 <= 16^3, (H / tile)^2 <= 64^2
 constexpr int MIN_WINDOW_ITEM = 64;  // smaller items deposit and gather straight from global memory
@@ -58,18 +64,21 @@ int particle_threads() { return PT; }
 int particle_chunk() { return CH; }
 int sort_max_keys() { return MAX_KEYS; }
 
+// Bit b of v (< 32) moved to bit 3b: three shift-or-mask steps that move
+// groups of bits apart by 8, 4 and 2 places.
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int b = 0; b < 5; ++b) r |= ((v >> b) & 1u) << (3 * b);
-    return r;
+    v &= 31u;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    return (v | (v << 2)) & 0x09249249u;
 }
 
+// Bit b of v (< 64) moved to bit 2b.
 __device__ __forceinline__ uint32_t spread2(uint32_t v) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int b = 0; b < 6; ++b) r |= ((v >> b) & 1u) << (2 * b);
-    return r;
+    v &= 63u;
+    v = (v | (v << 4)) & 0x0F0Fu;
+    v = (v | (v << 2)) & 0x3333u;
+    return (v | (v << 1)) & 0x5555u;
 }
 
 // Tile coordinate of position v along one axis: a shift when H and the tile
@@ -1109,6 +1118,23 @@ hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* n
 // own segment; the combine pass concatenates the segments into one list that
 // the (persistent) particle pass walks.
 // ---------------------------------------------------------------------------
+// Runs of equal keys in consecutive lanes of a wave (call with the whole
+// wave).  Returns the run's length at its first lane and 0 at the others;
+// head receives the first lane of the caller's run.  The particles are in
+// tile order from the previous sort and mostly still in their tiles, so a
+// wave's 64 keys form one or a few runs: one LDS atomic per run instead of
+// per particle (atomics of a wave on one LDS word serialise).
+__device__ __forceinline__ uint32_t lane_runs(uint32_t key, int& head) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool first = lane == 0 || prev != key;
+    const uint64_t heads = __ballot(first);
+    head = 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));  // bit 0 is always set
+    if (!first) return 0u;
+    const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+    return after ? (uint32_t)__builtin_ctzll(after) + 1u : (uint32_t)(64 - lane);
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* __restrict__ pds,
                                                             const SortChunk* __restrict__ chunks,
@@ -1118,11 +1144,29 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* _
     const PartDesc<T> a = pds[ch.inst];
     const int nk = a.nkeys;
     const int tid = threadIdx.x;
+    const int64_t end = min(ch.beg + (int64_t)SORT_CHUNK, a.P);
+    // all loads first (lanes past the end re-read the chunk's first particle),
+    // so that the chunk costs one memory round trip, overlapped with the
+    // clearing of the histogram
+    T px[SORT_PER_THREAD], py[SORT_PER_THREAD], pz[SORT_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < SORT_PER_THREAD; ++k) {
+        const int64_t i = ch.beg + tid + (int64_t)k * SORT_THREADS;
+        const int64_t j = i < end ? i : ch.beg;
+        px[k] = gp(a.x)[j];
+        py[k] = gp(a.y)[j];
+        pz[k] = DIM == 3 ? gp(a.z)[j] : (T)0;
+    }
     for (int i = tid; i < nk; i += SORT_THREADS) h[i] = 0;
     __syncthreads();
-    const int64_t end = min(ch.beg + (int64_t)SORT_CHUNK, a.P);
-    for (int64_t i = ch.beg + tid; i < end; i += SORT_THREADS)
-        atomicAdd(&h[key_of<T, DIM>(a, a.x[i], a.y[i], DIM == 3 ? a.z[i] : (T)0)], 1u);
+#pragma unroll
+    for (int k = 0; k < SORT_PER_THREAD; ++k) {
+        const bool ok = ch.beg + tid + (int64_t)k * SORT_THREADS < end;
+        const uint32_t key = ok ? key_of<T, DIM>(a, px[k], py[k], pz[k]) : 0xFFFFFFFFu;
+        int head;
+        const uint32_t len = lane_runs(key, head);
+        if (ok && len) atomicAdd(&h[key], len);
+    }
     __syncthreads();
     uint32_t* cnt = counts + (size_t)ch.inst * MAX_KEYS;
     for (int i = tid; i < nk; i += SORT_THREADS)
@@ -1179,26 +1223,31 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* p
 // its segment of `seg`.  Items of at least chunk / 2 particles come first and
 // the single items of sparser tiles last, so that the persistent passes, which
 // draw items in list order, end on the small ones.  Clears the counts for the
-// next sort.
-template <typename T>
+// next sort.  DIRECT (a single instance): the segment is the item list itself
+// and the scan writes its count, so no combine pass follows.
+template <typename T, bool DIRECT>
 __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restrict__ pds, uint32_t* counts,
                                                     uint32_t* cursor, WorkItem* seg, const int* __restrict__ seg_off,
-                                                    int* seg_n, int chunk) {
+                                                    int* seg_n, int chunk, int* nitems) {
     __shared__ uint32_t part[1024];
     const int inst = blockIdx.x;
     const int nk = pds[inst].nkeys;
     uint32_t* cnt = counts + (size_t)inst * MAX_KEYS;
     uint32_t* cur = cursor + (size_t)inst * MAX_KEYS;
-    WorkItem* items = seg + seg_off[inst];
+    WorkItem* items = DIRECT ? seg : seg + seg_off[inst];
     const int tid = threadIdx.x;
     constexpr int PER = MAX_KEYS / 1024;  // keys per thread, consecutive in key order
     const uint32_t half = ((uint32_t)chunk + 1u) / 2u;
+    static_assert(PER == 4, "one 16-byte load of counts per thread");
     uint32_t loc[PER], nit[PER];
     uint32_t sum = 0, ibig = 0, ismall = 0;
+    // the instance's MAX_KEYS counts are 16-byte aligned: one load per thread
+    const uint4 c4 = reinterpret_cast<const uint4*>(cnt)[tid];
+    const uint32_t cv[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int i = tid * PER + j;
-        loc[j] = i < nk ? cnt[i] : 0u;
+        loc[j] = i < nk ? cv[j] : 0u;
         nit[j] = (loc[j] + chunk - 1) / chunk;
         sum += loc[j];
         if (loc[j] >= half) ibig += nit[j];
@@ -1237,24 +1286,39 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
         }
         run += loc[j];
     }
-    if (tid == 0) seg_n[inst] = (int)(tbig + tsmall);
+    if (tid == 0) {
+        seg_n[inst] = (int)(tbig + tsmall);
+        if constexpr (DIRECT) nitems[0] = (int)(tbig + tsmall);
+    }
 }
 
-// Concatenate the instances' item segments into one list (one workgroup).
+// Concatenate the instances' item segments into one list (one workgroup):
+// list entry k belongs to the last instance whose start is <= k (binary
+// search over the starts in LDS), so every copy is independent of the others.
 __global__ __launch_bounds__(1024) void k_items_combine(const WorkItem* __restrict__ seg,
                                                         const int* __restrict__ seg_off, const int* __restrict__ seg_n,
                                                         int ninst, WorkItem* items, int* nitems) {
     __shared__ uint32_t part[1024];
     __shared__ int start[1024];
+    __shared__ int from[1024];
     const int tid = threadIdx.x;
     const uint32_t v = tid < ninst ? (uint32_t)seg_n[tid] : 0u;
+    const int o = tid < ninst ? seg_off[tid] : 0;
     uint32_t total;
     const uint32_t off = block_exclusive_scan(v, part, total);
-    if (tid < ninst) start[tid] = (int)off;
+    if (tid < ninst) {
+        start[tid] = (int)off;
+        from[tid] = o;
+    }
     __syncthreads();
-    for (int i = 0; i < ninst; ++i) {
-        const int n = seg_n[i], o = seg_off[i], dst = start[i];
-        for (int k = tid; k < n; k += 1024) items[dst + k] = seg[o + k];
+    for (int k = tid; k < (int)total; k += 1024) {
+        int lo = 0, hi = ninst - 1;  // start[lo] <= k always holds (start[0] = 0)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        items[k] = seg[from[lo] + (k - start[lo])];
     }
     if (tid == 0) *nitems = (int)total;
 }
@@ -1264,43 +1328,52 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>
                                                                const PartDesc<T>* __restrict__ dst,
                                                                const SortChunk* __restrict__ chunks,
                                                                uint32_t* cursor) {
-    __shared__ uint32_t lc[MAX_KEYS];
-    __shared__ uint32_t lb[MAX_KEYS];
+    __shared__ uint32_t lc[MAX_KEYS];  // counts of the chunk's keys, then their first slots
     const SortChunk ch = chunks[blockIdx.x];
     const PartDesc<T> a = src[ch.inst];
     const PartDesc<T> b = dst[ch.inst];
     const int nk = a.nkeys;
     uint32_t* cur = cursor + (size_t)ch.inst * MAX_KEYS;
     const int tid = threadIdx.x;
-    for (int i = tid; i < nk; i += SORT_THREADS) lc[i] = 0;
-    __syncthreads();
     T px[SORT_PER_THREAD], py[SORT_PER_THREAD], pz[SORT_PER_THREAD];
     uint32_t pid[SORT_PER_THREAD], key[SORT_PER_THREAD], rank[SORT_PER_THREAD];
+    const int lane = tid & 63;
+    const int64_t end = min(ch.beg + (int64_t)SORT_CHUNK, a.P);
+    // all loads first (lanes past the end re-read the chunk's first particle)
 #pragma unroll
     for (int k = 0; k < SORT_PER_THREAD; ++k) {
         const int64_t i = ch.beg + tid + (int64_t)k * SORT_THREADS;
-        if (i < a.P && i < ch.beg + SORT_CHUNK) {
-            px[k] = a.x[i];
-            py[k] = a.y[i];
-            pz[k] = DIM == 3 ? a.z[i] : (T)0;
-            pid[k] = a.id[i];
-            key[k] = key_of<T, DIM>(a, px[k], py[k], pz[k]);
-            rank[k] = atomicAdd(&lc[key[k]], 1u);
-        }
+        const int64_t j = i < end ? i : ch.beg;
+        px[k] = gp(a.x)[j];
+        py[k] = gp(a.y)[j];
+        pz[k] = DIM == 3 ? gp(a.z)[j] : (T)0;
+        pid[k] = gp(a.id)[j];
+    }
+    for (int i = tid; i < nk; i += SORT_THREADS) lc[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SORT_PER_THREAD; ++k) {
+        const bool ok = ch.beg + tid + (int64_t)k * SORT_THREADS < end;
+        key[k] = ok ? key_of<T, DIM>(a, px[k], py[k], pz[k]) : 0xFFFFFFFFu;
+        // rank inside the chunk's tile: one LDS atomic per run of equal keys
+        int head;
+        const uint32_t len = lane_runs(key[k], head);
+        uint32_t base = 0u;
+        if (ok && len) base = atomicAdd(&lc[key[k]], len);
+        rank[k] = (uint32_t)__shfl((int)base, head, 64) + (uint32_t)(lane - head);
     }
     __syncthreads();
     for (int i = tid; i < nk; i += SORT_THREADS)
-        if (lc[i]) lb[i] = atomicAdd(&cur[i], lc[i]);
+        if (lc[i]) lc[i] = atomicAdd(&cur[i], lc[i]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < SORT_PER_THREAD; ++k) {
-        const int64_t i = ch.beg + tid + (int64_t)k * SORT_THREADS;
-        if (i < a.P && i < ch.beg + SORT_CHUNK) {
-            const uint32_t d = lb[key[k]] + rank[k];
-            b.x[d] = px[k];
-            b.y[d] = py[k];
-            if constexpr (DIM == 3) b.z[d] = pz[k];
-            b.id[d] = pid[k];
+        if (ch.beg + tid + (int64_t)k * SORT_THREADS < end) {
+            const uint32_t d = lc[key[k]] + rank[k];
+            gp(b.x)[d] = px[k];
+            gp(b.y)[d] = py[k];
+            if constexpr (DIM == 3) gp(b.z)[d] = pz[k];
+            gp(b.id)[d] = pid[k];
         }
     }
 }
@@ -1315,9 +1388,14 @@ hipError_t launch_sort(int dim, const PartDesc<T>* src, const PartDesc<T>* dst, 
     if (ninst < 1 || ninst > 1024 || (dim != 2 && dim != 3)) return hipErrorInvalidValue;
     if (dim == 3) launch_kernel((k_tile_hist<T, 3>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
     else launch_kernel((k_tile_hist<T, 2>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
-    launch_kernel((k_tile_scan<T>), dim3(ninst), dim3(1024), 0, s, src, counts, cursor, seg, seg_off, seg_n,
-                       chunk);
-    launch_kernel(k_items_combine, dim3(1), dim3(1024), 0, s, seg, seg_off, seg_n, ninst, items, nitems);
+    if (ninst == 1) {
+        launch_kernel((k_tile_scan<T, true>), dim3(1), dim3(1024), 0, s, src, counts, cursor, items, seg_off, seg_n,
+                      chunk, nitems);
+    } else {
+        launch_kernel((k_tile_scan<T, false>), dim3(ninst), dim3(1024), 0, s, src, counts, cursor, seg, seg_off,
+                      seg_n, chunk, nitems);
+        launch_kernel(k_items_combine, dim3(1), dim3(1024), 0, s, seg, seg_off, seg_n, ninst, items, nitems);
+    }
     if (dim == 3)
         launch_kernel((k_tile_scatter<T, 3>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, dst, chunks, cursor);
     else
