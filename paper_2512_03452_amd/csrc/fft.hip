@@ -69,7 +69,40 @@ constexpr int PLANE_THREADS = SIPF_INV_THREADS;
 // x-pencil and y-column passes: 512 threads (measured x-pencil pass: H = 128
 // 25.1 / 22.1 / 31.4 us and H = 64 11.0 / 8.7 / 7.9 us at 256 / 512 / 1024)
 constexpr int PENCIL_THREADS = 512;
-constexpr int KB = 16;  // kz columns per x-pencil workgroup
+#ifndef SIPF_KB
+#define SIPF_KB 16
+#endif
+constexpr int KB = SIPF_KB;  // kz columns per x-pencil workgroup
+
+// v, or zero when ok is false (per component: a select of whole vector
+// values goes through scratch memory).
+template <typename V> __device__ __forceinline__ V keep_if(bool ok, const V& v) {
+    V r;
+    r.x = ok ? v.x : 0;
+    r.y = ok ? v.y : 0;
+    return r;
+}
+
+// Copy of N elements by the NT threads of a workgroup, element u read by
+// ld(u) and written by st(u, v): every read of a thread is issued before its
+// first write, so a copy between HBM and LDS costs one memory round trip (a
+// loop of read-then-write pairs waits for each read in turn).  Threads past
+// the end re-read element N - 1 and write nothing.
+template <int NT, int N, typename V, typename Ld, typename St>
+__device__ __forceinline__ void stage(const Ld& ld, const St& st) {
+    constexpr int R = (N + NT - 1) / NT;
+    V v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int u = (int)threadIdx.x + q * NT;
+        v[q] = ld(N % NT == 0 ? u : min(u, N - 1));
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int u = (int)threadIdx.x + q * NT;
+        if (N % NT == 0 || u < N) st(u, v[q]);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Pass 1: x-plane -> half spectrum along z, transformed along y.
@@ -100,14 +133,13 @@ __global__ __launch_bounds__(FWD_THREADS) void k_fwd_planes(const FieldDesc<T>* 
     make_twiddles<T, H>(tw);
     make_twiddles<T, M>(twm);
     T* plane = fd.phi + ((size_t)comp * H + ix) * H * H;
-    for (int u = tid; u < H * M; u += nt) {
-        const int row = u / M, m = u % M;
-        buf[row * OP + m] = cmake<V, T>(plane[row * H + 2 * m], plane[row * H + 2 * m + 1]);
-    }
+    V* pv = reinterpret_cast<V*>(plane);  // (x[2m], x[2m+1]) of row r at r M + m
+    stage<FWD_THREADS, H * M, V>([&](int u) { return pv[u]; },
+                                 [&](int u, const V& v) { buf[(u / M) * OP + u % M] = v; });
     __syncthreads();
     if (consume) {
         // the deposit grid is consumed: clear it for the next step's particle pass
-        for (int u = tid; u < H * H; u += nt) plane[u] = (T)0;
+        for (int u = tid; u < H * M; u += nt) pv[u] = cmake<V, T>(0, 0);
         if (ix == 0 && comp == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
     }
     lds_fft<T, M, -1>(buf, H, OP, 1, twm);
@@ -140,7 +172,7 @@ __global__ __launch_bounds__(FWD_THREADS) void k_fwd_planes(const FieldDesc<T>* 
     lds_fft<T, H, -1>(buf, HH, 1, OP, tw);
     __syncthreads();
     V* out = fd.B1 + ((size_t)comp * H + ix) * H * HH;
-    for (int u = tid; u < H * HH; u += nt) out[u] = buf[u];
+    stage<FWD_THREADS, H * HH, V>([&](int u) { return buf[u]; }, [&](int u, const V& v) { out[u] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -148,7 +180,7 @@ __global__ __launch_bounds__(FWD_THREADS) void k_fwd_planes(const FieldDesc<T>* 
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MODE>
 __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp, int kz0, int ncol, T qy, int ky,
-                                                cplx_t<T>* buf, cplx_t<T>* abuf, const cplx_t<T>* tw);
+                                                cplx_t<T>* lds, const cplx_t<T>* tw);
 
 // MODE_STEP: forward x of B1, mode update of alpha, three gradient spectra
 //            i xi_d Phi alpha, inverse x into gspec.
@@ -165,37 +197,47 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
 //            right after accumulating it).
 enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3, MODE_RHO = 4, MODE_ADJ_ACC_SRC = 5 };
 
+// At H = 128 (FP32) the registers are budgeted for three workgroups per CU
+// (six waves per SIMD), so that all 640 blocks are resident at once; smaller
+// grids have fewer blocks than CUs and leave the count to the compiler.
 template <typename T, int H, int MODE>
-__global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>* __restrict__ fds) {
+__global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(H >= 128 ? 6 : 1))) void k_xpencils(
+    const FieldDesc<T>* __restrict__ fds) {
     constexpr bool UPDATE = MODE == MODE_STEP;
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
     constexpr int NKB = (HH + KB - 1) / KB;
-    constexpr int BP = KB + 1;  // pitch (complex) of one x row in LDS
-    __shared__ V buf[H * BP];
-    __shared__ V abuf[H * BP];
+    constexpr int BP = KB + 1;       // pitch (complex) of one x row in LDS, one grid
+    constexpr int BP3 = 3 * KB + 1;  // the same for the three gradient components side by side
+    constexpr int NB = H * KB;       // entries of the block
+    constexpr int NT = PENCIL_THREADS;
+    constexpr int R = (NB + NT - 1) / NT;
+    __shared__ V lds[H * BP3];
     __shared__ V tw[H];
+    V* buf = lds;
     const FieldDesc<T>& fd = fds[blockIdx.y];
     const int kyp = blockIdx.x / NKB;
     const int kz0 = (blockIdx.x % NKB) * KB;
     const int ncol = min(KB, HH - kz0);
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     make_twiddles<T, H>(tw);
     const int ky = perm_freq<H>(kyp);
     const T qy = (T)(ky < H / 2 ? ky : ky - H);
+    // entry u of the block: x row (or permuted kx position) u / KB, column u % KB
+    // (columns past ncol read the last valid one and are written as zero)
+    auto gidx = [&](int u) { return ((size_t)(u / KB) * H + kyp) * HH + kz0 + min(u % KB, ncol - 1); };
     if constexpr (MODE == MODE_ADJ_SRC || MODE == MODE_ADJ_ACC || MODE == MODE_ADJ_ACC_SRC) {
-        adjoint_pencils<T, H, MODE>(fd, kyp, kz0, ncol, qy, ky, buf, abuf, tw);
+        adjoint_pencils<T, H, MODE>(fd, kyp, kz0, ncol, qy, ky, lds, tw);
         return;
     }
+    const V zero = cmake<V, T>(0, 0);
     if constexpr (MODE == MODE_RHO) {
-        for (int u = tid; u < H * KB; u += nt) {
-            const int ix = u / KB, j = u % KB;
-            buf[ix * BP + j] = j < ncol ? fd.B1[((size_t)ix * H + kyp) * HH + kz0 + j] : cmake<V, T>(0, 0);
-        }
+        stage<NT, NB, V>([&](int u) { return fd.B1[gidx(u)]; },
+                         [&](int u, const V& v) { buf[(u / KB) * BP + u % KB] = keep_if(u % KB < ncol, v); });
         __syncthreads();
         lds_fft<T, H, -1>(buf, KB, 1, BP, tw);
         __syncthreads();
-        for (int u = tid; u < H * KB; u += nt) {
+        for (int u = tid; u < NB; u += NT) {
             const int p = u / KB, j = u % KB;
             const int kx = perm_freq<H>(p);
             const T qx = (T)(kx < H / 2 ? kx : kx - H);
@@ -203,84 +245,96 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_xpencils(const FieldDesc<T>*
             const T q2 = qx * qx + qy * qy + qz * qz;
             const T f = (fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1) * fd.inv_Ld;
             const V b = buf[p * BP + j];
-            buf[p * BP + j] = j < ncol ? cmake<V, T>(b.x * f, b.y * f) : cmake<V, T>(0, 0);
+            buf[p * BP + j] = j < ncol ? cmake<V, T>(b.x * f, b.y * f) : zero;
         }
         __syncthreads();
         lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
         __syncthreads();
-        for (int u = tid; u < H * KB; u += nt) {
-            const int ix = u / KB, j = u % KB;
-            if (j < ncol) fd.gspec[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
-        }
+        stage<NT, NB, V>([&](int u) { return buf[(u / KB) * BP + u % KB]; },
+                         [&](int u, const V& v) { if (u % KB < ncol) fd.gspec[gidx(u)] = v; });
         return;
     }
+    // alpha of the block, read together with B1 (before the transform)
+    V av[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) av[q] = fd.alpha[gidx(min(tid + q * NT, NB - 1))];
     if (UPDATE) {
-        for (int u = tid; u < H * KB; u += nt) {
-            const int ix = u / KB, j = u % KB;
-            buf[ix * BP + j] = j < ncol ? fd.B1[((size_t)ix * H + kyp) * HH + kz0 + j] : cmake<V, T>(0, 0);
-        }
+        stage<NT, NB, V>([&](int u) { return fd.B1[gidx(u)]; },
+                         [&](int u, const V& v) { buf[(u / KB) * BP + u % KB] = keep_if(u % KB < ncol, v); });
         __syncthreads();
         lds_fft<T, H, -1>(buf, KB, 1, BP, tw);
         __syncthreads();
     }
-    // spectral update in permuted kx order: position p holds kx = perm_freq(p)
-    for (int u = tid; u < H * KB; u += nt) {
+    // spectral update in permuted kx order (position p holds kx = perm_freq(p)),
+    // then Phi alpha, kept in registers
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int u = tid + q * NT;
         const int p = u / KB, j = u % KB;
-        if (j >= ncol) {
-            abuf[p * BP + j] = cmake<V, T>(0, 0);
-            continue;
+        V a = zero;
+        if (u < NB && j < ncol) {
+            const int kx = perm_freq<H>(p);
+            const T qx = (T)(kx < H / 2 ? kx : kx - H);
+            const T qz = (T)(kz0 + j);
+            const T q2 = qx * qx + qy * qy + qz * qz;
+            a = av[q];
+            if (UPDATE) {
+                const T xi2 = q2 * fd.two_pi_over_L * fd.two_pi_over_L;
+                T A, B;
+                mode_ab(fd, xi2 + fd.k2, A, B);
+                const V beta = buf[p * BP + j];
+                const T bs = B * fd.inv_Ld;
+                a = cmake<V, T>(A * a.x + bs * beta.x, A * a.y + bs * beta.y);
+                fd.alpha[gidx(u)] = a;
+            }
+            const T phi = fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1;
+            a = cmake<V, T>(a.x * phi, a.y * phi);
         }
-        const int kx = perm_freq<H>(p);
-        const int kz = kz0 + j;
-        const T qx = (T)(kx < H / 2 ? kx : kx - H);
-        const T qz = (T)kz;
-        const T q2 = qx * qx + qy * qy + qz * qz;
-        const T xi2 = q2 * fd.two_pi_over_L * fd.two_pi_over_L;
-        const size_t ai = ((size_t)p * H + kyp) * HH + kz;
-        V a = fd.alpha[ai];
-        if (UPDATE) {
-            T A, B;
-            mode_ab(fd, xi2 + fd.k2, A, B);
-            const V beta = buf[p * BP + j];
-            const T bs = B * fd.inv_Ld;
-            a = cmake<V, T>(A * a.x + bs * beta.x, A * a.y + bs * beta.y);
-            fd.alpha[ai] = a;
-        }
-        const T phi = fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1;
-        abuf[p * BP + j] = cmake<V, T>(a.x * phi, a.y * phi);
+        av[q] = a;
     }
-    for (int d = 0; d < 3; ++d) {
-        __syncthreads();
-        for (int u = tid; u < H * KB; u += nt) {
+    if (UPDATE) __syncthreads();  // beta is read: the three components overwrite it
+    // i xi_d Phi alpha for d = 0, 1, 2 in columns d KB + j (zero at the Nyquist
+    // frequency |q_d| = H/2), transformed along x together
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int u = tid + q * NT;
+        if (u < NB) {
             const int p = u / KB, j = u % KB;
-            int kd;
-            if (d == 0) kd = perm_freq<H>(p);
-            else if (d == 1) kd = ky;
-            else kd = kz0 + j;
-            // derivative factor i xi_d, zero at the Nyquist frequency |q_d| = H/2
-            const T q = (T)(kd == H / 2 ? 0 : (kd < H / 2 ? kd : kd - H));
-            const T xi = q * fd.two_pi_over_L;
-            const V a = abuf[p * BP + j];
-            buf[p * BP + j] = cmake<V, T>(-xi * a.y, xi * a.x);
-        }
-        __syncthreads();
-        lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
-        __syncthreads();
-        V* out = fd.gspec + (size_t)d * H * H * HH;
-        for (int u = tid; u < H * KB; u += nt) {
-            const int ix = u / KB, j = u % KB;
-            if (j < ncol) out[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
+            const int kd[3] = {perm_freq<H>(p), ky, kz0 + j};
+            const V a = av[q];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T qd = (T)(kd[d] == H / 2 ? 0 : (kd[d] < H / 2 ? kd[d] : kd[d] - H));
+                const T xi = qd * fd.two_pi_over_L;
+                lds[p * BP3 + d * KB + j] = cmake<V, T>(-xi * a.y, xi * a.x);
+            }
         }
     }
+    __syncthreads();
+    lds_fft<T, H, +1>(lds, 3 * KB, 1, BP3, tw);
+    __syncthreads();
+    // component d of entry u at column d KB + u % KB
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        stage<NT, NB, V>([&](int u) { return lds[(u / KB) * BP3 + d * KB + u % KB]; },
+                         [&](int u, const V& v) { if (u % KB < ncol) fd.gspec[(size_t)d * H * H * HH + gidx(u)] = v; });
 }
 
+// lds holds H (3 KB + 1) values: one grid block at pitch KB + 1, or the three
+// components side by side at pitch 3 KB + 1.
 template <typename T, int H, int MODE>
 __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp, int kz0, int ncol, T qy, int ky,
-                                                cplx_t<T>* buf, cplx_t<T>* abuf, const cplx_t<T>* tw) {
+                                                cplx_t<T>* lds, const cplx_t<T>* tw) {
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
     constexpr int BP = KB + 1;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    constexpr int BP3 = 3 * KB + 1;
+    constexpr int NB = H * KB;
+    constexpr int NT = PENCIL_THREADS;
+    constexpr int R = (NB + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const V zero = cmake<V, T>(0, 0);
+    auto gidx = [&](int u) { return ((size_t)(u / KB) * H + kyp) * HH + kz0 + min(u % KB, ncol - 1); };
     auto factors = [&](int p, int j, T& A, T& B, T& phi, T (&xi)[3]) {
         const int kx = perm_freq<H>(p);
         const int kz = kz0 + j;
@@ -291,85 +345,80 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
         mode_ab(fd, xi2 + fd.k2, A, B);
         phi = fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1;
         const int kd[3] = {kx, ky, kz};
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             const T q = (T)(kd[d] == H / 2 ? 0 : (kd[d] < H / 2 ? kd[d] : kd[d] - H));
             xi[d] = q * fd.two_pi_over_L;
         }
     };
+    // L^-3 B a of the block into lds (pitch BP), inverse along x, into gspec component 0
+    auto source_out = [&]() {
+        __syncthreads();
+        lds_fft<T, H, +1>(lds, KB, 1, BP, tw);
+        __syncthreads();
+        stage<NT, NB, V>([&](int u) { return lds[(u / KB) * BP + u % KB]; },
+                         [&](int u, const V& v) { if (u % KB < ncol) fd.gspec[gidx(u)] = v; });
+    };
     if constexpr (MODE == MODE_ADJ_SRC) {
-        for (int u = tid; u < H * KB; u += nt) {
-            const int p = u / KB, j = u % KB;
-            V v = cmake<V, T>(0, 0);
-            if (j < ncol) {
-                T A, B, phi, xi[3];
-                factors(p, j, A, B, phi, xi);
-                const V a = fd.alpha[((size_t)p * H + kyp) * HH + kz0 + j];
-                const T s = B * fd.inv_Ld;
-                v = cmake<V, T>(a.x * s, a.y * s);
-            }
-            buf[p * BP + j] = v;
-        }
-        __syncthreads();
-        lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
-        __syncthreads();
-        for (int u = tid; u < H * KB; u += nt) {
-            const int ix = u / KB, j = u % KB;
-            if (j < ncol) fd.gspec[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
-        }
+        stage<NT, NB, V>([&](int u) { return fd.alpha[gidx(u)]; },
+                         [&](int u, const V& a) {
+                             const int p = u / KB, j = u % KB;
+                             V v = zero;
+                             if (j < ncol) {
+                                 T A, B, phi, xi[3];
+                                 factors(p, j, A, B, phi, xi);
+                                 const T sc = B * fd.inv_Ld;
+                                 v = cmake<V, T>(a.x * sc, a.y * sc);
+                             }
+                             lds[p * BP + j] = v;
+                         });
+        source_out();
     } else {
-        // accumulate sum_d (-i xi_d Phi) F(Gbar_d) in abuf
-        for (int u = tid; u < H * KB; u += nt) abuf[(u / KB) * BP + (u % KB)] = cmake<V, T>(0, 0);
-        for (int d = 0; d < 3; ++d) {
-            __syncthreads();
-            const V* in = fd.B1 + (size_t)d * H * H * HH;
-            for (int u = tid; u < H * KB; u += nt) {
-                const int ix = u / KB, j = u % KB;
-                buf[ix * BP + j] = j < ncol ? in[((size_t)ix * H + kyp) * HH + kz0 + j] : cmake<V, T>(0, 0);
-            }
-            __syncthreads();
-            lds_fft<T, H, -1>(buf, KB, 1, BP, tw);
-            __syncthreads();
-            for (int u = tid; u < H * KB; u += nt) {
-                const int p = u / KB, j = u % KB;
-                if (j >= ncol) continue;
+        // abar of the block, read together with the three transformed grids
+        V av[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) av[q] = fd.alpha[gidx(min(tid + q * NT, NB - 1))];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            stage<NT, NB, V>([&](int u) { return fd.B1[(size_t)d * H * H * HH + gidx(u)]; },
+                             [&](int u, const V& v) { lds[(u / KB) * BP3 + d * KB + u % KB] = keep_if(u % KB < ncol, v); });
+        __syncthreads();
+        lds_fft<T, H, -1>(lds, 3 * KB, 1, BP3, tw);
+        __syncthreads();
+        // abar <- A abar + sum_d (-i xi_d Phi) F(Gbar_d)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int u = tid + q * NT;
+            const int p = u / KB, j = u % KB;
+            V out = zero;
+            if (u < NB && j < ncol) {
                 T A, B, phi, xi[3];
                 factors(p, j, A, B, phi, xi);
-                const V g = buf[p * BP + j];
-                const T c = xi[d] * phi;
-                V acc = abuf[p * BP + j];
-                // (-i c) g = (c g.y, -c g.x)
-                acc.x += c * g.y;
-                acc.y -= c * g.x;
-                abuf[p * BP + j] = acc;
-            }
-        }
-        __syncthreads();
-        for (int u = tid; u < H * KB; u += nt) {
-            const int p = u / KB, j = u % KB;
-            if (j >= ncol) {
-                if (MODE == MODE_ADJ_ACC_SRC) buf[p * BP + j] = cmake<V, T>(0, 0);
-                continue;
-            }
-            T A, B, phi, xi[3];
-            factors(p, j, A, B, phi, xi);
-            const size_t ai = ((size_t)p * H + kyp) * HH + kz0 + j;
-            const V a = fd.alpha[ai];
-            const V acc = abuf[p * BP + j];
-            const V na = cmake<V, T>(A * a.x + acc.x, A * a.y + acc.y);
-            fd.alpha[ai] = na;
-            if (MODE == MODE_ADJ_ACC_SRC) {
+                V acc = zero;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const V g = lds[p * BP3 + d * KB + j];
+                    const T c = xi[d] * phi;
+                    // (-i c) g = (c g.y, -c g.x)
+                    acc.x += c * g.y;
+                    acc.y -= c * g.x;
+                }
+                const V a = av[q];
+                const V na = cmake<V, T>(A * a.x + acc.x, A * a.y + acc.y);
+                fd.alpha[gidx(u)] = na;
                 const T sc = B * fd.inv_Ld;
-                buf[p * BP + j] = cmake<V, T>(na.x * sc, na.y * sc);
+                out = cmake<V, T>(na.x * sc, na.y * sc);
             }
+            av[q] = out;
         }
         if constexpr (MODE == MODE_ADJ_ACC_SRC) {
-            __syncthreads();
-            lds_fft<T, H, +1>(buf, KB, 1, BP, tw);
-            __syncthreads();
-            for (int u = tid; u < H * KB; u += nt) {
-                const int ix = u / KB, j = u % KB;
-                if (j < ncol) fd.gspec[((size_t)ix * H + kyp) * HH + kz0 + j] = buf[ix * BP + j];
+            __syncthreads();  // the transformed grids are read
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int u = tid + q * NT;
+                if (u < NB) lds[(u / KB) * BP + u % KB] = av[q];
             }
+            source_out();
         }
     }
 }
@@ -406,11 +455,11 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
         d = b % ncomp;
         ix = b / ncomp;
     }
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     make_twiddles<T, H>(tw);
     make_twiddles<T, M>(twm);
     const V* in = fd.gspec + ((size_t)d * H + ix) * H * HH;
-    for (int u = tid; u < H * HH; u += nt) buf[u] = in[u];
+    stage<PLANE_THREADS, H * HH, V>([&](int u) { return in[u]; }, [&](int u, const V& v) { buf[u] = v; });
     __syncthreads();
     lds_fft<T, H, +1>(buf, HH, 1, OP, tw);
     __syncthreads();
@@ -444,13 +493,9 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_inv_planes(const FieldDesc<T>
     __syncthreads();
     lds_fft<T, M, +1>(buf, H, OP, 1, twm);
     __syncthreads();
-    T* outp = fd.G + ((size_t)d * H + ix) * H * H;
-    for (int u = tid; u < H * M; u += nt) {
-        const int row = u / M, m = u % M;
-        const V v = buf[row * OP + m];
-        outp[row * H + 2 * m] = v.x;
-        outp[row * H + 2 * m + 1] = v.y;
-    }
+    V* outp = reinterpret_cast<V*>(fd.G + ((size_t)d * H + ix) * H * H);  // (x[2m], x[2m+1]) pairs
+    stage<PLANE_THREADS, H * M, V>([&](int u) { return buf[(u / M) * OP + u % M]; },
+                                   [&](int u, const V& v) { outp[u] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -487,13 +532,12 @@ __global__ __launch_bounds__(ROW_THREADS) void k_fwd_zrows(const FieldDesc<T>* _
     make_twiddles<T, H>(tw);
     make_twiddles<T, M>(twm);
     T* rows = fd.phi + ((size_t)comp * H * H + row0) * H;
-    for (int u = tid; u < ZROWS * M; u += nt) {
-        const int row = u / M, m = u % M;
-        buf[row * OP + m] = cmake<V, T>(rows[row * H + 2 * m], rows[row * H + 2 * m + 1]);
-    }
+    V* rv = reinterpret_cast<V*>(rows);
+    stage<ROW_THREADS, ZROWS * M, V>([&](int u) { return rv[u]; },
+                                     [&](int u, const V& v) { buf[(u / M) * OP + u % M] = v; });
     __syncthreads();
     if (consume) {
-        for (int u = tid; u < ZROWS * H; u += nt) rows[u] = (T)0;
+        for (int u = tid; u < ZROWS * M; u += nt) rv[u] = cmake<V, T>(0, 0);
         if (blockIdx.x == 0 && tid == 0 && fd.step != nullptr) *fd.step += 1u;
     }
     lds_fft<T, M, -1>(buf, ZROWS, OP, 1, twm);
@@ -524,7 +568,7 @@ __global__ __launch_bounds__(ROW_THREADS) void k_fwd_zrows(const FieldDesc<T>* _
     }
     __syncthreads();
     V* out = fd.B1 + ((size_t)comp * H * H + row0) * HH;
-    for (int u = tid; u < ZROWS * HH; u += nt) out[u] = buf[u];
+    stage<ROW_THREADS, ZROWS * HH, V>([&](int u) { return buf[u]; }, [&](int u, const V& v) { out[u] = v; });
 }
 
 template <typename T, int H, int DIR>
@@ -540,20 +584,17 @@ __global__ __launch_bounds__(PENCIL_THREADS) void k_ycols(const FieldDesc<T>* __
     const int x = rest % H, comp = rest / H;
     const int kz0 = kb * KB;
     const int ncol = min(KB, HH - kz0);
-    const int tid = threadIdx.x, nt = blockDim.x;
     V* base = (DIR < 0 ? fd.B1 : fd.gspec) + ((size_t)comp * H + x) * H * HH;
     make_twiddles<T, H>(tw);
-    for (int u = tid; u < H * KB; u += nt) {
-        const int y = u / KB, j = u % KB;
-        buf[y * BP + j] = j < ncol ? base[(size_t)y * HH + kz0 + j] : cmake<V, T>(0, 0);
-    }
+    auto gi = [&](int u) { return (size_t)(u / KB) * HH + kz0 + min(u % KB, ncol - 1); };
+    stage<PENCIL_THREADS, H * KB, V>(
+        [&](int u) { return base[gi(u)]; },
+        [&](int u, const V& v) { buf[(u / KB) * BP + u % KB] = keep_if(u % KB < ncol, v); });
     __syncthreads();
     lds_fft<T, H, DIR>(buf, KB, 1, BP, tw);
     __syncthreads();
-    for (int u = tid; u < H * KB; u += nt) {
-        const int y = u / KB, j = u % KB;
-        if (j < ncol) base[(size_t)y * HH + kz0 + j] = buf[y * BP + j];
-    }
+    stage<PENCIL_THREADS, H * KB, V>([&](int u) { return buf[(u / KB) * BP + u % KB]; },
+                                     [&](int u, const V& v) { if (u % KB < ncol) base[gi(u)] = v; });
 }
 
 template <typename T, int H>
@@ -571,11 +612,11 @@ __global__ __launch_bounds__(ROW_THREADS) void k_inv_zrows(const FieldDesc<T>* _
     const FieldDesc<T>& fd = fds[blockIdx.y];
     const int d = blockIdx.x / NRB;
     const size_t row0 = (size_t)(blockIdx.x % NRB) * ZROWS;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     make_twiddles<T, H>(tw);
     make_twiddles<T, M>(twm);
     const V* in = fd.gspec + ((size_t)d * H * H + row0) * HH;
-    for (int u = tid; u < ZROWS * HH; u += nt) buf[u] = in[u];
+    stage<ROW_THREADS, ZROWS * HH, V>([&](int u) { return in[u]; }, [&](int u, const V& v) { buf[u] = v; });
     __syncthreads();
     V xa[PPT], xb[PPT];
 #pragma unroll
@@ -606,20 +647,19 @@ __global__ __launch_bounds__(ROW_THREADS) void k_inv_zrows(const FieldDesc<T>* _
     __syncthreads();
     lds_fft<T, M, +1>(buf, ZROWS, OP, 1, twm);
     __syncthreads();
-    T* outp = fd.G + ((size_t)d * H * H + row0) * H;
-    for (int u = tid; u < ZROWS * M; u += nt) {
-        const int row = u / M, m = u % M;
-        const V v = buf[row * OP + m];
-        outp[row * H + 2 * m] = v.x;
-        outp[row * H + 2 * m + 1] = v.y;
-    }
+    V* outp = reinterpret_cast<V*>(fd.G + ((size_t)d * H * H + row0) * H);
+    stage<ROW_THREADS, ZROWS * M, V>([&](int u) { return buf[(u / M) * OP + u % M]; },
+                                     [&](int u, const V& v) { outp[u] = v; });
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 // grids above 128 take the split passes (a plane of half spectrum does not fit in LDS)
-constexpr int MAX_PLANE_H = 128;
+#ifndef SIPF_MAX_PLANE_H
+#define SIPF_MAX_PLANE_H 128
+#endif
+constexpr int MAX_PLANE_H = SIPF_MAX_PLANE_H;
 
 template <typename T, int H>
 static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, int ncomp, bool consume, hipStream_t s) {
