@@ -11,7 +11,9 @@
 // The exponentials are separable: for a fixed (qx, qy) the phases along qz
 // form a geometric sequence, so a thread evaluates one sincos and then
 // advances by a complex multiplication per qz (exp(-/+ i 2 pi z / L) per
-// particle, computed once).  Three kernels per step:
+// particle, computed once).  In FP32 the sequence is re-anchored with a fresh
+// sincos every DIR_ANCHOR terms, so that the rounding of the repeated
+// multiplication stays that of a few steps.  Three kernels per step:
 //   dir_beta    thread = (kx, ky, run of QZ consecutive q_z); the particles of
 //               one slice of the particle range pass through LDS; per-slice
 //               partial sums.  Also advances the step counter.
@@ -32,6 +34,7 @@ namespace sipf {
 constexpr int DIR_THREADS = 256;
 constexpr int DIR_PCHUNK = 256;  // particles staged per LDS pass of dir_beta
 constexpr int DIR_PAIRS = 8;     // (kx, ky) pairs staged per LDS pass of dir_push
+constexpr int DIR_ANCHOR = 8;    // FP32: phase terms between fresh sincos evaluations
 
 __device__ __forceinline__ int signed_q(int k, int H) { return k < H / 2 ? k : k - H; }
 
@@ -76,10 +79,12 @@ __global__ __launch_bounds__(DIR_THREADS) void k_dir_beta(DirDesc<T> d, cplx_t<T
         __syncthreads();
         if (active) {
             for (int i = 0; i < n; ++i) {
-                V e = cis_neg<T>((T)qx * sx[i] + (T)qy * sy[i] + (T)qz0 * sz[i]);
+                const T base = (T)qx * sx[i] + (T)qy * sy[i];
+                V e = cis_neg<T>(base + (T)qz0 * sz[i]);
                 const V st = sstep[i];
 #pragma unroll
                 for (int j = 0; j < QZ; ++j) {
+                    if (sizeof(T) == 4 && j > 0 && j % DIR_ANCHOR == 0) e = cis_neg<T>(base + (T)(qz0 + j) * sz[i]);
                     acc[j] = cadd(acc[j], e);
                     e = cmul(e, st);
                 }
@@ -173,9 +178,11 @@ __global__ __launch_bounds__(DIR_THREADS) void k_dir_grad(DirDesc<T> d, T* __res
         if (active) {
             for (int pr = 0; pr < npr; ++pr) {
                 const int kx = (pr0 + pr) / H, ky = (pr0 + pr) % H;
-                V e = cis_neg<T>(-((T)signed_q(kx, H) * xl + (T)signed_q(ky, H) * yl - (T)(H / 2) * zl));
+                const T base = (T)signed_q(kx, H) * xl + (T)signed_q(ky, H) * yl;
+                V e = cis_neg<T>(-(base - (T)(H / 2) * zl));
 #pragma unroll 8
                 for (int j = 0; j < H; ++j) {
+                    if (sizeof(T) == 4 && j > 0 && j % DIR_ANCHOR == 0) e = cis_neg<T>(-(base + (T)(j - H / 2) * zl));
                     const V a = sg[0][pr][j], b = sg[1][pr][j], c = sg[2][pr][j];
                     g0 += a.x * e.x - a.y * e.y;
                     g1 += b.x * e.x - b.y * e.y;

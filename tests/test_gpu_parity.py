@@ -248,6 +248,47 @@ def test_trajectory_fp32_h64_mix_100_steps(scheme, pp):
     assert rel_l2(A, osipf.half_spectrum(ao)) < 1e-5
 
 
+def _golden_mix_trajectory():
+    """ids, positions and low modes of alpha stored by
+    tests/golden/make_mix_h64_trajectory.py (FP64 oracle, 100 steps)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mix_h64_p1e6_100steps.txt")
+    ids, X, alpha = [], [], {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# alpha"):
+                _, _, qx, qy, qz, re_, im_ = line.split()
+                alpha[(int(qx), int(qy), int(qz))] = complex(float(re_), float(im_))
+            elif not line.startswith("#"):
+                i, x, y, z = line.split()
+                ids.append(int(i))
+                X.append((float(x), float(y), float(z)))
+    return np.array(ids), np.array(X), alpha
+
+
+@pytest.mark.parametrize("pp", ["sorted", "two_phase"])
+def test_trajectory_fp32_mix_full_size_100_steps(pp):
+    """The mixed workload at its full size (H = 64, P = 1e6, M0 = 80,
+    dt = 5e-5, the launch configuration the benchmark uses): after 100 steps
+    the 1024 stored particles lie within 1e-4 (minimum image) of the FP64
+    oracle's positions, and the modes 0 <= q <= 3 of alpha within 1e-5 of the
+    largest of them."""
+    cfg = workloads.CONFIGS["fp32_mix_h64"]
+    ids, Xg, ag = _golden_mix_trajectory()
+    say("trajectory fp32 mix full size", cfg["P"], pp)
+    X0 = cfg["init"](cfg["P"]).astype(np.float32)
+    sim = pkg.Sim(X0, **dict(cfg["params"], particle_pass=pp))
+    sim.run(100)
+    X = to_np(sim.positions()).astype(np.float64)
+    A = to_np(sim.field("alpha")).astype(np.complex128)
+    sim.close()
+    err = np.abs(osipf.min_image(X[ids] - Xg, 2.0)).max()
+    amax = max(abs(v) for v in ag.values())
+    aerr = max(abs(A[q] - v) for q, v in ag.items()) / amax
+    say(" max position error", err, "alpha error", aerr)
+    assert err < 1e-4
+    assert aerr < 1e-5
+
+
 @pytest.mark.parametrize("scheme", ["strang", "em"])
 def test_stepwise_parity_strong_aggregation(scheme):
     """M0 = 400: the dynamics amplifies rounding differences (the oracle itself
