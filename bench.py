@@ -336,6 +336,29 @@ def scheme_section(pkg, torch, X0, params, scheme, steps=100, warmup=20):
             "particle_steps_per_s": X0.shape[0] * steps / el}
 
 
+def full_run_section(pkg, torch, X0, params, steps):
+    """The workload's whole run (the configuration's step count from step 0,
+    graph-replayed) with each FP32 particle pass: the torus contracts over
+    the run and the pass that wins early is not the one that wins after the
+    collapse."""
+    out = {"steps": steps}
+    for pp in ("two_phase", "sorted"):
+        sim = pkg.Sim(X0, **dict(params, particle_pass=pp))
+        sim.prepare_run(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rho_max = sim.diagnostics()["rho_max"]
+        sim.close()
+        out[pp] = {"ms_total": 1e3 * el, "ms_per_step": 1e3 * el / steps,
+                   "particle_steps_per_s": X0.shape[0] * steps / el, "rho_max_end": rho_max}
+    return out
+
+
 def calibrate_copy(torch, nbytes=1 << 30, reps=5):
     """A plain device copy of nbytes, reps times: the reference whose HBM
     counters (FETCH_SIZE, WRITE_SIZE) scale those of the step's kernels."""
@@ -406,6 +429,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-positivity", action="store_true")
     ap.add_argument("--no-other-scheme", action="store_true")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the whole-run timing of the workload with each particle pass")
     ap.add_argument("--e1", default="reduced", choices=["none", "reduced", "full"],
                     help="convergence study of Sec. 5.1: 8 runs of 6 configurations, or the full 30 x 14")
     ap.add_argument("--e2", default="quick", choices=["none", "quick", "full"],
@@ -448,7 +473,6 @@ def main():
     print(f"# workload {args.workload}: P={P} H={H} scheme={args.scheme}", file=sys.stderr, flush=True)
     X0 = cfg["init"](P).astype(np.float32 if fp32 else np.float64)
     sim = pkg.Sim(X0, **params)
-    del X0
 
     sim.run(args.warmup)
     # capture the HIP graphs the timed run replays (runs no step), so that the
@@ -470,12 +494,30 @@ def main():
     sim.sync()
     steady = time.perf_counter() - t0
 
-    # per-kernel durations with HIP events on the library's stream, same steps again
+    # run-time diagnostics of the state (one call = deposit, three FFT passes, reductions)
+    sim.diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        diag = sim.diagnostics()
+    diag = dict(diag, ms_per_call=1e3 * (time.perf_counter() - t0) / 5)
+    sim.close()
+
+    # per-kernel durations with HIP events on the library's stream, over the
+    # timed steps again: a fresh context from the same input (the same seeded
+    # trajectory up to rounding) runs the warm-up, then the timed steps with
+    # phase timing on, so that the durations belong to the same states as the
+    # timed window (the torus contracts as it runs, and the pass slows down
+    # once it has collapsed)
+    sim = pkg.Sim(X0, **params)
+    del X0
+    sim.run(args.warmup)
     sim.profile(True)
     sim.run(args.steps)
     prof = sim.profile_read()
     sim.profile(False)
     sim.sync()
+    sim.close()
     phases = {k: {"ms_total": v[0], "launches": v[1], "us_avg": (1e3 * v[0] / v[1]) if v[1] else None}
               for k, v in prof.items()}
     dom = max((k for k in phases if phases[k]["launches"]), key=lambda k: phases[k]["ms_total"])
@@ -529,18 +571,16 @@ def main():
                                "implementation_GB_s": implementation_bytes(k, P, H, tsize) / (v["us_avg"] * 1e3)}
                            for k, v in phases.items() if v["launches"]},
     }
-    # run-time diagnostics of the state (one call = deposit, three FFT passes, reductions)
-    sim.diagnostics()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(5):
-        diag = sim.diagnostics()
-    out["diagnostics"] = dict(diag, ms_per_call=1e3 * (time.perf_counter() - t0) / 5)
-    sim.close()
+    out["diagnostics"] = diag
     if not args.no_positivity:
         print("# positivity-preserving deposit on the same workload", file=sys.stderr, flush=True)
         X0 = cfg["init"](P).astype(np.float32 if fp32 else np.float64)  # the same seeded input as the timed run
         out["positivity"] = positivity_section(pkg, torch, X0, params, ms_per_step)
+        del X0
+    if fp32 and not args.no_full_run:
+        print(f"# the whole {cfg['steps']}-step run with each particle pass", file=sys.stderr, flush=True)
+        X0 = cfg["init"](P).astype(np.float32)
+        out["full_run"] = full_run_section(pkg, torch, X0, params, cfg["steps"])
         del X0
     if not args.no_other_scheme:
         other = "em" if args.scheme == "strang" else "strang"
