@@ -418,6 +418,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="fp32_ring_h128")
     ap.add_argument("--scheme", default="strang", choices=["strang", "em"])
+    ap.add_argument("--particle-pass", default="default", choices=["default", "sorted", "two_phase"],
+                    help="FP32 particle pass of the timed workload (sipf_params.particle_pass)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--cpu-workers", type=int, default=0,
@@ -465,7 +467,7 @@ def main():
 
     cfg = workloads.CONFIGS[args.workload]
     P = cfg["P"]
-    params = dict(cfg["params"], scheme=args.scheme)
+    params = dict(cfg["params"], scheme=args.scheme, particle_pass=args.particle_pass)
     H = params["H"]
     fp32 = params["precision"] == "fp32"
     tsize = 4 if fp32 else 8
@@ -545,7 +547,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "P": P, "H": H, "scheme": args.scheme,
+        "config": {"workload": args.workload, "P": P, "H": H, "scheme": args.scheme, "particle_pass": args.particle_pass,
                    "dt": params["dt"], "M0": params["M0"], "init": "torus R=0.5 sd=0.05"
                    if "ring" in args.workload else args.workload},
         # dominant kernel: algorithmic bytes per launch (24 P + 16 H^3 for the
