@@ -228,10 +228,12 @@ int sipf_step(sipf_ctx* ctx);
  * profiling is on, every step is enqueued eagerly. */
 int sipf_run(sipf_ctx* ctx, int64_t nsteps);
 
-/* Capture, without running anything, every graph that sipf_run(ctx, nsteps)
- * issued next would replay, so that the run itself only replays.  The
- * context's state is unchanged.  Errors: SIPF_EINVAL (nsteps < 0),
- * SIPF_EDEVICE (capture or instantiation failed). */
+/* Capture, without running any step, every graph that sipf_run(ctx, nsteps)
+ * issued next would replay, and upload each to the device on the context's
+ * stream, so that the run itself only replays (graphs captured during a run
+ * are uploaded the same way before their first launch).  The context's state
+ * is unchanged.  Errors: SIPF_EINVAL (nsteps < 0), SIPF_EDEVICE (capture,
+ * instantiation or upload failed). */
 int sipf_prepare_run(sipf_ctx* ctx, int64_t nsteps);
 
 /* Switch graph replay in sipf_run on (1, the default) or off (0). */

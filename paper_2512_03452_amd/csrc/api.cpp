@@ -587,6 +587,15 @@ template <typename T> int capture_graph(Group* g, int len, hipGraphExec_t* out) 
         *out = nullptr;
         return fail(SIPF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
+    // move the graph's launch resources to the device now (on the library's
+    // stream, ahead of any launch of it), so that its first replay costs what
+    // every later one does
+    e = hipGraphUpload(*out, g->stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(*out);
+        *out = nullptr;
+        return fail(SIPF_EDEVICE, std::string("hipGraphUpload: ") + hipGetErrorString(e));
+    }
     return SIPF_OK;
 }
 
