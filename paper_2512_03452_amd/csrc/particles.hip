@@ -1,17 +1,20 @@
 // Particle pass of the SIPF-PIC step: binning, the fourth-order deposit
 // (Definition particle2grid, Algorithm 2), the trilinear gather of the
 // gradient (Definition grid2particle, Algorithm 3) and the stochastic push
-// (Algorithm 4 split step / eq. rho_hat_update), fused in one kernel that
-// reads each particle once.
+// (Algorithm 4 split step / eq. rho_hat_update), in one launch per step.
 //
 // Particles are kept approximately sorted by tile (T^3 cells, tiles in Morton
 // order) by a periodic counting sort.  A workgroup takes a contiguous chunk of
-// the sorted array, measures the bounding box of the chunk's cells, and, when
-// the box plus the stencil reach (-1..+2) fits, accumulates the deposit in an
-// LDS window in fixed point with integer LDS atomics, then adds the window into
-// the global grid once.  A chunk whose box does not fit (sparse regions, long
-// drift since the last sort) deposits straight into the global grid with
-// atomics; the result is the same sum in a different order.  The sort also
+// the sorted array (a work item), measures the bounding box of the chunk's
+// cells, and, when the box plus the stencil reach (-1..+2) fits, accumulates
+// the deposit in an LDS window in fixed point with integer LDS atomics, then
+// adds the window into the global grid once.  A chunk whose box does not fit
+// (sparse regions, long drift since the last sort) deposits straight into the
+// global grid with atomics; the result is the same sum in a different order.
+// Two forms of the FP32 pass: the two-phase one (deposit all of an item's
+// particles, then stage the gradient window and push them) and the sorted one
+// (each item kept sorted by cell between steps, runs of equal cells summed in
+// registers before the LDS adds, deposit and push in one loop).  The sort also
 // serves the two-dimensional pass (particles2d.hip): tiles of T^2 cells.
 #include <climits>
 
@@ -697,23 +700,6 @@ __device__ __forceinline__ void flush_run4(RunWin* win, int base, const float* a
 #undef SIPF_FL
 }
 
-// FP32 work item in one loop, with the item kept sorted by cell between
-// steps.  The particles arrive in the lane layout above, sorted by cell by
-// the previous step's write-out (in the order of the re-sort right after
-// one).  Each particle deposits its position X^(n-1) (Algorithm 4 reads only
-// the state after step n-1 in both branches, so the deposit and the push of a
-// particle are independent and one pass serves both): a lane adds the
-// weights of its consecutive particles into registers while they share a
-// cell and adds each run to the deposit window once (one set of 32 LDS
-// atomics per run instead of per particle; the lanes of a wave then work on
-// neighbouring cells, so those atomics spread over the LDS banks).  The
-// particle then draws its noise, gathers the gradient at Y from the gradient
-// window (neighbouring lanes read neighbouring rows) and is pushed.  The
-// pushed particles are counting-sorted by
-// their new cell inside the item's box (cells that left it go last) and
-// written back to the item's segment in the lane layout, which keeps the
-// order for the next step.  Returns false, touching nothing, when the item
-// does not fit the windows.
 // Particles of an FP32 item in the lane layout, loaded into registers.
 __device__ __forceinline__ void load_cols(const PartDesc<float>& a, int64_t beg, int cnt, float* px, float* py,
                                           float* pz, uint32_t* pid) {
@@ -739,6 +725,23 @@ __device__ __forceinline__ bool sorted_candidate(const PartDesc<float>& a, const
            win_bytes >= fused_bytes<float>();
 }
 
+// FP32 work item in one loop, with the item kept sorted by cell between
+// steps.  The particles arrive in the lane layout above, sorted by cell by
+// the previous step's write-out (in the order of the re-sort right after
+// one).  Each particle deposits its position X^(n-1) (Algorithm 4 reads only
+// the state after step n-1 in both branches, so the deposit and the push of a
+// particle are independent and one pass serves both): a lane adds the
+// weights of its consecutive particles into registers while they share a
+// cell and adds each run to the deposit window once (one set of 32 LDS
+// atomics per run instead of per particle; the lanes of a wave then work on
+// neighbouring cells, so those atomics spread over the LDS banks).  The
+// particle then draws its noise, gathers the gradient at Y from the gradient
+// window (neighbouring lanes read neighbouring rows) and is pushed.  The
+// pushed particles are counting-sorted by
+// their new cell inside the item's box (cells that left it go last) and
+// written back to the item's segment in the lane layout, which keeps the
+// order for the next step.  Returns false, touching nothing, when the item
+// does not fit the windows.
 template <int SCHEME, bool P2>
 __device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t beg, int cnt, unsigned char* lds,
                                             int* sh) {
