@@ -213,6 +213,7 @@ struct Group {
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     int resort = 4, chunk = 4096, adj_chunk = 2048, win_bytes = 65536, pgrid = 1024;
     bool sorted = false;  // FP32 3-D deposit + push: the sorted pass (else two-phase)
+    bool counts_ready = false;  // the last step's particle pass left the tile counts of the next sort
     int since_sort = 0;
     int cur = 0;  // which of the two particle buffer sets holds the current positions
     int64_t n_host = 0;
@@ -236,10 +237,11 @@ struct Group {
     std::vector<void*> allocs;
     void* diag = nullptr;  // diagnostics scratch, allocated on first use
     // captured graphs of run segments, by (buffer set, steps since the last
-    // sort, segment length): the only host state a step's launches depend on
+    // sort, segment length, whether the tile counts of a due sort are ready):
+    // the only host state a step's launches depend on
     bool graphs = true;
     struct GraphSeg {
-        int cur, since, len;
+        int cur, since, len, counted;
         hipGraphExec_t exec;
     };
     std::vector<GraphSeg> gcache;
@@ -416,20 +418,28 @@ template <typename T> int do_sort(Group* g) {
         Timed t(g, SIPF_PHASE_SORT);
         HIPCHK(launch_sort<T>(g->dim, pdesc_dev<T>(g, g->cur), pdesc_dev<T>(g, dst), g->chunks, g->nchunks, (int)g->in.size(),
                               g->counts, g->cursor, g->seg, g->seg_off, g->seg_n, g->items, g->nitems, g->chunk,
-                              g->stream));
+                              g->stream, g->counts_ready));
+        g->counts_ready = false;
     }
     g->cur = dst;
     g->since_sort = 0;
     return SIPF_OK;
 }
 
+// Whether the step's particle pass takes the tile counts of the next sort
+// (3-D SIPF-PIC steps without the positivity rounds, whose deposit and push
+// run apart).
+bool counts_in_pass(const Group* g) {
+    return g->dim == 3 && g->method == SIPF_METHOD_PIC && !g->positivity;
+}
+
 // The passes of a step in the group's dimension.
 template <typename T>
-hipError_t particles_any(const Group* g, const PartDesc<T>* pd, bool deposit, bool push) {
+hipError_t particles_any(const Group* g, const PartDesc<T>* pd, bool deposit, bool push, uint32_t* kcounts = nullptr) {
     return g->dim == 2 ? launch_particles2<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
                                               g->win_bytes, g->stream)
                        : launch_particles<T>(pd, g->items, g->nitems, g->pgrid, deposit, push, g->scheme,
-                                             g->win_bytes, g->pow2, g->sorted, g->stream);
+                                             g->win_bytes, g->pow2, g->sorted, g->stream, kcounts);
 }
 template <typename T> hipError_t field_fwd(const Group* g, int H, const FieldDesc<T>* fd, int count, bool consume) {
     return g->dim == 2 ? launch_fwd_rows2<T>(H, fd, count, consume, g->stream)
@@ -534,9 +544,13 @@ template <typename T> int enqueue_step(Group* g) {
         int rc = positivity_rounds<T>(g);
         if (rc) return rc;
         HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), false, true));
+        g->counts_ready = false;
     } else {
+        // the step before a due sort also counts the tiles of its output
         Timed t(g, SIPF_PHASE_PARTICLES);
-        HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, true));
+        const bool count = counts_in_pass(g) && g->since_sort + 1 >= g->resort;
+        HIPCHK(particles_any<T>(g, pdesc_dev<T>(g, g->cur), true, true, count ? g->counts : nullptr));
+        g->counts_ready = count;
     }
     {
         Timed t(g, SIPF_PHASE_FWD);
@@ -564,6 +578,7 @@ template <typename T> int capture_graph(Group* g, int len, hipGraphExec_t* out) 
     *out = nullptr;
     if (!g->cap) HIPCHK(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
     const int since = g->since_sort, cur = g->cur;
+    const bool counted = g->counts_ready;
     const int64_t nh = g->n_host;
     hipStream_t user = g->stream;
     g->stream = g->cap;
@@ -575,6 +590,7 @@ template <typename T> int capture_graph(Group* g, int len, hipGraphExec_t* out) 
     g->stream = user;
     g->since_sort = since;
     g->cur = cur;
+    g->counts_ready = counted;
     g->n_host = nh;
     if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -614,7 +630,9 @@ void advance_state(Group* g, int len) {
         if (g->since_sort >= g->resort) {
             g->cur = 1 - g->cur;
             g->since_sort = 0;
+            g->counts_ready = false;
         }
+        g->counts_ready = counts_in_pass(g) && g->since_sort + 1 >= g->resort;
         g->since_sort++;
     }
     g->n_host += len;
@@ -626,7 +644,7 @@ constexpr size_t GRAPH_CACHE_MAX = 16;
 // on first use.
 template <typename T> int segment_graph(Group* g, int len, hipGraphExec_t* out) {
     for (const auto& gs : g->gcache)
-        if (gs.cur == g->cur && gs.since == g->since_sort && gs.len == len) {
+        if (gs.cur == g->cur && gs.since == g->since_sort && gs.len == len && gs.counted == (int)g->counts_ready) {
             *out = gs.exec;
             return SIPF_OK;
         }
@@ -636,7 +654,7 @@ template <typename T> int segment_graph(Group* g, int len, hipGraphExec_t* out) 
     }
     int rc = capture_graph<T>(g, len, out);
     if (rc) return rc;
-    g->gcache.push_back({g->cur, g->since_sort, len, *out});
+    g->gcache.push_back({g->cur, g->since_sort, len, (int)g->counts_ready, *out});
     return SIPF_OK;
 }
 
@@ -665,6 +683,7 @@ template <typename T> int run_typed(Group* g, int64_t nsteps) {
 template <typename T> int prepare_typed(Group* g, int64_t nsteps) {
     if (!g->graphs) return SIPF_OK;
     const int since = g->since_sort, cur = g->cur;
+    const bool counted = g->counts_ready;
     const int64_t nh = g->n_host;
     int rc = SIPF_OK;
     for (int64_t left = nsteps; left > 0 && rc == SIPF_OK;) {
@@ -676,6 +695,7 @@ template <typename T> int prepare_typed(Group* g, int64_t nsteps) {
     }
     g->since_sort = since;
     g->cur = cur;
+    g->counts_ready = counted;
     g->n_host = nh;
     return rc;
 }
@@ -718,6 +738,7 @@ int check_err(Group* g) {
         const std::string who = n > 1 ? " (instance " + std::to_string(i) + ")" : std::string();
         if (e[i] & 2) return fail(SIPF_ENUMERIC, "non-finite initial position" + who);
         if (e[i] & 1) return fail(SIPF_ENUMERIC, "a step produced a non-finite position" + who);
+        if (e[i] & 4) return fail(SIPF_EDEVICE, "the sort's tile counts did not match the particle count" + who);
     }
     return SIPF_OK;
 }
@@ -1458,6 +1479,12 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         if ((rc = enqueue_step<T>(c))) return rc;
     }
     HIPCHK(hipMemcpyAsync(aN.p, I.alpha, nspec * sizeof(V), hipMemcpyDeviceToDevice, c->stream));
+    if (c->counts_ready) {
+        // the last forward step took the tile counts of a sort that the
+        // segment sorts below do not consume: clear them
+        HIPCHK(launch_fill<float>((float*)c->counts, (int64_t)sort_max_keys(), 0.0f, c->stream));
+        c->counts_ready = false;
+    }
 
     // ---- loss and its cotangent phibar^(N)
     HIPCHK(launch_zero_f64((double*)acc.p, 4, c->stream));

@@ -83,7 +83,7 @@ template <typename T> struct PartDesc {
     T* phi;                 // deposit target (H^3)
     const T* G;             // gradient grids (3 x H^3)
     const uint32_t* step;   // completed steps; this step is *step + 1
-    int* err;               // device error flags (bit 0: non-finite position)
+    int* err;               // device error flags (bit 0: non-finite position, bit 1: non-finite input, bit 2: sort counts inconsistent)
     int H;
     int dim;                // 2 or 3 (z unused in 2-D)
     int scheme;             // SIPF_STRANG or SIPF_EM
@@ -179,8 +179,12 @@ template <typename T>
 // sorted: the FP32 deposit + push pass keeps each item sorted by cell and
 // accumulates runs of equal cells (else the two-phase pass; FP64 and the
 // single-phase passes ignore it)
+// kcounts: when not null, the deposit + push pass also counts the pushed
+// particles' sort tiles into these counts (MAX_KEYS per instance, zero on
+// entry), so that the next sort can skip its histogram (launch_sort counted)
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
-                            bool push, int scheme, int win_bytes, bool pow2, bool sorted, hipStream_t s);
+                            bool push, int scheme, int win_bytes, bool pow2, bool sorted, hipStream_t s,
+                            uint32_t* kcounts = nullptr);
 // positivity-preserving deposit rounds (positivity.hip): flag nodes below
 // -thresh, switch the order-4 particles touching a flagged node to order 2
 // (count += switched; sw[i] = tag marks them), clamp negatives to zero; tmp
@@ -196,9 +200,14 @@ hipError_t launch_particles2(const PartDesc<T>* pd, const WorkItem* items, int* 
                              bool push, int scheme, int win_bytes, hipStream_t s);
 template <typename T> int particle_resident_blocks2(int scheme, int win_bytes);
 template <typename T>
+// counted: the counts already hold the tiles of src (taken by the previous
+// step's particle pass), so the histogram pass is skipped.  The scan checks
+// that the counts add up to each instance's P; if not, it lists no work items
+// and sets bit 2 of the instance's error flag (the scatter then writes
+// nothing past the array).
 hipError_t launch_sort(int dim, const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks, int ninst,
                        uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
-                       WorkItem* items, int* nitems, int chunk, hipStream_t s);
+                       WorkItem* items, int* nitems, int chunk, hipStream_t s, bool counted = false);
 int sort_chunk();
 template <typename T>
 hipError_t launch_cells(const T* X, int64_t n, int H, T hl, int32_t* cells, hipStream_t s);

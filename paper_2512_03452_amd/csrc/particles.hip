@@ -95,13 +95,151 @@ __device__ __forceinline__ uint32_t tile_coord(const PartDesc<T>& a, T v) {
     if (c < 0) c += a.H;
     return (uint32_t)(c / a.tile);
 }
-// Morton key of the tile of the cell containing (x, y, z) (up to 32 tiles per
-// axis in 3-D, 64 in 2-D)
+// Morton key of a tile (up to 32 tiles per axis in 3-D, 64 in 2-D)
+template <int DIM> __device__ __forceinline__ uint32_t key_of_tile(uint32_t tx, uint32_t ty, uint32_t tz) {
+    if constexpr (DIM == 3) return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tz);
+    else return (spread2(tx) << 1) | spread2(ty);
+}
+// Morton key of the tile of the cell containing (x, y, z)
 template <typename T, int DIM>
 __device__ __forceinline__ uint32_t key_of(const PartDesc<T>& a, T x, T y, T z) {
-    const uint32_t tx = tile_coord(a, x), ty = tile_coord(a, y);
-    if constexpr (DIM == 3) return (spread3(tx) << 2) | (spread3(ty) << 1) | spread3(tile_coord(a, z));
-    else return (spread2(tx) << 1) | spread2(ty);
+    return key_of_tile<DIM>(tile_coord(a, x), tile_coord(a, y), DIM == 3 ? tile_coord(a, z) : 0u);
+}
+// Tiles per axis of an instance's sort grid
+template <typename T> __device__ __forceinline__ int tiles_per_axis(const PartDesc<T>& a) {
+    return a.tshift >= 0 ? (a.H >> a.tshift) : (a.H + a.tile - 1) / a.tile;
+}
+
+// Runs of equal keys in consecutive lanes of a wave (call with the whole
+// wave).  Returns the run's length at its first lane and 0 at the others;
+// head receives the first lane of the caller's run.  The particles are in
+// tile order from the previous sort and mostly still in their tiles, so a
+// wave's 64 keys form one or a few runs: one LDS atomic per run instead of
+// per particle (atomics of a wave on one LDS word serialise).
+__device__ __forceinline__ uint32_t lane_runs(uint32_t key, int& head) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool first = lane == 0 || prev != key;
+    const uint64_t heads = __ballot(first);
+    head = 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));  // bit 0 is always set
+    if (!first) return 0u;
+    const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+    return after ? (uint32_t)__builtin_ctzll(after) + 1u : (uint32_t)(64 - lane);
+}
+
+// Tile counts of the next sort, taken by the 3-D particle pass of the step
+// before it, so that the sort needs no histogram pass of its own.  A work
+// item's particles shared one tile at the last sort and move less than a
+// tile per step, so the item sums its pushed particles' tiles in LDS slots
+// for the 5^3 tiles within two of a reference tile (that of the item's first
+// particle before the push), one LDS add per run of equal tiles in
+// consecutive lanes, and adds the nonzero slots to the counts once per item;
+// a particle whose tile lies farther away (or every particle, on grids of
+// fewer than 5 tiles per axis) adds to the counts directly.
+// The slot and reference accesses go through LDS-address-space pointers: the
+// generic pointers of the struct let the compiler merge the LDS and the
+// global adds into one flat atomic, which the barrier that follows did not
+// wait for (counts were lost).
+constexpr int TC_SLOTS = 125;
+#define LDS_AS __attribute__((address_space(3)))
+struct TileCount {
+    uint32_t* counts;  // the item's instance's counts (MAX_KEYS words), null when not counting
+    uint32_t* slot;    // LDS, TC_SLOTS words, zero between items
+    int* ref;          // LDS, the item's reference tile (3 words)
+    __device__ __forceinline__ LDS_AS uint32_t* lslot() const { return (LDS_AS uint32_t*)slot; }
+    __device__ __forceinline__ LDS_AS int* lref() const { return (LDS_AS int*)ref; }
+};
+
+// Thread 0: the reference tile of the item, from its first particle (read by
+// the item's threads after the next barrier).
+template <typename T>
+__device__ __forceinline__ void tc_reference(const TileCount& tc, const PartDesc<T>& a, T x, T y, T z) {
+    if (tc.counts != nullptr && threadIdx.x == 0) {
+        LDS_AS int* r = tc.lref();
+        r[0] = (int)tile_coord(a, x);
+        r[1] = (int)tile_coord(a, y);
+        r[2] = (int)tile_coord(a, z);
+    }
+}
+
+// Slot of tile t relative to the reference (or -1 when it lies farther than
+// two tiles on an axis, or the grid has fewer than 5 tiles per axis).
+__device__ __forceinline__ int tc_slot(const LDS_AS int* r, const uint32_t t[3], int nt) {
+    bool near = nt >= 5;
+    int slot = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int o = (int)t[d] - r[d];  // periodic offset in (-nt/2, nt/2]
+        if (o > nt / 2) o -= nt;
+        else if (o <= -((nt + 1) / 2)) o += nt;
+        near = near && o >= -2 && o <= 2;
+        slot = slot * 5 + (o + 2);
+    }
+    return near ? slot : -1;
+}
+
+// Count the tile of (x, y, z) for lanes with ok set (call with the whole wave).
+// Usually every particle of a wave is in lane 0's tile: then lane 0 adds the
+// wave's count once; otherwise each run of equal tiles in consecutive lanes
+// adds once.
+template <typename T>
+__device__ __forceinline__ void tc_add(const TileCount& tc, const PartDesc<T>& a, bool ok, T x, T y, T z) {
+    if (tc.counts == nullptr) return;
+    const int nt = tiles_per_axis(a);
+    const uint32_t t[3] = {ok ? tile_coord(a, x) : 0u, ok ? tile_coord(a, y) : 0u, ok ? tile_coord(a, z) : 0u};
+    const uint32_t code = t[0] | (t[1] << 5) | (t[2] << 10);  // at most 32 tiles per axis
+    const LDS_AS int* r = tc.lref();
+    const uint64_t valid = __ballot(ok);
+    if (valid == 0ull) return;
+    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)code);
+    if ((valid & 1ull) && __ballot(ok && code == c0) == valid) {
+        if ((threadIdx.x & 63) == 0) {
+            const uint32_t n = (uint32_t)__popcll(valid);
+            const int sl = tc_slot(r, t, nt);
+            if (sl >= 0)
+                __hip_atomic_fetch_add(tc.lslot() + sl, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+                __hip_atomic_fetch_add(gp(tc.counts) + key_of_tile<3>(t[0], t[1], t[2]), n, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    const int sl = tc_slot(r, t, nt);
+    const uint32_t id = !ok ? 0xFFFFFFFFu : sl >= 0 ? (uint32_t)sl : (uint32_t)TC_SLOTS + key_of_tile<3>(t[0], t[1], t[2]);
+    int head;
+    const uint32_t len = lane_runs(id, head);
+    if (ok && len) {
+        if (id < (uint32_t)TC_SLOTS)
+            __hip_atomic_fetch_add(tc.lslot() + id, len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_fetch_add(gp(tc.counts) + (id - TC_SLOTS), len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Add the item's slots to the counts and clear them (whole workgroup, after
+// the item's last tc_add).
+template <typename T> __device__ __forceinline__ void tc_flush(const TileCount& tc, const PartDesc<T>& a) {
+    if (tc.counts == nullptr) return;
+    __syncthreads();
+    const int s = threadIdx.x;
+    if (s < TC_SLOTS) {
+        LDS_AS uint32_t* sl = tc.lslot();
+        const LDS_AS int* r = tc.lref();
+        const uint32_t c = sl[s];
+        if (c != 0u) {
+            const int nt = tiles_per_axis(a);
+            const int off[3] = {s / 25 - 2, (s / 5) % 5 - 2, s % 5 - 2};
+            uint32_t t[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int v = (r[d] + off[d]) % nt;
+                t[d] = (uint32_t)(v < 0 ? v + nt : v);
+            }
+            __hip_atomic_fetch_add(gp(tc.counts) + key_of_tile<3>(t[0], t[1], t[2]), c, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            sl[s] = 0u;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +474,7 @@ __device__ __forceinline__ bool gather_fast(const T* Gw, int gx, int gy, int gz,
 // One work item: particles [beg, beg + cnt) of one instance, held in registers.
 template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
 __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int cnt, unsigned char* lds,
-                                          int win_bytes, int* sh) {
+                                          int win_bytes, int* sh, const TileCount& tc) {
     using I = typename Fixed<T>::I;
     const int tid = threadIdx.x;
     const int H = a.H, Hh = H / 2;
@@ -362,6 +500,10 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
 #if !SIPF_RELOAD
         if (PUSH) pid[k] = gp(iid)[jj];
 #endif
+    }
+    if (tc.counts != nullptr) {
+        tc_reference(tc, a, px[0], py[0], pz[0]);
+        __syncthreads();
     }
     const bool windows = cnt >= MIN_WINDOW_ITEM;
     int rx = 0, ry = 0, rz = 0;
@@ -531,7 +673,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
 #pragma unroll SIPF_PUSH_UNROLL
         for (int k = 0; k < PPT; ++k) {
             const int j = tid + k * PT;
-            if (j >= cnt) continue;
+            const bool valid = j < cnt;
+            T nx = (T)0, ny = (T)0, nz = (T)0;
+            if (valid) {
 #if SIPF_RELOAD
             // re-read from L2 rather than holding eight particles in registers
             const T x = gp(ix)[j], y = gp(iy)[j], z = gp(iz)[j];
@@ -579,9 +723,9 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
                 iz[0] = wr(gz); iz[1] = wr(gz + 1);
                 trilinear3<T>(gp(a.G), H3, H, H, ix, iy, iz, sx - fx, sy - fy, sz - fz, vx, vy, vz);
             }
-            const T nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
-            const T ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
-            const T nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
+            nx = wrap_box(yx + a.chitau * vx + a.s * w0, a.L, a.halfL, a.invL);
+            ny = wrap_box(yy + a.chitau * vy + a.s * w1, a.L, a.halfL, a.invL);
+            nz = wrap_box(yz + a.chitau * vz + a.s * w2, a.L, a.halfL, a.invL);
             if (!DEP && a.zout != nullptr) {
                 // keep the normals of this step for the reverse pass (adjoint recompute)
                 const int nz6 = SCHEME == SIPF_STRANG ? 6 : 3;
@@ -599,6 +743,8 @@ __device__ __forceinline__ void item_pass(const PartDesc<T>& a, int64_t beg, int
                 gp(a.z + beg)[j] = nz;
             }
             if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) atomicOr(a.err, 1);
+            }
+            tc_add(tc, a, valid, nx, ny, nz);
         }
     }
 }
@@ -744,7 +890,7 @@ __device__ __forceinline__ bool sorted_candidate(const PartDesc<float>& a, const
 // does not fit the windows.
 template <int SCHEME, bool P2>
 __device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t beg, int cnt, unsigned char* lds,
-                                            int* sh) {
+                                            int* sh, const TileCount& tc) {
     float px[PPT], py[PPT], pz[PPT];
     uint32_t pid[PPT];
     load_cols(a, beg, cnt, px, py, pz, pid);
@@ -762,6 +908,7 @@ __device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t be
         sh[9] = wr(ifloor(py[0] * hl));
         sh[10] = wr(ifloor(pz[0] * hl));
     }
+    tc_reference(tc, a, px[0], py[0], pz[0]);
     __syncthreads();
     const int rx = sh[8], ry = sh[9], rz = sh[10];
     {
@@ -901,6 +1048,8 @@ __device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t be
         const uint32_t sft = 16u * (kk & 1u);
         kr[k] = (kk << 16) | ((atomicAdd(&cw[kk >> 1], 1u << sft) >> sft) & 0xFFFFu);
     }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) tc_add(tc, a, cl.valid(tid, k), px[k], py[k], pz[k]);
     __syncthreads();
     // the deposit window into the grid
     {
@@ -967,31 +1116,44 @@ __device__ __forceinline__ bool item_sorted(const PartDesc<float>& a, int64_t be
     return true;
 }
 
-template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2, bool SORTED>
+// kcounts: the sort's tile counts of every instance (MAX_KEYS each) when this
+// step takes them for the next sort (3-D deposit + push passes), else null.
+// COUNT: the instantiation that takes the counts (the other one carries no
+// counting code, so its registers are those of the plain pass).
+template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2, bool SORTED, bool COUNT>
 __device__ __forceinline__ void particles_body(const PartDesc<T>* __restrict__ pds,
                                                const WorkItem* __restrict__ items, int* hdr, int win_bytes,
-                                               unsigned char* smem_raw, int* sh, int* slot_p) {
+                                               unsigned char* smem_raw, int* sh, int* slot_p, uint32_t* kcounts,
+                                               uint32_t* tslot, int* tref) {
     const int n = hdr[0];
+    if (!COUNT) kcounts = nullptr;
+    if (kcounts != nullptr)
+        for (int i = threadIdx.x; i < TC_SLOTS; i += PT)
+            ((LDS_AS uint32_t*)tslot)[i] = 0u;  // first read after the item's barriers
     for (int it = blockIdx.x; it < n; it = next_item(hdr, n, slot_p)) {
         const WorkItem w = items[it];
-        if constexpr (SORTED) {
-            const PartDesc<T>& a = pds[w.inst];
-            if (sorted_candidate(a, w, win_bytes) && item_sorted<SCHEME, P2>(a, w.beg, w.cnt, smem_raw, sh))
-                continue;
-        }
-        item_pass<T, DEP, PUSH, SCHEME, P2>(pds[w.inst], w.beg, w.cnt, smem_raw, win_bytes, sh);
+        const PartDesc<T>& a = pds[w.inst];
+        const TileCount tc{kcounts != nullptr ? kcounts + (size_t)w.inst * MAX_KEYS : nullptr, tslot, tref};
+        bool done = false;
+        if constexpr (SORTED) done = sorted_candidate(a, w, win_bytes) && item_sorted<SCHEME, P2>(a, w.beg, w.cnt, smem_raw, sh, tc);
+        if (!done) item_pass<T, DEP, PUSH, SCHEME, P2>(a, w.beg, w.cnt, smem_raw, win_bytes, sh, tc);
+        tc_flush(tc, a);
     }
 }
 
 // Two-phase passes: FP64 deposit + push, and the deposit-only and push-only
 // passes of both precisions.
-template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2>
+template <typename T, bool DEP, bool PUSH, int SCHEME, bool P2, bool COUNT = false>
 __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<T>* __restrict__ pds,
-                                                  const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
+                                                  const WorkItem* __restrict__ items, int* hdr, int win_bytes,
+                                                  uint32_t* kcounts) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[8];
     __shared__ int slot;
-    particles_body<T, DEP, PUSH, SCHEME, P2, false>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+    __shared__ uint32_t tslot[TC_SLOTS];
+    __shared__ int tref[3];
+    particles_body<T, DEP, PUSH, SCHEME, P2, false, COUNT>(pds, items, hdr, win_bytes, smem_raw, sh, &slot, kcounts,
+                                                           tslot, tref);
 }
 
 // The FP32 two-phase deposit + push pass (items kept in tile order, not
@@ -1000,13 +1162,17 @@ __global__ __launch_bounds__(PT) SIPF_PART_ATTR void k_particles(const PartDesc<
 #ifndef SIPF_TWO_WAVES
 #define SIPF_TWO_WAVES 6
 #endif
-template <int SCHEME, bool P2>
+template <int SCHEME, bool P2, bool COUNT = false>
 __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(SIPF_TWO_WAVES))) void k_particles_two(
-    const PartDesc<float>* __restrict__ pds, const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
+    const PartDesc<float>* __restrict__ pds, const WorkItem* __restrict__ items, int* hdr, int win_bytes,
+    uint32_t* kcounts) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[8];
     __shared__ int slot;
-    particles_body<float, true, true, SCHEME, P2, false>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+    __shared__ uint32_t tslot[TC_SLOTS];
+    __shared__ int tref[3];
+    particles_body<float, true, true, SCHEME, P2, false, COUNT>(pds, items, hdr, win_bytes, smem_raw, sh, &slot,
+                                                                kcounts, tslot, tref);
 }
 
 // The fused deposit + push pass: its two windows (and, in FP32, the sort
@@ -1015,13 +1181,17 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(SIPF_TWO_WAV
 #ifndef SIPF_FUSED_WAVES
 #define SIPF_FUSED_WAVES 4
 #endif
-template <typename T, int SCHEME, bool P2>
+template <typename T, int SCHEME, bool P2, bool COUNT = false>
 __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(SIPF_FUSED_WAVES))) void k_particles_fused(
-    const PartDesc<T>* __restrict__ pds, const WorkItem* __restrict__ items, int* hdr, int win_bytes) {
+    const PartDesc<T>* __restrict__ pds, const WorkItem* __restrict__ items, int* hdr, int win_bytes,
+    uint32_t* kcounts) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int sh[12];
     __shared__ int slot;
-    particles_body<T, true, true, SCHEME, P2, true>(pds, items, hdr, win_bytes, smem_raw, sh, &slot);
+    __shared__ uint32_t tslot[TC_SLOTS];
+    __shared__ int tref[3];
+    particles_body<T, true, true, SCHEME, P2, true, COUNT>(pds, items, hdr, win_bytes, smem_raw, sh, &slot, kcounts,
+                                                           tslot, tref);
 }
 
 // Workgroups of the fused particle pass that are resident on the whole device
@@ -1062,53 +1232,62 @@ template <typename T> int particle_resident_blocks(int scheme, int win_bytes, bo
 
 template <typename T, bool P2>
 static void particles_p2(const PartDesc<T>* pd, const WorkItem* items, int* nitems, dim3 g, bool deposit,
-                         bool push, int scheme, int win_bytes, bool sorted, hipStream_t s) {
+                         bool push, int scheme, int win_bytes, bool sorted, uint32_t* kcounts, hipStream_t s) {
     const dim3 b(PT);
+    // tile counts are taken only by the deposit + push pass, in its COUNT instantiation
+    const bool count = deposit && push && kcounts != nullptr;
+    const bool strang = scheme == SIPF_STRANG;
     if (deposit && push) {
         if constexpr (sizeof(T) == 4) {
             if (!sorted) {
                 const size_t shm = (size_t)win_bytes;
-                if (scheme == SIPF_STRANG)
-                    launch_kernel((k_particles_two<SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+                if (count)
+                    launch_kernel(strang ? k_particles_two<SIPF_STRANG, P2, true> : k_particles_two<SIPF_EM, P2, true>, g,
+                                  b, shm, s, pd, items, nitems, win_bytes, kcounts);
                 else
-                    launch_kernel((k_particles_two<SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+                    launch_kernel(strang ? k_particles_two<SIPF_STRANG, P2> : k_particles_two<SIPF_EM, P2>, g, b, shm, s,
+                                  pd, items, nitems, win_bytes, (uint32_t*)nullptr);
                 return;
             }
             // the sorted pass holds both windows and the sort counters at once
             if (win_bytes < fused_bytes<T>()) win_bytes = fused_bytes<T>();
             const size_t shm = (size_t)win_bytes;
-            if (scheme == SIPF_STRANG)
-                launch_kernel((k_particles_fused<T, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+            if (count)
+                launch_kernel(strang ? k_particles_fused<T, SIPF_STRANG, P2, true> : k_particles_fused<T, SIPF_EM, P2, true>,
+                              g, b, shm, s, pd, items, nitems, win_bytes, kcounts);
             else
-                launch_kernel((k_particles_fused<T, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+                launch_kernel(strang ? k_particles_fused<T, SIPF_STRANG, P2> : k_particles_fused<T, SIPF_EM, P2>, g, b, shm,
+                              s, pd, items, nitems, win_bytes, (uint32_t*)nullptr);
             return;
         }
     }
     const size_t shm = (size_t)win_bytes;
     if (deposit && push) {
         if constexpr (sizeof(T) == 8) {
-            if (scheme == SIPF_STRANG)
-                launch_kernel((k_particles<T, true, true, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems,
-                              win_bytes);
+            if (count)
+                launch_kernel(strang ? k_particles<T, true, true, SIPF_STRANG, P2, true>
+                                     : k_particles<T, true, true, SIPF_EM, P2, true>,
+                              g, b, shm, s, pd, items, nitems, win_bytes, kcounts);
             else
-                launch_kernel((k_particles<T, true, true, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+                launch_kernel(strang ? k_particles<T, true, true, SIPF_STRANG, P2> : k_particles<T, true, true, SIPF_EM, P2>,
+                              g, b, shm, s, pd, items, nitems, win_bytes, (uint32_t*)nullptr);
         }
     } else if (deposit) {
-        launch_kernel((k_particles<T, true, false, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+        launch_kernel((k_particles<T, true, false, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes,
+                      (uint32_t*)nullptr);
     } else if (push) {
-        if (scheme == SIPF_STRANG)
-            launch_kernel((k_particles<T, false, true, SIPF_STRANG, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
-        else
-            launch_kernel((k_particles<T, false, true, SIPF_EM, P2>), g, b, shm, s, pd, items, nitems, win_bytes);
+        launch_kernel(strang ? k_particles<T, false, true, SIPF_STRANG, P2> : k_particles<T, false, true, SIPF_EM, P2>, g,
+                      b, shm, s, pd, items, nitems, win_bytes, (uint32_t*)nullptr);
     }
 }
 
 template <typename T>
 hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* nitems, int grid, bool deposit,
-                            bool push, int scheme, int win_bytes, bool pow2, bool sorted, hipStream_t s) {
+                            bool push, int scheme, int win_bytes, bool pow2, bool sorted, hipStream_t s,
+                            uint32_t* kcounts) {
     if (grid <= 0) return hipSuccess;
-    if (pow2) particles_p2<T, true>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, sorted, s);
-    else particles_p2<T, false>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, sorted, s);
+    if (pow2) particles_p2<T, true>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, sorted, kcounts, s);
+    else particles_p2<T, false>(pd, items, nitems, dim3(grid), deposit, push, scheme, win_bytes, sorted, kcounts, s);
     return hipGetLastError();
 }
 
@@ -1121,23 +1300,6 @@ hipError_t launch_particles(const PartDesc<T>* pd, const WorkItem* items, int* n
 // own segment; the combine pass concatenates the segments into one list that
 // the (persistent) particle pass walks.
 // ---------------------------------------------------------------------------
-// Runs of equal keys in consecutive lanes of a wave (call with the whole
-// wave).  Returns the run's length at its first lane and 0 at the others;
-// head receives the first lane of the caller's run.  The particles are in
-// tile order from the previous sort and mostly still in their tiles, so a
-// wave's 64 keys form one or a few runs: one LDS atomic per run instead of
-// per particle (atomics of a wave on one LDS word serialise).
-__device__ __forceinline__ uint32_t lane_runs(uint32_t key, int& head) {
-    const int lane = (int)(threadIdx.x & 63);
-    const uint32_t prev = __shfl_up(key, 1, 64);
-    const bool first = lane == 0 || prev != key;
-    const uint64_t heads = __ballot(first);
-    head = 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));  // bit 0 is always set
-    if (!first) return 0u;
-    const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
-    return after ? (uint32_t)__builtin_ctzll(after) + 1u : (uint32_t)(64 - lane);
-}
-
 template <typename T, int DIM>
 __global__ __launch_bounds__(SORT_THREADS) void k_tile_hist(const PartDesc<T>* __restrict__ pds,
                                                             const SortChunk* __restrict__ chunks,
@@ -1258,6 +1420,23 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const PartDesc<T>* __restric
     }
     uint32_t sc[3] = {sum, ibig, ismall}, tot[3];
     block_exclusive_scan_n<3>(sc, part, tot);
+    if (tot[0] != (uint32_t)pds[inst].P) {
+        // the counts do not add up to the particle count: list no work items
+        // (the scatter drops what would land outside the array) and flag it
+        for (int j = 0; j < PER; ++j) {
+            const int i = tid * PER + j;
+            if (i < nk) {
+                cur[i] = (uint32_t)pds[inst].P;  // every scatter target lands past the end
+                cnt[i] = 0u;
+            }
+        }
+        if (tid == 0) {
+            seg_n[inst] = 0;
+            if constexpr (DIRECT) nitems[0] = 0;
+            atomicOr(pds[inst].err, 4);
+        }
+        return;
+    }
     const uint32_t tbig = tot[1], tsmall = tot[2];
     uint32_t run = sc[0];
     uint32_t rbig = sc[1];
@@ -1373,10 +1552,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_scatter(const PartDesc<T>
     for (int k = 0; k < SORT_PER_THREAD; ++k) {
         if (ch.beg + tid + (int64_t)k * SORT_THREADS < end) {
             const uint32_t d = lc[key[k]] + rank[k];
-            gp(b.x)[d] = px[k];
-            gp(b.y)[d] = py[k];
-            if constexpr (DIM == 3) gp(b.z)[d] = pz[k];
-            gp(b.id)[d] = pid[k];
+            if (d < (uint32_t)b.P) {
+                gp(b.x)[d] = px[k];
+                gp(b.y)[d] = py[k];
+                if constexpr (DIM == 3) gp(b.z)[d] = pz[k];
+                gp(b.id)[d] = pid[k];
+            } else {
+                atomicOr(b.err, 4);
+            }
         }
     }
 }
@@ -1386,11 +1569,13 @@ int sort_chunk() { return SORT_CHUNK; }
 template <typename T>
 hipError_t launch_sort(int dim, const PartDesc<T>* src, const PartDesc<T>* dst, const SortChunk* chunks, int nchunks,
                        int ninst, uint32_t* counts, uint32_t* cursor, WorkItem* seg, const int* seg_off, int* seg_n,
-                       WorkItem* items, int* nitems, int chunk, hipStream_t s) {
+                       WorkItem* items, int* nitems, int chunk, hipStream_t s, bool counted) {
     if (chunk <= 0 || chunk > CH) chunk = CH;
     if (ninst < 1 || ninst > 1024 || (dim != 2 && dim != 3)) return hipErrorInvalidValue;
-    if (dim == 3) launch_kernel((k_tile_hist<T, 3>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
-    else launch_kernel((k_tile_hist<T, 2>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+    if (!counted) {
+        if (dim == 3) launch_kernel((k_tile_hist<T, 3>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+        else launch_kernel((k_tile_hist<T, 2>), dim3(nchunks), dim3(SORT_THREADS), 0, s, src, chunks, counts);
+    }
     if (ninst == 1) {
         launch_kernel((k_tile_scan<T, true>), dim3(1), dim3(1024), 0, s, src, counts, cursor, items, seg_off, seg_n,
                       chunk, nitems);
@@ -1511,10 +1696,10 @@ hipError_t launch_philox_dbg(uint64_t seed, int64_t n, const uint32_t* ctr, uint
 #define SIPF_INST(T)                                                                                              \
     template int particle_resident_blocks<T>(int, int, bool);                                                     \
     template hipError_t launch_particles<T>(const PartDesc<T>*, const WorkItem*, int*, int, bool, bool, int, \
-                                            int, bool, bool, hipStream_t);                                        \
+                                            int, bool, bool, hipStream_t, uint32_t*);                             \
     template hipError_t launch_sort<T>(int, const PartDesc<T>*, const PartDesc<T>*, const SortChunk*, int, int,   \
                                        uint32_t*, uint32_t*, WorkItem*, const int*, int*, WorkItem*, int*, int,    \
-                                       hipStream_t);                                                               \
+                                       hipStream_t, bool);                                                         \
     template hipError_t launch_load_positions<T>(const T*, int64_t, T, PartDesc<T>, int*, hipStream_t);          \
     template hipError_t launch_unsort<T>(const PartDesc<T>*, T*, hipStream_t);                                    \
     template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                              \

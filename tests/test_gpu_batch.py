@@ -8,6 +8,7 @@ the summation order of the deposit, never the arithmetic.
 """
 
 import os
+import math
 import sys
 
 import numpy as np
@@ -182,6 +183,62 @@ def test_graph_replay_matches_eager(precision, tol):
         assert np.abs(osipf.min_image(Xa - Xo, 2.0)).max() < 1e-9
     a.close()
     e.close()
+
+
+@pytest.mark.parametrize("resort,pp", [(1, "two_phase"), (2, "sorted"), (3, "two_phase"), (5, "sorted")])
+def test_sort_counts_taken_by_the_particle_pass(resort, pp):
+    """The step before each re-sort counts its particles' tiles in the particle
+    pass and the sort skips its histogram; the sort's scan checks that the
+    counts add up to P (a mismatch raises at the next read).  Graph replay,
+    eager stepping, a batch and the adjoint (whose segment sorts take their own
+    histogram after the forward) agree, in FP64 with the oracle."""
+    say("counted sorts", resort, pp)
+    X0 = workloads.mix(6000, 0.15, seed=7)
+    kw = dict(L=2.0, chi=2.0, mu=1.0, eps=1.0, k=1.0, M0=60.0, dt=1e-3, H=32, seed=4, resort_every=resort,
+              particle_pass=pp)
+    # FP64: graph replay and eager stepping against the oracle
+    a = pkg.Sim(X0, precision="fp64", **kw)
+    e = pkg.Sim(X0, precision="fp64", **kw)
+    e.use_graphs(False)
+    for chunk in (4, 11, 2, 7):
+        a.run(chunk)
+        e.run(chunk)
+    Xo, _ = osipf.run(X0, oparams(**kw), 24)
+    for s in (a, e):
+        X = to_np(s.positions()).astype(np.float64)
+        assert np.abs(osipf.min_image(X - Xo, 2.0)).max() < 1e-9
+        s.close()
+    # FP32 batch of three instances (two grid sizes) against standalone contexts
+    # (the workloads' time step: FP32 rounding differences between the two
+    # sort orders stay at rounding level over the 17 steps)
+    inst = [dict(params=dict(kw, H=H, instance=i, precision="fp32", dt=5e-5),
+                 X0=workloads.blob(P, 0.15, seed=20 + i).astype(np.float32))
+            for i, (H, P) in enumerate(((32, 5000), (16, 3001), (32, 777)))]
+    b = pkg.Batch(inst)
+    b.run(17)
+    for i, it in enumerate(inst):
+        sim = pkg.Sim(it["X0"], **it["params"])
+        sim.run(17)
+        Xb, Xs = to_np(b.positions(i)).astype(np.float64), to_np(sim.positions()).astype(np.float64)
+        assert np.abs(osipf.min_image(Xb - Xs, 2.0)).max() < 1e-5, i
+        sim.close()
+    b.close()
+
+
+def test_adjoint_after_a_counting_step():
+    """A forward whose last step counted the tiles of a sort it never runs:
+    the adjoint's own segment sorts start from clear counts."""
+    kw = dict(L=2.0, chi=1.0, mu=1.0, eps=1.0, k=1.0, M0=40.0, dt=1e-3, H=16, seed=2, resort_every=3,
+              precision="fp64")
+    X0 = workloads.blob(2000, 0.15, seed=9)
+    sim = pkg.Sim(X0, **kw)
+    loss, dchi, dmu, dX0 = sim.adjoint(5, ckpt_every=2)  # steps 1..5: step 5 counts for the sort due at step 6
+    sim.run(4)  # the restored context keeps stepping (its re-sort after the adjoint takes a histogram)
+    X = to_np(sim.positions()).astype(np.float64)
+    Xo, _ = osipf.run(X0, oparams(**kw), 9)
+    assert np.abs(osipf.min_image(X - Xo, 2.0)).max() < 1e-9
+    assert math.isfinite(loss) and math.isfinite(dchi) and math.isfinite(dmu)
+    sim.close()
 
 
 def test_snapshot_round_trip(tmp_path):
