@@ -50,7 +50,10 @@ def step_algorithmic_bytes(P, H, tsize):
 def implementation_bytes(phase, P, H, tsize):
     """Bytes each pass of this implementation touches at least once: the
     algorithmic bytes plus ids (the noise counter), the half spectra passed
-    between the transform passes, and the re-sort's reads and writes."""
+    between the transform passes, and the re-sort's scatter, which reads and
+    writes X and the ids (the re-sorts of a 3-D run take their tile counts
+    from the particle pass of the step before, so no histogram pass reads X
+    again)."""
     spec = 2 * tsize * H * H * (H // 2 + 1)
     grid = tsize * H ** 3
     if phase == "particles":
@@ -62,7 +65,7 @@ def implementation_bytes(phase, P, H, tsize):
     if phase == "inv_planes":
         return 3 * spec + 3 * grid
     if phase == "sort":
-        return 3 * tsize * P + 2 * (3 * tsize + 4) * P
+        return 2 * (3 * tsize + 4) * P
     return 0
 
 
