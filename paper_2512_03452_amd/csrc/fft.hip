@@ -13,7 +13,7 @@
 //               spectrum (kz = 0..H/2); then the plane is transformed along y.
 //               Also zeroes the deposit grid for the next step and advances
 //               the step counter.
-//   xpencils    one workgroup per (ky, 16 kz) block of x-pencils: transform
+//   xpencils    one workgroup per 16 consecutive (ky, kz) x-pencils: transform
 //               along x, alpha <- A alpha + B beta, form i xi_d Phi alpha for
 //               d = 0,1,2 and inverse-transform each along x.
 //   inv_planes  one workgroup per (component, x-plane): inverse along y, then
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(FWD_THREADS) void k_fwd_planes(const FieldDesc<T>* 
 // Pass 2: x-pencils, mode update, filtered gradient spectra, inverse along x.
 // ---------------------------------------------------------------------------
 template <typename T, int H, int MODE>
-__device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp, int kz0, int ncol, T qy, int ky,
+__device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int c0, int ncol, T qy, int ky, int kz,
                                                 cplx_t<T>* lds, const cplx_t<T>* tw);
 
 // MODE_STEP: forward x of B1, mode update of alpha, three gradient spectra
@@ -197,8 +197,16 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
 //            right after accumulating it).
 enum { MODE_STEP = 0, MODE_GRAD = 1, MODE_ADJ_SRC = 2, MODE_ADJ_ACC = 3, MODE_RHO = 4, MODE_ADJ_ACC_SRC = 5 };
 
+// A block is KB consecutive columns of the half spectrum flattened over
+// (ky, kz) (column c = ky_position (H/2 + 1) + kz), all H x rows of each: a
+// row of the block is KB contiguous values starting at a multiple of KB, one
+// aligned 128-byte line in FP32 (blocks of KB kz values of one ky straddled
+// two lines, since H/2 + 1 is odd).  Every entry a thread touches lies in the
+// same column (the thread count is a multiple of KB), so ky and kz are the
+// thread's own.
+//
 // At H = 128 (FP32) the registers are budgeted for three workgroups per CU
-// (six waves per SIMD), so that all 640 blocks are resident at once; smaller
+// (six waves per SIMD), so that all 520 blocks are resident at once; smaller
 // grids have fewer blocks than CUs and leave the count to the compiler.
 template <typename T, int H, int MODE>
 __global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(H >= 128 ? 6 : 1))) void k_xpencils(
@@ -206,28 +214,32 @@ __global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(
     constexpr bool UPDATE = MODE == MODE_STEP;
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
-    constexpr int NKB = (HH + KB - 1) / KB;
+    constexpr int NC = H * HH;       // columns (ky, kz): the pitch of an x row in HBM
     constexpr int BP = KB + 1;       // pitch (complex) of one x row in LDS, one grid
     constexpr int BP3 = 3 * KB + 1;  // the same for the three gradient components side by side
     constexpr int NB = H * KB;       // entries of the block
     constexpr int NT = PENCIL_THREADS;
     constexpr int R = (NB + NT - 1) / NT;
+    static_assert(NT % KB == 0, "a thread's entries share one column");
     __shared__ V lds[H * BP3];
     __shared__ V tw[H];
     V* buf = lds;
     const FieldDesc<T>& fd = fds[blockIdx.y];
-    const int kyp = blockIdx.x / NKB;
-    const int kz0 = (blockIdx.x % NKB) * KB;
-    const int ncol = min(KB, HH - kz0);
+    const int c0 = blockIdx.x * KB;
+    const int ncol = min(KB, NC - c0);
     const int tid = threadIdx.x;
     make_twiddles<T, H>(tw);
+    // the thread's column (a column past ncol takes the last valid one)
+    const int cc = c0 + min(tid % KB, ncol - 1);
+    const int kyp = cc / HH;
+    const int kz = cc - kyp * HH;
     const int ky = perm_freq<H>(kyp);
     const T qy = (T)(ky < H / 2 ? ky : ky - H);
     // entry u of the block: x row (or permuted kx position) u / KB, column u % KB
     // (columns past ncol read the last valid one and are written as zero)
-    auto gidx = [&](int u) { return ((size_t)(u / KB) * H + kyp) * HH + kz0 + min(u % KB, ncol - 1); };
+    auto gidx = [&](int u) { return (size_t)(u / KB) * NC + c0 + min(u % KB, ncol - 1); };
     if constexpr (MODE == MODE_ADJ_SRC || MODE == MODE_ADJ_ACC || MODE == MODE_ADJ_ACC_SRC) {
-        adjoint_pencils<T, H, MODE>(fd, kyp, kz0, ncol, qy, ky, lds, tw);
+        adjoint_pencils<T, H, MODE>(fd, c0, ncol, qy, ky, kz, lds, tw);
         return;
     }
     const V zero = cmake<V, T>(0, 0);
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(
             const int p = u / KB, j = u % KB;
             const int kx = perm_freq<H>(p);
             const T qx = (T)(kx < H / 2 ? kx : kx - H);
-            const T qz = (T)(kz0 + j);
+            const T qz = (T)kz;
             const T q2 = qx * qx + qy * qy + qz * qz;
             const T f = (fd.filt > (T)0 ? exp(-fd.filt * q2) : (T)1) * fd.inv_Ld;
             const V b = buf[p * BP + j];
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(
         if (u < NB && j < ncol) {
             const int kx = perm_freq<H>(p);
             const T qx = (T)(kx < H / 2 ? kx : kx - H);
-            const T qz = (T)(kz0 + j);
+            const T qz = (T)kz;
             const T q2 = qx * qx + qy * qy + qz * qz;
             a = av[q];
             if (UPDATE) {
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(
         const int u = tid + q * NT;
         if (u < NB) {
             const int p = u / KB, j = u % KB;
-            const int kd[3] = {perm_freq<H>(p), ky, kz0 + j};
+            const int kd[3] = {perm_freq<H>(p), ky, kz};
             const V a = av[q];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(PENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(
 // lds holds H (3 KB + 1) values: one grid block at pitch KB + 1, or the three
 // components side by side at pitch 3 KB + 1.
 template <typename T, int H, int MODE>
-__device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp, int kz0, int ncol, T qy, int ky,
+__device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int c0, int ncol, T qy, int ky, int kz,
                                                 cplx_t<T>* lds, const cplx_t<T>* tw) {
     using V = cplx_t<T>;
     constexpr int HH = H / 2 + 1;
@@ -334,10 +346,10 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
     constexpr int R = (NB + NT - 1) / NT;
     const int tid = threadIdx.x;
     const V zero = cmake<V, T>(0, 0);
-    auto gidx = [&](int u) { return ((size_t)(u / KB) * H + kyp) * HH + kz0 + min(u % KB, ncol - 1); };
-    auto factors = [&](int p, int j, T& A, T& B, T& phi, T (&xi)[3]) {
+    constexpr int NC = H * HH;
+    auto gidx = [&](int u) { return (size_t)(u / KB) * NC + c0 + min(u % KB, ncol - 1); };
+    auto factors = [&](int p, T& A, T& B, T& phi, T (&xi)[3]) {
         const int kx = perm_freq<H>(p);
-        const int kz = kz0 + j;
         const T qx = (T)(kx < H / 2 ? kx : kx - H);
         const T qz = (T)kz;
         const T q2 = qx * qx + qy * qy + qz * qz;
@@ -366,7 +378,7 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
                              V v = zero;
                              if (j < ncol) {
                                  T A, B, phi, xi[3];
-                                 factors(p, j, A, B, phi, xi);
+                                 factors(p, A, B, phi, xi);
                                  const T sc = B * fd.inv_Ld;
                                  v = cmake<V, T>(a.x * sc, a.y * sc);
                              }
@@ -393,7 +405,7 @@ __device__ __forceinline__ void adjoint_pencils(const FieldDesc<T>& fd, int kyp,
             V out = zero;
             if (u < NB && j < ncol) {
                 T A, B, phi, xi[3];
-                factors(p, j, A, B, phi, xi);
+                factors(p, A, B, phi, xi);
                 V acc = zero;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
@@ -676,8 +688,7 @@ static hipError_t fwd_planes_h(const FieldDesc<T>* fd, int count, int ncomp, boo
 }
 template <typename T, int H>
 static hipError_t xpencils_h(const FieldDesc<T>* fd, int count, int mode, hipStream_t s) {
-    constexpr int NKB = (H / 2 + 1 + KB - 1) / KB;
-    const dim3 g(H * NKB, count), b(PENCIL_THREADS);
+    const dim3 g((H * (H / 2 + 1) + KB - 1) / KB, count), b(PENCIL_THREADS);
     switch (mode) {
         case MODE_STEP: launch_kernel((k_xpencils<T, H, MODE_STEP>), g, b, 0, s, fd); break;
         case MODE_GRAD: launch_kernel((k_xpencils<T, H, MODE_GRAD>), g, b, 0, s, fd); break;
