@@ -1375,6 +1375,11 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     // 48 bytes per particle written and read once).  FP32 redraws them: there
     // the draw hides under the pass's other work.
     const bool keep_noise = sizeof(T) == 8 && K > 1;
+    // The gradient grids of a segment's taped alpha states do not depend on
+    // its recomputed positions: they are made GB steps at a time in one
+    // batched launch per field pass (each step with its own spectra), instead
+    // of one small launch pair per step.
+    const int GB = std::min(K, 16);
     if ((rc = need(tape, (size_t)N * nspec * sizeof(V)))) return rc;
     if ((rc = need(ckpt, (size_t)nseg * pos_bytes))) return rc;
     if ((rc = need(seg, (size_t)K * pos_bytes))) return rc;
@@ -1385,7 +1390,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
     if ((rc = need(phibar, H3 * sizeof(T)))) return rc;
     if ((rc = need(abar, nspec * sizeof(V)))) return rc;
     if ((rc = need(aN, nspec * sizeof(V)))) return rc;
-    if ((rc = need(scr, 3 * nspec * sizeof(V)))) return rc;
+    if ((rc = need(scr, (size_t)GB * 3 * nspec * sizeof(V)))) return rc;
     if ((rc = need(gs1, nspec * sizeof(V)))) return rc;
     if ((rc = need(fdS, sizeof(FieldDesc<T>)))) return rc;
     if ((rc = need(fdA, sizeof(FieldDesc<T>)))) return rc;
@@ -1426,7 +1431,7 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         for (int64_t t = 0; t < N; ++t) {
             fr[t] = make_fdesc<T>(c, 0);
             fr[t].alpha = (V*)tape.p + (size_t)t * nspec;
-            fr[t].gspec = (V*)scr.p;
+            fr[t].gspec = (V*)scr.p + (size_t)((t % K) % GB) * 3 * nspec;
             fr[t].G = gseg + (size_t)(t % K) * 3 * H3;
             fr[t].step = nullptr;
             // reads segment slot t mod K, writes slot t mod K + 1 (used while that is < K)
@@ -1459,9 +1464,14 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         HIPCHK(launch_iota_u32((uint32_t*)consts.p, N, c->stream));
     }
     const FieldDesc<T>* fr_dev = (const FieldDesc<T>*)fdR.p;
-    auto grad_of_tape = [&](int64_t t) -> int {
-        HIPCHK(launch_xpencils<T>(H, fr_dev + t, 1, XP_GRAD, c->stream));
-        HIPCHK(launch_inv_planes<T>(H, fr_dev + t, 1, 3, c->stream));
+    // gradient grids of the taped alpha^(t), t = t0 .. t0 + len - 1 (within one
+    // segment), into the segment store
+    auto grad_of_tape = [&](int64_t t0, int len) -> int {
+        for (int b = 0; b < len; b += GB) {
+            const int cnt = std::min(GB, len - b);
+            HIPCHK(launch_xpencils<T>(H, fr_dev + t0 + b, cnt, XP_GRAD, c->stream));
+            HIPCHK(launch_inv_planes<T>(H, fr_dev + t0 + b, cnt, 3, c->stream));
+        }
         return SIPF_OK;
     };
 
@@ -1539,13 +1549,12 @@ int adjoint_typed(Group* c, int64_t N, int K, const T* phibar_in, double* loss_o
         const int len = (int)std::min<int64_t>(K, N - base);
         HIPCHK(launch_sort<T>(3, ps_dev + sgi, ps_dev + nseg, c->chunks, c->nchunks, 1, c->counts, c->cursor, c->seg,
                               c->seg_off, c->seg_n, c->items, c->nitems, c->adj_chunk, c->stream));
-        if ((rc = grad_of_tape(base))) return rc;
+        if ((rc = grad_of_tape(base, len))) return rc;
         for (int m = 1; m < len; ++m) {
             // X^(base+m) = push of X^(base+m-1) (slot m-1 -> slot m) with G^(base+m-1)
-            // (step base+m), then G^(base+m)
+            // (step base+m)
             HIPCHK(launch_particles<T>((const PartDesc<T>*)pdR.p + (base + m - 1), c->items, c->nitems, c->pgrid,
                                        false, true, c->scheme, c->win_bytes, c->pow2, c->sorted, c->stream));
-            if ((rc = grad_of_tape(base + m))) return rc;
         }
         {
             T *x, *y, *z;
