@@ -35,6 +35,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("precision,H,P,N,K,scheme", [
+    ("fp64", 8, 300, 4, 2, "strang"),  # 40 (ky, kz) columns: a part-filled x-pencil block
     ("fp64", 16, 400, 5, 2, "strang"),
     ("fp64", 16, 300, 4, 4, "em"),
     ("fp64", 32, 1000, 6, 5, "strang"),
